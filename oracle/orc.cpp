@@ -1,0 +1,678 @@
+// orc.cpp -- FP64 CPU reference for the Yee FDTD hot path (test infrastructure).
+//
+// Plain triple loops, one per field component, written from the equations of
+// Section 2.1 of the paper (eqs. 2-5) and the readings stated below.  No
+// tiling, no fusion, no reordering beyond "all H, then all E, then the
+// sources, then the probes" within a step.  OpenMP splits the outer k loop of
+// each component update; every update reads only values that the same loop
+// does not write, so the result is independent of the thread count.
+#include "orc.h"
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+#include <omp.h>
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+const double kMu0 = 4.0e-7 * kPi;                 // H/m
+const double kC0 = 299792458.0;                   // m/s
+const double kEps0 = 1.0 / (kMu0 * kC0 * kC0);    // F/m
+const double kEta0 = std::sqrt(kMu0 / kEps0);     // ohm
+
+// A 3D array of doubles with its own extent (x fastest).
+struct A3 {
+  int n0 = 0, n1 = 0, n2 = 0;
+  std::vector<double> v;
+  void init(int a, int b, int c, double x = 0.0) {
+    n0 = a; n1 = b; n2 = c;
+    v.assign((size_t)a * b * c, x);
+  }
+  double& operator()(int i, int j, int k) { return v[((size_t)k * n1 + j) * n0 + i]; }
+  bool in(int i, int j, int k) const {
+    return i >= 0 && j >= 0 && k >= 0 && i < n0 && j < n1 && k < n2;
+  }
+};
+
+struct Wire { int axis, p[3], n; double radius; };
+struct Source { int axis, p[3]; std::vector<double> amps; };
+struct Probe { int kind, axis, p[3], n; std::vector<double> rec; };
+
+}  // namespace
+
+struct orc_sim {
+  orc_params P{};
+  double dx = 0, dt = 0;
+  int N[3] = {0, 0, 0};
+  bool finalized = false;
+  long step = 0;
+  std::string err;
+
+  // per-cell materials (x fastest)
+  std::vector<double> c_eps, c_sig, c_mu;
+  std::vector<Wire> wires;
+  std::vector<Source> srcs;
+  std::vector<Probe> probes;
+
+  // fields at their natural Yee extents
+  A3 E[3], H[3];
+  // per-edge / per-face material and coefficients
+  A3 eps[3], sig[3], mu[3], Ca[3], Cb[3], Db[3];
+  std::vector<char> pec[3];         // wire axial edges (perfect conductor)
+  std::vector<char> emod[3], hmod[3];  // already modified by an earlier wire
+  // CPML: psi[c][u] for component c (0..2 E, 3..5 H) and derivative axis u
+  A3 psi[6][3];
+  std::vector<double> be[3], ce[3], ike[3], bh[3], ch[3], ikh[3];
+};
+
+namespace {
+
+int fail(orc_sim* s, int code, const std::string& msg) {
+  s->err = msg;
+  return code;
+}
+
+// Natural extents: E_a has N_a entries along a and N_b + 1 along the others;
+// H_a has N_a + 1 along a and N_b along the others.
+void e_extent(const orc_sim* s, int a, int ext[3]) {
+  for (int b = 0; b < 3; ++b) ext[b] = (b == a) ? s->N[b] : s->N[b] + 1;
+}
+void h_extent(const orc_sim* s, int a, int ext[3]) {
+  for (int b = 0; b < 3; ++b) ext[b] = (b == a) ? s->N[b] + 1 : s->N[b];
+}
+
+size_t cell_index(const orc_sim* s, int i, int j, int k) {
+  return ((size_t)k * s->N[1] + j) * s->N[0] + i;
+}
+
+bool cell_in(const orc_sim* s, const int c[3]) {
+  for (int b = 0; b < 3; ++b)
+    if (c[b] < 0 || c[b] >= s->N[b]) return false;
+  return true;
+}
+
+// Is the E_a edge at node p one that the update touches?  Tangential E on the
+// six outer faces is held at zero (perfect conductor walls).
+bool e_interior(const orc_sim* s, int a, const int p[3]) {
+  for (int b = 0; b < 3; ++b) {
+    if (b == a) {
+      if (p[b] < 0 || p[b] >= s->N[b]) return false;
+    } else {
+      if (p[b] < 1 || p[b] > s->N[b] - 1) return false;
+    }
+  }
+  return true;
+}
+
+// Interface rules (the paper is silent): eps and sigma of an edge are the
+// arithmetic mean over the in-domain cells that share the edge (tangential E
+// is continuous across interfaces, so the cells act in parallel); mu of a
+// face is the harmonic mean of the cells on either side (normal B is
+// continuous, so they act in series).
+void build_materials(orc_sim* s) {
+  for (int a = 0; a < 3; ++a) {
+    int ext[3];
+    e_extent(s, a, ext);
+    s->eps[a].init(ext[0], ext[1], ext[2], kEps0);
+    s->sig[a].init(ext[0], ext[1], ext[2], 0.0);
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    for (int k = 0; k < ext[2]; ++k)
+      for (int j = 0; j < ext[1]; ++j)
+        for (int i = 0; i < ext[0]; ++i) {
+          const int p[3] = {i, j, k};
+          double se = 0, ss = 0;
+          int cnt = 0;
+          for (int db = -1; db <= 0; ++db)
+            for (int dc = -1; dc <= 0; ++dc) {
+              int q[3] = {p[0], p[1], p[2]};
+              q[b] += db;
+              q[c] += dc;
+              if (!cell_in(s, q)) continue;
+              const size_t ci = cell_index(s, q[0], q[1], q[2]);
+              se += s->c_eps[ci];
+              ss += s->c_sig[ci];
+              ++cnt;
+            }
+          if (cnt) {
+            s->eps[a](i, j, k) = se / cnt;
+            s->sig[a](i, j, k) = ss / cnt;
+          }
+        }
+    h_extent(s, a, ext);
+    s->mu[a].init(ext[0], ext[1], ext[2], kMu0);
+    for (int k = 0; k < ext[2]; ++k)
+      for (int j = 0; j < ext[1]; ++j)
+        for (int i = 0; i < ext[0]; ++i) {
+          double inv = 0;
+          int cnt = 0;
+          for (int da = -1; da <= 0; ++da) {
+            int q[3] = {i, j, k};
+            q[a] += da;
+            if (!cell_in(s, q)) continue;
+            inv += 1.0 / s->c_mu[cell_index(s, q[0], q[1], q[2])];
+            ++cnt;
+          }
+          if (cnt) s->mu[a](i, j, k) = cnt / inv;
+        }
+    s->pec[a].assign(s->E[a].v.size(), 0);
+    s->emod[a].assign(s->E[a].v.size(), 0);
+    s->hmod[a].assign(s->H[a].v.size(), 0);
+  }
+}
+
+// Thin wire (Section 2.3, the assigned-parameter modification model).  The
+// paper cites the model without formulas; the reading used here:
+//  * the wire's own (axial) edges are perfect conductors;
+//  * the four radial E edges at every wire node have eps and sigma multiplied
+//    by m = ln(dx / r0) / ln(dx / a), r0 = wire_r0_factor * dx being the
+//    equivalent radius of a bare conductor edge (default exp(-pi/2) dx);
+//  * the four H components circulating around every wire segment, and
+//    around the one segment beyond each end, have mu divided by m;
+//  * the four H components parallel to the wire around every wire node have
+//    mu divided by m.
+// The last two rules keep every coupling of a radial edge at its unmodified
+// strength: scaling only the radial edges and the circulating H inside the
+// wire raises the coupling of a radial edge to its parallel H and to the
+// circulating H past an end by 1/sqrt(m), which pushes the scheme past its
+// stability limit at 0.99 of the Courant step.  All changes are material
+// changes, so the discrete energy identity of the Yee scheme still holds.
+// A perfect-conductor edge ignores any modification; a component next to two
+// wires keeps the factor of the first wire added.
+void scale_mu(orc_sim* s, int a, const int p[3], double m) {
+  A3& h = s->mu[a];
+  if (!h.in(p[0], p[1], p[2])) return;
+  const size_t li = ((size_t)p[2] * h.n1 + p[1]) * h.n0 + p[0];
+  if (s->hmod[a][li]) return;
+  s->hmod[a][li] = 1;
+  h.v[li] /= m;
+}
+
+void apply_wires(orc_sim* s) {
+  for (const Wire& w : s->wires) {
+    const int u = w.axis, v = (u + 1) % 3, x = (u + 2) % 3;
+    const double m = std::log(1.0 / s->P.wire_r0_factor) / std::log(s->dx / w.radius);
+    for (int t = 0; t < w.n; ++t) {  // axial edges
+      int p[3] = {w.p[0], w.p[1], w.p[2]};
+      p[u] += t;
+      if (s->E[u].in(p[0], p[1], p[2]))
+        s->pec[u][((size_t)p[2] * s->E[u].n1 + p[1]) * s->E[u].n0 + p[0]] = 1;
+    }
+    for (int t = 0; t <= w.n; ++t) {  // radial edges at every wire node
+      for (int d = -1; d <= 0; ++d) {
+        const int ax[2] = {v, x};
+        for (int r = 0; r < 2; ++r) {
+          const int a = ax[r];
+          int p[3] = {w.p[0], w.p[1], w.p[2]};
+          p[u] += t;
+          p[a] += d;
+          A3& e = s->eps[a];
+          if (!e.in(p[0], p[1], p[2])) continue;
+          const size_t li = ((size_t)p[2] * e.n1 + p[1]) * e.n0 + p[0];
+          if (s->emod[a][li]) continue;
+          s->emod[a][li] = 1;
+          s->eps[a].v[li] *= m;
+          s->sig[a].v[li] *= m;
+        }
+      }
+    }
+    for (int t = -1; t <= w.n; ++t) {  // circulating H, segments s0-1 .. s1
+      // H_v sits at v = wire, x = wire +- 1/2; H_x at x = wire, v = wire +- 1/2.
+      for (int d = -1; d <= 0; ++d) {
+        int p[3] = {w.p[0], w.p[1], w.p[2]};
+        p[u] += t;
+        p[x] += d;
+        scale_mu(s, v, p, m);
+        int q[3] = {w.p[0], w.p[1], w.p[2]};
+        q[u] += t;
+        q[v] += d;
+        scale_mu(s, x, q, m);
+      }
+    }
+    for (int t = 0; t <= w.n; ++t)  // parallel H around every node
+      for (int dv = -1; dv <= 0; ++dv)
+        for (int dx = -1; dx <= 0; ++dx) {
+          int p[3] = {w.p[0], w.p[1], w.p[2]};
+          p[u] += t;
+          p[v] += dv;
+          p[x] += dx;
+          scale_mu(s, u, p, m);
+        }
+  }
+}
+
+// Lossy coefficients for E = Ca E + Cb curl H.  Literal eq. 4:
+// Ca = 1 - sigma dt / eps, Cb = dt / eps.  Semi-implicit (sigma E taken at
+// n + 1/2 as the mean of n and n + 1, the modification the paper points to
+// for better accuracy): Ca = (1 - x) / (1 + x), Cb = (dt / eps) / (1 + x),
+// x = sigma dt / (2 eps).  H: Db = dt / mu (eq. 5).
+int build_coefficients(orc_sim* s) {
+  const double dt = s->dt;
+  for (int a = 0; a < 3; ++a) {
+    const A3& e = s->eps[a];
+    s->Ca[a].init(e.n0, e.n1, e.n2, 0.0);
+    s->Cb[a].init(e.n0, e.n1, e.n2, 0.0);
+    for (size_t li = 0; li < e.v.size(); ++li) {
+      const double ep = s->eps[a].v[li], sg = s->sig[a].v[li];
+      if (s->P.loss_mode == ORC_LOSS_EXPLICIT) {
+        if (sg * dt / ep >= 2.0) return fail(s, ORC_EUNSTABLE, "explicit loss factor below -1");
+        s->Ca[a].v[li] = 1.0 - sg * dt / ep;
+        s->Cb[a].v[li] = dt / ep;
+      } else {
+        const double x = sg * dt / (2.0 * ep);
+        s->Ca[a].v[li] = (1.0 - x) / (1.0 + x);
+        s->Cb[a].v[li] = (dt / ep) / (1.0 + x);
+      }
+    }
+    const A3& m = s->mu[a];
+    s->Db[a].init(m.n0, m.n1, m.n2, 0.0);
+    for (size_t li = 0; li < m.v.size(); ++li) s->Db[a].v[li] = dt / m.v[li];
+  }
+  return ORC_OK;
+}
+
+// Convolutional PML (Section 2.2; recursive convolution).  Depth rho (cells)
+// is measured from the inner face of the layer at the component's own
+// position along the axis; s = rho / npml;
+//   sigma = sigma_max s^m,  kappa = 1 + (kappa_max - 1) s^m,
+//   alpha = alpha_max (1 - s)^m_a,  b = exp(-(sigma / kappa + alpha) dt / eps0),
+//   c = sigma (b - 1) / (kappa (sigma + kappa alpha)),
+// sigma_max = sigma_factor * 0.8 (m + 1) / (eta0 dx).  Outside the layer
+// b = c = 0 and 1/kappa = 1, so psi stays 0 and the term is the plain
+// difference.
+void profile_at(const orc_sim* s, int n_ax, double pos, double& b, double& c, double& ik) {
+  b = 0.0; c = 0.0; ik = 1.0;
+  const int np = s->P.npml;
+  if (np <= 0) return;
+  double rho = 0.0;
+  if (pos < np) rho = np - pos;
+  if (pos > n_ax - np) rho = pos - (n_ax - np);
+  if (rho <= 0.0) return;
+  const double sfrac = rho / np;
+  const double m = s->P.pml_m;
+  const double smax = s->P.pml_sigma_factor * 0.8 * (m + 1.0) / (kEta0 * s->dx);
+  const double sg = smax * std::pow(sfrac, m);
+  const double ka = 1.0 + (s->P.pml_kappa_max - 1.0) * std::pow(sfrac, m);
+  const double al = s->P.pml_alpha_max * std::pow(1.0 - sfrac, s->P.pml_ma);
+  b = std::exp(-(sg / ka + al) * s->dt / kEps0);
+  c = (sg > 0.0) ? sg * (b - 1.0) / (ka * (sg + ka * al)) : 0.0;
+  ik = 1.0 / ka;
+}
+
+void build_cpml(orc_sim* s) {
+  for (int u = 0; u < 3; ++u) {
+    const int n = s->N[u];
+    s->be[u].resize(n + 1); s->ce[u].resize(n + 1); s->ike[u].resize(n + 1);
+    s->bh[u].resize(n); s->ch[u].resize(n); s->ikh[u].resize(n);
+    for (int p = 0; p <= n; ++p) profile_at(s, n, p, s->be[u][p], s->ce[u][p], s->ike[u][p]);
+    for (int p = 0; p < n; ++p) profile_at(s, n, p + 0.5, s->bh[u][p], s->ch[u][p], s->ikh[u][p]);
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int u = 0; u < 3; ++u) {
+      if (u == a) continue;
+      s->psi[a][u].init(s->E[a].n0, s->E[a].n1, s->E[a].n2);
+      s->psi[3 + a][u].init(s->H[a].n0, s->H[a].n1, s->H[a].n2);
+    }
+}
+
+int finalize(orc_sim* s) {
+  if (s->finalized) return ORC_OK;
+  for (int a = 0; a < 3; ++a) {
+    int ext[3];
+    e_extent(s, a, ext);
+    s->E[a].init(ext[0], ext[1], ext[2]);
+    h_extent(s, a, ext);
+    s->H[a].init(ext[0], ext[1], ext[2]);
+  }
+  for (const Source& q : s->srcs)
+    for (const Wire& w : s->wires)
+      if (w.axis == q.axis) {
+        const int u = w.axis;
+        bool on = true;
+        for (int b = 0; b < 3; ++b)
+          if (b != u && q.p[b] != w.p[b]) on = false;
+        if (on && q.p[u] >= w.p[u] && q.p[u] < w.p[u] + w.n)
+          return fail(s, ORC_ERANGE, "source on a wire (perfect-conductor) edge");
+      }
+  build_materials(s);
+  apply_wires(s);
+  int rc = build_coefficients(s);
+  if (rc) return rc;
+  for (int a = 0; a < 3; ++a) {  // the update needs only the coefficients
+    s->eps[a] = A3(); s->sig[a] = A3(); s->mu[a] = A3();
+    std::vector<char>().swap(s->emod[a]);
+    std::vector<char>().swap(s->hmod[a]);
+  }
+  build_cpml(s);
+  for (Probe& pr : s->probes) pr.rec.assign(s->P.max_steps, 0.0);
+  s->finalized = true;
+  return ORC_OK;
+}
+
+void update_h(orc_sim* s) {
+  const int nx = s->N[0], ny = s->N[1], nz = s->N[2];
+  const double d = s->dx;
+  A3 &Ex = s->E[0], &Ey = s->E[1], &Ez = s->E[2];
+  A3 &Hx = s->H[0], &Hy = s->H[1], &Hz = s->H[2];
+  // Hx at (i, j+1/2, k+1/2): eq. 5.
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 1; i < nx; ++i) {
+        const double dz = (Ey(i, j, k + 1) - Ey(i, j, k)) / d;
+        const double dy = (Ez(i, j + 1, k) - Ez(i, j, k)) / d;
+        double& pz = s->psi[3][2](i, j, k);
+        double& py = s->psi[3][1](i, j, k);
+        pz = s->bh[2][k] * pz + s->ch[2][k] * dz;
+        py = s->bh[1][j] * py + s->ch[1][j] * dy;
+        Hx(i, j, k) += s->Db[0](i, j, k) * ((dz * s->ikh[2][k] + pz) - (dy * s->ikh[1][j] + py));
+      }
+  // Hy at (i+1/2, j, k+1/2): dHy/dt = (dEz/dx - dEx/dz) / mu.
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < nz; ++k)
+    for (int j = 1; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const double dxv = (Ez(i + 1, j, k) - Ez(i, j, k)) / d;
+        const double dz = (Ex(i, j, k + 1) - Ex(i, j, k)) / d;
+        double& px = s->psi[4][0](i, j, k);
+        double& pz = s->psi[4][2](i, j, k);
+        px = s->bh[0][i] * px + s->ch[0][i] * dxv;
+        pz = s->bh[2][k] * pz + s->ch[2][k] * dz;
+        Hy(i, j, k) += s->Db[1](i, j, k) * ((dxv * s->ikh[0][i] + px) - (dz * s->ikh[2][k] + pz));
+      }
+  // Hz at (i+1/2, j+1/2, k): dHz/dt = (dEx/dy - dEy/dx) / mu.
+#pragma omp parallel for schedule(static)
+  for (int k = 1; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const double dy = (Ex(i, j + 1, k) - Ex(i, j, k)) / d;
+        const double dxv = (Ey(i + 1, j, k) - Ey(i, j, k)) / d;
+        double& py = s->psi[5][1](i, j, k);
+        double& px = s->psi[5][0](i, j, k);
+        py = s->bh[1][j] * py + s->ch[1][j] * dy;
+        px = s->bh[0][i] * px + s->ch[0][i] * dxv;
+        Hz(i, j, k) += s->Db[2](i, j, k) * ((dy * s->ikh[1][j] + py) - (dxv * s->ikh[0][i] + px));
+      }
+}
+
+void update_e(orc_sim* s) {
+  const int nx = s->N[0], ny = s->N[1], nz = s->N[2];
+  const double d = s->dx;
+  A3 &Ex = s->E[0], &Ey = s->E[1], &Ez = s->E[2];
+  A3 &Hx = s->H[0], &Hy = s->H[1], &Hz = s->H[2];
+  // Ex at (i+1/2, j, k): eq. 4.
+#pragma omp parallel for schedule(static)
+  for (int k = 1; k < nz; ++k)
+    for (int j = 1; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const size_t li = ((size_t)k * Ex.n1 + j) * Ex.n0 + i;
+        if (s->pec[0][li]) continue;
+        const double dy = (Hz(i, j, k) - Hz(i, j - 1, k)) / d;
+        const double dz = (Hy(i, j, k) - Hy(i, j, k - 1)) / d;
+        double& py = s->psi[0][1](i, j, k);
+        double& pz = s->psi[0][2](i, j, k);
+        py = s->be[1][j] * py + s->ce[1][j] * dy;
+        pz = s->be[2][k] * pz + s->ce[2][k] * dz;
+        Ex(i, j, k) = s->Ca[0](i, j, k) * Ex(i, j, k) +
+                      s->Cb[0](i, j, k) * ((dy * s->ike[1][j] + py) - (dz * s->ike[2][k] + pz));
+      }
+  // Ey at (i, j+1/2, k): dEy/dt = ((dHx/dz - dHz/dx) - sigma Ey) / eps.
+#pragma omp parallel for schedule(static)
+  for (int k = 1; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 1; i < nx; ++i) {
+        const size_t li = ((size_t)k * Ey.n1 + j) * Ey.n0 + i;
+        if (s->pec[1][li]) continue;
+        const double dz = (Hx(i, j, k) - Hx(i, j, k - 1)) / d;
+        const double dxv = (Hz(i, j, k) - Hz(i - 1, j, k)) / d;
+        double& pz = s->psi[1][2](i, j, k);
+        double& px = s->psi[1][0](i, j, k);
+        pz = s->be[2][k] * pz + s->ce[2][k] * dz;
+        px = s->be[0][i] * px + s->ce[0][i] * dxv;
+        Ey(i, j, k) = s->Ca[1](i, j, k) * Ey(i, j, k) +
+                      s->Cb[1](i, j, k) * ((dz * s->ike[2][k] + pz) - (dxv * s->ike[0][i] + px));
+      }
+  // Ez at (i, j, k+1/2): dEz/dt = ((dHy/dx - dHx/dy) - sigma Ez) / eps.
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < nz; ++k)
+    for (int j = 1; j < ny; ++j)
+      for (int i = 1; i < nx; ++i) {
+        const size_t li = ((size_t)k * Ez.n1 + j) * Ez.n0 + i;
+        if (s->pec[2][li]) continue;
+        const double dxv = (Hy(i, j, k) - Hy(i - 1, j, k)) / d;
+        const double dy = (Hx(i, j, k) - Hx(i, j - 1, k)) / d;
+        double& px = s->psi[2][0](i, j, k);
+        double& py = s->psi[2][1](i, j, k);
+        px = s->be[0][i] * px + s->ce[0][i] * dxv;
+        py = s->be[1][j] * py + s->ce[1][j] * dy;
+        Ez(i, j, k) = s->Ca[2](i, j, k) * Ez(i, j, k) +
+                      s->Cb[2](i, j, k) * ((dxv * s->ike[0][i] + px) - (dy * s->ike[1][j] + py));
+      }
+}
+
+// Ideal lumped current source (the J term of eq. 1): after the normal update
+// of its edge, E -= Cb * I / (cross-section area), with I sampled at
+// (n + 1/2) dt; I > 0 drives current toward +axis.
+void inject_sources(orc_sim* s) {
+  const double area = s->dx * s->dx;
+  for (const Source& q : s->srcs) {
+    const double I = (s->step < (long)q.amps.size()) ? q.amps[s->step] : 0.0;
+    const int a = q.axis;
+    s->E[a](q.p[0], q.p[1], q.p[2]) -= s->Cb[a](q.p[0], q.p[1], q.p[2]) * I / area;
+  }
+}
+
+// Probe record n: E and line voltage at (n + 1) dt (after the E update of
+// step n); loop current at (n + 1/2) dt (the H level of step n).
+double probe_value(orc_sim* s, const Probe& pr) {
+  const int a = pr.axis;
+  if (pr.kind == ORC_PR_E) return s->E[a](pr.p[0], pr.p[1], pr.p[2]);
+  if (pr.kind == ORC_PR_VLINE) {
+    double v = 0.0;
+    for (int t = 0; t < pr.n; ++t) {
+      int p[3] = {pr.p[0], pr.p[1], pr.p[2]};
+      p[a] += t;
+      v += s->E[a](p[0], p[1], p[2]) * s->dx;
+    }
+    return v;
+  }
+  // Loop integral of H around the edge, right-hand rule about +axis:
+  // I = (H_w(p) - H_w(p - e_v)) dv - (H_v(p) - H_v(p - e_w)) dw.
+  const int v = (a + 1) % 3, w = (a + 2) % 3;
+  int pv[3] = {pr.p[0], pr.p[1], pr.p[2]};
+  pv[v] -= 1;
+  int pw[3] = {pr.p[0], pr.p[1], pr.p[2]};
+  pw[w] -= 1;
+  return (s->H[w](pr.p[0], pr.p[1], pr.p[2]) - s->H[w](pv[0], pv[1], pv[2])) * s->dx -
+         (s->H[v](pr.p[0], pr.p[1], pr.p[2]) - s->H[v](pw[0], pw[1], pw[2])) * s->dx;
+}
+
+}  // namespace
+
+extern "C" {
+
+int orc_create(const orc_params* p, orc_sim** out) {
+  if (!p || !out) return ORC_EINVAL;
+  *out = nullptr;
+  if (p->nx < 2 || p->ny < 2 || p->nz < 2 || !(p->dx > 0) || p->npml < 0 || p->max_steps < 1)
+    return ORC_EINVAL;
+  if (p->loss_mode != ORC_LOSS_SEMI && p->loss_mode != ORC_LOSS_EXPLICIT) return ORC_EINVAL;
+  if (p->npml > 0 && (p->nx <= 2 * p->npml || p->ny <= 2 * p->npml || p->nz <= 2 * p->npml))
+    return ORC_EINVAL;
+  if (!(p->wire_r0_factor > 0 && p->wire_r0_factor < 1)) return ORC_EINVAL;
+  const double dtmax = p->dx / (kC0 * std::sqrt(3.0));
+  const double dt = (p->dt > 0) ? p->dt : 0.99 * dtmax;
+  if (dt > dtmax) return ORC_EUNSTABLE;
+  orc_sim* s = new orc_sim;
+  s->P = *p;
+  s->dx = p->dx;
+  s->dt = dt;
+  s->N[0] = p->nx; s->N[1] = p->ny; s->N[2] = p->nz;
+  const size_t nc = (size_t)p->nx * p->ny * p->nz;
+  s->c_eps.assign(nc, kEps0);
+  s->c_sig.assign(nc, 0.0);
+  s->c_mu.assign(nc, kMu0);
+  *out = s;
+  return ORC_OK;
+}
+
+void orc_destroy(orc_sim* s) { delete s; }
+
+int orc_set_threads(int n) {
+  if (n < 1) return ORC_EINVAL;
+  omp_set_num_threads(n);
+  return ORC_OK;
+}
+
+double orc_dt(const orc_sim* s) { return s ? s->dt : 0.0; }
+const char* orc_last_error(const orc_sim* s) { return s ? s->err.c_str() : "null handle"; }
+
+int orc_set_materials(orc_sim* s, const uint8_t* cm, const orc_material* tab, int n_mat) {
+  if (!s || !cm || !tab || n_mat < 1 || n_mat > 256) return ORC_EINVAL;
+  if (s->finalized) return fail(s, ORC_ESTATE, "setup after finalize");
+  for (int m = 0; m < n_mat; ++m)
+    if (!(tab[m].eps_r > 0) || !(tab[m].mu_r > 0) || !(tab[m].sigma >= 0))
+      return fail(s, ORC_EINVAL, "bad material");
+  const size_t nc = s->c_eps.size();
+  for (size_t c = 0; c < nc; ++c) {
+    if (cm[c] >= n_mat) return fail(s, ORC_ERANGE, "material id out of table");
+    const orc_material& m = tab[cm[c]];
+    s->c_eps[c] = m.eps_r * kEps0;
+    s->c_sig[c] = m.sigma;
+    s->c_mu[c] = m.mu_r * kMu0;
+  }
+  return ORC_OK;
+}
+
+int orc_add_wire(orc_sim* s, int axis, int i, int j, int k, int n, double radius) {
+  if (!s || axis < 0 || axis > 2 || n < 1) return ORC_EINVAL;
+  if (s->finalized) return fail(s, ORC_ESTATE, "setup after finalize");
+  if (!(radius > 0) || !(radius < 0.5 * s->dx)) return fail(s, ORC_EINVAL, "radius out of (0, dx/2)");
+  const int p[3] = {i, j, k};
+  for (int b = 0; b < 3; ++b) {
+    const int hi = s->N[b];
+    if (p[b] < 0 || p[b] > hi) return fail(s, ORC_ERANGE, "wire node outside the grid");
+  }
+  if (p[axis] + n > s->N[axis]) return fail(s, ORC_ERANGE, "wire leaves the grid");
+  Wire w{axis, {i, j, k}, n, radius};
+  s->wires.push_back(w);
+  return ORC_OK;
+}
+
+int orc_add_source(orc_sim* s, int axis, int i, int j, int k, const double* amps, int n) {
+  if (!s || axis < 0 || axis > 2 || !amps || n < 1) return ORC_EINVAL;
+  if (s->finalized) return fail(s, ORC_ESTATE, "setup after finalize");
+  const int p[3] = {i, j, k};
+  if (!e_interior(s, axis, p)) return fail(s, ORC_ERANGE, "source edge outside the updated edges");
+  for (int t = 0; t < n; ++t)
+    if (!std::isfinite(amps[t])) return fail(s, ORC_EINVAL, "non-finite source sample");
+  Source q{axis, {i, j, k}, std::vector<double>(amps, amps + n)};
+  s->srcs.push_back(q);
+  return ORC_OK;
+}
+
+int orc_add_probe(orc_sim* s, int kind, int axis, int i, int j, int k, int n, int* id) {
+  if (!s || axis < 0 || axis > 2 || kind < 0 || kind > 2 || n < 1) return ORC_EINVAL;
+  if (s->finalized) return fail(s, ORC_ESTATE, "setup after finalize");
+  const int p[3] = {i, j, k};
+  for (int b = 0; b < 3; ++b)
+    if (p[b] < 0 || p[b] >= s->N[b]) return fail(s, ORC_ERANGE, "probe node outside the grid");
+  if (kind == ORC_PR_VLINE && p[axis] + n > s->N[axis]) return fail(s, ORC_ERANGE, "line leaves the grid");
+  if (kind != ORC_PR_VLINE && n != 1) return ORC_EINVAL;
+  if (kind == ORC_PR_ILOOP) {
+    const int v = (axis + 1) % 3, w = (axis + 2) % 3;
+    if (p[v] < 1 || p[w] < 1) return fail(s, ORC_ERANGE, "loop touches a wall");
+  }
+  Probe pr{kind, axis, {i, j, k}, n, {}};
+  s->probes.push_back(pr);
+  if (id) *id = (int)s->probes.size() - 1;
+  return ORC_OK;
+}
+
+int orc_step(orc_sim* s, int n_steps) {
+  if (!s || n_steps < 0) return ORC_EINVAL;
+  int rc = finalize(s);
+  if (rc) return rc;
+  if (s->step + n_steps > s->P.max_steps) return fail(s, ORC_ERANGE, "beyond max_steps");
+  for (int t = 0; t < n_steps; ++t) {
+    update_h(s);
+    update_e(s);
+    inject_sources(s);
+    for (Probe& pr : s->probes) pr.rec[s->step] = probe_value(s, pr);
+    ++s->step;
+  }
+  return ORC_OK;
+}
+
+int orc_probe(orc_sim* s, int id, double* out, int n_max, int* n_written) {
+  if (!s || !out || id < 0 || id >= (int)s->probes.size()) return ORC_EINVAL;
+  int rc = finalize(s);
+  if (rc) return rc;
+  const int n = (int)std::min<long>(s->step, n_max);
+  std::memcpy(out, s->probes[id].rec.data(), sizeof(double) * n);
+  if (n_written) *n_written = n;
+  return ORC_OK;
+}
+
+static A3* comp_array(orc_sim* s, int comp) {
+  if (comp < 0 || comp > 5) return nullptr;
+  return comp < 3 ? &s->E[comp] : &s->H[comp - 3];
+}
+
+int orc_set_field(orc_sim* s, int comp, const double* v) {
+  if (!s || !v) return ORC_EINVAL;
+  int rc = finalize(s);
+  if (rc) return rc;
+  A3* f = comp_array(s, comp);
+  if (!f) return ORC_EINVAL;
+  const int nx = s->N[0], ny = s->N[1], nz = s->N[2];
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        double x = v[((size_t)k * ny + j) * nx + i];
+        if (comp < 3) {
+          const int p[3] = {i, j, k};
+          const size_t li = ((size_t)k * f->n1 + j) * f->n0 + i;
+          if (!e_interior(s, comp, p) || s->pec[comp][li]) x = 0.0;  // perfect conductors
+        }
+        (*f)(i, j, k) = x;
+      }
+  return ORC_OK;
+}
+
+int orc_get_field(orc_sim* s, int comp, double* v) {
+  if (!s || !v) return ORC_EINVAL;
+  int rc = finalize(s);
+  if (rc) return rc;
+  A3* f = comp_array(s, comp);
+  if (!f) return ORC_EINVAL;
+  const int nx = s->N[0], ny = s->N[1], nz = s->N[2];
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) v[((size_t)k * ny + j) * nx + i] = (*f)(i, j, k);
+  return ORC_OK;
+}
+
+int orc_get_coef(orc_sim* s, int comp, int which, double* v) {
+  if (!s || !v || comp < 0 || comp > 5 || which < 0 || which > 1) return ORC_EINVAL;
+  if (comp >= 3 && which == 1) return ORC_EINVAL;
+  int rc = finalize(s);
+  if (rc) return rc;
+  A3* f = comp < 3 ? (which == 0 ? &s->Ca[comp] : &s->Cb[comp]) : &s->Db[comp - 3];
+  const int nx = s->N[0], ny = s->N[1], nz = s->N[2];
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        double x = (*f)(i, j, k);
+        if (comp < 3) {
+          const int p[3] = {i, j, k};
+          const size_t li = ((size_t)k * f->n1 + j) * f->n0 + i;
+          if (!e_interior(s, comp, p) || s->pec[comp][li]) x = 0.0;
+        }
+        v[((size_t)k * ny + j) * nx + i] = x;
+      }
+  return ORC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,343 @@
+"""Seeded synthetic inputs for the FDTD hot path.
+
+This module builds *inputs only*: grid sizes, per-cell material ids and
+material tables, thin-wire runs, lumped current sources with their sampled
+waveforms, and probe lists.  It holds none of the method's arithmetic (no
+coefficients, no averaging, no field updates), so both the HIP library and
+the FP64 reference can be fed from it without sharing any computation.
+
+Geometry conventions (shared by every backend):
+  * node (i, j, k) is the point (i, j, k) * dx; cell (i, j, k) spans
+    [i, i+1] x [j, j+1] x [k, k+1] in units of dx;
+  * an edge is (axis u, start node) and spans node -> node + e_u;
+  * ``cell_mat`` is a uint8 array of shape (nz, ny, nx) (x fastest);
+  * waveform sample n is the source current at time (n + 1/2) * dt, which
+    is the time level of the electric-field update it enters (the lumped
+    current density term of the Ampere-Maxwell law, eq. 1).
+
+The three workloads follow the paper's model-file templates (Section 4.1,
+Fig. 3 for the feed topology of a buried electrode) scaled to the sizes of
+the three FDTD benchmark configurations.  Readings of points the paper does
+not fix (waveform definitions, electrode placement) are listed in the design doc.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Tuple
+
+import numpy as np
+
+# Speed of light, used only to pick the default time step for sampling the
+# source waveforms (inputs).  Each backend evaluates its own field equations.
+C0 = 299792458.0
+
+AX_X, AX_Y, AX_Z = 0, 1, 2
+PR_E, PR_VLINE, PR_ILOOP = 0, 1, 2
+LOSS_SEMI, LOSS_EXPLICIT = 0, 1
+
+
+def courant_dt(dx: float, factor: float = 0.99) -> float:
+    """Time step at ``factor`` times the 3D Courant limit for a cubic cell."""
+    return factor * dx / (C0 * math.sqrt(3.0))
+
+
+# ---------------------------------------------------------------------------
+# Source waveforms (harness inputs)
+# ---------------------------------------------------------------------------
+
+def sample_times(n_steps: int, dt: float) -> np.ndarray:
+    """Times (n + 1/2) dt at which current sample n is taken."""
+    return (np.arange(n_steps, dtype=np.float64) + 0.5) * dt
+
+
+def gaussian(n_steps: int, dt: float, t0: float, width: float, amp: float = 1.0) -> np.ndarray:
+    """amp * exp(-((t - t0) / width)^2) sampled at (n + 1/2) dt."""
+    t = sample_times(n_steps, dt)
+    return amp * np.exp(-(((t - t0) / width) ** 2))
+
+
+def _dexp_shape(alpha: float, beta: float):
+    tp = math.log(beta / alpha) / (beta - alpha)
+    k = 1.0 / (math.exp(-alpha * tp) - math.exp(-beta * tp))
+
+    def f(t):
+        return k * (math.exp(-alpha * t) - math.exp(-beta * t))
+
+    return tp, k, f
+
+
+def _bisect(g, lo, hi, it=200):
+    glo = g(lo)
+    for _ in range(it):
+        mid = 0.5 * (lo + hi)
+        gm = g(mid)
+        if (gm > 0) == (glo > 0):
+            lo, glo = mid, gm
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def dexp_times(alpha: float, beta: float) -> Tuple[float, float]:
+    """(T1, T2) of a normalised double exponential.
+
+    T1 = 1.25 (t90 - t10) on the front; the virtual origin is where the line
+    through the 10 % and 90 % points meets zero, t_O = t10 - 0.1 T1; T2 is the
+    time from t_O to the 50 % point on the tail (IEC impulse convention).
+    """
+    tp, _k, f = _dexp_shape(alpha, beta)
+    t10 = _bisect(lambda t: f(t) - 0.1, 0.0, tp)
+    t90 = _bisect(lambda t: f(t) - 0.9, 0.0, tp)
+    hi = tp
+    while f(hi) > 0.5:
+        hi *= 2.0
+    t50 = _bisect(lambda t: f(t) - 0.5, tp, hi)
+    T1 = 1.25 * (t90 - t10)
+    t0 = t10 - 0.1 * T1
+    return T1, t50 - t0
+
+
+def dexp_params(T1: float, T2: float) -> Tuple[float, float, float]:
+    """Solve (alpha, beta, k) so that k (e^{-alpha t} - e^{-beta t}) has peak 1,
+    front time T1 and time to half value T2 (see :func:`dexp_times`)."""
+    from scipy.optimize import fsolve
+
+    def resid(x):
+        a, b = math.exp(x[0]), math.exp(x[1])
+        if b <= a * 1.0001:
+            return [1e3, 1e3]
+        t1, t2 = dexp_times(a, b)
+        return [math.log(t1 / T1), math.log(t2 / T2)]
+
+    x0 = [math.log(0.7 / T2), math.log(2.5 / T1)]
+    x = fsolve(resid, x0, xtol=1e-13, maxfev=2000)
+    a, b = math.exp(x[0]), math.exp(x[1])
+    _tp, k, _f = _dexp_shape(a, b)
+    return a, b, k
+
+
+def double_exponential(n_steps: int, dt: float, I0: float, T1: float, T2: float) -> np.ndarray:
+    """I0 k (e^{-alpha t} - e^{-beta t}) sampled at (n + 1/2) dt."""
+    a, b, k = dexp_params(T1, T2)
+    t = sample_times(n_steps, dt)
+    return I0 * k * (np.exp(-a * t) - np.exp(-b * t))
+
+
+# ---------------------------------------------------------------------------
+# Scenario container
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Scenario:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dt: float
+    n_steps: int
+    cell_mat: np.ndarray                      # uint8 (nz, ny, nx)
+    materials: List[Tuple[float, float, float]]  # (eps_r, sigma [S/m], mu_r)
+    npml: int = 0
+    pml: Tuple[float, float, float, float, float] = (3.0, 1.0, 1.0, 0.0, 1.0)  # m, sigma_factor, kappa_max, alpha_max, m_a
+    loss_mode: int = LOSS_SEMI
+    wire_r0_factor: float = math.exp(-math.pi / 2)  # equivalent radius of a bare wire edge / dx
+    wires: List[Tuple[int, int, int, int, int, float]] = field(default_factory=list)   # axis, i, j, k, n_cells, radius
+    sources: List[Tuple[int, int, int, int, np.ndarray]] = field(default_factory=list)  # axis, i, j, k, amps
+    probes: List[Tuple[str, int, int, int, int, int, int]] = field(default_factory=list)  # name, kind, axis, i, j, k, n_cells
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def params(self) -> dict:
+        m, sf, km, am, ma = self.pml
+        return dict(nx=self.nx, ny=self.ny, nz=self.nz, dx=self.dx, dt=self.dt,
+                    npml=self.npml, pml_m=m, pml_sigma_factor=sf, pml_kappa_max=km,
+                    pml_alpha_max=am, pml_ma=ma, loss_mode=self.loss_mode,
+                    wire_r0_factor=self.wire_r0_factor, max_steps=self.n_steps)
+
+
+def apply(sc: Scenario, sim) -> List[int]:
+    """Feed a scenario into any backend exposing set_materials / add_wire /
+    add_source / add_probe (duck-typed).  Returns the probe ids in order."""
+    sim.set_materials(sc.cell_mat, sc.materials)
+    for w in sc.wires:
+        sim.add_wire(*w)
+    for (ax, i, j, k, amps) in sc.sources:
+        sim.add_source(ax, i, j, k, amps)
+    ids = []
+    for (_name, kind, ax, i, j, k, n) in sc.probes:
+        ids.append(sim.add_probe(kind, ax, i, j, k, n))
+    return ids
+
+
+# ---------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------
+
+AIR = (1.0, 0.0, 1.0)
+
+
+def config1(n_steps: int = 300) -> Scenario:
+    """48^3 cells, dx 0.5 m, PEC box; lower 16 layers soil (eps_r 10,
+    sigma 0.01 S/m); Gaussian soft current on Ez at the centre; 8 Ez probes
+    at cells chosen by numpy.random.default_rng(1)."""
+    n = 48
+    dx = 0.5
+    dt = courant_dt(dx)
+    cm = np.zeros((n, n, n), np.uint8)
+    cm[:16] = 1
+    mats = [AIR, (10.0, 0.01, 1.0)]
+    amps = gaussian(n_steps, dt, 40 * dt, 12 * dt, 1.0)
+    rng = np.random.default_rng(1)
+    probes = []
+    seen = {(24, 24, 24)}
+    while len(probes) < 8:
+        i, j = (int(v) for v in rng.integers(1, 48, size=2))
+        k = int(rng.integers(0, 48))
+        if (i, j, k) in seen:
+            continue
+        seen.add((i, j, k))
+        probes.append((f"Ez[{i},{j},{k}]", PR_E, AX_Z, i, j, k, 1))
+    return Scenario("config1_48cube_pec", n, n, n, dx, dt, n_steps, cm, mats,
+                    sources=[(AX_Z, 24, 24, 24, amps)], probes=probes)
+
+
+def config2(nx: int = 512, ny: int = 512, nz: int = 384, dx: float = 0.5, npml: int = 10,
+            wire_cells: int = 60, n_steps: int = 4000, e_probe_offsets=(10, 20, 40, 80, 160),
+            I0: float = 1.0e4) -> Scenario:
+    """Vertical thin wire over two-layer soil in an open (CPML) domain.
+
+    Full size: 512 x 512 x 384 cells, dx 0.5 m, 10-cell CPML; soil below the
+    mid plane k_s = nz/2: top 4 m sigma 0.005 S/m eps_r 15, below sigma
+    0.02 S/m eps_r 8.  A 5 mm wire rises ``wire_cells`` cells from the
+    ground surface, a current-source gap sits at its top, and a channel lead
+    continues to the top of the domain.  10 kA double exponential 1/50 us.
+    """
+    dt = courant_dt(dx)
+    ks = nz // 2
+    l1 = int(round(4.0 / dx))
+    cm = np.zeros((nz, ny, nx), np.uint8)
+    cm[ks - l1:ks] = 1
+    cm[:ks - l1] = 2
+    mats = [AIR, (15.0, 0.005, 1.0), (8.0, 0.02, 1.0)]
+    ic, jc = nx // 2, ny // 2
+    kg = ks + wire_cells
+    a = 0.005
+    wires = [(AX_Z, ic, jc, ks, wire_cells, a),
+             (AX_Z, ic, jc, kg + 1, nz - kg - 1, a)]
+    amps = double_exponential(n_steps, dt, I0, 1.0e-6, 50.0e-6)
+    probes = []
+    iend = nx - npml
+    for k in np.linspace(ks, kg, 4).round().astype(int):
+        probes.append((f"V_Ex(k={k})", PR_VLINE, AX_X, ic, jc, int(k), iend - ic))
+    for d in e_probe_offsets:
+        if ic + d < iend:
+            probes.append((f"Ex[{ic + d},{jc},{ks}]", PR_E, AX_X, ic + d, jc, ks, 1))
+            probes.append((f"Ez[{ic + d},{jc},{ks}]", PR_E, AX_Z, ic + d, jc, ks, 1))
+    probes.append(("I_base", PR_ILOOP, AX_Z, ic, jc, ks, 1))
+    probes.append(("I_source", PR_ILOOP, AX_Z, ic, jc, kg, 1))
+    return Scenario(f"config2_{nx}x{ny}x{nz}_cpml{npml}", nx, ny, nz, dx, dt, n_steps, cm, mats,
+                    npml=npml, wires=wires, sources=[(AX_Z, ic, jc, kg, amps)], probes=probes,
+                    meta=dict(ks=ks, kg=kg))
+
+
+def config2_small(n_steps: int = 1200) -> Scenario:
+    """The config-2 structure on a 96 x 96 x 80 grid (oracle-sized)."""
+    return config2(nx=96, ny=96, nz=80, dx=0.5, npml=10, wire_cells=12, n_steps=n_steps,
+                   e_probe_offsets=(5, 10, 20, 30))
+
+
+@dataclass
+class ElectrodeCase:
+    """Physical inputs of one buried-electrode case (the surrogate's inputs)."""
+    log10_sigma: float
+    eps_r: float
+    length: float    # m
+    depth: float     # m
+    T1: float        # s (front time of the injected current)
+
+
+CONFIG3_RANGES = dict(log10_sigma=(-4.0, -1.0), eps_r=(4.0, 40.0), length=(5.0, 18.5),
+                      depth=(0.5, 1.0), T1=(0.5e-6, 1.5e-6))
+
+
+def electrode_grid(case: ElectrodeCase, dims: Tuple[int, int, int], dx: float = 0.25,
+                   npml: int = 8, n_steps: int = 2000, T2: float = 10e-6,
+                   name: str = "electrode") -> Scenario:
+    """Buried horizontal electrode fed like the ground-potential-rise model
+    file of Section 4.1 (Fig. 3): a riser from the electrode to one cell above
+    the surface, a current-source gap on a horizontal stub with a lead into
+    the absorbing layer, and a voltage gap on a perpendicular stub with its own
+    lead (the remote reference)."""
+    nx, ny, nz = dims
+    dt = courant_dt(dx)
+    n_w = int(round(case.length / dx))
+    n_air = max(4, int(round(0.25 * (nz - 16))))
+    ks = nz - npml - n_air
+    ke = ks - int(round(case.depth / dx))
+    i_f, jc = 12, ny // 2
+    kw = ks + 1
+    if i_f + n_w + npml + 2 > nx:
+        raise ValueError("electrode does not fit the grid")
+    cm = np.zeros((nz, ny, nx), np.uint8)
+    cm[:ks] = 1
+    mats = [AIR, (case.eps_r, 10.0 ** case.log10_sigma, 1.0)]
+    a = 0.005
+    wires = [
+        (AX_X, i_f, jc, ke, n_w, a),            # electrode
+        (AX_Z, i_f, jc, ke, kw - ke, a),        # riser
+        (AX_X, i_f - 2, jc, kw, 2, a),          # current stub
+        (AX_X, 0, jc, kw, i_f - 3, a),          # current lead into the CPML
+        (AX_Y, i_f, jc - 2, kw, 2, a),          # voltage stub
+        (AX_Y, i_f, 0, kw, jc - 3, a),          # voltage lead into the CPML
+    ]
+    amps = double_exponential(n_steps, dt, 1.0, case.T1, T2)
+    probes = [("V_gap", PR_VLINE, AX_Y, i_f, jc - 3, kw, 1),
+              ("I_source", PR_ILOOP, AX_X, i_f - 3, jc, kw, 1)]
+    return Scenario(name, nx, ny, nz, dx, dt, n_steps, cm, mats, npml=npml, wires=wires,
+                    sources=[(AX_X, i_f - 3, jc, kw, amps)], probes=probes,
+                    meta=dict(case=case, ks=ks, ke=ke))
+
+
+def draw_cases(n: int, seed: int, widen: float = 0.0) -> List[ElectrodeCase]:
+    """Electrode cases drawn uniformly from the configuration ranges
+    (log-uniform in sigma), each range widened by ``widen`` of its width on
+    each side (eps_r clamped at 1)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        vals = {}
+        for key, (lo, hi) in CONFIG3_RANGES.items():
+            w = hi - lo
+            lo2, hi2 = lo - widen * w, hi + widen * w
+            if key == "eps_r":
+                lo2 = max(lo2, 1.0)
+            vals[key] = float(rng.uniform(lo2, hi2))
+        out.append(ElectrodeCase(**vals))
+    return out
+
+
+def grid_dims_for(case: ElectrodeCase, rng: np.random.Generator, dx: float = 0.25,
+                  lo: int = 32, hi: int = 96) -> Tuple[int, int, int]:
+    n_w = int(round(case.length / dx))
+    nx_min = max(lo, n_w + 22)
+    nx = int(rng.integers(nx_min, max(hi, nx_min) + 1))
+    ny = int(rng.integers(lo, hi + 1))
+    nz = int(rng.integers(lo, hi + 1))
+    return nx, ny, nz
+
+
+def config3(n_grids: int = 256, seed: int = 3, n_steps: int = 2000) -> List[Scenario]:
+    """256 uneven electrode grids, sizes uniform in [32, 96]^3 (x grown to fit
+    the electrode), dx 0.25 m, 8-cell CPML, 2000 steps each."""
+    cases = draw_cases(n_grids, seed)
+    rng = np.random.default_rng(seed + 1000)
+    out = []
+    for g, c in enumerate(cases):
+        dims = grid_dims_for(c, rng)
+        out.append(electrode_grid(c, dims, n_steps=n_steps, name=f"config3_g{g}"))
+    return out
