@@ -1,0 +1,180 @@
+/*
+ * fdtd.h -- C ABI of the MI355X (gfx950) Yee FDTD library.
+ *
+ * The library advances Maxwell's curl equations (Kuklin, "elecode",
+ * Section 2.1, eq. 1) on a uniform staggered Yee grid: the E update of eq. 4
+ * and the H update of eq. 5, with the other components by cyclic permutation,
+ * per-cell eps, sigma and mu (eqs. 2-3), an ideal lumped current source
+ * (Section 2.1), a convolutional PML backed by perfect-conductor walls
+ * (Section 2.2) and thin wires along grid edges by modification of the
+ * assigned material parameters (Section 2.3).
+ *
+ * Geometry.  Node (i, j, k) is the point (i, j, k) dx.  Cell (i, j, k) spans
+ * [i, i+1] x [j, j+1] x [k, k+1] (units of dx).  An edge is (axis, start node)
+ * and spans node -> node + e_axis.  The component stored at node (i, j, k) is
+ * Ex at (i+1/2, j, k), Ey at (i, j+1/2, k), Ez at (i, j, k+1/2),
+ * Hx at (i, j+1/2, k+1/2), Hy at (i+1/2, j, k+1/2), Hz at (i+1/2, j+1/2, k).
+ * Host arrays are x fastest: element (i, j, k) at i + nx (j + ny k).
+ *
+ * Time levels.  The state entering step n is (E^n, H^{n-1/2}), all zero at
+ * creation.  Step n updates H to n+1/2, then E to n+1 including the source
+ * current sampled at (n+1/2) dt, then records the probes: E and line-voltage
+ * probes hold E^{n+1}, loop-current probes hold H^{n+1/2}.
+ *
+ * Ownership.  The caller owns every host array it passes (copied during the
+ * call) and the device workspace (allocated by the caller, e.g. as a PyTorch
+ * tensor, and bound by pointer).  The library never allocates device memory
+ * on the stepping path; it places its fields, tables and probe records inside
+ * the workspace and owns their contents.  All device work is issued on the
+ * stream given at creation (NULL = the default stream).
+ *
+ * Errors.  Every int-returning call returns FDTD_OK (0) or a negative FDTD_E*
+ * code and records a message for fdtd_last_error.  No call aborts or exits.
+ * Set-up calls validate on the host before any HIP call, so every error path
+ * except FDTD_EDEVICE is reachable without a GPU.  A context is not
+ * thread-safe; distinct contexts are independent.
+ */
+#ifndef MI355_FDTD_H
+#define MI355_FDTD_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FDTD_OK = 0,
+  FDTD_EINVAL = -1,     /* null pointer, bad axis / kind / count, radius not in (0, dx/2) */
+  FDTD_ERANGE = -2,     /* index outside the grid, source on a wall or wire edge, beyond max_steps */
+  FDTD_ESTATE = -3,     /* set-up call after the workspace size was taken, step before binding */
+  FDTD_EUNSTABLE = -4,  /* dt above the Courant limit, or literal eq. 4 loss with sigma dt / eps >= 2 */
+  FDTD_ENOMEM = -5,     /* workspace smaller than fdtd_workspace_bytes, or misaligned */
+  FDTD_EDEVICE = -6,    /* a HIP runtime call failed */
+  FDTD_ENONFINITE = -7, /* NaN or Inf in an input array */
+  FDTD_ECLASS = -8      /* more than 65535 distinct coefficient classes */
+};
+enum { FDTD_EX = 0, FDTD_EY, FDTD_EZ, FDTD_HX, FDTD_HY, FDTD_HZ };
+enum { FDTD_PR_E = 0, FDTD_PR_VLINE = 1, FDTD_PR_ILOOP = 2 };
+enum { FDTD_LOSS_SEMI = 0, FDTD_LOSS_EXPLICIT = 1 };
+enum { FDTD_SRC_CURRENT = 0 };
+/* Kernel variants for fdtd_set_kernel. */
+enum { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_SPLIT = 1, FDTD_KERNEL_FUSED = 2 };
+
+typedef struct fdtd_ctx fdtd_ctx;
+typedef struct { double eps_r, sigma, mu_r; } fdtd_material;
+
+typedef struct {
+  int nx, ny, nz;            /* cells along x, y, z (>= 2 each) */
+  double dx;                 /* cubic cell size [m] */
+  double dt;                 /* time step [s]; <= 0 selects 0.99 dx / (c0 sqrt(3)) */
+  int npml;                  /* CPML cells on each of the six faces; 0 = bare PEC box */
+  double pml_m;              /* grading order m of sigma and kappa (default 3) */
+  double pml_sigma_factor;   /* sigma_max = factor * 0.8 (m + 1) / (eta0 dx) (default 1) */
+  double pml_kappa_max;      /* default 1 */
+  double pml_alpha_max;      /* [S/m], default 0 */
+  double pml_ma;             /* grading order of alpha (default 1) */
+  int loss_mode;             /* FDTD_LOSS_SEMI (default) or FDTD_LOSS_EXPLICIT (eq. 4 as printed) */
+  double wire_r0_factor;     /* equivalent radius of a bare wire edge / dx, in (0, 1); default exp(-pi/2) */
+  int max_steps;             /* capacity of the probe records (total steps allowed) */
+  int precision;             /* 32 (default) or 64: floating-point type of fields and arithmetic */
+} fdtd_params;
+
+/* Fill *p with the defaults above (grid size and dx left at zero). */
+void fdtd_default_params(fdtd_params* p);
+
+/* Validate p and create a host-side context.  hip_stream is a hipStream_t or
+ * NULL.  Errors: EINVAL (bad sizes, npml leaves no interior, bad precision or
+ * loss mode), EUNSTABLE (dt above the Courant limit). */
+int fdtd_create(const fdtd_params* p, void* hip_stream, fdtd_ctx** out);
+
+/* Per-cell material ids (nx*ny*nz bytes, x fastest) into a table of n_mat
+ * materials (eps_r > 0, sigma >= 0, mu_r > 0).  Without this call every cell
+ * is vacuum.  Edge eps and sigma are the arithmetic mean over the cells
+ * sharing the edge; face mu is the harmonic mean of the two cells sharing the
+ * face.  Errors: EINVAL, ERANGE (id >= n_mat), ENONFINITE, ESTATE. */
+int fdtd_set_materials(fdtd_ctx* c, const uint8_t* cell_mat, const fdtd_material* tab, int n_mat);
+
+/* Perfect-conductor thin wire of the given radius along +axis from node
+ * (i, j, k) over n_cells edges (Section 2.3).  The wire's edges are held at
+ * zero; eps and sigma of the radial edges at its nodes are multiplied by
+ * m = ln(1 / wire_r0_factor) / ln(dx / radius); mu of the H circulating
+ * around its segments (and the one segment past each end) and of the H
+ * parallel to it around its nodes is divided by m.  Errors: EINVAL, ERANGE,
+ * ESTATE. */
+int fdtd_add_wire(fdtd_ctx* c, int axis, int i, int j, int k, int n_cells, double radius);
+
+/* Ideal current source on the edge (axis, i, j, k): after the edge's update,
+ * E -= Cb * I / dx^2 with Cb the edge's curl coefficient and I = amps[n] at
+ * step n (amperes at (n+1/2) dt, positive toward +axis; 0 beyond n_samples).
+ * The edge must be one the update touches (not on a wall) and not a wire
+ * edge (checked when stepping starts).  Errors: EINVAL, ERANGE, ENONFINITE,
+ * ESTATE. */
+int fdtd_add_source(fdtd_ctx* c, int kind, int axis, int i, int j, int k,
+                    const double* amps, int n_samples);
+
+/* Probe (recorded every step, FP64):
+ *   FDTD_PR_E      value of the edge (axis, i, j, k) (n_cells = 1);
+ *   FDTD_PR_VLINE  sum of E_axis dx over n_cells edges from node (i, j, k)
+ *                  along +axis, i.e. phi(start) - phi(end);
+ *   FDTD_PR_ILOOP  loop integral of H around the edge (axis, i, j, k),
+ *                  right-handed about +axis (n_cells = 1).
+ * Errors: EINVAL, ERANGE, ESTATE. */
+int fdtd_add_probe(fdtd_ctx* c, int kind, int axis, int i, int j, int k, int n_cells, int* probe_id);
+
+/* Freeze the set-up (later set-up calls return ESTATE) and build the
+ * coefficient classes, CPML profiles, source and probe tables on the host.
+ * Idempotent.  Errors: ERANGE (source on a wire edge), EUNSTABLE (literal
+ * eq. 4 loss with sigma dt / eps >= 2), ECLASS. */
+int fdtd_finalize(fdtd_ctx* c);
+
+/* Device bytes the context needs (calls fdtd_finalize first).  Returns 0 on
+ * error (see fdtd_last_error). */
+size_t fdtd_workspace_bytes(fdtd_ctx* c);
+
+/* Bind caller-owned device memory of at least fdtd_workspace_bytes bytes,
+ * 256-byte aligned.  Uploads the tables and zeroes the fields on the stream.
+ * Errors: ENOMEM, ESTATE, EDEVICE. */
+int fdtd_bind_workspace(fdtd_ctx* c, void* dev_ptr, size_t bytes);
+
+/* Select a kernel variant (FDTD_KERNEL_*) and tile parameters (0 = default).
+ * Results do not depend on the choice.  Errors: EINVAL. */
+int fdtd_set_kernel(fdtd_ctx* c, int variant, int tile_y, int tile_z);
+
+/* Advance n_steps steps, asynchronously on the stream.  Errors: ESTATE (not
+ * bound), ERANGE (beyond max_steps), EDEVICE. */
+int fdtd_step(fdtd_ctx* c, int n_steps);
+
+/* Copy probe_id's record (one double per completed step, at most n_max) to
+ * out; synchronises the stream.  Errors: EINVAL, ESTATE, EDEVICE,
+ * ENONFINITE (the record holds NaN or Inf; the data is still copied). */
+int fdtd_probe(fdtd_ctx* c, int probe_id, double* out, int n_max, int* n_written);
+
+/* Whole-component host copies (nx*ny*nz doubles, x fastest; comp FDTD_EX ..
+ * FDTD_HZ).  set_field zeroes perfect-conductor edges (walls, wires).
+ * Both synchronise the stream.  Errors: EINVAL, ESTATE, EDEVICE. */
+int fdtd_set_field(fdtd_ctx* c, int comp, const double* host);
+int fdtd_get_field(fdtd_ctx* c, int comp, double* host);
+
+/* Diagnostics: the time step in use, steps taken, coefficient classes, and
+ * the bytes one step moves at the algorithmic minimum (fields read and
+ * written once, class ids, CPML state) -- the roofline numerator. */
+double fdtd_dt(const fdtd_ctx* c);
+long long fdtd_steps_done(const fdtd_ctx* c);
+int fdtd_num_classes(const fdtd_ctx* c);
+double fdtd_algorithmic_bytes_per_step(const fdtd_ctx* c);
+
+/* Kernel timing for roofline measurement: while enabled, fdtd_step records a
+ * HIP event pair on the context's stream around the update kernels of every
+ * step (not around the probe-recording kernel).  fdtd_kernel_time
+ * synchronises, returns the summed event time and the number of timed steps
+ * since the last call, and resets both.  Errors: EINVAL, EDEVICE. */
+int fdtd_timing(fdtd_ctx* c, int enable);
+int fdtd_kernel_time(fdtd_ctx* c, double* total_ms, long long* n_steps);
+
+const char* fdtd_last_error(const fdtd_ctx* c);
+void fdtd_destroy(fdtd_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,73 @@
+// fdtd_dev.h -- device-side views of one grid, shared by the host runtime and
+// the HIP kernels of this library.
+#pragma once
+#include <stdint.h>
+
+namespace mi355fdtd {
+
+// Coefficients of one class: the 9 numbers a node needs to update the six
+// components it owns (Ex..Hz at the node's Yee positions).
+//   E_a^{n+1} = ca_a E_a^n + cb_a (difference of H)        [cb = Cb / dx]
+//   H_a^{n+1/2} = H_a^{n-1/2} + db_a (difference of E)      [db = Db / dx]
+enum { K_CAX = 0, K_CBX, K_CAY, K_CBY, K_CAZ, K_CBZ, K_DBX, K_DBY, K_DBZ, K_NCOEF };
+
+// CPML profile table of one axis: 6 rows of 2*npml entries, indexed by the
+// slab-local position l (l < npml: low slab, position l; l >= npml: high
+// slab, position n - 2 npml + l).  Rows: b - 1, c, 1/kappa at the integer
+// (E) position, then b - 1, c, 1/kappa at the half-integer (H) position.
+enum { P_BE = 0, P_CE, P_IKE, P_BH, P_CH, P_IKH, P_NROW };
+
+// Class table rows are padded to K_STRIDE values so a row loads as 3 x 4-wide.
+enum { K_STRIDE = 12 };
+
+// Device view of one grid for one launch.  Input and output pointers are
+// resolved on the host (the in-place split variant passes the same set for
+// both), so kernels index them only with compile-time constants.
+template <typename T>
+struct GridView {
+  int nx, ny, nz, npml;
+  long long sxy;                 // nx * ny
+  long long ncell;               // nx * ny * nz
+  int ncls;                      // number of coefficient classes
+  int pad0;
+  const T* fi[6];                // fields read  (E^n, H^{n-1/2}), components Ex..Hz
+  T* fo[6];                      // fields written (E^{n+1}, H^{n+1/2})
+  // CPML state [axis][kind 0 = E-type, 1 = H-type][component 0 / 1]; component
+  // 0 is the one along axis+1, component 1 along axis+2.
+  const T* pi[3][2][2];
+  T* po[3][2][2];
+  const void* cls;               // class id per node (uint8 or uint16)
+  const T* ctab;                 // [ncls][K_STRIDE]
+  const T* prof[3];              // per axis [P_NROW][2*npml]
+  // sources: E[src_comp][src_idx] -= src_amp[s * max_steps + n] after the update
+  int n_src;
+  int max_steps;
+  const int* src_comp;
+  const long long* src_idx;
+  const T* src_amp;
+  // probes: value p = sum over terms t in [pr_off[p], pr_off[p+1]) of
+  // term_w[t] * field[term_comp[t]][term_idx[t]]
+  int n_probe;
+  int pad1;
+  const int* pr_off;
+  const int* term_comp;
+  const long long* term_idx;
+  const double* term_w;
+  double* pr_out;                // [n_probe][max_steps]
+};
+
+}  // namespace mi355fdtd
+
+namespace mi355fdtd {
+
+// Kernel launchers (fdtd_kernels.hip).  `view` points to a GridView<float>
+// (prec 32) or GridView<double> (prec 64) whose in/out pointers are already
+// resolved: the split variant updates in place (in == out), the fused variant
+// reads one set and writes the other.  `step` selects the source sample.
+// Returns 0 or a hipError_t value.
+int launch_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, int tile_z,
+                void* stream);
+
+// Record the probes of step `step` from the view's output set.
+int launch_probes(int prec, const void* view, int step, void* stream);
+}  // namespace mi355fdtd

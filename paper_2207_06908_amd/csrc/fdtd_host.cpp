@@ -1,0 +1,871 @@
+// fdtd_host.cpp -- host runtime of the MI355X FDTD library: validation, the
+// coefficient-class tables, CPML profiles, source and probe tables, the
+// workspace layout and the step loop.  Everything here runs on the host;
+// device work is issued on the context's stream.
+#include <hip/hip_runtime_api.h>
+
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/fdtd.h"
+#include "fdtd_dev.h"
+
+using namespace mi355fdtd;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kC0 = 299792458.0;               // speed of light [m/s]
+constexpr double kMu0 = 4.0e-7 * kPi;             // [H/m]
+const double kEps0 = 1.0 / (kMu0 * kC0 * kC0);    // [F/m]
+const double kEta0 = std::sqrt(kMu0 / kEps0);     // free-space impedance [ohm]
+
+struct WireRec { int axis, p[3], n; double radius; };
+struct SrcRec { int axis, p[3]; std::vector<double> amps; };
+struct ProbeRec { int kind, axis, p[3], n; };
+
+// Per-node modifications made by thin wires.
+struct NodeMod {
+  uint8_t pec = 0;            // bit a: E_a edge is a wire (perfect conductor)
+  uint8_t emod = 0, hmod = 0; // bit a: E_a / H_a parameter already scaled
+  double em[3] = {1, 1, 1};   // eps and sigma factor of E_a
+  double hm[3] = {1, 1, 1};   // mu divisor of H_a
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct fdtd_ctx {
+  fdtd_params P{};
+  hipStream_t stream = nullptr;
+  double dt = 0;
+  int N[3] = {0, 0, 0};
+  long long ncell = 0;
+  std::string err;
+
+  // set-up inputs
+  std::vector<uint8_t> cell_mat;
+  std::vector<fdtd_material> mats;
+  std::vector<WireRec> wires;
+  std::vector<SrcRec> srcs;
+  std::vector<ProbeRec> probes;
+
+  // frozen tables (host copies)
+  bool frozen = false;
+  int ncls = 0;
+  int cls16 = 0;
+  std::vector<uint16_t> cls_id;       // per node
+  std::vector<double> ctab;           // [ncls][K_NCOEF], Cb and Db already / dx
+  std::vector<double> prof[3];        // [P_NROW][2 npml]
+  std::vector<int> src_comp;
+  std::vector<long long> src_idx;
+  std::vector<double> src_amp;        // [n_src][max_steps], Cb I / dx^2
+  std::vector<int> pr_off, term_comp;
+  std::vector<long long> term_idx;
+  std::vector<double> term_w;
+  size_t ws_bytes = 0;
+  // workspace offsets (bytes from the workspace base)
+  size_t off_f = 0, off_psi[2][3] = {{0, 0, 0}, {0, 0, 0}}, off_cls = 0, off_ctab = 0, off_prof = 0;
+  size_t off_src_comp = 0, off_src_idx = 0, off_amp = 0, off_pr_off = 0, off_term_comp = 0;
+  size_t off_term_idx = 0, off_term_w = 0, off_out = 0, psi_elems[3] = {0, 0, 0};
+  std::vector<uint8_t> cls8;          // staging for 1-byte class ids
+
+  // bound state
+  char* ws = nullptr;
+  int cur = 0;
+  long long steps_done = 0;
+  int variant = FDTD_KERNEL_AUTO, tile_y = 0, tile_z = 0;
+  // kernel timing: a ring of event pairs, drained when a slot is reused
+  bool timing = false;
+  static constexpr int kRing = 64;
+  hipEvent_t ev0[kRing] = {}, ev1[kRing] = {};
+  int ev_next = 0, ev_pending = 0;
+  double timed_ms = 0;
+  long long timed_steps = 0;
+  GridView<float> v32[2][2] = {};   // [input set][output set]
+  GridView<double> v64[2][2] = {};
+};
+
+namespace {
+
+int fail(fdtd_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int tsize(const fdtd_ctx* c) { return c->P.precision == 64 ? 8 : 4; }
+
+long long node_index(const fdtd_ctx* c, int i, int j, int k) {
+  return (long long)i + (long long)c->N[0] * ((long long)j + (long long)c->N[1] * k);
+}
+
+bool node_in(const fdtd_ctx* c, const int p[3]) {
+  for (int b = 0; b < 3; ++b)
+    if (p[b] < 0 || p[b] >= c->N[b]) return false;
+  return true;
+}
+
+// An E edge the update touches: every transverse index in [1, n-1].
+bool edge_updated(const fdtd_ctx* c, int a, const int p[3]) {
+  for (int b = 0; b < 3; ++b) {
+    if (b == a) {
+      if (p[b] < 0 || p[b] >= c->N[b]) return false;
+    } else if (p[b] < 1 || p[b] > c->N[b] - 1) {
+      return false;
+    }
+  }
+  return true;
+}
+
+// -------------------------------------------------------------------------
+// Coefficient classes
+// -------------------------------------------------------------------------
+
+// Material id of cell (i, j, k), or 0xFF outside the grid.
+inline uint8_t cell_id(const fdtd_ctx* c, int i, int j, int k) {
+  if (i < 0 || j < 0 || k < 0 || i >= c->N[0] || j >= c->N[1] || k >= c->N[2]) return 0xFF;
+  return c->cell_mat.empty() ? 0 : c->cell_mat[node_index(c, i, j, k)];
+}
+
+// The 8 cells around node (i, j, k): bit pattern di + 2 dj + 4 dk selects
+// cell (i - 1 + di, j - 1 + dj, k - 1 + dk).
+inline uint64_t node_key(const fdtd_ctx* c, int i, int j, int k) {
+  uint64_t key = 0;
+  for (int q = 0; q < 8; ++q) {
+    const uint64_t id = cell_id(c, i - 1 + (q & 1), j - 1 + ((q >> 1) & 1), k - 1 + ((q >> 2) & 1));
+    key |= id << (8 * q);
+  }
+  return key;
+}
+
+// Coefficients of a node from its 8 surrounding cells and wire changes.
+// E_a: eps, sigma = arithmetic mean over the 4 cells sharing the edge (all
+// must be inside the grid, else the edge lies on a wall and is held at 0).
+// H_a: mu = harmonic mean over the (1 or 2) in-grid cells sharing the face.
+int node_coefs(fdtd_ctx* c, uint64_t key, const NodeMod* mod, std::array<double, K_NCOEF>& out) {
+  const double dt = c->dt, dx = c->P.dx;
+  auto cell = [&](int q) -> int { return (int)((key >> (8 * q)) & 0xFF); };
+  for (int a = 0; a < 3; ++a) {
+    // cells sharing E_a: index along a fixed at +0 (bit a set), others vary
+    double eps = 0, sig = 0;
+    bool wall = false;
+    for (int s = 0; s < 4; ++s) {
+      int bits[3];
+      int t = 0;
+      for (int b = 0; b < 3; ++b) bits[b] = (b == a) ? 1 : ((s >> (t++)) & 1);
+      const int id = cell(bits[0] | (bits[1] << 1) | (bits[2] << 2));
+      if (id == 0xFF) { wall = true; break; }
+      eps += c->mats[id].eps_r * kEps0;
+      sig += c->mats[id].sigma;
+    }
+    double ca = 0, cb = 0;
+    const bool pec = wall || (mod && (mod->pec >> a) & 1);
+    if (!pec) {
+      eps *= 0.25;
+      sig *= 0.25;
+      if (mod) { eps *= mod->em[a]; sig *= mod->em[a]; }
+      if (c->P.loss_mode == FDTD_LOSS_EXPLICIT) {
+        if (sig * dt / eps >= 2.0) return fail(c, FDTD_EUNSTABLE, "literal eq. 4 loss factor below -1");
+        ca = 1.0 - sig * dt / eps;
+        cb = dt / eps;
+      } else {
+        const double x = 0.5 * sig * dt / eps;
+        ca = (1.0 - x) / (1.0 + x);
+        cb = (dt / eps) / (1.0 + x);
+      }
+    }
+    out[2 * a] = ca;
+    out[2 * a + 1] = cb / dx;
+    // cells sharing H_a: index along a varies, others fixed at +0 (bit set)
+    double inv = 0;
+    int cnt = 0;
+    for (int s = 0; s < 2; ++s) {
+      int bits[3];
+      for (int b = 0; b < 3; ++b) bits[b] = (b == a) ? s : 1;
+      const int id = cell(bits[0] | (bits[1] << 1) | (bits[2] << 2));
+      if (id == 0xFF) continue;
+      inv += 1.0 / (c->mats[id].mu_r * kMu0);
+      ++cnt;
+    }
+    double mu = cnt ? cnt / inv : kMu0;
+    if (mod) mu /= mod->hm[a];
+    out[K_DBX + a] = dt / mu / dx;
+  }
+  return FDTD_OK;
+}
+
+// Thin-wire modifications (Section 2.3, assigned-parameter model): axial
+// edges become perfect conductors; radial E edges at every node get eps and
+// sigma times m; H circulating around every segment and the segment past
+// each end, and H parallel to the wire around every node, get mu / m.  The
+// first wire to touch a component sets its factor; a perfect conductor
+// overrides any factor.
+void collect_wire_mods(fdtd_ctx* c, std::unordered_map<long long, NodeMod>& mods) {
+  for (const WireRec& w : c->wires) {
+    const int u = w.axis, v = (u + 1) % 3, x = (u + 2) % 3;
+    const double m = std::log(1.0 / c->P.wire_r0_factor) / std::log(c->P.dx / w.radius);
+    auto scale_e = [&](const int q[3], int a) {
+      if (!node_in(c, q)) return;
+      NodeMod& nm = mods[node_index(c, q[0], q[1], q[2])];
+      if ((nm.emod >> a) & 1) return;
+      nm.emod |= 1 << a;
+      nm.em[a] = m;
+    };
+    auto scale_h = [&](const int q[3], int a) {
+      if (!node_in(c, q)) return;
+      NodeMod& nm = mods[node_index(c, q[0], q[1], q[2])];
+      if ((nm.hmod >> a) & 1) return;
+      nm.hmod |= 1 << a;
+      nm.hm[a] = m;
+    };
+    for (int t = 0; t < w.n; ++t) {
+      int q[3] = {w.p[0], w.p[1], w.p[2]};
+      q[u] += t;
+      if (node_in(c, q)) mods[node_index(c, q[0], q[1], q[2])].pec |= 1 << u;
+    }
+    for (int t = 0; t <= w.n; ++t)
+      for (int d = -1; d <= 0; ++d) {
+        int q[3] = {w.p[0], w.p[1], w.p[2]};
+        q[u] += t;
+        q[v] += d;
+        scale_e(q, v);
+        int r[3] = {w.p[0], w.p[1], w.p[2]};
+        r[u] += t;
+        r[x] += d;
+        scale_e(r, x);
+      }
+    for (int t = -1; t <= w.n; ++t)
+      for (int d = -1; d <= 0; ++d) {
+        int q[3] = {w.p[0], w.p[1], w.p[2]};  // H_v at x = wire +- 1/2
+        q[u] += t;
+        q[x] += d;
+        scale_h(q, v);
+        int r[3] = {w.p[0], w.p[1], w.p[2]};  // H_x at v = wire +- 1/2
+        r[u] += t;
+        r[v] += d;
+        scale_h(r, x);
+      }
+    for (int t = 0; t <= w.n; ++t)
+      for (int dv = -1; dv <= 0; ++dv)
+        for (int dw = -1; dw <= 0; ++dw) {
+          int q[3] = {w.p[0], w.p[1], w.p[2]};
+          q[u] += t;
+          q[v] += dv;
+          q[x] += dw;
+          scale_h(q, u);
+        }
+  }
+}
+
+struct TupleKey {
+  std::array<uint64_t, K_NCOEF> b;
+  bool operator<(const TupleKey& o) const { return b < o.b; }
+};
+
+TupleKey tuple_key(const fdtd_ctx* c, const std::array<double, K_NCOEF>& v) {
+  TupleKey k;
+  for (int q = 0; q < K_NCOEF; ++q) {
+    if (c->P.precision == 64) {
+      std::memcpy(&k.b[q], &v[q], 8);
+    } else {
+      const float f = (float)v[q];
+      uint32_t u;
+      std::memcpy(&u, &f, 4);
+      k.b[q] = u;
+    }
+  }
+  return k;
+}
+
+int build_classes(fdtd_ctx* c) {
+  std::unordered_map<long long, NodeMod> mods;
+  collect_wire_mods(c, mods);
+  std::map<TupleKey, int> by_tuple;
+  std::unordered_map<uint64_t, int> by_key;
+  c->ctab.clear();
+  auto intern = [&](const std::array<double, K_NCOEF>& v) -> int {
+    const TupleKey k = tuple_key(c, v);
+    auto it = by_tuple.find(k);
+    if (it != by_tuple.end()) return it->second;
+    const int id = (int)by_tuple.size();
+    by_tuple.emplace(k, id);
+    c->ctab.insert(c->ctab.end(), v.begin(), v.end());
+    return id;
+  };
+  c->cls_id.assign((size_t)c->ncell, 0);
+  std::array<double, K_NCOEF> v;
+  for (int k = 0; k < c->N[2]; ++k)
+    for (int j = 0; j < c->N[1]; ++j) {
+      uint64_t last = ~0ull;
+      int last_id = -1;
+      for (int i = 0; i < c->N[0]; ++i) {
+        const uint64_t key = node_key(c, i, j, k);
+        if (key != last) {
+          auto it = by_key.find(key);
+          if (it == by_key.end()) {
+            int rc = node_coefs(c, key, nullptr, v);
+            if (rc) return rc;
+            it = by_key.emplace(key, intern(v)).first;
+          }
+          last = key;
+          last_id = it->second;
+        }
+        c->cls_id[node_index(c, i, j, k)] = (uint16_t)std::min(last_id, 65535);
+        if ((int)by_tuple.size() > 65535) return fail(c, FDTD_ECLASS, "more than 65535 classes");
+      }
+    }
+  for (const auto& kv : mods) {
+    const long long n = kv.first;
+    const int i = (int)(n % c->N[0]);
+    const int j = (int)((n / c->N[0]) % c->N[1]);
+    const int k = (int)(n / ((long long)c->N[0] * c->N[1]));
+    int rc = node_coefs(c, node_key(c, i, j, k), &kv.second, v);
+    if (rc) return rc;
+    const int id = intern(v);
+    if ((int)by_tuple.size() > 65535) return fail(c, FDTD_ECLASS, "more than 65535 classes");
+    c->cls_id[n] = (uint16_t)id;
+  }
+  c->ncls = (int)by_tuple.size();
+  c->cls16 = c->ncls > 256 ? 1 : 0;
+  // a source must not sit on a wire edge
+  for (const SrcRec& s : c->srcs) {
+    auto it = mods.find(node_index(c, s.p[0], s.p[1], s.p[2]));
+    if (it != mods.end() && ((it->second.pec >> s.axis) & 1))
+      return fail(c, FDTD_ERANGE, "source on a wire (perfect-conductor) edge");
+  }
+  return FDTD_OK;
+}
+
+// CPML (Section 2.2, recursive convolution).  For depth rho (cells) from the
+// layer's inner face, s = rho / npml: sigma = sigma_max s^m,
+// kappa = 1 + (kappa_max - 1) s^m, alpha = alpha_max (1 - s)^m_a,
+// b = exp(-(sigma / kappa + alpha) dt / eps0),
+// c = sigma (b - 1) / (kappa (sigma + kappa alpha)); outside the layer
+// b = c = 0, 1/kappa = 1.  The kernels work on raw differences, so c is used
+// as is with psi stored premultiplied by dx.  The table holds b - 1 (from
+// expm1) rather than b: near the inner face b is within 1e-4 of 1, and an
+// FP32 b would keep only a few bits of 1 - b; the kernels update
+// psi += (b - 1) psi + c d, which is the same recursion.
+void profile(const fdtd_ctx* c, int n, double pos, double& bm1, double& cc, double& ik) {
+  bm1 = -1; cc = 0; ik = 1;
+  const int np = c->P.npml;
+  double rho = 0;
+  if (pos < np) rho = np - pos;
+  else if (pos > n - np) rho = pos - (n - np);
+  if (rho <= 0) return;
+  const double s = rho / np, m = c->P.pml_m;
+  const double smax = c->P.pml_sigma_factor * 0.8 * (m + 1.0) / (kEta0 * c->P.dx);
+  const double sg = smax * std::pow(s, m);
+  const double ka = 1.0 + (c->P.pml_kappa_max - 1.0) * std::pow(s, m);
+  const double al = c->P.pml_alpha_max * std::pow(1.0 - s, c->P.pml_ma);
+  bm1 = std::expm1(-(sg / ka + al) * c->dt / kEps0);
+  cc = sg > 0 ? sg * bm1 / (ka * (sg + ka * al)) : 0.0;
+  ik = 1.0 / ka;
+}
+
+void build_cpml(fdtd_ctx* c) {
+  const int np = c->P.npml;
+  for (int u = 0; u < 3; ++u) {
+    c->prof[u].assign((size_t)P_NROW * 2 * np, 0.0);
+    for (int l = 0; l < 2 * np; ++l) {
+      const int pos = l < np ? l : c->N[u] - 2 * np + l;
+      double* r = c->prof[u].data();
+      profile(c, c->N[u], pos, r[P_BE * 2 * np + l], r[P_CE * 2 * np + l], r[P_IKE * 2 * np + l]);
+      profile(c, c->N[u], pos + 0.5, r[P_BH * 2 * np + l], r[P_CH * 2 * np + l], r[P_IKH * 2 * np + l]);
+    }
+  }
+}
+
+void build_sources_probes(fdtd_ctx* c) {
+  const int ms = c->P.max_steps;
+  c->src_comp.clear(); c->src_idx.clear(); c->src_amp.assign((size_t)c->srcs.size() * ms, 0.0);
+  for (size_t s = 0; s < c->srcs.size(); ++s) {
+    const SrcRec& r = c->srcs[s];
+    const long long n = node_index(c, r.p[0], r.p[1], r.p[2]);
+    c->src_comp.push_back(r.axis);
+    c->src_idx.push_back(n);
+    const double cb = c->ctab[(size_t)c->cls_id[n] * K_NCOEF + 2 * r.axis + 1] * c->P.dx;  // Cb
+    const double area = c->P.dx * c->P.dx;
+    for (int t = 0; t < ms && t < (int)r.amps.size(); ++t) c->src_amp[s * ms + t] = cb * r.amps[t] / area;
+  }
+  c->pr_off.assign(1, 0); c->term_comp.clear(); c->term_idx.clear(); c->term_w.clear();
+  const double d = c->P.dx;
+  auto term = [&](int comp, int i, int j, int k, double w) {
+    c->term_comp.push_back(comp);
+    c->term_idx.push_back(node_index(c, i, j, k));
+    c->term_w.push_back(w);
+  };
+  for (const ProbeRec& p : c->probes) {
+    const int a = p.axis;
+    if (p.kind == FDTD_PR_E) {
+      term(a, p.p[0], p.p[1], p.p[2], 1.0);
+    } else if (p.kind == FDTD_PR_VLINE) {
+      for (int t = 0; t < p.n; ++t) {
+        int q[3] = {p.p[0], p.p[1], p.p[2]};
+        q[a] += t;
+        term(a, q[0], q[1], q[2], d);
+      }
+    } else {  // loop: (H_w(p) - H_w(p - e_v)) dv - (H_v(p) - H_v(p - e_w)) dw
+      const int v = (a + 1) % 3, w = (a + 2) % 3;
+      int qv[3] = {p.p[0], p.p[1], p.p[2]};
+      qv[v] -= 1;
+      int qw[3] = {p.p[0], p.p[1], p.p[2]};
+      qw[w] -= 1;
+      term(3 + w, p.p[0], p.p[1], p.p[2], d);
+      term(3 + w, qv[0], qv[1], qv[2], -d);
+      term(3 + v, p.p[0], p.p[1], p.p[2], -d);
+      term(3 + v, qw[0], qw[1], qw[2], d);
+    }
+    c->pr_off.push_back((int)c->term_comp.size());
+  }
+}
+
+void layout(fdtd_ctx* c) {
+  const size_t ts = tsize(c);
+  const size_t N = (size_t)c->ncell;
+  const int np = c->P.npml;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  c->off_f = take(12 * N * ts);
+  for (int u = 0; u < 3; ++u) c->psi_elems[u] = 0;
+  if (np > 0) {
+    c->psi_elems[0] = (size_t)2 * np * c->N[1] * c->N[2];
+    c->psi_elems[1] = (size_t)2 * np * c->N[0] * c->N[2];
+    c->psi_elems[2] = (size_t)2 * np * c->N[0] * c->N[1];
+  }
+  for (int s = 0; s < 2; ++s)
+    for (int u = 0; u < 3; ++u) c->off_psi[s][u] = take(4 * c->psi_elems[u] * ts);
+  c->off_cls = take(N * (c->cls16 ? 2 : 1));
+  c->off_ctab = take((size_t)c->ncls * K_STRIDE * ts);
+  c->off_prof = take(3 * (size_t)P_NROW * 2 * np * ts);
+  c->off_src_comp = take(c->srcs.size() * sizeof(int));
+  c->off_src_idx = take(c->srcs.size() * sizeof(long long));
+  c->off_amp = take(c->src_amp.size() * ts);
+  c->off_pr_off = take(c->pr_off.size() * sizeof(int));
+  c->off_term_comp = take(c->term_comp.size() * sizeof(int));
+  c->off_term_idx = take(c->term_idx.size() * sizeof(long long));
+  c->off_term_w = take(c->term_w.size() * sizeof(double));
+  c->off_out = take(c->probes.size() * (size_t)c->P.max_steps * sizeof(double));
+  c->ws_bytes = o;
+}
+
+template <typename T>
+GridView<T>& view_of(fdtd_ctx* c, int in, int out);
+template <>
+GridView<float>& view_of<float>(fdtd_ctx* c, int in, int out) { return c->v32[in][out]; }
+template <>
+GridView<double>& view_of<double>(fdtd_ctx* c, int in, int out) { return c->v64[in][out]; }
+
+template <typename T>
+void fill_view(fdtd_ctx* c, GridView<T>& g, int in, int out) {
+  const size_t N = (size_t)c->ncell;
+  const int np = c->P.npml;
+  char* w = c->ws;
+  g.nx = c->N[0]; g.ny = c->N[1]; g.nz = c->N[2]; g.npml = np;
+  g.sxy = (long long)c->N[0] * c->N[1];
+  g.ncell = c->ncell;
+  g.ncls = c->ncls;
+  for (int q = 0; q < 6; ++q) {
+    g.fi[q] = (const T*)(w + c->off_f) + (size_t)(in * 6 + q) * N;
+    g.fo[q] = (T*)(w + c->off_f) + (size_t)(out * 6 + q) * N;
+  }
+  for (int u = 0; u < 3; ++u)
+    for (int kind = 0; kind < 2; ++kind)
+      for (int q = 0; q < 2; ++q) {
+        const size_t o = (size_t)(kind * 2 + q) * c->psi_elems[u];
+        g.pi[u][kind][q] = np ? (const T*)(w + c->off_psi[in][u]) + o : nullptr;
+        g.po[u][kind][q] = np ? (T*)(w + c->off_psi[out][u]) + o : nullptr;
+      }
+  g.cls = w + c->off_cls;
+  g.ctab = (const T*)(w + c->off_ctab);
+  for (int u = 0; u < 3; ++u) g.prof[u] = (const T*)(w + c->off_prof) + (size_t)u * P_NROW * 2 * np;
+  g.n_src = (int)c->srcs.size();
+  g.max_steps = c->P.max_steps;
+  g.src_comp = (const int*)(w + c->off_src_comp);
+  g.src_idx = (const long long*)(w + c->off_src_idx);
+  g.src_amp = (const T*)(w + c->off_amp);
+  g.n_probe = (int)c->probes.size();
+  g.pr_off = (const int*)(w + c->off_pr_off);
+  g.term_comp = (const int*)(w + c->off_term_comp);
+  g.term_idx = (const long long*)(w + c->off_term_idx);
+  g.term_w = (const double*)(w + c->off_term_w);
+  g.pr_out = (double*)(w + c->off_out);
+}
+
+template <typename T>
+std::vector<T> convert(const std::vector<double>& v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+int hip_fail(fdtd_ctx* c, hipError_t e, const char* what) {
+  return fail(c, FDTD_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+int upload(fdtd_ctx* c) {
+  for (int in = 0; in < 2; ++in)
+    for (int out = 0; out < 2; ++out) fill_view<T>(c, view_of<T>(c, in, out), in, out);
+  const GridView<T>& g = view_of<T>(c, 0, 0);
+  hipStream_t st = c->stream;
+  // zero fields and CPML state (both sets)
+  hipError_t e = hipMemsetAsync(c->ws + c->off_f, 0, c->off_cls - c->off_f, st);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
+  const void* cls_src = c->cls_id.data();
+  size_t cls_bytes = c->cls_id.size() * 2;
+  if (!c->cls16) {
+    c->cls8.assign(c->cls_id.begin(), c->cls_id.end());
+    cls_src = c->cls8.data();
+    cls_bytes = c->cls8.size();
+  }
+  std::vector<T> tab((size_t)c->ncls * K_STRIDE, T(0)), amp = convert<T>(c->src_amp), prof;
+  for (int q = 0; q < c->ncls; ++q)
+    for (int t = 0; t < K_NCOEF; ++t) tab[(size_t)q * K_STRIDE + t] = (T)c->ctab[(size_t)q * K_NCOEF + t];
+  for (int u = 0; u < 3; ++u)
+    for (double x : c->prof[u]) prof.push_back((T)x);
+  struct Up { void* dst; const void* src; size_t n; };
+  const Up ups[] = {
+      {(void*)g.cls, cls_src, cls_bytes},
+      {(void*)g.ctab, tab.data(), tab.size() * sizeof(T)},
+      {(void*)g.prof[0], prof.data(), prof.size() * sizeof(T)},
+      {(void*)g.src_comp, c->src_comp.data(), c->src_comp.size() * sizeof(int)},
+      {(void*)g.src_idx, c->src_idx.data(), c->src_idx.size() * sizeof(long long)},
+      {(void*)g.src_amp, amp.data(), amp.size() * sizeof(T)},
+      {(void*)g.pr_off, c->pr_off.data(), c->pr_off.size() * sizeof(int)},
+      {(void*)g.term_comp, c->term_comp.data(), c->term_comp.size() * sizeof(int)},
+      {(void*)g.term_idx, c->term_idx.data(), c->term_idx.size() * sizeof(long long)},
+      {(void*)g.term_w, c->term_w.data(), c->term_w.size() * sizeof(double)},
+  };
+  for (const Up& u : ups) {
+    if (!u.n) continue;
+    e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(c, e, "upload tables");
+  }
+  e = hipMemsetAsync(g.pr_out, 0, c->probes.size() * (size_t)c->P.max_steps * sizeof(double), st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // staging buffers are freed on return
+  if (e != hipSuccess) return hip_fail(c, e, "upload");
+  return FDTD_OK;
+}
+
+int freeze(fdtd_ctx* c) {
+  if (c->frozen) return FDTD_OK;
+  for (const SrcRec& s : c->srcs)
+    if (!edge_updated(c, s.axis, s.p)) return fail(c, FDTD_ERANGE, "source edge on a wall");
+  int rc = build_classes(c);
+  if (rc) return rc;
+  build_cpml(c);
+  build_sources_probes(c);
+  layout(c);
+  c->frozen = true;
+  return FDTD_OK;
+}
+
+bool finite_all(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fdtd_default_params(fdtd_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->pml_m = 3.0;
+  p->pml_sigma_factor = 1.0;
+  p->pml_kappa_max = 1.0;
+  p->pml_alpha_max = 0.0;
+  p->pml_ma = 1.0;
+  p->loss_mode = FDTD_LOSS_SEMI;
+  p->wire_r0_factor = std::exp(-kPi / 2.0);
+  p->max_steps = 1;
+  p->precision = 32;
+}
+
+int fdtd_create(const fdtd_params* p, void* hip_stream, fdtd_ctx** out) {
+  if (!p || !out) return FDTD_EINVAL;
+  *out = nullptr;
+  if (p->nx < 2 || p->ny < 2 || p->nz < 2 || !(p->dx > 0) || !std::isfinite(p->dx)) return FDTD_EINVAL;
+  if (p->npml < 0 || (p->npml > 0 && (p->nx <= 2 * p->npml || p->ny <= 2 * p->npml || p->nz <= 2 * p->npml)))
+    return FDTD_EINVAL;
+  if (p->loss_mode != FDTD_LOSS_SEMI && p->loss_mode != FDTD_LOSS_EXPLICIT) return FDTD_EINVAL;
+  if (p->precision != 32 && p->precision != 64) return FDTD_EINVAL;
+  if (!(p->wire_r0_factor > 0 && p->wire_r0_factor < 1) || p->max_steps < 1) return FDTD_EINVAL;
+  if ((long long)p->nx * p->ny * p->nz > (1ll << 34)) return FDTD_EINVAL;
+  if (p->npml > 0 && (!(p->pml_m >= 0) || !(p->pml_kappa_max >= 1) || !(p->pml_alpha_max >= 0) ||
+                      !(p->pml_sigma_factor >= 0)))
+    return FDTD_EINVAL;
+  const double dtmax = p->dx / (kC0 * std::sqrt(3.0));
+  const double dt = p->dt > 0 ? p->dt : 0.99 * dtmax;
+  if (dt > dtmax) return FDTD_EUNSTABLE;
+  fdtd_ctx* c = new fdtd_ctx;
+  c->P = *p;
+  c->stream = (hipStream_t)hip_stream;
+  c->dt = dt;
+  c->N[0] = p->nx; c->N[1] = p->ny; c->N[2] = p->nz;
+  c->ncell = (long long)p->nx * p->ny * p->nz;
+  c->mats.push_back({1.0, 0.0, 1.0});
+  *out = c;
+  return FDTD_OK;
+}
+
+int fdtd_set_materials(fdtd_ctx* c, const uint8_t* cm, const fdtd_material* tab, int n_mat) {
+  if (!c || !cm || !tab || n_mat < 1 || n_mat > 255) return fail(c, FDTD_EINVAL, "bad materials arguments");
+  if (c->frozen) return fail(c, FDTD_ESTATE, "set-up after the workspace size was taken");
+  for (int m = 0; m < n_mat; ++m) {
+    if (!std::isfinite(tab[m].eps_r) || !std::isfinite(tab[m].sigma) || !std::isfinite(tab[m].mu_r))
+      return fail(c, FDTD_ENONFINITE, "non-finite material");
+    if (!(tab[m].eps_r > 0) || !(tab[m].mu_r > 0) || !(tab[m].sigma >= 0))
+      return fail(c, FDTD_EINVAL, "material out of range");
+  }
+  for (long long n = 0; n < c->ncell; ++n)
+    if (cm[n] >= n_mat) return fail(c, FDTD_ERANGE, "material id outside the table");
+  c->cell_mat.assign(cm, cm + c->ncell);
+  c->mats.assign(tab, tab + n_mat);
+  return FDTD_OK;
+}
+
+int fdtd_add_wire(fdtd_ctx* c, int axis, int i, int j, int k, int n, double radius) {
+  if (!c || axis < 0 || axis > 2 || n < 1) return fail(c, FDTD_EINVAL, "bad wire arguments");
+  if (c->frozen) return fail(c, FDTD_ESTATE, "set-up after the workspace size was taken");
+  if (!(radius > 0) || !(radius < 0.5 * c->P.dx)) return fail(c, FDTD_EINVAL, "wire radius not in (0, dx/2)");
+  const int p[3] = {i, j, k};
+  for (int b = 0; b < 3; ++b)
+    if (p[b] < 0 || p[b] > c->N[b]) return fail(c, FDTD_ERANGE, "wire node outside the grid");
+  if (p[axis] + n > c->N[axis]) return fail(c, FDTD_ERANGE, "wire leaves the grid");
+  c->wires.push_back({axis, {i, j, k}, n, radius});
+  return FDTD_OK;
+}
+
+int fdtd_add_source(fdtd_ctx* c, int kind, int axis, int i, int j, int k, const double* amps, int n) {
+  if (!c || kind != FDTD_SRC_CURRENT || axis < 0 || axis > 2 || !amps || n < 1)
+    return fail(c, FDTD_EINVAL, "bad source arguments");
+  if (c->frozen) return fail(c, FDTD_ESTATE, "set-up after the workspace size was taken");
+  const int p[3] = {i, j, k};
+  if (!edge_updated(c, axis, p)) return fail(c, FDTD_ERANGE, "source edge outside the updated edges");
+  if (!finite_all(amps, (size_t)n)) return fail(c, FDTD_ENONFINITE, "non-finite source sample");
+  c->srcs.push_back({axis, {i, j, k}, std::vector<double>(amps, amps + n)});
+  return FDTD_OK;
+}
+
+int fdtd_add_probe(fdtd_ctx* c, int kind, int axis, int i, int j, int k, int n, int* id) {
+  if (!c || kind < 0 || kind > 2 || axis < 0 || axis > 2 || n < 1) return fail(c, FDTD_EINVAL, "bad probe arguments");
+  if (kind != FDTD_PR_VLINE && n != 1) return fail(c, FDTD_EINVAL, "only line probes span several cells");
+  if (c->frozen) return fail(c, FDTD_ESTATE, "set-up after the workspace size was taken");
+  const int p[3] = {i, j, k};
+  if (!node_in(c, p)) return fail(c, FDTD_ERANGE, "probe node outside the grid");
+  if (kind == FDTD_PR_VLINE && p[axis] + n > c->N[axis]) return fail(c, FDTD_ERANGE, "line leaves the grid");
+  if (kind == FDTD_PR_ILOOP && (p[(axis + 1) % 3] < 1 || p[(axis + 2) % 3] < 1))
+    return fail(c, FDTD_ERANGE, "loop touches a wall");
+  c->probes.push_back({kind, axis, {i, j, k}, n});
+  if (id) *id = (int)c->probes.size() - 1;
+  return FDTD_OK;
+}
+
+int fdtd_finalize(fdtd_ctx* c) {
+  if (!c) return FDTD_EINVAL;
+  return freeze(c);
+}
+
+size_t fdtd_workspace_bytes(fdtd_ctx* c) {
+  if (!c) return 0;
+  if (freeze(c)) return 0;
+  return c->ws_bytes;
+}
+
+int fdtd_bind_workspace(fdtd_ctx* c, void* dev, size_t bytes) {
+  if (!c) return FDTD_EINVAL;
+  int rc = freeze(c);
+  if (rc) return rc;
+  if (c->ws) return fail(c, FDTD_ESTATE, "workspace already bound");
+  if (!dev || bytes < c->ws_bytes) return fail(c, FDTD_ENOMEM, "workspace too small");
+  if (((uintptr_t)dev & 255) != 0) return fail(c, FDTD_ENOMEM, "workspace not 256-byte aligned");
+  c->ws = (char*)dev;
+  rc = c->P.precision == 64 ? upload<double>(c) : upload<float>(c);
+  if (rc) c->ws = nullptr;
+  return rc;
+}
+
+int fdtd_set_kernel(fdtd_ctx* c, int variant, int tile_y, int tile_z) {
+  if (!c || variant < FDTD_KERNEL_AUTO || variant > FDTD_KERNEL_FUSED || tile_z < 0 ||
+      (tile_y != 0 && tile_y != 4 && tile_y != 8))
+    return fail(c, FDTD_EINVAL, "bad kernel selection (tile_y in {0, 4, 8}, tile_z >= 0)");
+  c->variant = variant;
+  c->tile_y = tile_y;
+  c->tile_z = tile_z;
+  return FDTD_OK;
+}
+
+int fdtd_step(fdtd_ctx* c, int n) {
+  if (!c || n < 0) return fail(c, FDTD_EINVAL, "bad step count");
+  if (!c->ws) return fail(c, FDTD_ESTATE, "no workspace bound");
+  if (c->steps_done + n > c->P.max_steps) return fail(c, FDTD_ERANGE, "beyond max_steps");
+  const int variant = c->variant == FDTD_KERNEL_AUTO ? FDTD_KERNEL_FUSED : c->variant;
+  for (int t = 0; t < n; ++t) {
+    const int in = c->cur, out = variant == FDTD_KERNEL_FUSED ? 1 - c->cur : c->cur;
+    const void* view = c->P.precision == 64 ? (const void*)&c->v64[in][out] : (const void*)&c->v32[in][out];
+    const void* pview = c->P.precision == 64 ? (const void*)&c->v64[out][out] : (const void*)&c->v32[out][out];
+    int slot = -1;
+    if (c->timing) {
+      slot = c->ev_next;
+      if (c->ev_pending == fdtd_ctx::kRing) {  // drain the oldest pair before reuse
+        float ms = 0;
+        hipError_t e = hipEventSynchronize(c->ev1[slot]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev0[slot], c->ev1[slot]);
+        if (e != hipSuccess) return hip_fail(c, e, "kernel timing");
+        c->timed_ms += ms;
+        ++c->timed_steps;
+        --c->ev_pending;
+      }
+      hipError_t er = hipEventRecord(c->ev0[slot], c->stream);
+      if (er != hipSuccess) return hip_fail(c, er, "hipEventRecord");
+    }
+    int e = launch_step(c->P.precision, view, c->cls16, variant, (int)c->steps_done, c->tile_y, c->tile_z,
+                        (void*)c->stream);
+    if (e) return fail(c, FDTD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString((hipError_t)e));
+    if (variant == FDTD_KERNEL_FUSED) c->cur ^= 1;
+    if (slot >= 0) {
+      hipError_t er = hipEventRecord(c->ev1[slot], c->stream);
+      if (er != hipSuccess) return hip_fail(c, er, "hipEventRecord");
+      c->ev_next = (slot + 1) % fdtd_ctx::kRing;
+      ++c->ev_pending;
+    }
+    e = launch_probes(c->P.precision, pview, (int)c->steps_done, (void*)c->stream);
+    if (e) return fail(c, FDTD_EDEVICE, std::string("probe launch: ") + hipGetErrorString((hipError_t)e));
+    ++c->steps_done;
+  }
+  return FDTD_OK;
+}
+
+int fdtd_timing(fdtd_ctx* c, int enable) {
+  if (!c) return FDTD_EINVAL;
+  if (enable && !c->ev0[0]) {
+    for (int q = 0; q < fdtd_ctx::kRing; ++q) {
+      hipError_t e = hipEventCreate(&c->ev0[q]);
+      if (e == hipSuccess) e = hipEventCreate(&c->ev1[q]);
+      if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+    }
+  }
+  c->timing = enable != 0;
+  return FDTD_OK;
+}
+
+int fdtd_kernel_time(fdtd_ctx* c, double* total_ms, long long* n_steps) {
+  if (!c || !total_ms || !n_steps) return FDTD_EINVAL;
+  while (c->ev_pending > 0) {
+    const int slot = (c->ev_next - c->ev_pending + fdtd_ctx::kRing) % fdtd_ctx::kRing;
+    float ms = 0;
+    hipError_t e = hipEventSynchronize(c->ev1[slot]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev0[slot], c->ev1[slot]);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel timing");
+    c->timed_ms += ms;
+    ++c->timed_steps;
+    --c->ev_pending;
+  }
+  *total_ms = c->timed_ms;
+  *n_steps = c->timed_steps;
+  c->timed_ms = 0;
+  c->timed_steps = 0;
+  return FDTD_OK;
+}
+
+int fdtd_probe(fdtd_ctx* c, int id, double* out, int n_max, int* n_written) {
+  if (!c || !out || id < 0 || id >= (int)c->probes.size() || n_max < 0) return fail(c, FDTD_EINVAL, "bad probe");
+  if (!c->ws) return fail(c, FDTD_ESTATE, "no workspace bound");
+  const int n = (int)std::min<long long>(c->steps_done, n_max);
+  const double* src = (const double*)(c->ws + c->off_out) + (size_t)id * c->P.max_steps;
+  hipError_t e = hipMemcpyAsync(out, src, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "probe copy");
+  if (n_written) *n_written = n;
+  if (!finite_all(out, (size_t)n)) return fail(c, FDTD_ENONFINITE, "probe record holds NaN or Inf");
+  return FDTD_OK;
+}
+
+static int field_ptr(fdtd_ctx* c, int comp, char** p) {
+  if (comp < 0 || comp > 5) return FDTD_EINVAL;
+  const size_t ts = tsize(c);
+  *p = c->ws + c->off_f + ((size_t)(c->cur * 6 + comp)) * (size_t)c->ncell * ts;
+  return FDTD_OK;
+}
+
+int fdtd_set_field(fdtd_ctx* c, int comp, const double* host) {
+  if (!c || !host || comp < 0 || comp > 5) return fail(c, FDTD_EINVAL, "bad field arguments");
+  if (!c->ws) return fail(c, FDTD_ESTATE, "no workspace bound");
+  char* dst;
+  field_ptr(c, comp, &dst);
+  const size_t N = (size_t)c->ncell;
+  std::vector<double> v(host, host + N);
+  if (comp < 3)  // perfect-conductor edges (walls, wires) have Cb = 0
+    for (size_t n = 0; n < N; ++n)
+      if (c->ctab[(size_t)c->cls_id[n] * K_NCOEF + 2 * comp + 1] == 0.0) v[n] = 0.0;
+  hipError_t e;
+  if (c->P.precision == 64) {
+    e = hipMemcpyAsync(dst, v.data(), N * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  } else {
+    std::vector<float> f(v.begin(), v.end());
+    e = hipMemcpyAsync(dst, f.data(), N * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "set_field");
+  return FDTD_OK;
+}
+
+int fdtd_get_field(fdtd_ctx* c, int comp, double* host) {
+  if (!c || !host || comp < 0 || comp > 5) return fail(c, FDTD_EINVAL, "bad field arguments");
+  if (!c->ws) return fail(c, FDTD_ESTATE, "no workspace bound");
+  char* src;
+  field_ptr(c, comp, &src);
+  const size_t N = (size_t)c->ncell;
+  hipError_t e;
+  if (c->P.precision == 64) {
+    e = hipMemcpyAsync(host, src, N * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  } else {
+    std::vector<float> f(N);
+    e = hipMemcpyAsync(f.data(), src, N * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    for (size_t n = 0; n < N; ++n) host[n] = f[n];
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "get_field");
+  return FDTD_OK;
+}
+
+double fdtd_dt(const fdtd_ctx* c) { return c ? c->dt : 0.0; }
+long long fdtd_steps_done(const fdtd_ctx* c) { return c ? c->steps_done : -1; }
+int fdtd_num_classes(const fdtd_ctx* c) { return c ? c->ncls : -1; }
+
+double fdtd_algorithmic_bytes_per_step(const fdtd_ctx* c) {
+  if (!c) return 0.0;
+  const double ts = c->P.precision == 64 ? 8.0 : 4.0;
+  double b = (double)c->ncell * (12.0 * ts + (c->cls16 ? 2.0 : 1.0));
+  // each CPML slab cell reads and writes 4 psi values per axis it lies in
+  for (int u = 0; u < 3; ++u) b += (double)c->psi_elems[u] * 4.0 * 2.0 * ts;
+  // (psi_elems counts the whole 2 npml slab pair of an axis)
+  return b;
+}
+
+const char* fdtd_last_error(const fdtd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void fdtd_destroy(fdtd_ctx* c) {
+  if (!c) return;
+  for (int q = 0; q < fdtd_ctx::kRing; ++q) {
+    if (c->ev0[q]) (void)hipEventDestroy(c->ev0[q]);
+    if (c->ev1[q]) (void)hipEventDestroy(c->ev1[q]);
+  }
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,452 @@
+// fdtd_kernels.hip -- HIP kernels of the Yee FDTD step for gfx950.
+//
+// Layout (all device memory lives in the caller's workspace): each field
+// component is an nx*ny*nz array, x fastest, holding the component owned by
+// node (i, j, k).  Values on the upper walls (index n along an axis) are not
+// stored: they are the zero tangential E of a perfect conductor or the zero
+// normal H next to it, so reads past the last node return 0.  Each node
+// carries a 1- or 2-byte coefficient class id; the class table holds the 9
+// coefficients of the node's six components.
+//
+// Variants:
+//   split  two passes (H over the grid, then E), in place;
+//   fused  one pass per step over x-y tiles marching up z; each block
+//          recomputes the H it needs on a one-node low-side halo; reads one
+//          field set and writes the other.
+// Both evaluate every component through h_point / e_point below and are
+// compiled with FP contraction off, so they agree bit for bit.
+#include <hip/hip_runtime.h>
+
+#include "fdtd_dev.h"
+#include "yee_update.h"
+
+namespace mi355fdtd {
+
+// ---------------------------------------------------------------------------
+// per-point updates shared by all variants
+// ---------------------------------------------------------------------------
+
+// H^{n+1/2} at node (x, y, k) from E^n at the node (ex, ey, ez), at x+1
+// (ey_i, ez_i), y+1 (ex_j, ez_j) and k+1 (ex_k, ey_k).  CPML state is read
+// from the input set and, if store_psi, written to the output set.
+template <typename T, bool PML>
+__device__ __forceinline__ void h_point(const GridView<T>& g, int x, int y, int k, const T* cf, T ex, T ey,
+                                        T ez, T ex_j, T ex_k, T ey_i, T ey_k, T ez_i, T ez_j, const T hold[3],
+                                        bool store_psi, T hnew[3]) {
+  T a_hx = ey_k - ey, b_hx = ez_j - ez;  // Hx: dEy/dz - dEz/dy
+  T a_hy = ez_i - ez, b_hy = ex_k - ex;  // Hy: dEz/dx - dEx/dz
+  T a_hz = ex_j - ex, b_hz = ey_i - ey;  // Hz: dEx/dy - dEy/dx
+  if (PML) {
+    const int np = g.npml, tn = 2 * np;
+    const int lx = slab_pos(x, g.nx, np), ly = slab_pos(y, g.ny, np), lz = slab_pos(k, g.nz, np);
+    if (lx >= 0) {
+      const long long q = psi_index(0, lx, x, y, k, g.nx, g.ny, np);
+      T s0 = g.pi[0][1][0][q], s1 = g.pi[0][1][1][q];  // Hy (dEz/dx), Hz (dEy/dx)
+      a_hy = pml_term(a_hy, s0, g.prof[0], lx, tn, P_BH);
+      b_hz = pml_term(b_hz, s1, g.prof[0], lx, tn, P_BH);
+      if (store_psi) { g.po[0][1][0][q] = s0; g.po[0][1][1][q] = s1; }
+    }
+    if (ly >= 0) {
+      const long long q = psi_index(1, ly, x, y, k, g.nx, g.ny, np);
+      T s0 = g.pi[1][1][0][q], s1 = g.pi[1][1][1][q];  // Hz (dEx/dy), Hx (dEz/dy)
+      a_hz = pml_term(a_hz, s0, g.prof[1], ly, tn, P_BH);
+      b_hx = pml_term(b_hx, s1, g.prof[1], ly, tn, P_BH);
+      if (store_psi) { g.po[1][1][0][q] = s0; g.po[1][1][1][q] = s1; }
+    }
+    if (lz >= 0) {
+      const long long q = psi_index(2, lz, x, y, k, g.nx, g.ny, np);
+      T s0 = g.pi[2][1][0][q], s1 = g.pi[2][1][1][q];  // Hx (dEy/dz), Hy (dEx/dz)
+      a_hx = pml_term(a_hx, s0, g.prof[2], lz, tn, P_BH);
+      b_hy = pml_term(b_hy, s1, g.prof[2], lz, tn, P_BH);
+      if (store_psi) { g.po[2][1][0][q] = s0; g.po[2][1][1][q] = s1; }
+    }
+  }
+  hnew[0] = h_new(hold[0], cf[K_DBX], a_hx, b_hx);
+  hnew[1] = h_new(hold[1], cf[K_DBY], a_hy, b_hy);
+  hnew[2] = h_new(hold[2], cf[K_DBZ], a_hz, b_hz);
+}
+
+// E^{n+1} at node (x, y, k) from H^{n+1/2} at the node (hx, hy, hz), at x-1
+// (hy_i, hz_i), y-1 (hx_j, hz_j) and k-1 (hx_k, hy_k); then the sources.
+template <typename T, bool PML>
+__device__ __forceinline__ void e_point(const GridView<T>& g, int x, int y, int k, long long n, const T* cf,
+                                        T hx, T hy, T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j,
+                                        const T eold[3], int step, T enew[3]) {
+  T a_ex = hz - hz_j, b_ex = hy - hy_k;  // Ex: dHz/dy - dHy/dz
+  T a_ey = hx - hx_k, b_ey = hz - hz_i;  // Ey: dHx/dz - dHz/dx
+  T a_ez = hy - hy_i, b_ez = hx - hx_j;  // Ez: dHy/dx - dHx/dy
+  if (PML) {
+    const int np = g.npml, tn = 2 * np;
+    const int lx = slab_pos(x, g.nx, np), ly = slab_pos(y, g.ny, np), lz = slab_pos(k, g.nz, np);
+    if (lx >= 0) {
+      const long long q = psi_index(0, lx, x, y, k, g.nx, g.ny, np);
+      T s0 = g.pi[0][0][0][q], s1 = g.pi[0][0][1][q];  // Ey (dHz/dx), Ez (dHy/dx)
+      b_ey = pml_term(b_ey, s0, g.prof[0], lx, tn, P_BE);
+      a_ez = pml_term(a_ez, s1, g.prof[0], lx, tn, P_BE);
+      g.po[0][0][0][q] = s0;
+      g.po[0][0][1][q] = s1;
+    }
+    if (ly >= 0) {
+      const long long q = psi_index(1, ly, x, y, k, g.nx, g.ny, np);
+      T s0 = g.pi[1][0][0][q], s1 = g.pi[1][0][1][q];  // Ez (dHx/dy), Ex (dHz/dy)
+      b_ez = pml_term(b_ez, s0, g.prof[1], ly, tn, P_BE);
+      a_ex = pml_term(a_ex, s1, g.prof[1], ly, tn, P_BE);
+      g.po[1][0][0][q] = s0;
+      g.po[1][0][1][q] = s1;
+    }
+    if (lz >= 0) {
+      const long long q = psi_index(2, lz, x, y, k, g.nx, g.ny, np);
+      T s0 = g.pi[2][0][0][q], s1 = g.pi[2][0][1][q];  // Ex (dHy/dz), Ey (dHx/dz)
+      b_ex = pml_term(b_ex, s0, g.prof[2], lz, tn, P_BE);
+      a_ey = pml_term(a_ey, s1, g.prof[2], lz, tn, P_BE);
+      g.po[2][0][0][q] = s0;
+      g.po[2][0][1][q] = s1;
+    }
+  }
+  enew[0] = e_new(eold[0], cf[K_CAX], cf[K_CBX], a_ex, b_ex);
+  enew[1] = e_new(eold[1], cf[K_CAY], cf[K_CBY], a_ey, b_ey);
+  enew[2] = e_new(eold[2], cf[K_CAZ], cf[K_CBZ], a_ez, b_ez);
+  // ideal current sources: E -= Cb I / dx^2 (precomputed per step)
+  for (int s = 0; s < g.n_src; ++s) {
+    if (g.src_idx[s] != n) continue;
+    const T v = g.src_amp[(long long)s * g.max_steps + step];
+    const int comp = g.src_comp[s];
+    enew[0] = comp == 0 ? enew[0] - v : enew[0];
+    enew[1] = comp == 1 ? enew[1] - v : enew[1];
+    enew[2] = comp == 2 ? enew[2] - v : enew[2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// split variant: two in-place passes
+// ---------------------------------------------------------------------------
+
+template <typename T, typename CI, bool PML>
+__global__ __launch_bounds__(256) void k_h_split(GridView<T> g) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const long long n = i + (long long)g.nx * j + g.sxy * k;
+  const T* cf = g.ctab + (int)((const CI*)g.cls)[n] * K_STRIDE;
+  const T ex = g.fi[0][n], ey = g.fi[1][n], ez = g.fi[2][n];
+  const T ex_j = (j + 1 < g.ny) ? g.fi[0][n + g.nx] : T(0);
+  const T ex_k = (k + 1 < g.nz) ? g.fi[0][n + g.sxy] : T(0);
+  const T ey_i = (i + 1 < g.nx) ? g.fi[1][n + 1] : T(0);
+  const T ey_k = (k + 1 < g.nz) ? g.fi[1][n + g.sxy] : T(0);
+  const T ez_i = (i + 1 < g.nx) ? g.fi[2][n + 1] : T(0);
+  const T ez_j = (j + 1 < g.ny) ? g.fi[2][n + g.nx] : T(0);
+  const T hold[3] = {g.fi[3][n], g.fi[4][n], g.fi[5][n]};
+  T h[3];
+  h_point<T, PML>(g, i, j, k, cf, ex, ey, ez, ex_j, ex_k, ey_i, ey_k, ez_i, ez_j, hold, true, h);
+  g.fo[3][n] = h[0];
+  g.fo[4][n] = h[1];
+  g.fo[5][n] = h[2];
+}
+
+template <typename T, typename CI, bool PML>
+__global__ __launch_bounds__(256) void k_e_split(GridView<T> g, int step) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const long long n = i + (long long)g.nx * j + g.sxy * k;
+  const T* cf = g.ctab + (int)((const CI*)g.cls)[n] * K_STRIDE;
+  const T hx = g.fi[3][n], hy = g.fi[4][n], hz = g.fi[5][n];
+  const T hx_j = (j > 0) ? g.fi[3][n - g.nx] : T(0);
+  const T hx_k = (k > 0) ? g.fi[3][n - g.sxy] : T(0);
+  const T hy_i = (i > 0) ? g.fi[4][n - 1] : T(0);
+  const T hy_k = (k > 0) ? g.fi[4][n - g.sxy] : T(0);
+  const T hz_i = (i > 0) ? g.fi[5][n - 1] : T(0);
+  const T hz_j = (j > 0) ? g.fi[5][n - g.nx] : T(0);
+  const T eold[3] = {g.fi[0][n], g.fi[1][n], g.fi[2][n]};
+  T e[3];
+  e_point<T, PML>(g, i, j, k, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, e);
+  g.fo[0][n] = e[0];
+  g.fo[1][n] = e[1];
+  g.fo[2][n] = e[2];
+}
+
+// ---------------------------------------------------------------------------
+// fused variant
+//
+// Block = TY waves owning the x-y tile [i0, i0+64) x [j0, j0+TY) over the
+// z-chunk [k0, k1); thread (tx, ty) owns column (i0+tx, j0+ty) and keeps its
+// own E and H in registers.  LDS holds only what neighbours need: E^n of
+// planes k and k+1 on the region [i0-1, i0+64] x [j0-1, j0+TY] (2-plane
+// ring) and H^{n+1/2} of plane k on [i0-1, i0+63] x [j0-1, j0+TY-1].  The
+// low-side H halo (row j0-1, column i0-1) is recomputed by the first
+// threads with the owners' arithmetic; the E halo is loaded by the last
+// threads.  Loads for plane k+1 are issued before plane k is computed.
+// Per plane: stage E(k+1) -> barrier -> H(k) -> barrier -> E(k).
+// ---------------------------------------------------------------------------
+
+// Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous run
+// of tiles so that neighbouring tiles share that XCD's L2 for their halos.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb / 8, r = nb % 8, x = b % 8, t = b / 8;
+  return x * q + (x < r ? x : r) + t;
+}
+
+template <typename T>
+__device__ __forceinline__ void load3(const GridView<T>& g, bool ok, long long n, T v[3]) {
+  v[0] = ok ? g.fi[0][n] : T(0);
+  v[1] = ok ? g.fi[1][n] : T(0);
+  v[2] = ok ? g.fi[2][n] : T(0);
+}
+template <typename T>
+__device__ __forceinline__ void load3h(const GridView<T>& g, bool ok, long long n, T v[3]) {
+  v[0] = ok ? g.fi[3][n] : T(0);
+  v[1] = ok ? g.fi[4][n] : T(0);
+  v[2] = ok ? g.fi[5][n] : T(0);
+}
+
+template <typename T, typename CI, bool PML, int TY>
+__global__ __launch_bounds__(64 * TY) void k_fused(GridView<T> g, int step, int kz, int ntx, int nty) {
+  constexpr int NT = 64 * TY, EW = 66, EH = TY + 2, HW = 65, HH = TY + 1;
+  constexpr int NHE = 2 * EW + 2 * TY;  // E halo points
+  constexpr int NHH = HW + TY;          // H halo points
+  constexpr bool LDS_TAB = sizeof(CI) == 1;
+  __shared__ T se[2][3][EH][EW];
+  __shared__ T sh[3][HH][HW];
+  __shared__ T stab[LDS_TAB ? 256 * K_STRIDE : 1];
+
+  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile_x = tile % ntx, rest = tile / ntx;
+  const int i0 = tile_x * 64, j0 = (rest % nty) * TY, k0 = (rest / nty) * kz;
+  const int k1 = min(k0 + kz, g.nz);
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const long long sxy = g.sxy;
+  const CI* cls = (const CI*)g.cls;
+
+  if (LDS_TAB) {
+    for (int q = tid; q < g.ncls * K_STRIDE; q += NT) stab[q] = g.ctab[q];
+  }
+  auto coef = [&](int c) -> const T* { return LDS_TAB ? stab + c * K_STRIDE : g.ctab + c * K_STRIDE; };
+
+  // own column
+  const int i = i0 + tx, j = j0 + ty;
+  const bool own = i < nx && j < ny;
+  const long long n0 = own ? (long long)i + (long long)nx * j : 0;  // + sxy * k
+  // E halo point (threads NT-NHE .. NT-1)
+  int er = 0, ec = 0;
+  bool eh = false;
+  {
+    const int h = tid - (NT - NHE);
+    if (h >= 0) {
+      eh = true;
+      if (h < EW) { er = 0; ec = h; }
+      else if (h < 2 * EW) { er = EH - 1; ec = h - EW; }
+      else if (h < 2 * EW + TY) { er = h - 2 * EW + 1; ec = 0; }
+      else { er = h - 2 * EW - TY + 1; ec = EW - 1; }
+    }
+  }
+  const int ex_x = i0 - 1 + ec, ex_y = j0 - 1 + er;
+  const bool eh_in = eh && ex_x >= 0 && ex_x < nx && ex_y >= 0 && ex_y < ny;
+  const long long en0 = eh_in ? (long long)ex_x + (long long)nx * ex_y : 0;
+  // H halo point (threads 0 .. NHH-1): row j0-1 (c = 0..64) then column i0-1
+  const bool hh = tid < NHH;
+  const int hr = tid < HW ? 0 : tid - HW + 1, hc = tid < HW ? tid : 0;
+  const int hx_x = i0 - 1 + hc, hx_y = j0 - 1 + hr;
+  const bool hh_in = hh && hx_x >= 0 && hx_x < nx && hx_y >= 0 && hx_y < ny;
+  const long long hn0 = hh_in ? (long long)hx_x + (long long)nx * hx_y : 0;
+
+  // ---- prologue: H^{n+1/2} of plane k0-1 at the own column (needed as H(k-1))
+  T ecur[3], enext[3], xe_next[3], hold[3], xh_old[3], hm[2] = {T(0), T(0)};
+  int cls_cur = 0, xcls_cur = 0;
+  {
+    const int kb = k0 - 1;
+    T eb[3], xeb[3], xe0[3], hb[3];
+    load3(g, own && kb >= 0, n0 + sxy * kb, eb);
+    load3(g, eh_in && kb >= 0, en0 + sxy * kb, xeb);
+    load3(g, own, n0 + sxy * k0, ecur);
+    load3(g, eh_in, en0 + sxy * k0, xe0);
+    load3h(g, own && kb >= 0, n0 + sxy * kb, hb);
+    const int cb = (own && kb >= 0) ? (int)cls[n0 + sxy * kb] : 0;
+    const int sb = (kb + 2) & 1, s0 = k0 & 1;
+    for (int c = 0; c < 3; ++c) {
+      se[sb][c][ty + 1][tx + 1] = eb[c];
+      se[s0][c][ty + 1][tx + 1] = ecur[c];
+      if (eh) {
+        se[sb][c][er][ec] = xeb[c];
+        se[s0][c][er][ec] = xe0[c];
+      }
+    }
+    __syncthreads();
+    if (own && kb >= 0) {
+      T h[3];
+      h_point<T, PML>(g, i, j, kb, coef(cb), eb[0], eb[1], eb[2], se[sb][0][ty + 2][tx + 1], ecur[0],
+                      se[sb][1][ty + 1][tx + 2], ecur[1], se[sb][2][ty + 1][tx + 2], se[sb][2][ty + 2][tx + 1],
+                      hb, false, h);
+      hm[0] = h[0];
+      hm[1] = h[1];
+    }
+    // plane k0 inputs and plane k0+1 E
+    load3h(g, own, n0 + sxy * k0, hold);
+    load3h(g, hh_in, hn0 + sxy * k0, xh_old);
+    cls_cur = own ? (int)cls[n0 + sxy * k0] : 0;
+    xcls_cur = hh_in ? (int)cls[hn0 + sxy * k0] : 0;
+    const bool nxt = k0 + 1 < nz;
+    load3(g, own && nxt, n0 + sxy * (k0 + 1), enext);
+    load3(g, eh_in && nxt, en0 + sxy * (k0 + 1), xe_next);
+    __syncthreads();  // plane kb's LDS slot is rewritten below
+  }
+
+  for (int k = k0; k < k1; ++k) {
+    const int s = k & 1, s1 = s ^ 1;
+    // (a) stage E(k+1)
+    for (int c = 0; c < 3; ++c) {
+      se[s1][c][ty + 1][tx + 1] = enext[c];
+      if (eh) se[s1][c][er][ec] = xe_next[c];
+    }
+    // (b) prefetch plane k+1 inputs and E(k+2)
+    T epf[3], xepf[3], hpf[3], xhpf[3];
+    const bool n1 = k + 1 < k1, n2 = k + 2 < nz;
+    load3(g, own && n2, n0 + sxy * (k + 2), epf);
+    load3(g, eh_in && n2, en0 + sxy * (k + 2), xepf);
+    load3h(g, own && n1, n0 + sxy * (k + 1), hpf);
+    load3h(g, hh_in && n1, hn0 + sxy * (k + 1), xhpf);
+    const int cpf = (own && n1) ? (int)cls[n0 + sxy * (k + 1)] : 0;
+    const int xcpf = (hh_in && n1) ? (int)cls[hn0 + sxy * (k + 1)] : 0;
+    __syncthreads();
+    // (c) H(k): own column, then the low-side halo point
+    T hown[3] = {T(0), T(0), T(0)};
+    if (own) {
+      h_point<T, PML>(g, i, j, k, coef(cls_cur), ecur[0], ecur[1], ecur[2], se[s][0][ty + 2][tx + 1], enext[0],
+                      se[s][1][ty + 1][tx + 2], enext[1], se[s][2][ty + 1][tx + 2], se[s][2][ty + 2][tx + 1],
+                      hold, true, hown);
+      const long long n = n0 + sxy * k;
+      g.fo[3][n] = hown[0];
+      g.fo[4][n] = hown[1];
+      g.fo[5][n] = hown[2];
+    }
+    sh[0][ty + 1][tx + 1] = hown[0];
+    sh[1][ty + 1][tx + 1] = hown[1];
+    sh[2][ty + 1][tx + 1] = hown[2];
+    if (hh) {
+      T hx3[3] = {T(0), T(0), T(0)};
+      if (hh_in) {
+        h_point<T, PML>(g, hx_x, hx_y, k, coef(xcls_cur), se[s][0][hr][hc], se[s][1][hr][hc], se[s][2][hr][hc],
+                        se[s][0][hr + 1][hc], se[s1][0][hr][hc], se[s][1][hr][hc + 1], se[s1][1][hr][hc],
+                        se[s][2][hr][hc + 1], se[s][2][hr + 1][hc], xh_old, false, hx3);
+      }
+      sh[0][hr][hc] = hx3[0];
+      sh[1][hr][hc] = hx3[1];
+      sh[2][hr][hc] = hx3[2];
+    }
+    __syncthreads();
+    // (d) E(k) at the own column
+    if (own) {
+      const long long n = n0 + sxy * k;
+      T e[3];
+      e_point<T, PML>(g, i, j, k, n, coef(cls_cur), hown[0], hown[1], hown[2], sh[0][ty][tx + 1], hm[0],
+                      sh[1][ty + 1][tx], hm[1], sh[2][ty + 1][tx], sh[2][ty][tx + 1], ecur, step, e);
+      g.fo[0][n] = e[0];
+      g.fo[1][n] = e[1];
+      g.fo[2][n] = e[2];
+    }
+    // rotate the pipeline
+    hm[0] = hown[0];
+    hm[1] = hown[1];
+    for (int c = 0; c < 3; ++c) {
+      ecur[c] = enext[c];
+      enext[c] = epf[c];
+      xe_next[c] = xepf[c];
+      hold[c] = hpf[c];
+      xh_old[c] = xhpf[c];
+    }
+    cls_cur = cpf;
+    xcls_cur = xcpf;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// probes: one wave per probe, FP64 sum in a fixed order (deterministic)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_probes(GridView<T> g, int step) {
+  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (p >= g.n_probe) return;  // uniform per wave
+  double acc = 0.0;
+  for (int t = g.pr_off[p] + lane; t < g.pr_off[p + 1]; t += 64) {
+    const int c = g.term_comp[t];
+    const T* f = c == 0 ? g.fi[0] : c == 1 ? g.fi[1] : c == 2 ? g.fi[2] : c == 3 ? g.fi[3] : c == 4 ? g.fi[4] : g.fi[5];
+    acc += g.term_w[t] * (double)f[g.term_idx[t]];
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if (lane == 0) g.pr_out[(long long)p * g.max_steps + step] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <typename T, typename CI>
+hipError_t step_split(const GridView<T>& g, int step, hipStream_t st) {
+  const dim3 blk(64, 4, 1), grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+  if (g.npml > 0) {
+    hipLaunchKernelGGL((k_h_split<T, CI, true>), grd, blk, 0, st, g);
+    hipLaunchKernelGGL((k_e_split<T, CI, true>), grd, blk, 0, st, g, step);
+  } else {
+    hipLaunchKernelGGL((k_h_split<T, CI, false>), grd, blk, 0, st, g);
+    hipLaunchKernelGGL((k_e_split<T, CI, false>), grd, blk, 0, st, g, step);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, typename CI, bool PML, int TY>
+hipError_t launch_fused(const GridView<T>& g, int step, int kz, hipStream_t st) {
+  const int ntx = (g.nx + 63) / 64, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + kz - 1) / kz;
+  const long long nb = (long long)ntx * nty * ntz;
+  if (nb > 0x7fffffff || (sizeof(CI) == 1 && g.ncls > 256)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_fused<T, CI, PML, TY>), dim3((unsigned)nb), dim3(64 * TY), 0, st, g, step, kz, ntx,
+                     nty);
+  return hipGetLastError();
+}
+
+template <typename T, typename CI>
+hipError_t step_fused(const GridView<T>& g, int step, int tile_y, int tile_z, hipStream_t st) {
+  const int kz = tile_z > 0 ? tile_z : 32;
+  const bool pml = g.npml > 0;
+  if (tile_y == 4)
+    return pml ? launch_fused<T, CI, true, 4>(g, step, kz, st) : launch_fused<T, CI, false, 4>(g, step, kz, st);
+  return pml ? launch_fused<T, CI, true, 8>(g, step, kz, st) : launch_fused<T, CI, false, 8>(g, step, kz, st);
+}
+
+template <typename T>
+hipError_t step_any(const GridView<T>& g, int cls16, int variant, int step, int tile_y, int tile_z,
+                    hipStream_t st) {
+  if (variant == 2)
+    return cls16 ? step_fused<T, uint16_t>(g, step, tile_y, tile_z, st)
+                 : step_fused<T, uint8_t>(g, step, tile_y, tile_z, st);
+  return cls16 ? step_split<T, uint16_t>(g, step, st) : step_split<T, uint8_t>(g, step, st);
+}
+
+int launch_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, int tile_z,
+                void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (prec == 64)
+    e = step_any<double>(*(const GridView<double>*)view, cls16, variant, step, tile_y, tile_z, st);
+  else
+    e = step_any<float>(*(const GridView<float>*)view, cls16, variant, step, tile_y, tile_z, st);
+  return (int)e;
+}
+
+template <typename T>
+hipError_t probes_any(const GridView<T>& g, int step, hipStream_t st) {
+  if (g.n_probe <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_probes<T>), dim3((g.n_probe + 3) / 4), dim3(256), 0, st, g, step);
+  return hipGetLastError();
+}
+
+int launch_probes(int prec, const void* view, int step, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == 64) return (int)probes_any<double>(*(const GridView<double>*)view, step, st);
+  return (int)probes_any<float>(*(const GridView<float>*)view, step, st);
+}
+
+}  // namespace mi355fdtd

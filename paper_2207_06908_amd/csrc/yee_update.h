@@ -1,0 +1,63 @@
+// yee_update.h -- per-element arithmetic of the Yee update, shared by every
+// kernel variant so that all variants produce bit-identical fields.
+//
+// Section 2.1 of the paper: the H update of eq. 5 and the E update of eq. 4
+// (semi-implicit or literal loss factor folded into ca / cb), the other
+// components by cyclic permutation; Section 2.2: inside the CPML each
+// derivative term d of axis u becomes d / kappa_u + psi with
+// psi <- b_u psi + c_u d (recursive convolution).  Differences are raw (not
+// divided by dx): 1/dx is folded into cb and db, and psi is stored times dx.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fdtd_dev.h"
+
+namespace mi355fdtd {
+
+// One CPML-stretched derivative term.  `prof` is the axis table, `l` the
+// slab-local position, `row` P_BE (E position) or P_BH (H position).  The
+// table holds b - 1, so the recursion psi <- b psi + c d is evaluated as
+// psi + ((b - 1) psi + c d), which keeps FP32 accurate where b is near 1.
+template <typename T>
+__device__ __forceinline__ T pml_term(T d, T& psi, const T* prof, int l, int two_np, int row) {
+  const T bm1 = prof[(row + 0) * two_np + l];
+  const T c = prof[(row + 1) * two_np + l];
+  const T ik = prof[(row + 2) * two_np + l];
+  psi = psi + fma(bm1, psi, c * d);
+  return fma(d, ik, psi);
+}
+
+// Slab-local position of node index `pos` along an axis of n cells, or -1.
+__device__ __forceinline__ int slab_pos(int pos, int n, int np) {
+  if (pos < np) return pos;
+  if (pos >= n - np) return pos - n + 2 * np;
+  return -1;
+}
+
+// Index of node (i, j, k) inside the psi slab of axis u at local position l.
+__device__ __forceinline__ long long psi_index(int u, int l, int i, int j, int k, int nx, int ny, int np) {
+  const int t = 2 * np;
+  if (u == 0) return (long long)l + (long long)t * (j + (long long)ny * k);
+  if (u == 1) return (long long)i + (long long)nx * (l + (long long)t * k);
+  return (long long)i + (long long)nx * (j + (long long)ny * l);
+}
+
+// H update of one node from raw E differences.
+//   Hx += db_x ((Ey[k+1] - Ey) - (Ez[j+1] - Ez))
+//   Hy += db_y ((Ez[i+1] - Ez) - (Ex[k+1] - Ex))
+//   Hz += db_z ((Ex[j+1] - Ex) - (Ey[i+1] - Ey))
+template <typename T>
+__device__ __forceinline__ T h_new(T h, T db, T t_plus, T t_minus) {
+  return fma(db, t_plus - t_minus, h);
+}
+
+// E update of one node from raw H differences.
+//   Ex = ca_x Ex + cb_x ((Hz - Hz[j-1]) - (Hy - Hy[k-1]))
+//   Ey = ca_y Ey + cb_y ((Hx - Hx[k-1]) - (Hz - Hz[i-1]))
+//   Ez = ca_z Ez + cb_z ((Hy - Hy[i-1]) - (Hx - Hx[j-1]))
+template <typename T>
+__device__ __forceinline__ T e_new(T e, T ca, T cb, T t_plus, T t_minus) {
+  return fma(ca, e, cb * (t_plus - t_minus));
+}
+
+}  // namespace mi355fdtd

@@ -1,0 +1,229 @@
+"""Python binding of the HIP FDTD library (argument marshalling only).
+
+Every step of the method runs in the HIP kernels of ``libmi355fdtd.so``;
+PyTorch only provides the device workspace and the stream.  If the library
+is missing this module raises at import time -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmi355fdtd.so")
+
+FDTD_EX, FDTD_EY, FDTD_EZ, FDTD_HX, FDTD_HY, FDTD_HZ = range(6)
+PR_E, PR_VLINE, PR_ILOOP = 0, 1, 2
+KERNEL_AUTO, KERNEL_SPLIT, KERNEL_FUSED = 0, 1, 2
+ERRORS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ESTATE", -4: "EUNSTABLE", -5: "ENOMEM",
+          -6: "EDEVICE", -7: "ENONFINITE", -8: "ECLASS"}
+
+
+class Params(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("dx", C.c_double),
+                ("dt", C.c_double), ("npml", C.c_int), ("pml_m", C.c_double),
+                ("pml_sigma_factor", C.c_double), ("pml_kappa_max", C.c_double),
+                ("pml_alpha_max", C.c_double), ("pml_ma", C.c_double), ("loss_mode", C.c_int),
+                ("wire_r0_factor", C.c_double), ("max_steps", C.c_int), ("precision", C.c_int)]
+
+
+class Material(C.Structure):
+    _fields_ = [("eps_r", C.c_double), ("sigma", C.c_double), ("mu_r", C.c_double)]
+
+
+# (name, restype, argtypes) of every exported symbol declared in include/fdtd.h
+_vp = C.c_void_p
+SIGNATURES = [
+    ("fdtd_default_params", None, [C.POINTER(Params)]),
+    ("fdtd_create", C.c_int, [C.POINTER(Params), _vp, C.POINTER(_vp)]),
+    ("fdtd_set_materials", C.c_int, [_vp, _vp, C.POINTER(Material), C.c_int]),
+    ("fdtd_add_wire", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]),
+    ("fdtd_add_source", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int]),
+    ("fdtd_add_probe", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                 C.POINTER(C.c_int)]),
+    ("fdtd_finalize", C.c_int, [_vp]),
+    ("fdtd_workspace_bytes", C.c_size_t, [_vp]),
+    ("fdtd_bind_workspace", C.c_int, [_vp, _vp, C.c_size_t]),
+    ("fdtd_set_kernel", C.c_int, [_vp, C.c_int, C.c_int, C.c_int]),
+    ("fdtd_step", C.c_int, [_vp, C.c_int]),
+    ("fdtd_probe", C.c_int, [_vp, C.c_int, _vp, C.c_int, C.POINTER(C.c_int)]),
+    ("fdtd_set_field", C.c_int, [_vp, C.c_int, _vp]),
+    ("fdtd_get_field", C.c_int, [_vp, C.c_int, _vp]),
+    ("fdtd_dt", C.c_double, [_vp]),
+    ("fdtd_steps_done", C.c_longlong, [_vp]),
+    ("fdtd_num_classes", C.c_int, [_vp]),
+    ("fdtd_algorithmic_bytes_per_step", C.c_double, [_vp]),
+    ("fdtd_timing", C.c_int, [_vp, C.c_int]),
+    ("fdtd_kernel_time", C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
+    ("fdtd_last_error", C.c_char_p, [_vp]),
+    ("fdtd_destroy", None, [_vp]),
+]
+
+_lib = None
+
+
+def lib():
+    """Load libmi355fdtd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_2207_06908_amd/csrc/build.py` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class FdtdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _stream_handle(device):
+    import torch
+    if not torch.cuda.is_available():
+        return None
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Grid:
+    """One FDTD grid on the GPU.  Same call surface as the FP64 reference."""
+
+    def __init__(self, nx, ny, nz, dx, dt=0.0, npml=0, pml_m=3.0, pml_sigma_factor=1.0,
+                 pml_kappa_max=1.0, pml_alpha_max=0.0, pml_ma=1.0, loss_mode=0,
+                 wire_r0_factor=math.exp(-math.pi / 2), max_steps=1, precision=32,
+                 device="cuda:0", stream=None):
+        self.shape = (nz, ny, nx)
+        self.max_steps = max_steps
+        self.device = device
+        p = Params(nx, ny, nz, dx, dt, npml, pml_m, pml_sigma_factor, pml_kappa_max, pml_alpha_max,
+                   pml_ma, loss_mode, wire_r0_factor, max_steps, precision)
+        h = C.c_void_p()
+        st = stream if stream is not None else _stream_handle(device)
+        rc = lib().fdtd_create(C.byref(p), st, C.byref(h))
+        if rc:
+            raise FdtdError(rc, "fdtd_create rejected the parameters")
+        self._h = h
+        self._ws = None
+
+    @classmethod
+    def from_params(cls, params: dict, **kw):
+        return cls(**params, **kw)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().fdtd_destroy(h)
+            self._h = None
+
+    def _chk(self, rc):
+        if rc:
+            raise FdtdError(rc, lib().fdtd_last_error(self._h).decode())
+
+    # -- set-up ------------------------------------------------------------
+    def set_materials(self, cell_mat, materials):
+        cm = np.ascontiguousarray(cell_mat, dtype=np.uint8)
+        if cm.shape != self.shape:
+            raise ValueError(f"cell_mat shape {cm.shape} != {self.shape}")
+        tab = (Material * len(materials))(*[Material(*m) for m in materials])
+        self._chk(lib().fdtd_set_materials(self._h, cm.ctypes.data, tab, len(materials)))
+
+    def add_wire(self, axis, i, j, k, n, radius):
+        self._chk(lib().fdtd_add_wire(self._h, axis, i, j, k, n, radius))
+
+    def add_source(self, axis, i, j, k, amps):
+        a = np.ascontiguousarray(amps, dtype=np.float64)
+        self._chk(lib().fdtd_add_source(self._h, 0, axis, i, j, k, a.ctypes.data, a.size))
+
+    def add_probe(self, kind, axis, i, j, k, n=1) -> int:
+        pid = C.c_int(-1)
+        self._chk(lib().fdtd_add_probe(self._h, kind, axis, i, j, k, n, C.byref(pid)))
+        return pid.value
+
+    def set_kernel(self, variant=KERNEL_AUTO, tile_y=0, tile_z=0):
+        self._chk(lib().fdtd_set_kernel(self._h, variant, tile_y, tile_z))
+
+    # -- device ------------------------------------------------------------
+    def finalize(self):
+        self._chk(lib().fdtd_finalize(self._h))
+
+    def workspace_bytes(self) -> int:
+        self.finalize()
+        n = lib().fdtd_workspace_bytes(self._h)
+        if n == 0:
+            raise FdtdError(-1, lib().fdtd_last_error(self._h).decode())
+        return n
+
+    def bind(self):
+        if self._ws is not None:
+            return
+        import torch
+        nbytes = self.workspace_bytes()
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._chk(lib().fdtd_bind_workspace(self._h, C.c_void_p(self._ws.data_ptr()), nbytes))
+
+    def step(self, n):
+        self.bind()
+        self._chk(lib().fdtd_step(self._h, int(n)))
+
+    def probe(self, pid) -> np.ndarray:
+        self.bind()
+        out = np.zeros(self.max_steps, np.float64)
+        nw = C.c_int(0)
+        self._chk(lib().fdtd_probe(self._h, pid, out.ctypes.data, out.size, C.byref(nw)))
+        return out[:nw.value].copy()
+
+    def set_field(self, comp, arr):
+        self.bind()
+        a = np.ascontiguousarray(arr, dtype=np.float64)
+        if a.shape != self.shape:
+            raise ValueError("field shape mismatch")
+        self._chk(lib().fdtd_set_field(self._h, comp, a.ctypes.data))
+
+    def get_field(self, comp) -> np.ndarray:
+        self.bind()
+        out = np.zeros(self.shape, np.float64)
+        self._chk(lib().fdtd_get_field(self._h, comp, out.ctypes.data))
+        return out
+
+    # -- diagnostics -------------------------------------------------------
+    def timing(self, enable=True):
+        self._chk(lib().fdtd_timing(self._h, int(enable)))
+
+    def kernel_time(self):
+        """(total ms, steps) of the update kernels timed since the last call."""
+        ms, n = C.c_double(0), C.c_longlong(0)
+        self._chk(lib().fdtd_kernel_time(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    @property
+    def dt(self) -> float:
+        return lib().fdtd_dt(self._h)
+
+    @property
+    def steps_done(self) -> int:
+        return lib().fdtd_steps_done(self._h)
+
+    @property
+    def num_classes(self) -> int:
+        return lib().fdtd_num_classes(self._h)
+
+    def algorithmic_bytes_per_step(self) -> float:
+        return lib().fdtd_algorithmic_bytes_per_step(self._h)
+
+
+def run_scenario(sc, apply_fn, precision=32, variant=KERNEL_AUTO, tile_y=0, tile_z=0):
+    """Run a scenario to completion on the GPU; returns {probe name: waveform}."""
+    g = Grid.from_params(sc.params(), precision=precision)
+    ids = apply_fn(sc, g)
+    g.set_kernel(variant, tile_y, tile_z)
+    g.step(sc.n_steps)
+    return {p[0]: g.probe(i) for p, i in zip(sc.probes, ids)}

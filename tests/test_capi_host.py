@@ -1,0 +1,113 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol its
+header declares, and rejects bad set-up on the host before any HIP call."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2207_06908_amd import fdtd
+from paper_2207_06908_amd import scenarios as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    txt = open(os.path.join(ROOT, "include", header)).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:fdtd|sur)_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = fdtd.lib()
+    names = _declared("fdtd.h")
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(n for n, _r, _a in fdtd.SIGNATURES) == names
+
+
+def _grid(**kw):
+    base = dict(nx=12, ny=10, nz=9, dx=0.5, max_steps=10)
+    base.update(kw)
+    return fdtd.Grid(**base)
+
+
+def _code(fn):
+    with pytest.raises(fdtd.FdtdError) as e:
+        fn()
+    return e.value.code
+
+
+def test_create_validation():
+    assert _code(lambda: _grid(nx=1)) == -1
+    assert _code(lambda: _grid(dt=1e-6)) == -4                  # above Courant
+    assert _code(lambda: _grid(npml=5)) == -1                   # 2 npml >= ny
+    assert _code(lambda: _grid(precision=16)) == -1
+    assert _code(lambda: _grid(loss_mode=3)) == -1
+    assert _code(lambda: _grid(wire_r0_factor=1.5)) == -1
+    g = _grid()
+    assert g.dt == pytest.approx(0.99 * 0.5 / (299792458.0 * math.sqrt(3)), rel=1e-15)
+
+
+def test_setup_validation():
+    g = _grid()
+    cm = np.zeros(g.shape, np.uint8)
+    assert _code(lambda: g.set_materials(cm + 2, [(1, 0, 1)])) == -2         # id outside table
+    assert _code(lambda: g.set_materials(cm, [(-1, 0, 1)])) == -1
+    assert _code(lambda: g.set_materials(cm, [(float("nan"), 0, 1)])) == -7
+    assert _code(lambda: g.add_wire(0, 2, 2, 2, 3, 0.3)) == -1               # radius >= dx/2
+    assert _code(lambda: g.add_wire(0, 10, 2, 2, 3, 0.01)) == -2             # leaves the grid
+    assert _code(lambda: g.add_wire(3, 1, 1, 1, 1, 0.01)) == -1
+    assert _code(lambda: g.add_source(2, 0, 5, 5, np.ones(3))) == -2          # x = 0 wall
+    assert _code(lambda: g.add_source(0, 3, 0, 5, np.ones(3))) == -2          # y = 0 wall
+    assert _code(lambda: g.add_source(2, 3, 3, 3, np.array([1.0, np.inf]))) == -7
+    assert _code(lambda: g.add_probe(2, 2, 0, 3, 3)) == -2                    # loop on a wall
+    assert _code(lambda: g.add_probe(1, 0, 3, 3, 3, 20)) == -2                # line leaves
+    assert _code(lambda: g.add_probe(0, 0, 3, 3, 3, 2)) == -1
+    g.add_probe(0, 2, 3, 3, 3)
+    assert g.workspace_bytes() > 0
+    assert _code(lambda: g.add_wire(0, 2, 2, 2, 3, 0.01)) == -3               # frozen
+    assert fdtd.lib().fdtd_step(g._h, 1) == -3                                # no workspace bound
+
+
+def test_source_on_wire_edge_rejected_at_freeze():
+    g = _grid()
+    g.add_wire(2, 5, 5, 2, 4, 0.01)
+    g.add_source(2, 5, 5, 3, np.ones(3))
+    assert _code(g.workspace_bytes) == -2
+
+
+def test_explicit_loss_stability_check():
+    g = _grid(loss_mode=1, dx=0.5)
+    cm = np.zeros(g.shape, np.uint8)
+    g.set_materials(cm, [(1.0, 50.0, 1.0)])   # sigma dt / eps >> 2
+    assert _code(g.workspace_bytes) == -4
+    g2 = _grid(loss_mode=0, dx=0.5)
+    g2.set_materials(cm, [(1.0, 50.0, 1.0)])  # semi-implicit stays stable
+    assert g2.workspace_bytes() > 0
+
+
+def test_classes_and_bytes_config1():
+    sc = S.config1(n_steps=2)
+    g = fdtd.Grid.from_params(sc.params())
+    S.apply(sc, g)
+    nb = g.workspace_bytes()
+    # air, soil, the interface, and the wall patterns: a handful of classes
+    assert 3 <= g.num_classes <= 64
+    # two field sets of six FP32 components dominate the workspace
+    assert nb >= 12 * 4 * sc.cells
+    assert g.algorithmic_bytes_per_step() == pytest.approx(sc.cells * 49.0)
+
+
+def test_classes_config2_small_with_cpml():
+    sc = S.config2_small(n_steps=2)
+    g = fdtd.Grid.from_params(sc.params())
+    S.apply(sc, g)
+    g.workspace_bytes()
+    assert g.num_classes <= 256
+    # CPML state: 4 psi of 4 bytes read and written per slab node and axis
+    n, npml = sc.nx, sc.npml
+    slab = 2 * npml * (sc.ny * sc.nz + sc.nx * sc.nz + sc.nx * sc.ny)
+    assert g.algorithmic_bytes_per_step() == pytest.approx(sc.cells * 49.0 + slab * 32.0)
