@@ -41,14 +41,51 @@ def cpu_baseline(steps: int):
             "sample": f"FP64 oracle, full 512x512x384 grid, {steps} steps after table build"}
 
 
+def bench_batch(warmup: int = 100, graph_steps: int = 100):
+    """The 256-grid electrode sweep (uneven 32-96^3 grids, dx 0.25 m, 8-cell
+    CPML, 2000 steps) in the batched engine with HIP-graph replay."""
+    import torch
+    from paper_2207_06908_amd import fdtd
+    from paper_2207_06908_amd import scenarios as S
+    steps = 2000
+    scs = S.config3(n_steps=warmup + steps)
+    grids = []
+    for sc in scs:
+        g = fdtd.Grid.from_params(sc.params(), precision=32)
+        S.apply(sc, g)
+        grids.append(g)
+    b = fdtd.Batch(grids, tile=(32, 8, 32), graph_steps=graph_steps)
+    b.run(warmup)
+    torch.cuda.synchronize()
+    b.timing(True)
+    b.run(steps)
+    ms, n = b.time()
+    cells = b.cells
+    bytes_step = b.algorithmic_bytes_per_step()
+    achieved = bytes_step * steps / (ms / 1e3) / 1e9
+    out = {"workload": f"{len(scs)} independent electrode grids, 32-96^3 (x grown to fit the electrode), "
+                       f"dx 0.25 m, 8-cell CPML, {steps} steps, one launch per step, HIP graph of "
+                       f"{graph_steps} steps",
+           "cells": cells, "value": round(cells * steps / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
+           "cases_per_s": round(len(scs) / (ms / 1e3), 2), "ms_per_step": round(ms / steps, 5),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_step": bytes_step}}
+    del b, grids
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--variant", default="auto", choices=["auto", "split", "fused"])
+    ap.add_argument("--variant", default="auto", choices=["auto", "split", "fused", "tb2"])
+    ap.add_argument("--tile-y", type=int, default=0)
+    ap.add_argument("--tile-z", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-grid sweep measurement")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU "
@@ -59,11 +96,11 @@ def main():
     from paper_2207_06908_amd import fdtd
     from paper_2207_06908_amd import scenarios as S
 
-    variant = {"auto": 0, "split": 1, "fused": 2}[a.variant]
+    variant = {"auto": 0, "split": 1, "fused": 2, "tb2": 3}[a.variant]
     sc = S.config2(n_steps=a.warmup + a.steps)
     g = fdtd.Grid.from_params(sc.params(), precision=32)
     S.apply(sc, g)
-    g.set_kernel(variant)
+    g.set_kernel(variant, a.tile_y, a.tile_z)
     g.bind()
     g.step(a.warmup)
     torch.cuda.synchronize()
@@ -97,7 +134,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "512x512x384 Yee FDTD, dx 0.5 m, 10-cell CPML, two-layer soil, "
                                "30 m thin wire, 10 kA 1/50 us source, 14 probes",
-                   "cells": cells, "kernel_variant": a.variant,
+                   "cells": cells, "kernel_variant": a.variant, "tile_y": a.tile_y, "tile_z": a.tile_z,
                    "coefficient_classes": g.num_classes},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
@@ -107,6 +144,8 @@ def main():
     }
     del g
     torch.cuda.empty_cache()
+    if not a.no_batch:
+        out["batched"] = bench_batch()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -57,8 +57,10 @@ enum { FDTD_EX = 0, FDTD_EY, FDTD_EZ, FDTD_HX, FDTD_HY, FDTD_HZ };
 enum { FDTD_PR_E = 0, FDTD_PR_VLINE = 1, FDTD_PR_ILOOP = 2 };
 enum { FDTD_LOSS_SEMI = 0, FDTD_LOSS_EXPLICIT = 1 };
 enum { FDTD_SRC_CURRENT = 0 };
-/* Kernel variants for fdtd_set_kernel. */
-enum { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_SPLIT = 1, FDTD_KERNEL_FUSED = 2 };
+/* Kernel variants for fdtd_set_kernel: two passes per step (H, then E), one
+ * fused pass per step, or one temporally blocked pass per two steps (an odd
+ * remaining step takes one fused pass). */
+enum { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_SPLIT = 1, FDTD_KERNEL_FUSED = 2, FDTD_KERNEL_TB2 = 3 };
 
 typedef struct fdtd_ctx fdtd_ctx;
 typedef struct { double eps_r, sigma, mu_r; } fdtd_material;
@@ -173,6 +175,41 @@ int fdtd_kernel_time(fdtd_ctx* c, double* total_ms, long long* n_steps);
 
 const char* fdtd_last_error(const fdtd_ctx* c);
 void fdtd_destroy(fdtd_ctx* c);
+
+/* ---------------------------------------------------------------------------
+ * Batched engine: many independent grids (e.g. a parameter sweep of small,
+ * uneven electrode grids) stepped together, one kernel launch per step over
+ * a tile list that spans every grid, optionally replayed from a captured
+ * HIP graph.  Each grid's results are bit-identical to running it alone.
+ * ------------------------------------------------------------------------- */
+typedef struct fdtd_batch fdtd_batch;
+
+/* Pack n fully set-up contexts (finalized here if needed, not yet bound to a
+ * workspace; same precision, all with or all without CPML, all with 1-byte
+ * or all with 2-byte class ids).  The batch borrows the contexts: destroy
+ * the batch before them.  After binding, fdtd_probe / fdtd_get_field on a
+ * member context read its part of the batch workspace.  Errors: EINVAL,
+ * ESTATE (a context already bound), and fdtd_finalize's errors. */
+int fdtd_batch_create(fdtd_ctx* const* grids, int n, void* hip_stream, fdtd_batch** out);
+size_t fdtd_batch_workspace_bytes(const fdtd_batch* b);
+/* Caller-owned device memory, 256-byte aligned.  Errors: ENOMEM, ESTATE, EDEVICE. */
+int fdtd_batch_bind_workspace(fdtd_batch* b, void* dev_ptr, size_t bytes);
+/* Tile shape (tile_x, tile_y) in {(32, 8), (32, 16), (64, 8)}, z-chunk
+ * tile_z in [8, 4096]; graph_steps (even, 0 = off): steps captured in one
+ * HIP graph and replayed.  Default (32, 8, 32, 0).  Errors: EINVAL. */
+int fdtd_batch_set_kernel(fdtd_batch* b, int tile_x, int tile_y, int tile_z, int graph_steps);
+/* Advance every grid n_steps steps.  Errors: ESTATE, ERANGE (beyond the
+ * smallest max_steps), EDEVICE. */
+int fdtd_batch_run(fdtd_batch* b, int n_steps);
+int fdtd_batch_probe(fdtd_batch* b, int grid, int probe_id, double* out, int n_max, int* n_written);
+/* Wall time of fdtd_batch_run calls made while timing is enabled (HIP
+ * events on the stream); fdtd_batch_time returns and resets the totals. */
+int fdtd_batch_timing(fdtd_batch* b, int enable);
+int fdtd_batch_time(fdtd_batch* b, double* total_ms, long long* n_steps);
+long long fdtd_batch_cells(const fdtd_batch* b);
+double fdtd_batch_algorithmic_bytes_per_step(const fdtd_batch* b);
+const char* fdtd_batch_last_error(const fdtd_batch* b);
+void fdtd_batch_destroy(fdtd_batch* b);
 
 #ifdef __cplusplus
 }

@@ -6,9 +6,10 @@
 namespace mi355fdtd {
 
 // Coefficients of one class: the 9 numbers a node needs to update the six
-// components it owns (Ex..Hz at the node's Yee positions).
-//   E_a^{n+1} = ca_a E_a^n + cb_a (difference of H)        [cb = Cb / dx]
-//   H_a^{n+1/2} = H_a^{n-1/2} + db_a (difference of E)      [db = Db / dx]
+// components it owns (Ex..Hz at the node's Yee positions).  The K_CA* slots
+// hold ca - 1:
+//   E_a^{n+1} = E_a^n + ((ca_a - 1) E_a^n + cb_a (difference of H))  [cb = Cb / dx]
+//   H_a^{n+1/2} = H_a^{n-1/2} + db_a (difference of E)                [db = Db / dx]
 enum { K_CAX = 0, K_CBX, K_CAY, K_CBY, K_CAZ, K_CBZ, K_DBX, K_DBY, K_DBZ, K_NCOEF };
 
 // CPML profile table of one axis: 6 rows of 2*npml entries, indexed by the
@@ -62,12 +63,29 @@ namespace mi355fdtd {
 
 // Kernel launchers (fdtd_kernels.hip).  `view` points to a GridView<float>
 // (prec 32) or GridView<double> (prec 64) whose in/out pointers are already
-// resolved: the split variant updates in place (in == out), the fused variant
-// reads one set and writes the other.  `step` selects the source sample.
-// Returns 0 or a hipError_t value.
+// resolved: the split variant (1) updates in place (in == out), the fused
+// variant (2) reads one set and writes the other, the two-step variant (3)
+// advances two steps from the input set to the output set.  `step` selects
+// the (first) source sample.  Returns 0 or a hipError_t value.
 int launch_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, int tile_z,
                 void* stream);
 
 // Record the probes of step `step` from the view's output set.
 int launch_probes(int prec, const void* view, int step, void* stream);
+
+// After a two-step pass (variant 3) from view.fi to view.fo: record the
+// probes of steps `step` (recomputed from the input set) and `step` + 1.
+int launch_probes2(int prec, const void* view, int cls16, int step, void* stream);
+
+// Batched step over a tile list.  `views` is a device array of GridView (one
+// per grid, already resolved for this step's field-set parity), `tiles` a
+// device array of int4 (grid, i0, j0, k0 | kz << 16).  The step index is
+// *d_step + offset.  Tile shapes (tx, ty): (32, 8), (32, 16), (64, 8).
+int launch_batch_step(int prec, int cls16, int pml, const void* views, const void* tiles, int n_tiles, int tx,
+                      int ty, const int* d_step, int offset, void* stream);
+// Batched probes: `plist` is a device array of int2 (grid, probe id).
+int launch_batch_probes(int prec, const void* views, const void* plist, int n, const int* d_step, int offset,
+                        void* stream);
+// *d += v on the stream (advances the device step counter).
+int launch_add(int* d, int v, void* stream);
 }  // namespace mi355fdtd

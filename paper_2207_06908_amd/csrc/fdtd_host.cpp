@@ -4,6 +4,7 @@
 // device work is issued on the context's stream.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstring>
@@ -85,6 +86,7 @@ struct fdtd_ctx {
   bool timing = false;
   static constexpr int kRing = 64;
   hipEvent_t ev0[kRing] = {}, ev1[kRing] = {};
+  int ev_steps[kRing] = {};          // steps covered by each event pair
   int ev_next = 0, ev_pending = 0;
   double timed_ms = 0;
   long long timed_steps = 0;
@@ -164,7 +166,10 @@ int node_coefs(fdtd_ctx* c, uint64_t key, const NodeMod* mod, std::array<double,
       eps += c->mats[id].eps_r * kEps0;
       sig += c->mats[id].sigma;
     }
-    double ca = 0, cb = 0;
+    // The table stores ca - 1, not ca: in a conductor ca is close to 1 and an
+    // FP32 ca would keep only a few bits of 1 - ca (the loss per step); the
+    // kernels evaluate E + ((ca - 1) E + cb curl), the same update.
+    double cam1 = -1.0, cb = 0;  // perfect conductor: E stays 0
     const bool pec = wall || (mod && (mod->pec >> a) & 1);
     if (!pec) {
       eps *= 0.25;
@@ -172,15 +177,15 @@ int node_coefs(fdtd_ctx* c, uint64_t key, const NodeMod* mod, std::array<double,
       if (mod) { eps *= mod->em[a]; sig *= mod->em[a]; }
       if (c->P.loss_mode == FDTD_LOSS_EXPLICIT) {
         if (sig * dt / eps >= 2.0) return fail(c, FDTD_EUNSTABLE, "literal eq. 4 loss factor below -1");
-        ca = 1.0 - sig * dt / eps;
+        cam1 = -sig * dt / eps;             // ca = 1 - sigma dt / eps
         cb = dt / eps;
       } else {
         const double x = 0.5 * sig * dt / eps;
-        ca = (1.0 - x) / (1.0 + x);
+        cam1 = -2.0 * x / (1.0 + x);         // ca = (1 - x) / (1 + x)
         cb = (dt / eps) / (1.0 + x);
       }
     }
-    out[2 * a] = ca;
+    out[2 * a] = cam1;
     out[2 * a + 1] = cb / dx;
     // cells sharing H_a: index along a varies, others fixed at +0 (bit set)
     double inv = 0;
@@ -698,7 +703,7 @@ int fdtd_bind_workspace(fdtd_ctx* c, void* dev, size_t bytes) {
 }
 
 int fdtd_set_kernel(fdtd_ctx* c, int variant, int tile_y, int tile_z) {
-  if (!c || variant < FDTD_KERNEL_AUTO || variant > FDTD_KERNEL_FUSED || tile_z < 0 ||
+  if (!c || variant < FDTD_KERNEL_AUTO || variant > FDTD_KERNEL_TB2 || tile_z < 0 ||
       (tile_y != 0 && tile_y != 4 && tile_y != 8))
     return fail(c, FDTD_EINVAL, "bad kernel selection (tile_y in {0, 4, 8}, tile_z >= 0)");
   c->variant = variant;
@@ -711,9 +716,12 @@ int fdtd_step(fdtd_ctx* c, int n) {
   if (!c || n < 0) return fail(c, FDTD_EINVAL, "bad step count");
   if (!c->ws) return fail(c, FDTD_ESTATE, "no workspace bound");
   if (c->steps_done + n > c->P.max_steps) return fail(c, FDTD_ERANGE, "beyond max_steps");
-  const int variant = c->variant == FDTD_KERNEL_AUTO ? FDTD_KERNEL_FUSED : c->variant;
-  for (int t = 0; t < n; ++t) {
-    const int in = c->cur, out = variant == FDTD_KERNEL_FUSED ? 1 - c->cur : c->cur;
+  const int chosen = c->variant == FDTD_KERNEL_AUTO ? FDTD_KERNEL_FUSED : c->variant;
+  for (int t = 0; t < n;) {
+    // the two-step pass needs two steps; an odd remainder takes one fused step
+    const int variant = (chosen == FDTD_KERNEL_TB2 && n - t < 2) ? FDTD_KERNEL_FUSED : chosen;
+    const int adv = variant == FDTD_KERNEL_TB2 ? 2 : 1;
+    const int in = c->cur, out = variant == FDTD_KERNEL_SPLIT ? c->cur : 1 - c->cur;
     const void* view = c->P.precision == 64 ? (const void*)&c->v64[in][out] : (const void*)&c->v32[in][out];
     const void* pview = c->P.precision == 64 ? (const void*)&c->v64[out][out] : (const void*)&c->v32[out][out];
     int slot = -1;
@@ -725,7 +733,7 @@ int fdtd_step(fdtd_ctx* c, int n) {
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev0[slot], c->ev1[slot]);
         if (e != hipSuccess) return hip_fail(c, e, "kernel timing");
         c->timed_ms += ms;
-        ++c->timed_steps;
+        c->timed_steps += c->ev_steps[slot];
         --c->ev_pending;
       }
       hipError_t er = hipEventRecord(c->ev0[slot], c->stream);
@@ -734,16 +742,21 @@ int fdtd_step(fdtd_ctx* c, int n) {
     int e = launch_step(c->P.precision, view, c->cls16, variant, (int)c->steps_done, c->tile_y, c->tile_z,
                         (void*)c->stream);
     if (e) return fail(c, FDTD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString((hipError_t)e));
-    if (variant == FDTD_KERNEL_FUSED) c->cur ^= 1;
+    if (variant != FDTD_KERNEL_SPLIT) c->cur ^= 1;
     if (slot >= 0) {
       hipError_t er = hipEventRecord(c->ev1[slot], c->stream);
       if (er != hipSuccess) return hip_fail(c, er, "hipEventRecord");
+      c->ev_steps[slot] = adv;
       c->ev_next = (slot + 1) % fdtd_ctx::kRing;
       ++c->ev_pending;
     }
-    e = launch_probes(c->P.precision, pview, (int)c->steps_done, (void*)c->stream);
+    if (variant == FDTD_KERNEL_TB2)
+      e = launch_probes2(c->P.precision, view, c->cls16, (int)c->steps_done, (void*)c->stream);
+    else
+      e = launch_probes(c->P.precision, pview, (int)c->steps_done, (void*)c->stream);
     if (e) return fail(c, FDTD_EDEVICE, std::string("probe launch: ") + hipGetErrorString((hipError_t)e));
-    ++c->steps_done;
+    c->steps_done += adv;
+    t += adv;
   }
   return FDTD_OK;
 }
@@ -770,7 +783,7 @@ int fdtd_kernel_time(fdtd_ctx* c, double* total_ms, long long* n_steps) {
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev0[slot], c->ev1[slot]);
     if (e != hipSuccess) return hip_fail(c, e, "kernel timing");
     c->timed_ms += ms;
-    ++c->timed_steps;
+    c->timed_steps += c->ev_steps[slot];
     --c->ev_pending;
   }
   *total_ms = c->timed_ms;
@@ -858,6 +871,334 @@ double fdtd_algorithmic_bytes_per_step(const fdtd_ctx* c) {
 }
 
 const char* fdtd_last_error(const fdtd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched engine: many independent grids stepped together.
+// ===========================================================================
+
+struct fdtd_batch {
+  std::vector<fdtd_ctx*> grids;
+  hipStream_t stream = nullptr;
+  int prec = 32, cls16 = 0, pml = 0;
+  int tx = 32, ty = 8, kz = 32;
+  int max_steps = 0;
+  std::string err;
+  // layout
+  std::vector<size_t> off;            // sub-workspace of each grid
+  size_t off_views = 0, off_pviews = 0, off_tiles = 0, off_plist = 0, off_step = 0, ws_bytes = 0;
+  std::vector<int> tiles;             // int4 entries (grid, i0, j0, k0 | kz << 16)
+  std::vector<int> plist;             // int2 entries (grid, probe)
+  char* ws = nullptr;
+  int cur = 0;
+  long long steps_done = 0;
+  bool tiles_dirty = true;
+  // graph replay (captured on a private stream, launched on `stream`)
+  hipStream_t cap_stream = nullptr;
+  int graph_steps = 0;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_tiles = -1;
+  // timing
+  bool timing = false;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  double timed_ms = 0;
+  long long timed_steps = 0;
+};
+
+namespace {
+
+int bfail(fdtd_batch* b, int code, const std::string& m) {
+  if (b) b->err = m;
+  return code;
+}
+
+size_t view_bytes(int prec) { return prec == 64 ? sizeof(GridView<double>) : sizeof(GridView<float>); }
+
+// Tile list: every grid cut into tx x ty x kz tiles; larger grids first so
+// the long-running tiles start early (longest-processing-time order).
+void build_tiles(fdtd_batch* b) {
+  std::vector<int> order(b->grids.size());
+  for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) { return b->grids[a]->ncell > b->grids[c]->ncell; });
+  b->tiles.clear();
+  for (int g : order) {
+    const fdtd_ctx* c = b->grids[g];
+    for (int k0 = 0; k0 < c->N[2]; k0 += b->kz)
+      for (int j0 = 0; j0 < c->N[1]; j0 += b->ty)
+        for (int i0 = 0; i0 < c->N[0]; i0 += b->tx) {
+          b->tiles.push_back(g);
+          b->tiles.push_back(i0);
+          b->tiles.push_back(j0);
+          b->tiles.push_back(k0 | (b->kz << 16));
+        }
+  }
+}
+
+template <typename T>
+int batch_upload(fdtd_batch* b) {
+  const size_t nv = b->grids.size();
+  std::vector<GridView<T>> views(2 * nv), pviews(2 * nv);
+  for (size_t g = 0; g < nv; ++g) {
+    fdtd_ctx* c = b->grids[g];
+    for (int p = 0; p < 2; ++p) {
+      views[p * nv + g] = view_of<T>(c, p, 1 - p);       // step reading set p
+      pviews[p * nv + g] = view_of<T>(c, 1 - p, 1 - p);  // probes after it
+    }
+  }
+  hipError_t e = hipMemcpyAsync(b->ws + b->off_views, views.data(), views.size() * sizeof(GridView<T>),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->ws + b->off_pviews, pviews.data(), pviews.size() * sizeof(GridView<T>),
+                       hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess && !b->plist.empty())
+    e = hipMemcpyAsync(b->ws + b->off_plist, b->plist.data(), b->plist.size() * sizeof(int),
+                       hipMemcpyHostToDevice, b->stream);
+  const int zero = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(b->ws + b->off_step, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, std::string("batch upload: ") + hipGetErrorString(e));
+  return FDTD_OK;
+}
+
+int upload_tiles(fdtd_batch* b) {
+  build_tiles(b);
+  hipError_t e = hipMemcpyAsync(b->ws + b->off_tiles, b->tiles.data(), b->tiles.size() * sizeof(int),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, std::string("tile upload: ") + hipGetErrorString(e));
+  b->tiles_dirty = false;
+  return FDTD_OK;
+}
+
+size_t max_tiles(const fdtd_batch* b) {  // upper bound over the allowed tile shapes
+  size_t n = 0;
+  for (const fdtd_ctx* c : b->grids)
+    n += (size_t)((c->N[0] + 31) / 32) * ((c->N[1] + 7) / 8) * ((c->N[2] + 7) / 8);
+  return n;
+}
+
+// Launch one step (kernel + probes) on stream `st` with step offset `off`
+// relative to the device counter; parity p selects the view tables.
+int batch_launch_step(fdtd_batch* b, hipStream_t st, int p, int off) {
+  const size_t nv = b->grids.size();
+  const size_t vb = view_bytes(b->prec);
+  const int* d_step = (const int*)(b->ws + b->off_step);
+  int e = launch_batch_step(b->prec, b->cls16, b->pml, b->ws + b->off_views + p * nv * vb, b->ws + b->off_tiles,
+                            (int)(b->tiles.size() / 4), b->tx, b->ty, d_step, off, (void*)st);
+  if (e) return bfail(b, FDTD_EDEVICE, std::string("batch kernel: ") + hipGetErrorString((hipError_t)e));
+  e = launch_batch_probes(b->prec, b->ws + b->off_pviews + p * nv * vb, b->ws + b->off_plist,
+                          (int)(b->plist.size() / 2), d_step, off, (void*)st);
+  if (e) return bfail(b, FDTD_EDEVICE, std::string("batch probes: ") + hipGetErrorString((hipError_t)e));
+  return FDTD_OK;
+}
+
+void drop_graph(fdtd_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdtd_batch_create(fdtd_ctx* const* grids, int n, void* hip_stream, fdtd_batch** out) {
+  if (!grids || n < 1 || !out) return FDTD_EINVAL;
+  *out = nullptr;
+  fdtd_batch* b = new fdtd_batch;
+  b->stream = (hipStream_t)hip_stream;
+  b->max_steps = 1 << 30;
+  for (int g = 0; g < n; ++g) {
+    fdtd_ctx* c = grids[g];
+    if (!c) { delete b; return FDTD_EINVAL; }
+    int rc = freeze(c);
+    if (rc) { delete b; return rc; }
+    if (c->ws) { delete b; return FDTD_ESTATE; }  // already bound on its own
+    if (g == 0) {
+      b->prec = c->P.precision;
+      b->cls16 = c->cls16;
+      b->pml = c->P.npml > 0;
+    } else if (c->P.precision != b->prec || c->cls16 != b->cls16 || (c->P.npml > 0) != (b->pml != 0)) {
+      delete b;
+      return FDTD_EINVAL;  // one kernel instantiation serves the whole batch
+    }
+    b->max_steps = std::min(b->max_steps, c->P.max_steps);
+    b->grids.push_back(c);
+    for (size_t q = 0; q < c->probes.size(); ++q) {
+      b->plist.push_back(g);
+      b->plist.push_back((int)q);
+    }
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  for (fdtd_ctx* c : b->grids) b->off.push_back(take(c->ws_bytes));
+  b->off_views = take(2 * b->grids.size() * view_bytes(b->prec));
+  b->off_pviews = take(2 * b->grids.size() * view_bytes(b->prec));
+  b->off_tiles = take(max_tiles(b) * 4 * sizeof(int));
+  b->off_plist = take(b->plist.size() * sizeof(int) + 8);
+  b->off_step = take(sizeof(int));
+  b->ws_bytes = o;
+  *out = b;
+  return FDTD_OK;
+}
+
+size_t fdtd_batch_workspace_bytes(const fdtd_batch* b) { return b ? b->ws_bytes : 0; }
+
+int fdtd_batch_bind_workspace(fdtd_batch* b, void* dev, size_t bytes) {
+  if (!b) return FDTD_EINVAL;
+  if (b->ws) return bfail(b, FDTD_ESTATE, "batch workspace already bound");
+  if (!dev || bytes < b->ws_bytes) return bfail(b, FDTD_ENOMEM, "batch workspace too small");
+  if (((uintptr_t)dev & 255) != 0) return bfail(b, FDTD_ENOMEM, "batch workspace not 256-byte aligned");
+  b->ws = (char*)dev;
+  for (size_t g = 0; g < b->grids.size(); ++g) {
+    fdtd_ctx* c = b->grids[g];
+    c->stream = b->stream;
+    c->ws = b->ws + b->off[g];
+    int rc = b->prec == 64 ? upload<double>(c) : upload<float>(c);
+    if (rc) { b->ws = nullptr; return bfail(b, rc, "grid " + std::to_string(g) + ": " + c->err); }
+  }
+  int rc = b->prec == 64 ? batch_upload<double>(b) : batch_upload<float>(b);
+  if (rc) return rc;
+  return upload_tiles(b);
+}
+
+int fdtd_batch_set_kernel(fdtd_batch* b, int tile_x, int tile_y, int tile_z, int graph_steps) {
+  if (!b) return FDTD_EINVAL;
+  const bool ok = (tile_x == 32 && (tile_y == 8 || tile_y == 16)) || (tile_x == 64 && tile_y == 8);
+  if (!ok || tile_z < 8 || tile_z > 4096 || graph_steps < 0 || (graph_steps & 1))
+    return bfail(b, FDTD_EINVAL, "tiles (32, 8|16) or (64, 8), tile_z in [8, 4096], even graph_steps");
+  b->tx = tile_x;
+  b->ty = tile_y;
+  b->kz = tile_z;
+  b->graph_steps = graph_steps;
+  b->tiles_dirty = true;
+  drop_graph(b);
+  return FDTD_OK;
+}
+
+int fdtd_batch_run(fdtd_batch* b, int n) {
+  if (!b || n < 0) return FDTD_EINVAL;
+  if (!b->ws) return bfail(b, FDTD_ESTATE, "no batch workspace bound");
+  if (b->steps_done + n > b->max_steps) return bfail(b, FDTD_ERANGE, "beyond max_steps");
+  if (b->tiles_dirty) {
+    int rc = upload_tiles(b);
+    if (rc) return rc;
+  }
+  hipError_t e = hipSuccess;
+  if (b->timing) {
+    if (!b->t0) {
+      e = hipEventCreate(&b->t0);
+      if (e == hipSuccess) e = hipEventCreate(&b->t1);
+    }
+    if (e == hipSuccess) e = hipEventRecord(b->t0, b->stream);
+    if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, hipGetErrorString(e));
+  }
+  int left = n;
+  const int G = b->graph_steps;
+  while (left > 0) {
+    if (G > 0 && left >= G && b->cur == 0) {
+      if (!b->gexec) {  // capture G steps once: offsets 0..G-1, then advance the counter by G
+        if (!b->cap_stream) {  // the legacy default stream cannot be captured
+          e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+          if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, std::string("capture stream: ") + hipGetErrorString(e));
+        }
+        hipStream_t cs = b->cap_stream;
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+        int rc = FDTD_OK;
+        for (int t = 0; t < G && rc == FDTD_OK; ++t) rc = batch_launch_step(b, cs, t & 1, t);
+        if (rc == FDTD_OK && launch_add((int*)(b->ws + b->off_step), G, (void*)cs))
+          rc = bfail(b, FDTD_EDEVICE, "capture: counter");
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(cs, &gr);
+        if (rc) { if (gr) (void)hipGraphDestroy(gr); return rc; }
+        if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, std::string("end capture: ") + hipGetErrorString(e));
+        b->graph = gr;
+        e = hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) { drop_graph(b); return bfail(b, FDTD_EDEVICE, std::string("instantiate: ") + hipGetErrorString(e)); }
+      }
+      e = hipGraphLaunch(b->gexec, b->stream);
+      if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+      left -= G;
+      b->steps_done += G;
+      continue;
+    }
+    int rc = batch_launch_step(b, b->stream, b->cur, 0);
+    if (rc) return rc;
+    if (launch_add((int*)(b->ws + b->off_step), 1, (void*)b->stream)) return bfail(b, FDTD_EDEVICE, "counter");
+    b->cur ^= 1;
+    ++b->steps_done;
+    --left;
+  }
+  if (b->timing) {
+    float ms = 0;
+    e = hipEventRecord(b->t1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b->t1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->t0, b->t1);
+    if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, hipGetErrorString(e));
+    b->timed_ms += ms;
+    b->timed_steps += n;
+  }
+  for (fdtd_ctx* c : b->grids) {  // keep the member contexts consistent
+    c->cur = b->cur;
+    c->steps_done = b->steps_done;
+  }
+  return FDTD_OK;
+}
+
+int fdtd_batch_timing(fdtd_batch* b, int enable) {
+  if (!b) return FDTD_EINVAL;
+  b->timing = enable != 0;
+  return FDTD_OK;
+}
+
+int fdtd_batch_time(fdtd_batch* b, double* total_ms, long long* n_steps) {
+  if (!b || !total_ms || !n_steps) return FDTD_EINVAL;
+  *total_ms = b->timed_ms;
+  *n_steps = b->timed_steps;
+  b->timed_ms = 0;
+  b->timed_steps = 0;
+  return FDTD_OK;
+}
+
+int fdtd_batch_probe(fdtd_batch* b, int g, int probe_id, double* out, int n_max, int* n_written) {
+  if (!b || g < 0 || g >= (int)b->grids.size()) return FDTD_EINVAL;
+  return fdtd_probe(b->grids[g], probe_id, out, n_max, n_written);
+}
+
+long long fdtd_batch_cells(const fdtd_batch* b) {
+  if (!b) return -1;
+  long long n = 0;
+  for (const fdtd_ctx* c : b->grids) n += c->ncell;
+  return n;
+}
+
+double fdtd_batch_algorithmic_bytes_per_step(const fdtd_batch* b) {
+  if (!b) return 0.0;
+  double s = 0;
+  for (const fdtd_ctx* c : b->grids) s += fdtd_algorithmic_bytes_per_step(c);
+  return s;
+}
+
+const char* fdtd_batch_last_error(const fdtd_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+void fdtd_batch_destroy(fdtd_batch* b) {
+  if (!b) return;
+  drop_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->t0) (void)hipEventDestroy(b->t0);
+  if (b->t1) (void)hipEventDestroy(b->t1);
+  for (fdtd_ctx* c : b->grids) c->ws = nullptr;  // the workspace belonged to the batch
+  delete b;
+}
 
 void fdtd_destroy(fdtd_ctx* c) {
   if (!c) return;

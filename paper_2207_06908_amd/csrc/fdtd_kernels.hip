@@ -26,39 +26,63 @@ namespace mi355fdtd {
 // per-point updates shared by all variants
 // ---------------------------------------------------------------------------
 
-// H^{n+1/2} at node (x, y, k) from E^n at the node (ex, ey, ez), at x+1
-// (ey_i, ez_i), y+1 (ex_j, ez_j) and k+1 (ex_k, ey_k).  CPML state is read
-// from the input set and, if store_psi, written to the output set.
+// Slab-local CPML positions of node (x, y, k) along each axis (-1 outside).
+template <typename T>
+__device__ __forceinline__ void slabs(const GridView<T>& g, int x, int y, int k, int l[3]) {
+  l[0] = slab_pos(x, g.nx, g.npml);
+  l[1] = slab_pos(y, g.ny, g.npml);
+  l[2] = slab_pos(k, g.nz, g.npml);
+}
+
+// CPML state of one node: ps[axis][q], q = 0 for the component along
+// axis+1, q = 1 for axis+2; kind 0 = E-type, 1 = H-type.
+template <typename T>
+__device__ __forceinline__ void psi_load(const GridView<T>& g, int kind, const int l[3], int x, int y, int k,
+                                         T ps[3][2]) {
+  for (int u = 0; u < 3; ++u) {
+    ps[u][0] = ps[u][1] = T(0);
+    if (l[u] >= 0) {
+      const long long q = psi_index(u, l[u], x, y, k, g.nx, g.ny, g.npml);
+      ps[u][0] = g.pi[u][kind][0][q];
+      ps[u][1] = g.pi[u][kind][1][q];
+    }
+  }
+}
+template <typename T>
+__device__ __forceinline__ void psi_store(const GridView<T>& g, int kind, const int l[3], int x, int y, int k,
+                                          const T ps[3][2]) {
+  for (int u = 0; u < 3; ++u) {
+    if (l[u] >= 0) {
+      const long long q = psi_index(u, l[u], x, y, k, g.nx, g.ny, g.npml);
+      g.po[u][kind][0][q] = ps[u][0];
+      g.po[u][kind][1][q] = ps[u][1];
+    }
+  }
+}
+
+// H^{n+1/2} of one node from E^n at the node (ex, ey, ez), at x+1 (ey_i,
+// ez_i), y+1 (ex_j, ez_j) and k+1 (ex_k, ey_k); ps is the node's H-type CPML
+// state, advanced in place.
 template <typename T, bool PML>
-__device__ __forceinline__ void h_point(const GridView<T>& g, int x, int y, int k, const T* cf, T ex, T ey,
-                                        T ez, T ex_j, T ex_k, T ey_i, T ey_k, T ez_i, T ez_j, const T hold[3],
-                                        bool store_psi, T hnew[3]) {
+__device__ __forceinline__ void h_core(const GridView<T>& g, const int l[3], const T* cf, T ex, T ey, T ez,
+                                       T ex_j, T ex_k, T ey_i, T ey_k, T ez_i, T ez_j, const T hold[3],
+                                       T ps[3][2], T hnew[3]) {
   T a_hx = ey_k - ey, b_hx = ez_j - ez;  // Hx: dEy/dz - dEz/dy
   T a_hy = ez_i - ez, b_hy = ex_k - ex;  // Hy: dEz/dx - dEx/dz
   T a_hz = ex_j - ex, b_hz = ey_i - ey;  // Hz: dEx/dy - dEy/dx
   if (PML) {
-    const int np = g.npml, tn = 2 * np;
-    const int lx = slab_pos(x, g.nx, np), ly = slab_pos(y, g.ny, np), lz = slab_pos(k, g.nz, np);
-    if (lx >= 0) {
-      const long long q = psi_index(0, lx, x, y, k, g.nx, g.ny, np);
-      T s0 = g.pi[0][1][0][q], s1 = g.pi[0][1][1][q];  // Hy (dEz/dx), Hz (dEy/dx)
-      a_hy = pml_term(a_hy, s0, g.prof[0], lx, tn, P_BH);
-      b_hz = pml_term(b_hz, s1, g.prof[0], lx, tn, P_BH);
-      if (store_psi) { g.po[0][1][0][q] = s0; g.po[0][1][1][q] = s1; }
+    const int tn = 2 * g.npml;
+    if (l[0] >= 0) {  // Hy (dEz/dx), Hz (dEy/dx)
+      a_hy = pml_term(a_hy, ps[0][0], g.prof[0], l[0], tn, P_BH);
+      b_hz = pml_term(b_hz, ps[0][1], g.prof[0], l[0], tn, P_BH);
     }
-    if (ly >= 0) {
-      const long long q = psi_index(1, ly, x, y, k, g.nx, g.ny, np);
-      T s0 = g.pi[1][1][0][q], s1 = g.pi[1][1][1][q];  // Hz (dEx/dy), Hx (dEz/dy)
-      a_hz = pml_term(a_hz, s0, g.prof[1], ly, tn, P_BH);
-      b_hx = pml_term(b_hx, s1, g.prof[1], ly, tn, P_BH);
-      if (store_psi) { g.po[1][1][0][q] = s0; g.po[1][1][1][q] = s1; }
+    if (l[1] >= 0) {  // Hz (dEx/dy), Hx (dEz/dy)
+      a_hz = pml_term(a_hz, ps[1][0], g.prof[1], l[1], tn, P_BH);
+      b_hx = pml_term(b_hx, ps[1][1], g.prof[1], l[1], tn, P_BH);
     }
-    if (lz >= 0) {
-      const long long q = psi_index(2, lz, x, y, k, g.nx, g.ny, np);
-      T s0 = g.pi[2][1][0][q], s1 = g.pi[2][1][1][q];  // Hx (dEy/dz), Hy (dEx/dz)
-      a_hx = pml_term(a_hx, s0, g.prof[2], lz, tn, P_BH);
-      b_hy = pml_term(b_hy, s1, g.prof[2], lz, tn, P_BH);
-      if (store_psi) { g.po[2][1][0][q] = s0; g.po[2][1][1][q] = s1; }
+    if (l[2] >= 0) {  // Hx (dEy/dz), Hy (dEx/dz)
+      a_hx = pml_term(a_hx, ps[2][0], g.prof[2], l[2], tn, P_BH);
+      b_hy = pml_term(b_hy, ps[2][1], g.prof[2], l[2], tn, P_BH);
     }
   }
   hnew[0] = h_new(hold[0], cf[K_DBX], a_hx, b_hx);
@@ -66,41 +90,29 @@ __device__ __forceinline__ void h_point(const GridView<T>& g, int x, int y, int 
   hnew[2] = h_new(hold[2], cf[K_DBZ], a_hz, b_hz);
 }
 
-// E^{n+1} at node (x, y, k) from H^{n+1/2} at the node (hx, hy, hz), at x-1
-// (hy_i, hz_i), y-1 (hx_j, hz_j) and k-1 (hx_k, hy_k); then the sources.
+// E^{n+1} of node n from H^{n+1/2} at the node (hx, hy, hz), at x-1 (hy_i,
+// hz_i), y-1 (hx_j, hz_j) and k-1 (hx_k, hy_k), then the sources of `step`;
+// ps is the node's E-type CPML state, advanced in place.
 template <typename T, bool PML>
-__device__ __forceinline__ void e_point(const GridView<T>& g, int x, int y, int k, long long n, const T* cf,
-                                        T hx, T hy, T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j,
-                                        const T eold[3], int step, T enew[3]) {
+__device__ __forceinline__ void e_core(const GridView<T>& g, const int l[3], long long n, const T* cf, T hx, T hy,
+                                       T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j, const T eold[3],
+                                       int step, T ps[3][2], T enew[3]) {
   T a_ex = hz - hz_j, b_ex = hy - hy_k;  // Ex: dHz/dy - dHy/dz
   T a_ey = hx - hx_k, b_ey = hz - hz_i;  // Ey: dHx/dz - dHz/dx
   T a_ez = hy - hy_i, b_ez = hx - hx_j;  // Ez: dHy/dx - dHx/dy
   if (PML) {
-    const int np = g.npml, tn = 2 * np;
-    const int lx = slab_pos(x, g.nx, np), ly = slab_pos(y, g.ny, np), lz = slab_pos(k, g.nz, np);
-    if (lx >= 0) {
-      const long long q = psi_index(0, lx, x, y, k, g.nx, g.ny, np);
-      T s0 = g.pi[0][0][0][q], s1 = g.pi[0][0][1][q];  // Ey (dHz/dx), Ez (dHy/dx)
-      b_ey = pml_term(b_ey, s0, g.prof[0], lx, tn, P_BE);
-      a_ez = pml_term(a_ez, s1, g.prof[0], lx, tn, P_BE);
-      g.po[0][0][0][q] = s0;
-      g.po[0][0][1][q] = s1;
+    const int tn = 2 * g.npml;
+    if (l[0] >= 0) {  // Ey (dHz/dx), Ez (dHy/dx)
+      b_ey = pml_term(b_ey, ps[0][0], g.prof[0], l[0], tn, P_BE);
+      a_ez = pml_term(a_ez, ps[0][1], g.prof[0], l[0], tn, P_BE);
     }
-    if (ly >= 0) {
-      const long long q = psi_index(1, ly, x, y, k, g.nx, g.ny, np);
-      T s0 = g.pi[1][0][0][q], s1 = g.pi[1][0][1][q];  // Ez (dHx/dy), Ex (dHz/dy)
-      b_ez = pml_term(b_ez, s0, g.prof[1], ly, tn, P_BE);
-      a_ex = pml_term(a_ex, s1, g.prof[1], ly, tn, P_BE);
-      g.po[1][0][0][q] = s0;
-      g.po[1][0][1][q] = s1;
+    if (l[1] >= 0) {  // Ez (dHx/dy), Ex (dHz/dy)
+      b_ez = pml_term(b_ez, ps[1][0], g.prof[1], l[1], tn, P_BE);
+      a_ex = pml_term(a_ex, ps[1][1], g.prof[1], l[1], tn, P_BE);
     }
-    if (lz >= 0) {
-      const long long q = psi_index(2, lz, x, y, k, g.nx, g.ny, np);
-      T s0 = g.pi[2][0][0][q], s1 = g.pi[2][0][1][q];  // Ex (dHy/dz), Ey (dHx/dz)
-      b_ex = pml_term(b_ex, s0, g.prof[2], lz, tn, P_BE);
-      a_ey = pml_term(a_ey, s1, g.prof[2], lz, tn, P_BE);
-      g.po[2][0][0][q] = s0;
-      g.po[2][0][1][q] = s1;
+    if (l[2] >= 0) {  // Ex (dHy/dz), Ey (dHx/dz)
+      b_ex = pml_term(b_ex, ps[2][0], g.prof[2], l[2], tn, P_BE);
+      a_ey = pml_term(a_ey, ps[2][1], g.prof[2], l[2], tn, P_BE);
     }
   }
   enew[0] = e_new(eold[0], cf[K_CAX], cf[K_CBX], a_ex, b_ex);
@@ -115,6 +127,36 @@ __device__ __forceinline__ void e_point(const GridView<T>& g, int x, int y, int 
     enew[1] = comp == 1 ? enew[1] - v : enew[1];
     enew[2] = comp == 2 ? enew[2] - v : enew[2];
   }
+}
+
+// One-step wrappers: CPML state from the input set, written (optionally for
+// H) to the output set.
+template <typename T, bool PML>
+__device__ __forceinline__ void h_point(const GridView<T>& g, int x, int y, int k, const T* cf, T ex, T ey,
+                                        T ez, T ex_j, T ex_k, T ey_i, T ey_k, T ez_i, T ez_j, const T hold[3],
+                                        bool store_psi, T hnew[3]) {
+  int l[3] = {-1, -1, -1};
+  T ps[3][2];
+  if (PML) {
+    slabs(g, x, y, k, l);
+    psi_load(g, 1, l, x, y, k, ps);
+  }
+  h_core<T, PML>(g, l, cf, ex, ey, ez, ex_j, ex_k, ey_i, ey_k, ez_i, ez_j, hold, ps, hnew);
+  if (PML && store_psi) psi_store(g, 1, l, x, y, k, ps);
+}
+
+template <typename T, bool PML>
+__device__ __forceinline__ void e_point(const GridView<T>& g, int x, int y, int k, long long n, const T* cf,
+                                        T hx, T hy, T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j,
+                                        const T eold[3], int step, T enew[3]) {
+  int l[3] = {-1, -1, -1};
+  T ps[3][2];
+  if (PML) {
+    slabs(g, x, y, k, l);
+    psi_load(g, 0, l, x, y, k, ps);
+  }
+  e_core<T, PML>(g, l, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, ps, enew);
+  if (PML) psi_store(g, 0, l, x, y, k, ps);
 }
 
 // ---------------------------------------------------------------------------
@@ -201,21 +243,29 @@ __device__ __forceinline__ void load3h(const GridView<T>& g, bool ok, long long 
   v[2] = ok ? g.fi[5][n] : T(0);
 }
 
-template <typename T, typename CI, bool PML, int TY>
-__global__ __launch_bounds__(64 * TY) void k_fused(GridView<T> g, int step, int kz, int ntx, int nty) {
-  constexpr int NT = 64 * TY, EW = 66, EH = TY + 2, HW = 65, HH = TY + 1;
+template <typename T, int TX, int TY>
+struct FusedSmem {
+  static constexpr int EW = TX + 2, EH = TY + 2, HW = TX + 1, HH = TY + 1;
+  T se[2][3][EH][EW];
+  T sh[3][HH][HW];
+  T stab[256 * K_STRIDE];
+};
+
+// One tile [i0, i0+TX) x [j0, j0+TY) x [k0, k1) of one grid, one step.
+template <typename T, typename CI, bool PML, int TX, int TY>
+__device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX, TY>& sm, int i0, int j0,
+                                           int k0, int k1, int step) {
+  constexpr int NT = TX * TY, EW = TX + 2, EH = TY + 2, HW = TX + 1;
   constexpr int NHE = 2 * EW + 2 * TY;  // E halo points
   constexpr int NHH = HW + TY;          // H halo points
+  static_assert(NHE <= NT && NHH <= NT, "tile too small for its halo");
   constexpr bool LDS_TAB = sizeof(CI) == 1;
-  __shared__ T se[2][3][EH][EW];
-  __shared__ T sh[3][HH][HW];
-  __shared__ T stab[LDS_TAB ? 256 * K_STRIDE : 1];
+  auto& se = sm.se;
+  auto& sh = sm.sh;
+  T* stab = sm.stab;
 
-  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tile_x = tile % ntx, rest = tile / ntx;
-  const int i0 = tile_x * 64, j0 = (rest % nty) * TY, k0 = (rest / nty) * kz;
-  const int k1 = min(k0 + kz, g.nz);
+  if (k0 >= k1) return;  // uniform per block, before any barrier
+  const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const long long sxy = g.sxy;
   const CI* cls = (const CI*)g.cls;
@@ -361,6 +411,275 @@ __global__ __launch_bounds__(64 * TY) void k_fused(GridView<T> g, int step, int 
   }
 }
 
+template <typename T, typename CI, bool PML, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_fused(GridView<T> g, int step, int kz, int ntx, int nty) {
+  __shared__ FusedSmem<T, TX, TY> sm;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile_x = tile % ntx, rest = tile / ntx;
+  const int k0 = (rest / nty) * kz;
+  fused_tile<T, CI, PML, TX, TY>(g, sm, tile_x * TX, (rest % nty) * TY, k0, min(k0 + kz, g.nz), step);
+}
+
+// Batched: one block per entry of a tile list spanning many grids; each
+// grid's view is read from a device table (one table per field-set parity).
+// The step index is a device counter (plus a per-launch offset) so that a
+// captured graph of several steps can be replayed unchanged.
+template <typename T, typename CI, bool PML, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_fused_batch(const GridView<T>* __restrict__ views,
+                                                        const int4* __restrict__ tiles,
+                                                        const int* __restrict__ d_step, int offset) {
+  __shared__ FusedSmem<T, TX, TY> sm;
+  const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];  // (grid, i0, j0, k0 | kz << 16)
+  const GridView<T>& g = views[t.x];
+  const int k0 = t.w & 0xffff, kz = t.w >> 16;
+  fused_tile<T, CI, PML, TX, TY>(g, sm, t.y, t.z, k0, min(k0 + kz, g.nz), *d_step + offset);
+}
+
+// ---------------------------------------------------------------------------
+// temporally blocked variant: two steps per pass
+//
+// Block = TY + 4 waves; wave v, lane u own the point x = i0 - 2 + u,
+// y = j0 - 2 + v of a 64 x (TY + 4) region around the 60 x TY output tile
+// [i0, i0+60) x [j0, j0+TY).  Each point is updated by the same thread in
+// every stage it belongs to (the dependency cone shrinks by one node per
+// half step on the high or low side):
+//   A  H^{n+1/2} on u <= 62, v <= TY+2            (from E^n, H^{n-1/2})
+//   B  E^{n+1}   on 1 <= u <= 62, 1 <= v <= TY+2  (sources of step n)
+//   C  H^{n+3/2} on 1 <= u <= 61, 1 <= v <= TY+1
+//   D  E^{n+2}   on 2 <= u <= 61, 2 <= v <= TY+1  (the tile; sources n+1)
+// Marching up z, iteration k does A and B of plane k and C and D of plane
+// k-1; the chunk [k0, k1) starts its pipeline at k0-2.  Neighbours are read
+// from LDS planes; a point's own values of earlier planes stay in
+// registers, as does its CPML state between the two steps.  Only E^{n+2},
+// H^{n+3/2} and the CPML state after two steps reach memory (output set).
+// ---------------------------------------------------------------------------
+
+template <typename T, int TY>
+struct TB2Smem {
+  static constexpr int R = TY + 4;
+  T se0[3][R][64];      // E^n, plane k
+  T sh1[3][R][64];      // H^{n+1/2}, plane k
+  T se1[2][3][R][64];   // E^{n+1}, planes k and k-1
+  T sh2[3][R][64];      // H^{n+3/2}, plane k-1
+  T stab[256 * K_STRIDE];
+};
+
+template <typename T, typename CI, bool PML, int TY>
+__global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, int kz, int ntx, int nty) {
+  constexpr int TX = 60, NT = 64 * (TY + 4);
+  constexpr bool LDS_TAB = sizeof(CI) == 1;
+  __shared__ TB2Smem<T, TY> sm;
+  const int tid = threadIdx.x, u = tid & 63, v = tid >> 6;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile_x = tile % ntx, rest = tile / ntx;
+  const int i0 = tile_x * TX, j0 = (rest % nty) * TY, k0 = (rest / nty) * kz;
+  const int k1 = min(k0 + kz, g.nz);
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const long long sxy = g.sxy;
+  const CI* cls = (const CI*)g.cls;
+  if (LDS_TAB) {
+    for (int q = tid; q < g.ncls * K_STRIDE; q += NT) sm.stab[q] = g.ctab[q];
+  }
+  auto coef = [&](int c) -> const T* { return LDS_TAB ? sm.stab + c * K_STRIDE : g.ctab + c * K_STRIDE; };
+
+  const int x = i0 - 2 + u, y = j0 - 2 + v;
+  const bool dom = x >= 0 && x < nx && y >= 0 && y < ny;
+  const bool inA = dom && u <= TX + 2 && v <= TY + 2;
+  const bool inB = inA && u >= 1 && v >= 1;
+  const bool inC = inB && u <= TX + 1 && v <= TY + 1;
+  const bool inD = inC && u >= 2 && v >= 2;
+  const long long n0 = dom ? (long long)x + (long long)nx * y : 0;
+  const int lx = PML && dom ? slab_pos(x, nx, g.npml) : -1;
+  const int ly = PML && dom ? slab_pos(y, ny, g.npml) : -1;
+
+  auto ld_e = [&](bool ok, int k, T e[3]) {
+    const bool in = ok && k >= 0 && k < nz;
+    const long long n = n0 + sxy * (in ? k : 0);
+    e[0] = in ? g.fi[0][n] : T(0);
+    e[1] = in ? g.fi[1][n] : T(0);
+    e[2] = in ? g.fi[2][n] : T(0);
+  };
+  auto ld_h = [&](bool ok, int k, T h[3]) {
+    const bool in = ok && k >= 0 && k < nz;
+    const long long n = n0 + sxy * (in ? k : 0);
+    h[0] = in ? g.fi[3][n] : T(0);
+    h[1] = in ? g.fi[4][n] : T(0);
+    h[2] = in ? g.fi[5][n] : T(0);
+  };
+  auto ld_c = [&](bool ok, int k) -> int { return (ok && k >= 0 && k < nz) ? (int)cls[n0 + sxy * k] : 0; };
+
+  // pipeline registers of this thread's point
+  T e0c[3], e0n[3], h0c[3];
+  T h1p[3] = {T(0), T(0), T(0)};   // H^{n+1/2}, plane k-1
+  T e1p[3] = {T(0), T(0), T(0)};   // E^{n+1},   plane k-1
+  T h2p[2] = {T(0), T(0)};         // H^{n+3/2}, plane k-2 (x, y)
+  T psh[3][2], pse[3][2];          // CPML state after step n+1, plane k-1
+  for (int a = 0; a < 3; ++a) psh[a][0] = psh[a][1] = pse[a][0] = pse[a][1] = T(0);
+  const int kb = k0 - 2;
+  ld_e(dom, kb, e0c);
+  ld_e(dom, kb + 1, e0n);
+  ld_h(inA, kb, h0c);
+  int cc = ld_c(inA, kb), cp = 0;
+
+  for (int k = kb; k <= k1; ++k) {
+    // prefetch: E^n of plane k+2, H^{n-1/2} and classes of plane k+1
+    T e0f[3], h0f[3];
+    ld_e(dom, k + 2, e0f);
+    ld_h(inA, k + 1, h0f);
+    const int cf1 = ld_c(inA, k + 1);
+    const bool kin = k >= 0 && k < nz;
+    for (int c = 0; c < 3; ++c) sm.se0[c][v][u] = e0c[c];
+    __syncthreads();
+    // A: H^{n+1/2}, plane k
+    T h1c[3] = {T(0), T(0), T(0)};
+    T pshn[3][2];
+    if (inA && kin) {
+      int l[3] = {lx, ly, PML ? slab_pos(k, nz, g.npml) : -1};
+      if (PML) psi_load(g, 1, l, x, y, k, pshn);
+      h_core<T, PML>(g, l, coef(cc), e0c[0], e0c[1], e0c[2], sm.se0[0][v + 1][u], e0n[0], sm.se0[1][v][u + 1],
+                     e0n[1], sm.se0[2][v][u + 1], sm.se0[2][v + 1][u], h0c, pshn, h1c);
+    }
+    for (int c = 0; c < 3; ++c) sm.sh1[c][v][u] = h1c[c];
+    __syncthreads();
+    // B: E^{n+1}, plane k (needs H^{n+1/2} of plane k-1: valid from k0-1 on)
+    T e1c[3] = {T(0), T(0), T(0)};
+    T psen[3][2];
+    if (inB && kin && k >= k0 - 1) {
+      int l[3] = {lx, ly, PML ? slab_pos(k, nz, g.npml) : -1};
+      if (PML) psi_load(g, 0, l, x, y, k, psen);
+      e_core<T, PML>(g, l, n0 + sxy * k, coef(cc), h1c[0], h1c[1], h1c[2], sm.sh1[0][v - 1][u], h1p[0],
+                     sm.sh1[1][v][u - 1], h1p[1], sm.sh1[2][v][u - 1], sm.sh1[2][v - 1][u], e0c, step, psen, e1c);
+    }
+    const int s1 = (k + 2) & 1, s1m = s1 ^ 1;
+    for (int c = 0; c < 3; ++c) sm.se1[s1][c][v][u] = e1c[c];
+    __syncthreads();
+    // C: H^{n+3/2}, plane k-1
+    const int km = k - 1;
+    T h2c[3] = {T(0), T(0), T(0)};
+    if (inC && k >= k0 && km >= 0 && km < nz) {
+      int l[3] = {lx, ly, PML ? slab_pos(km, nz, g.npml) : -1};
+      h_core<T, PML>(g, l, coef(cp), e1p[0], e1p[1], e1p[2], sm.se1[s1m][0][v + 1][u], e1c[0],
+                     sm.se1[s1m][1][v][u + 1], e1c[1], sm.se1[s1m][2][v][u + 1], sm.se1[s1m][2][v + 1][u], h1p, psh,
+                     h2c);
+      if (inD && km >= k0) {
+        const long long n = n0 + sxy * km;
+        g.fo[3][n] = h2c[0];
+        g.fo[4][n] = h2c[1];
+        g.fo[5][n] = h2c[2];
+        if (PML) psi_store(g, 1, l, x, y, km, psh);
+      }
+    }
+    for (int c = 0; c < 3; ++c) sm.sh2[c][v][u] = h2c[c];
+    __syncthreads();
+    // D: E^{n+2}, plane k-1 (the output tile)
+    if (inD && k >= k0 + 1 && km < k1) {
+      int l[3] = {lx, ly, PML ? slab_pos(km, nz, g.npml) : -1};
+      const long long n = n0 + sxy * km;
+      T e2[3];
+      e_core<T, PML>(g, l, n, coef(cp), h2c[0], h2c[1], h2c[2], sm.sh2[0][v - 1][u], h2p[0], sm.sh2[1][v][u - 1],
+                     h2p[1], sm.sh2[2][v][u - 1], sm.sh2[2][v - 1][u], e1p, step + 1, pse, e2);
+      g.fo[0][n] = e2[0];
+      g.fo[1][n] = e2[1];
+      g.fo[2][n] = e2[2];
+      if (PML) psi_store(g, 0, l, x, y, km, pse);
+    }
+    // rotate the pipeline
+    h2p[0] = h2c[0];
+    h2p[1] = h2c[1];
+    for (int c = 0; c < 3; ++c) {
+      h1p[c] = h1c[c];
+      e1p[c] = e1c[c];
+      e0c[c] = e0n[c];
+      e0n[c] = e0f[c];
+      h0c[c] = h0f[c];
+    }
+    if (PML)
+      for (int a = 0; a < 3; ++a) {
+        psh[a][0] = pshn[a][0];
+        psh[a][1] = pshn[a][1];
+        pse[a][0] = psen[a][0];
+        pse[a][1] = psen[a][1];
+      }
+    cp = cc;
+    cc = cf1;
+  }
+}
+
+// Probes of a two-step pass: the intermediate step's values are recomputed
+// point by point from the input set (which the pass leaves untouched) with
+// the same per-point arithmetic; the second step's values are read from the
+// output set.
+template <typename T, typename CI, bool PML>
+__device__ __forceinline__ void h1_at(const GridView<T>& g, int x, int y, int k, T h[3]) {
+  h[0] = h[1] = h[2] = T(0);
+  if (x < 0 || y < 0 || k < 0 || x >= g.nx || y >= g.ny || k >= g.nz) return;
+  const long long n = x + (long long)g.nx * y + g.sxy * k;
+  const T* cf = g.ctab + (int)((const CI*)g.cls)[n] * K_STRIDE;
+  const T ex = g.fi[0][n], ey = g.fi[1][n], ez = g.fi[2][n];
+  const T ex_j = (y + 1 < g.ny) ? g.fi[0][n + g.nx] : T(0);
+  const T ex_k = (k + 1 < g.nz) ? g.fi[0][n + g.sxy] : T(0);
+  const T ey_i = (x + 1 < g.nx) ? g.fi[1][n + 1] : T(0);
+  const T ey_k = (k + 1 < g.nz) ? g.fi[1][n + g.sxy] : T(0);
+  const T ez_i = (x + 1 < g.nx) ? g.fi[2][n + 1] : T(0);
+  const T ez_j = (y + 1 < g.ny) ? g.fi[2][n + g.nx] : T(0);
+  const T hold[3] = {g.fi[3][n], g.fi[4][n], g.fi[5][n]};
+  int l[3] = {-1, -1, -1};
+  T ps[3][2];
+  if (PML) {
+    slabs(g, x, y, k, l);
+    psi_load(g, 1, l, x, y, k, ps);
+  }
+  h_core<T, PML>(g, l, cf, ex, ey, ez, ex_j, ex_k, ey_i, ey_k, ez_i, ez_j, hold, ps, h);
+}
+
+template <typename T, typename CI, bool PML>
+__device__ __forceinline__ void e1_at(const GridView<T>& g, int x, int y, int k, int step, T e[3]) {
+  const long long n = x + (long long)g.nx * y + g.sxy * k;
+  T h[3], hi[3], hj[3], hk[3];
+  h1_at<T, CI, PML>(g, x, y, k, h);
+  h1_at<T, CI, PML>(g, x - 1, y, k, hi);
+  h1_at<T, CI, PML>(g, x, y - 1, k, hj);
+  h1_at<T, CI, PML>(g, x, y, k - 1, hk);
+  const T* cf = g.ctab + (int)((const CI*)g.cls)[n] * K_STRIDE;
+  const T eold[3] = {g.fi[0][n], g.fi[1][n], g.fi[2][n]};
+  int l[3] = {-1, -1, -1};
+  T ps[3][2];
+  if (PML) {
+    slabs(g, x, y, k, l);
+    psi_load(g, 0, l, x, y, k, ps);
+  }
+  e_core<T, PML>(g, l, n, cf, h[0], h[1], h[2], hj[0], hk[0], hi[1], hk[1], hi[2], hj[2], eold, step, ps, e);
+}
+
+template <typename T, typename CI, bool PML>
+__global__ __launch_bounds__(256) void k_probes_tb2(GridView<T> g, int step) {
+  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (p >= g.n_probe) return;  // uniform per wave
+  double a1 = 0.0, a2 = 0.0;
+  for (int t = g.pr_off[p] + lane; t < g.pr_off[p + 1]; t += 64) {
+    const int c = g.term_comp[t];
+    const long long n = g.term_idx[t];
+    const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), k = (int)(n / g.sxy);
+    T v3[3];
+    if (c < 3) e1_at<T, CI, PML>(g, x, y, k, step, v3);
+    else h1_at<T, CI, PML>(g, x, y, k, v3);
+    const int cc = c < 3 ? c : c - 3;
+    const T v1 = cc == 0 ? v3[0] : cc == 1 ? v3[1] : v3[2];
+    const T* f = c == 0 ? g.fo[0] : c == 1 ? g.fo[1] : c == 2 ? g.fo[2] : c == 3 ? g.fo[3] : c == 4 ? g.fo[4] : g.fo[5];
+    a1 += g.term_w[t] * (double)v1;
+    a2 += g.term_w[t] * (double)f[n];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    a1 += __shfl_down(a1, o, 64);
+    a2 += __shfl_down(a2, o, 64);
+  }
+  if (lane == 0) {
+    g.pr_out[(long long)p * g.max_steps + step] = a1;
+    g.pr_out[(long long)p * g.max_steps + step + 1] = a2;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // probes: one wave per probe, FP64 sum in a fixed order (deterministic)
 // ---------------------------------------------------------------------------
@@ -380,6 +699,31 @@ __global__ __launch_bounds__(256) void k_probes(GridView<T> g, int step) {
   if (lane == 0) g.pr_out[(long long)p * g.max_steps + step] = acc;
 }
 
+// Batched probes: entry q of the list is (grid, probe); one wave each.
+template <typename T>
+__global__ __launch_bounds__(256) void k_probes_batch(const GridView<T>* __restrict__ views,
+                                                     const int2* __restrict__ plist, int n,
+                                                     const int* __restrict__ d_step, int offset) {
+  const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (q >= n) return;  // uniform per wave
+  const int2 e = plist[q];
+  const GridView<T>& g = views[e.x];
+  const int p = e.y, step = *d_step + offset;
+  double acc = 0.0;
+  for (int t = g.pr_off[p] + lane; t < g.pr_off[p + 1]; t += 64) {
+    const int c = g.term_comp[t];
+    const T* f = c == 0 ? g.fi[0] : c == 1 ? g.fi[1] : c == 2 ? g.fi[2] : c == 3 ? g.fi[3] : c == 4 ? g.fi[4] : g.fi[5];
+    acc += g.term_w[t] * (double)f[g.term_idx[t]];
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if (lane == 0) g.pr_out[(long long)p * g.max_steps + step] = acc;
+}
+
+__global__ void k_add(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p += v;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -397,12 +741,12 @@ hipError_t step_split(const GridView<T>& g, int step, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename T, typename CI, bool PML, int TY>
+template <typename T, typename CI, bool PML, int TX, int TY>
 hipError_t launch_fused(const GridView<T>& g, int step, int kz, hipStream_t st) {
-  const int ntx = (g.nx + 63) / 64, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + kz - 1) / kz;
+  const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + kz - 1) / kz;
   const long long nb = (long long)ntx * nty * ntz;
   if (nb > 0x7fffffff || (sizeof(CI) == 1 && g.ncls > 256)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_fused<T, CI, PML, TY>), dim3((unsigned)nb), dim3(64 * TY), 0, st, g, step, kz, ntx,
+  hipLaunchKernelGGL((k_fused<T, CI, PML, TX, TY>), dim3((unsigned)nb), dim3(TX * TY), 0, st, g, step, kz, ntx,
                      nty);
   return hipGetLastError();
 }
@@ -412,13 +756,35 @@ hipError_t step_fused(const GridView<T>& g, int step, int tile_y, int tile_z, hi
   const int kz = tile_z > 0 ? tile_z : 32;
   const bool pml = g.npml > 0;
   if (tile_y == 4)
-    return pml ? launch_fused<T, CI, true, 4>(g, step, kz, st) : launch_fused<T, CI, false, 4>(g, step, kz, st);
-  return pml ? launch_fused<T, CI, true, 8>(g, step, kz, st) : launch_fused<T, CI, false, 8>(g, step, kz, st);
+    return pml ? launch_fused<T, CI, true, 64, 4>(g, step, kz, st) : launch_fused<T, CI, false, 64, 4>(g, step, kz, st);
+  return pml ? launch_fused<T, CI, true, 64, 8>(g, step, kz, st) : launch_fused<T, CI, false, 64, 8>(g, step, kz, st);
+}
+
+template <typename T, typename CI, bool PML, int TY>
+hipError_t launch_tb2(const GridView<T>& g, int step, int kz, hipStream_t st) {
+  const int ntx = (g.nx + 59) / 60, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + kz - 1) / kz;
+  const long long nb = (long long)ntx * nty * ntz;
+  if (nb > 0x7fffffff || (sizeof(CI) == 1 && g.ncls > 256)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_tb2<T, CI, PML, TY>), dim3((unsigned)nb), dim3(64 * (TY + 4)), 0, st, g, step, kz, ntx,
+                     nty);
+  return hipGetLastError();
+}
+
+template <typename T, typename CI>
+hipError_t step_tb2(const GridView<T>& g, int step, int tile_y, int tile_z, hipStream_t st) {
+  const int kz = tile_z > 0 ? tile_z : 64;
+  const bool pml = g.npml > 0;
+  if (tile_y == 4)
+    return pml ? launch_tb2<T, CI, true, 4>(g, step, kz, st) : launch_tb2<T, CI, false, 4>(g, step, kz, st);
+  return pml ? launch_tb2<T, CI, true, 8>(g, step, kz, st) : launch_tb2<T, CI, false, 8>(g, step, kz, st);
 }
 
 template <typename T>
 hipError_t step_any(const GridView<T>& g, int cls16, int variant, int step, int tile_y, int tile_z,
                     hipStream_t st) {
+  if (variant == 3)
+    return cls16 ? step_tb2<T, uint16_t>(g, step, tile_y, tile_z, st)
+                 : step_tb2<T, uint8_t>(g, step, tile_y, tile_z, st);
   if (variant == 2)
     return cls16 ? step_fused<T, uint16_t>(g, step, tile_y, tile_z, st)
                  : step_fused<T, uint8_t>(g, step, tile_y, tile_z, st);
@@ -443,10 +809,85 @@ hipError_t probes_any(const GridView<T>& g, int step, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t probes2_any(const GridView<T>& g, int cls16, int step, hipStream_t st) {
+  if (g.n_probe <= 0) return hipSuccess;
+  const dim3 grd((g.n_probe + 3) / 4), blk(256);
+  const bool pml = g.npml > 0;
+  if (cls16) {
+    if (pml) hipLaunchKernelGGL((k_probes_tb2<T, uint16_t, true>), grd, blk, 0, st, g, step);
+    else hipLaunchKernelGGL((k_probes_tb2<T, uint16_t, false>), grd, blk, 0, st, g, step);
+  } else {
+    if (pml) hipLaunchKernelGGL((k_probes_tb2<T, uint8_t, true>), grd, blk, 0, st, g, step);
+    else hipLaunchKernelGGL((k_probes_tb2<T, uint8_t, false>), grd, blk, 0, st, g, step);
+  }
+  return hipGetLastError();
+}
+
+int launch_probes2(int prec, const void* view, int cls16, int step, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == 64) return (int)probes2_any<double>(*(const GridView<double>*)view, cls16, step, st);
+  return (int)probes2_any<float>(*(const GridView<float>*)view, cls16, step, st);
+}
+
 int launch_probes(int prec, const void* view, int step, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (prec == 64) return (int)probes_any<double>(*(const GridView<double>*)view, step, st);
   return (int)probes_any<float>(*(const GridView<float>*)view, step, st);
+}
+
+template <typename T, typename CI, bool PML>
+hipError_t batch_step_t(const void* views, const void* tiles, int n_tiles, int tx, int ty, const int* d_step,
+                        int offset, hipStream_t st) {
+  const GridView<T>* v = (const GridView<T>*)views;
+  const int4* t = (const int4*)tiles;
+  if (tx == 32 && ty == 8)
+    hipLaunchKernelGGL((k_fused_batch<T, CI, PML, 32, 8>), dim3(n_tiles), dim3(256), 0, st, v, t, d_step, offset);
+  else if (tx == 32 && ty == 16)
+    hipLaunchKernelGGL((k_fused_batch<T, CI, PML, 32, 16>), dim3(n_tiles), dim3(512), 0, st, v, t, d_step, offset);
+  else if (tx == 64 && ty == 8)
+    hipLaunchKernelGGL((k_fused_batch<T, CI, PML, 64, 8>), dim3(n_tiles), dim3(512), 0, st, v, t, d_step, offset);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+int launch_batch_step(int prec, int cls16, int pml, const void* views, const void* tiles, int n_tiles, int tx,
+                      int ty, const int* d_step, int offset, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (n_tiles <= 0) return 0;
+  hipError_t e;
+  if (prec == 64) {
+    if (cls16) e = pml ? batch_step_t<double, uint16_t, true>(views, tiles, n_tiles, tx, ty, d_step, offset, st)
+                       : batch_step_t<double, uint16_t, false>(views, tiles, n_tiles, tx, ty, d_step, offset, st);
+    else e = pml ? batch_step_t<double, uint8_t, true>(views, tiles, n_tiles, tx, ty, d_step, offset, st)
+                 : batch_step_t<double, uint8_t, false>(views, tiles, n_tiles, tx, ty, d_step, offset, st);
+  } else {
+    if (cls16) e = pml ? batch_step_t<float, uint16_t, true>(views, tiles, n_tiles, tx, ty, d_step, offset, st)
+                       : batch_step_t<float, uint16_t, false>(views, tiles, n_tiles, tx, ty, d_step, offset, st);
+    else e = pml ? batch_step_t<float, uint8_t, true>(views, tiles, n_tiles, tx, ty, d_step, offset, st)
+                 : batch_step_t<float, uint8_t, false>(views, tiles, n_tiles, tx, ty, d_step, offset, st);
+  }
+  return (int)e;
+}
+
+int launch_batch_probes(int prec, const void* views, const void* plist, int n, const int* d_step, int offset,
+                        void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (n <= 0) return 0;
+  const dim3 grd((n + 3) / 4), blk(256);
+  if (prec == 64)
+    hipLaunchKernelGGL((k_probes_batch<double>), grd, blk, 0, st, (const GridView<double>*)views,
+                       (const int2*)plist, n, d_step, offset);
+  else
+    hipLaunchKernelGGL((k_probes_batch<float>), grd, blk, 0, st, (const GridView<float>*)views,
+                       (const int2*)plist, n, d_step, offset);
+  return (int)hipGetLastError();
+}
+
+int launch_add(int* d, int v, void* stream) {
+  hipLaunchKernelGGL(k_add, dim3(1), dim3(64), 0, (hipStream_t)stream, d, v);
+  return (int)hipGetLastError();
 }
 
 }  // namespace mi355fdtd

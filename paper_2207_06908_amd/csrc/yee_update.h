@@ -51,13 +51,15 @@ __device__ __forceinline__ T h_new(T h, T db, T t_plus, T t_minus) {
   return fma(db, t_plus - t_minus, h);
 }
 
-// E update of one node from raw H differences.
-//   Ex = ca_x Ex + cb_x ((Hz - Hz[j-1]) - (Hy - Hy[k-1]))
-//   Ey = ca_y Ey + cb_y ((Hx - Hx[k-1]) - (Hz - Hz[i-1]))
-//   Ez = ca_z Ez + cb_z ((Hy - Hy[i-1]) - (Hx - Hx[j-1]))
+// E update of one node from raw H differences, with cam1 = ca - 1:
+//   Ex = Ex + ((ca_x - 1) Ex + cb_x ((Hz - Hz[j-1]) - (Hy - Hy[k-1])))
+//   Ey = Ey + ((ca_y - 1) Ey + cb_y ((Hx - Hx[k-1]) - (Hz - Hz[i-1])))
+//   Ez = Ez + ((ca_z - 1) Ez + cb_z ((Hy - Hy[i-1]) - (Hx - Hx[j-1])))
+// i.e. ca E + cb curl, written so that a loss factor close to 1 keeps its
+// full precision in FP32.
 template <typename T>
-__device__ __forceinline__ T e_new(T e, T ca, T cb, T t_plus, T t_minus) {
-  return fma(ca, e, cb * (t_plus - t_minus));
+__device__ __forceinline__ T e_new(T e, T cam1, T cb, T t_plus, T t_minus) {
+  return e + fma(cam1, e, cb * (t_plus - t_minus));
 }
 
 }  // namespace mi355fdtd

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmi355fdtd.so")
 
 FDTD_EX, FDTD_EY, FDTD_EZ, FDTD_HX, FDTD_HY, FDTD_HZ = range(6)
 PR_E, PR_VLINE, PR_ILOOP = 0, 1, 2
-KERNEL_AUTO, KERNEL_SPLIT, KERNEL_FUSED = 0, 1, 2
+KERNEL_AUTO, KERNEL_SPLIT, KERNEL_FUSED, KERNEL_TB2 = 0, 1, 2, 3
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ESTATE", -4: "EUNSTABLE", -5: "ENOMEM",
           -6: "EDEVICE", -7: "ENONFINITE", -8: "ECLASS"}
 
@@ -60,6 +60,18 @@ SIGNATURES = [
     ("fdtd_kernel_time", C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
     ("fdtd_last_error", C.c_char_p, [_vp]),
     ("fdtd_destroy", None, [_vp]),
+    ("fdtd_batch_create", C.c_int, [C.POINTER(_vp), C.c_int, _vp, C.POINTER(_vp)]),
+    ("fdtd_batch_workspace_bytes", C.c_size_t, [_vp]),
+    ("fdtd_batch_bind_workspace", C.c_int, [_vp, _vp, C.c_size_t]),
+    ("fdtd_batch_set_kernel", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int]),
+    ("fdtd_batch_run", C.c_int, [_vp, C.c_int]),
+    ("fdtd_batch_probe", C.c_int, [_vp, C.c_int, C.c_int, _vp, C.c_int, C.POINTER(C.c_int)]),
+    ("fdtd_batch_timing", C.c_int, [_vp, C.c_int]),
+    ("fdtd_batch_time", C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
+    ("fdtd_batch_cells", C.c_longlong, [_vp]),
+    ("fdtd_batch_algorithmic_bytes_per_step", C.c_double, [_vp]),
+    ("fdtd_batch_last_error", C.c_char_p, [_vp]),
+    ("fdtd_batch_destroy", None, [_vp]),
 ]
 
 _lib = None
@@ -227,3 +239,86 @@ def run_scenario(sc, apply_fn, precision=32, variant=KERNEL_AUTO, tile_y=0, tile
     g.set_kernel(variant, tile_y, tile_z)
     g.step(sc.n_steps)
     return {p[0]: g.probe(i) for p, i in zip(sc.probes, ids)}
+
+
+class Batch:
+    """Many independent grids stepped together (one launch per step over all
+    their tiles; optional HIP-graph replay).  Build each member with
+    :class:`Grid` (set-up only, no stepping), then pack them here."""
+
+    def __init__(self, grids, device="cuda:0", stream=None, tile=(32, 8, 32), graph_steps=0):
+        self.grids = list(grids)
+        self.device = device
+        arr = (C.c_void_p * len(self.grids))(*[g._h for g in self.grids])
+        h = C.c_void_p()
+        st = stream if stream is not None else _stream_handle(device)
+        rc = lib().fdtd_batch_create(arr, len(self.grids), st, C.byref(h))
+        if rc:
+            raise FdtdError(rc, "fdtd_batch_create rejected the grids")
+        self._h = h
+        self._ws = None
+        self.set_kernel(*tile, graph_steps)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().fdtd_batch_destroy(h)
+            self._h = None
+
+    def _chk(self, rc):
+        if rc:
+            raise FdtdError(rc, lib().fdtd_batch_last_error(self._h).decode())
+
+    def set_kernel(self, tile_x=32, tile_y=8, tile_z=32, graph_steps=0):
+        self._chk(lib().fdtd_batch_set_kernel(self._h, tile_x, tile_y, tile_z, graph_steps))
+
+    def bind(self):
+        if self._ws is not None:
+            return
+        import torch
+        n = lib().fdtd_batch_workspace_bytes(self._h)
+        self._ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        self._chk(lib().fdtd_batch_bind_workspace(self._h, C.c_void_p(self._ws.data_ptr()), n))
+        for g in self.grids:   # members read their fields/probes from the batch workspace
+            g._ws = self._ws
+
+    def run(self, n):
+        self.bind()
+        self._chk(lib().fdtd_batch_run(self._h, int(n)))
+
+    def probe(self, g, pid) -> np.ndarray:
+        out = np.zeros(self.grids[g].max_steps, np.float64)
+        nw = C.c_int(0)
+        self._chk(lib().fdtd_batch_probe(self._h, g, pid, out.ctypes.data, out.size, C.byref(nw)))
+        return out[:nw.value].copy()
+
+    def timing(self, enable=True):
+        self._chk(lib().fdtd_batch_timing(self._h, int(enable)))
+
+    def time(self):
+        ms, n = C.c_double(0), C.c_longlong(0)
+        self._chk(lib().fdtd_batch_time(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    @property
+    def cells(self) -> int:
+        return lib().fdtd_batch_cells(self._h)
+
+    def algorithmic_bytes_per_step(self) -> float:
+        return lib().fdtd_batch_algorithmic_bytes_per_step(self._h)
+
+
+def run_batch(scenarios, apply_fn, precision=32, tile=(32, 8, 32), graph_steps=0):
+    """Run scenarios (equal step counts) as one batch; returns a list of
+    {probe name: waveform} dicts."""
+    grids, ids = [], []
+    for sc in scenarios:
+        g = Grid.from_params(sc.params(), precision=precision)
+        ids.append(apply_fn(sc, g))
+        grids.append(g)
+    b = Batch(grids, tile=tile, graph_steps=graph_steps)
+    b.run(scenarios[0].n_steps)
+    out = [{p[0]: b.probe(gi, i) for p, i in zip(sc.probes, gid)}
+           for gi, (sc, gid) in enumerate(zip(scenarios, ids))]
+    del b
+    return out
