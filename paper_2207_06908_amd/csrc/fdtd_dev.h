@@ -33,10 +33,14 @@ struct GridView {
   int pad0;
   const T* fi[6];                // fields read  (E^n, H^{n-1/2}), components Ex..Hz
   T* fo[6];                      // fields written (E^{n+1}, H^{n+1/2})
-  // CPML state [axis][kind 0 = E-type, 1 = H-type][component 0 / 1]; component
-  // 0 is the one along axis+1, component 1 along axis+2.
-  const T* pi[3][2][2];
-  T* po[3][2][2];
+  // CPML state of axis u: 4 arrays of pel[u] values each, starting at
+  // pib[u] (input set) / pob[u] (output set), ordered [kind][component] with
+  // kind 0 = E-type, 1 = H-type and component 0 the one along axis+1,
+  // component 1 along axis+2.
+  const T* pib[3];
+  T* pob[3];
+  unsigned pel[3];
+  int pad2;
   const void* cls;               // class id per node (uint8 or uint16)
   const T* ctab;                 // [ncls][K_STRIDE]
   const T* prof[3];              // per axis [P_NROW][2*npml]

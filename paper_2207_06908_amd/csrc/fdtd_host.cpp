@@ -461,7 +461,9 @@ void layout(fdtd_ctx* c) {
   c->off_term_idx = take(c->term_idx.size() * sizeof(long long));
   c->off_term_w = take(c->term_w.size() * sizeof(double));
   c->off_out = take(c->probes.size() * (size_t)c->P.max_steps * sizeof(double));
-  c->ws_bytes = o;
+  bool psi_fits = true;
+  for (int u = 0; u < 3; ++u) psi_fits = psi_fits && 4 * c->psi_elems[u] * ts < (size_t(1) << 32);
+  c->ws_bytes = psi_fits ? o : 0;
 }
 
 template <typename T>
@@ -484,13 +486,11 @@ void fill_view(fdtd_ctx* c, GridView<T>& g, int in, int out) {
     g.fi[q] = (const T*)(w + c->off_f) + (size_t)(in * 6 + q) * N;
     g.fo[q] = (T*)(w + c->off_f) + (size_t)(out * 6 + q) * N;
   }
-  for (int u = 0; u < 3; ++u)
-    for (int kind = 0; kind < 2; ++kind)
-      for (int q = 0; q < 2; ++q) {
-        const size_t o = (size_t)(kind * 2 + q) * c->psi_elems[u];
-        g.pi[u][kind][q] = np ? (const T*)(w + c->off_psi[in][u]) + o : nullptr;
-        g.po[u][kind][q] = np ? (T*)(w + c->off_psi[out][u]) + o : nullptr;
-      }
+  for (int u = 0; u < 3; ++u) {
+    g.pib[u] = np ? (const T*)(w + c->off_psi[in][u]) : nullptr;
+    g.pob[u] = np ? (T*)(w + c->off_psi[out][u]) : nullptr;
+    g.pel[u] = (unsigned)c->psi_elems[u];
+  }
   g.cls = w + c->off_cls;
   g.ctab = (const T*)(w + c->off_ctab);
   for (int u = 0; u < 3; ++u) g.prof[u] = (const T*)(w + c->off_prof) + (size_t)u * P_NROW * 2 * np;
@@ -570,6 +570,7 @@ int freeze(fdtd_ctx* c) {
   build_cpml(c);
   build_sources_probes(c);
   layout(c);
+  if (c->ws_bytes == 0) return fail(c, FDTD_EINVAL, "a CPML state array exceeds 4 GiB");
   c->frozen = true;
   return FDTD_OK;
 }
@@ -607,7 +608,9 @@ int fdtd_create(const fdtd_params* p, void* hip_stream, fdtd_ctx** out) {
   if (p->loss_mode != FDTD_LOSS_SEMI && p->loss_mode != FDTD_LOSS_EXPLICIT) return FDTD_EINVAL;
   if (p->precision != 32 && p->precision != 64) return FDTD_EINVAL;
   if (!(p->wire_r0_factor > 0 && p->wire_r0_factor < 1) || p->max_steps < 1) return FDTD_EINVAL;
-  if ((long long)p->nx * p->ny * p->nz > (1ll << 34)) return FDTD_EINVAL;
+  // kernels address each field and CPML array with 32-bit byte offsets
+  const long long ts = p->precision == 64 ? 8 : 4;
+  if ((long long)p->nx * p->ny * p->nz * ts >= (1ll << 32)) return FDTD_EINVAL;
   if (p->npml > 0 && (!(p->pml_m >= 0) || !(p->pml_kappa_max >= 1) || !(p->pml_alpha_max >= 0) ||
                       !(p->pml_sigma_factor >= 0)))
     return FDTD_EINVAL;

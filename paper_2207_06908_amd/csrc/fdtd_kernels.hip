@@ -42,9 +42,9 @@ __device__ __forceinline__ void psi_load(const GridView<T>& g, int kind, const i
   for (int u = 0; u < 3; ++u) {
     ps[u][0] = ps[u][1] = T(0);
     if (l[u] >= 0) {
-      const long long q = psi_index(u, l[u], x, y, k, g.nx, g.ny, g.npml);
-      ps[u][0] = g.pi[u][kind][0][q];
-      ps[u][1] = g.pi[u][kind][1][q];
+      const unsigned q = psi_index(u, l[u], x, y, k, g.nx, g.ny, g.npml) + (unsigned)(2 * kind) * g.pel[u];
+      ps[u][0] = ldg(g.pib[u], q);
+      ps[u][1] = ldg(g.pib[u], q + g.pel[u]);
     }
   }
 }
@@ -53,9 +53,9 @@ __device__ __forceinline__ void psi_store(const GridView<T>& g, int kind, const 
                                           const T ps[3][2]) {
   for (int u = 0; u < 3; ++u) {
     if (l[u] >= 0) {
-      const long long q = psi_index(u, l[u], x, y, k, g.nx, g.ny, g.npml);
-      g.po[u][kind][0][q] = ps[u][0];
-      g.po[u][kind][1][q] = ps[u][1];
+      const unsigned q = psi_index(u, l[u], x, y, k, g.nx, g.ny, g.npml) + (unsigned)(2 * kind) * g.pel[u];
+      stg(g.pob[u], q, ps[u][0]);
+      stg(g.pob[u], q + g.pel[u], ps[u][1]);
     }
   }
 }
@@ -94,7 +94,7 @@ __device__ __forceinline__ void h_core(const GridView<T>& g, const int l[3], con
 // hz_i), y-1 (hx_j, hz_j) and k-1 (hx_k, hy_k), then the sources of `step`;
 // ps is the node's E-type CPML state, advanced in place.
 template <typename T, bool PML>
-__device__ __forceinline__ void e_core(const GridView<T>& g, const int l[3], long long n, const T* cf, T hx, T hy,
+__device__ __forceinline__ void e_core(const GridView<T>& g, const int l[3], unsigned n, const T* cf, T hx, T hy,
                                        T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j, const T eold[3],
                                        int step, T ps[3][2], T enew[3]) {
   T a_ex = hz - hz_j, b_ex = hy - hy_k;  // Ex: dHz/dy - dHy/dz
@@ -120,7 +120,7 @@ __device__ __forceinline__ void e_core(const GridView<T>& g, const int l[3], lon
   enew[2] = e_new(eold[2], cf[K_CAZ], cf[K_CBZ], a_ez, b_ez);
   // ideal current sources: E -= Cb I / dx^2 (precomputed per step)
   for (int s = 0; s < g.n_src; ++s) {
-    if (g.src_idx[s] != n) continue;
+    if ((unsigned)g.src_idx[s] != n) continue;
     const T v = g.src_amp[(long long)s * g.max_steps + step];
     const int comp = g.src_comp[s];
     enew[0] = comp == 0 ? enew[0] - v : enew[0];
@@ -146,7 +146,7 @@ __device__ __forceinline__ void h_point(const GridView<T>& g, int x, int y, int 
 }
 
 template <typename T, bool PML>
-__device__ __forceinline__ void e_point(const GridView<T>& g, int x, int y, int k, long long n, const T* cf,
+__device__ __forceinline__ void e_point(const GridView<T>& g, int x, int y, int k, unsigned n, const T* cf,
                                         T hx, T hy, T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j,
                                         const T eold[3], int step, T enew[3]) {
   int l[3] = {-1, -1, -1};
@@ -169,21 +169,21 @@ __global__ __launch_bounds__(256) void k_h_split(GridView<T> g) {
   const int j = blockIdx.y * 4 + threadIdx.y;
   const int k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
-  const long long n = i + (long long)g.nx * j + g.sxy * k;
-  const T* cf = g.ctab + (int)((const CI*)g.cls)[n] * K_STRIDE;
-  const T ex = g.fi[0][n], ey = g.fi[1][n], ez = g.fi[2][n];
-  const T ex_j = (j + 1 < g.ny) ? g.fi[0][n + g.nx] : T(0);
-  const T ex_k = (k + 1 < g.nz) ? g.fi[0][n + g.sxy] : T(0);
-  const T ey_i = (i + 1 < g.nx) ? g.fi[1][n + 1] : T(0);
-  const T ey_k = (k + 1 < g.nz) ? g.fi[1][n + g.sxy] : T(0);
-  const T ez_i = (i + 1 < g.nx) ? g.fi[2][n + 1] : T(0);
-  const T ez_j = (j + 1 < g.ny) ? g.fi[2][n + g.nx] : T(0);
-  const T hold[3] = {g.fi[3][n], g.fi[4][n], g.fi[5][n]};
+  const unsigned n = (unsigned)i + (unsigned)g.nx * ((unsigned)j + (unsigned)g.ny * (unsigned)k);
+  const T* cf = g.ctab + (int)ldg((const CI*)g.cls, n) * K_STRIDE;
+  const T ex = ldg(g.fi[0], n), ey = ldg(g.fi[1], n), ez = ldg(g.fi[2], n);
+  const T ex_j = (j + 1 < g.ny) ? ldg(g.fi[0], n + (unsigned)g.nx) : T(0);
+  const T ex_k = (k + 1 < g.nz) ? ldg(g.fi[0], n + (unsigned)g.sxy) : T(0);
+  const T ey_i = (i + 1 < g.nx) ? ldg(g.fi[1], n + 1) : T(0);
+  const T ey_k = (k + 1 < g.nz) ? ldg(g.fi[1], n + (unsigned)g.sxy) : T(0);
+  const T ez_i = (i + 1 < g.nx) ? ldg(g.fi[2], n + 1) : T(0);
+  const T ez_j = (j + 1 < g.ny) ? ldg(g.fi[2], n + (unsigned)g.nx) : T(0);
+  const T hold[3] = {ldg(g.fi[3], n), ldg(g.fi[4], n), ldg(g.fi[5], n)};
   T h[3];
   h_point<T, PML>(g, i, j, k, cf, ex, ey, ez, ex_j, ex_k, ey_i, ey_k, ez_i, ez_j, hold, true, h);
-  g.fo[3][n] = h[0];
-  g.fo[4][n] = h[1];
-  g.fo[5][n] = h[2];
+  stg(g.fo[3], n, h[0]);
+  stg(g.fo[4], n, h[1]);
+  stg(g.fo[5], n, h[2]);
 }
 
 template <typename T, typename CI, bool PML>
@@ -192,21 +192,21 @@ __global__ __launch_bounds__(256) void k_e_split(GridView<T> g, int step) {
   const int j = blockIdx.y * 4 + threadIdx.y;
   const int k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
-  const long long n = i + (long long)g.nx * j + g.sxy * k;
-  const T* cf = g.ctab + (int)((const CI*)g.cls)[n] * K_STRIDE;
-  const T hx = g.fi[3][n], hy = g.fi[4][n], hz = g.fi[5][n];
-  const T hx_j = (j > 0) ? g.fi[3][n - g.nx] : T(0);
-  const T hx_k = (k > 0) ? g.fi[3][n - g.sxy] : T(0);
-  const T hy_i = (i > 0) ? g.fi[4][n - 1] : T(0);
-  const T hy_k = (k > 0) ? g.fi[4][n - g.sxy] : T(0);
-  const T hz_i = (i > 0) ? g.fi[5][n - 1] : T(0);
-  const T hz_j = (j > 0) ? g.fi[5][n - g.nx] : T(0);
-  const T eold[3] = {g.fi[0][n], g.fi[1][n], g.fi[2][n]};
+  const unsigned n = (unsigned)i + (unsigned)g.nx * ((unsigned)j + (unsigned)g.ny * (unsigned)k);
+  const T* cf = g.ctab + (int)ldg((const CI*)g.cls, n) * K_STRIDE;
+  const T hx = ldg(g.fi[3], n), hy = ldg(g.fi[4], n), hz = ldg(g.fi[5], n);
+  const T hx_j = (j > 0) ? ldg(g.fi[3], n - (unsigned)g.nx) : T(0);
+  const T hx_k = (k > 0) ? ldg(g.fi[3], n - (unsigned)g.sxy) : T(0);
+  const T hy_i = (i > 0) ? ldg(g.fi[4], n - 1) : T(0);
+  const T hy_k = (k > 0) ? ldg(g.fi[4], n - (unsigned)g.sxy) : T(0);
+  const T hz_i = (i > 0) ? ldg(g.fi[5], n - 1) : T(0);
+  const T hz_j = (j > 0) ? ldg(g.fi[5], n - (unsigned)g.nx) : T(0);
+  const T eold[3] = {ldg(g.fi[0], n), ldg(g.fi[1], n), ldg(g.fi[2], n)};
   T e[3];
   e_point<T, PML>(g, i, j, k, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, e);
-  g.fo[0][n] = e[0];
-  g.fo[1][n] = e[1];
-  g.fo[2][n] = e[2];
+  stg(g.fo[0], n, e[0]);
+  stg(g.fo[1], n, e[1]);
+  stg(g.fo[2], n, e[2]);
 }
 
 // ---------------------------------------------------------------------------
@@ -231,16 +231,16 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 }
 
 template <typename T>
-__device__ __forceinline__ void load3(const GridView<T>& g, bool ok, long long n, T v[3]) {
-  v[0] = ok ? g.fi[0][n] : T(0);
-  v[1] = ok ? g.fi[1][n] : T(0);
-  v[2] = ok ? g.fi[2][n] : T(0);
+__device__ __forceinline__ void load3(const GridView<T>& g, bool ok, unsigned n, T v[3]) {
+  v[0] = ok ? ldg(g.fi[0], n) : T(0);
+  v[1] = ok ? ldg(g.fi[1], n) : T(0);
+  v[2] = ok ? ldg(g.fi[2], n) : T(0);
 }
 template <typename T>
-__device__ __forceinline__ void load3h(const GridView<T>& g, bool ok, long long n, T v[3]) {
-  v[0] = ok ? g.fi[3][n] : T(0);
-  v[1] = ok ? g.fi[4][n] : T(0);
-  v[2] = ok ? g.fi[5][n] : T(0);
+__device__ __forceinline__ void load3h(const GridView<T>& g, bool ok, unsigned n, T v[3]) {
+  v[0] = ok ? ldg(g.fi[3], n) : T(0);
+  v[1] = ok ? ldg(g.fi[4], n) : T(0);
+  v[2] = ok ? ldg(g.fi[5], n) : T(0);
 }
 
 template <typename T, int TX, int TY>
@@ -267,7 +267,7 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
   if (k0 >= k1) return;  // uniform per block, before any barrier
   const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const long long sxy = g.sxy;
+  const unsigned sxy = (unsigned)g.sxy;
   const CI* cls = (const CI*)g.cls;
 
   if (LDS_TAB) {
@@ -278,7 +278,7 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
   // own column
   const int i = i0 + tx, j = j0 + ty;
   const bool own = i < nx && j < ny;
-  const long long n0 = own ? (long long)i + (long long)nx * j : 0;  // + sxy * k
+  const unsigned n0 = own ? (unsigned)i + (unsigned)nx * (unsigned)j : 0u;  // + sxy * k
   // E halo point (threads NT-NHE .. NT-1)
   int er = 0, ec = 0;
   bool eh = false;
@@ -294,13 +294,13 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
   }
   const int ex_x = i0 - 1 + ec, ex_y = j0 - 1 + er;
   const bool eh_in = eh && ex_x >= 0 && ex_x < nx && ex_y >= 0 && ex_y < ny;
-  const long long en0 = eh_in ? (long long)ex_x + (long long)nx * ex_y : 0;
+  const unsigned en0 = eh_in ? (unsigned)ex_x + (unsigned)nx * (unsigned)ex_y : 0u;
   // H halo point (threads 0 .. NHH-1): row j0-1 (c = 0..64) then column i0-1
   const bool hh = tid < NHH;
   const int hr = tid < HW ? 0 : tid - HW + 1, hc = tid < HW ? tid : 0;
   const int hx_x = i0 - 1 + hc, hx_y = j0 - 1 + hr;
   const bool hh_in = hh && hx_x >= 0 && hx_x < nx && hx_y >= 0 && hx_y < ny;
-  const long long hn0 = hh_in ? (long long)hx_x + (long long)nx * hx_y : 0;
+  const unsigned hn0 = hh_in ? (unsigned)hx_x + (unsigned)nx * (unsigned)hx_y : 0u;
 
   // ---- prologue: H^{n+1/2} of plane k0-1 at the own column (needed as H(k-1))
   T ecur[3], enext[3], xe_next[3], hold[3], xh_old[3], hm[2] = {T(0), T(0)};
@@ -308,12 +308,12 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
   {
     const int kb = k0 - 1;
     T eb[3], xeb[3], xe0[3], hb[3];
-    load3(g, own && kb >= 0, n0 + sxy * kb, eb);
-    load3(g, eh_in && kb >= 0, en0 + sxy * kb, xeb);
-    load3(g, own, n0 + sxy * k0, ecur);
-    load3(g, eh_in, en0 + sxy * k0, xe0);
-    load3h(g, own && kb >= 0, n0 + sxy * kb, hb);
-    const int cb = (own && kb >= 0) ? (int)cls[n0 + sxy * kb] : 0;
+    load3(g, own && kb >= 0, n0 + sxy * (unsigned)(kb), eb);
+    load3(g, eh_in && kb >= 0, en0 + sxy * (unsigned)(kb), xeb);
+    load3(g, own, n0 + sxy * (unsigned)(k0), ecur);
+    load3(g, eh_in, en0 + sxy * (unsigned)(k0), xe0);
+    load3h(g, own && kb >= 0, n0 + sxy * (unsigned)(kb), hb);
+    const int cb = (own && kb >= 0) ? (int)ldg(cls, n0 + sxy * (unsigned)kb) : 0;
     const int sb = (kb + 2) & 1, s0 = k0 & 1;
     for (int c = 0; c < 3; ++c) {
       se[sb][c][ty + 1][tx + 1] = eb[c];
@@ -333,13 +333,13 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
       hm[1] = h[1];
     }
     // plane k0 inputs and plane k0+1 E
-    load3h(g, own, n0 + sxy * k0, hold);
-    load3h(g, hh_in, hn0 + sxy * k0, xh_old);
-    cls_cur = own ? (int)cls[n0 + sxy * k0] : 0;
-    xcls_cur = hh_in ? (int)cls[hn0 + sxy * k0] : 0;
+    load3h(g, own, n0 + sxy * (unsigned)(k0), hold);
+    load3h(g, hh_in, hn0 + sxy * (unsigned)(k0), xh_old);
+    cls_cur = own ? (int)ldg(cls, n0 + sxy * (unsigned)k0) : 0;
+    xcls_cur = hh_in ? (int)ldg(cls, hn0 + sxy * (unsigned)k0) : 0;
     const bool nxt = k0 + 1 < nz;
-    load3(g, own && nxt, n0 + sxy * (k0 + 1), enext);
-    load3(g, eh_in && nxt, en0 + sxy * (k0 + 1), xe_next);
+    load3(g, own && nxt, n0 + sxy * (unsigned)(k0 + 1), enext);
+    load3(g, eh_in && nxt, en0 + sxy * (unsigned)(k0 + 1), xe_next);
     __syncthreads();  // plane kb's LDS slot is rewritten below
   }
 
@@ -353,12 +353,12 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
     // (b) prefetch plane k+1 inputs and E(k+2)
     T epf[3], xepf[3], hpf[3], xhpf[3];
     const bool n1 = k + 1 < k1, n2 = k + 2 < nz;
-    load3(g, own && n2, n0 + sxy * (k + 2), epf);
-    load3(g, eh_in && n2, en0 + sxy * (k + 2), xepf);
-    load3h(g, own && n1, n0 + sxy * (k + 1), hpf);
-    load3h(g, hh_in && n1, hn0 + sxy * (k + 1), xhpf);
-    const int cpf = (own && n1) ? (int)cls[n0 + sxy * (k + 1)] : 0;
-    const int xcpf = (hh_in && n1) ? (int)cls[hn0 + sxy * (k + 1)] : 0;
+    load3(g, own && n2, n0 + sxy * (unsigned)(k + 2), epf);
+    load3(g, eh_in && n2, en0 + sxy * (unsigned)(k + 2), xepf);
+    load3h(g, own && n1, n0 + sxy * (unsigned)(k + 1), hpf);
+    load3h(g, hh_in && n1, hn0 + sxy * (unsigned)(k + 1), xhpf);
+    const int cpf = (own && n1) ? (int)ldg(cls, n0 + sxy * (unsigned)(k + 1)) : 0;
+    const int xcpf = (hh_in && n1) ? (int)ldg(cls, hn0 + sxy * (unsigned)(k + 1)) : 0;
     __syncthreads();
     // (c) H(k): own column, then the low-side halo point
     T hown[3] = {T(0), T(0), T(0)};
@@ -366,10 +366,10 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
       h_point<T, PML>(g, i, j, k, coef(cls_cur), ecur[0], ecur[1], ecur[2], se[s][0][ty + 2][tx + 1], enext[0],
                       se[s][1][ty + 1][tx + 2], enext[1], se[s][2][ty + 1][tx + 2], se[s][2][ty + 2][tx + 1],
                       hold, true, hown);
-      const long long n = n0 + sxy * k;
-      g.fo[3][n] = hown[0];
-      g.fo[4][n] = hown[1];
-      g.fo[5][n] = hown[2];
+      const unsigned n = n0 + sxy * (unsigned)k;
+      stg(g.fo[3], n, hown[0]);
+      stg(g.fo[4], n, hown[1]);
+      stg(g.fo[5], n, hown[2]);
     }
     sh[0][ty + 1][tx + 1] = hown[0];
     sh[1][ty + 1][tx + 1] = hown[1];
@@ -388,13 +388,13 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
     __syncthreads();
     // (d) E(k) at the own column
     if (own) {
-      const long long n = n0 + sxy * k;
+      const unsigned n = n0 + sxy * (unsigned)k;
       T e[3];
       e_point<T, PML>(g, i, j, k, n, coef(cls_cur), hown[0], hown[1], hown[2], sh[0][ty][tx + 1], hm[0],
                       sh[1][ty + 1][tx], hm[1], sh[2][ty + 1][tx], sh[2][ty][tx + 1], ecur, step, e);
-      g.fo[0][n] = e[0];
-      g.fo[1][n] = e[1];
-      g.fo[2][n] = e[2];
+      stg(g.fo[0], n, e[0]);
+      stg(g.fo[1], n, e[1]);
+      stg(g.fo[2], n, e[2]);
     }
     // rotate the pipeline
     hm[0] = hown[0];
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, 
   const int i0 = tile_x * TX, j0 = (rest % nty) * TY, k0 = (rest / nty) * kz;
   const int k1 = min(k0 + kz, g.nz);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const long long sxy = g.sxy;
+  const unsigned sxy = (unsigned)g.sxy;
   const CI* cls = (const CI*)g.cls;
   if (LDS_TAB) {
     for (int q = tid; q < g.ncls * K_STRIDE; q += NT) sm.stab[q] = g.ctab[q];
@@ -488,25 +488,25 @@ __global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, 
   const bool inB = inA && u >= 1 && v >= 1;
   const bool inC = inB && u <= TX + 1 && v <= TY + 1;
   const bool inD = inC && u >= 2 && v >= 2;
-  const long long n0 = dom ? (long long)x + (long long)nx * y : 0;
+  const unsigned n0 = dom ? (unsigned)x + (unsigned)nx * (unsigned)y : 0u;
   const int lx = PML && dom ? slab_pos(x, nx, g.npml) : -1;
   const int ly = PML && dom ? slab_pos(y, ny, g.npml) : -1;
 
   auto ld_e = [&](bool ok, int k, T e[3]) {
     const bool in = ok && k >= 0 && k < nz;
-    const long long n = n0 + sxy * (in ? k : 0);
-    e[0] = in ? g.fi[0][n] : T(0);
-    e[1] = in ? g.fi[1][n] : T(0);
-    e[2] = in ? g.fi[2][n] : T(0);
+    const unsigned n = n0 + sxy * (unsigned)(in ? k : 0);
+    e[0] = in ? ldg(g.fi[0], n) : T(0);
+    e[1] = in ? ldg(g.fi[1], n) : T(0);
+    e[2] = in ? ldg(g.fi[2], n) : T(0);
   };
   auto ld_h = [&](bool ok, int k, T h[3]) {
     const bool in = ok && k >= 0 && k < nz;
-    const long long n = n0 + sxy * (in ? k : 0);
-    h[0] = in ? g.fi[3][n] : T(0);
-    h[1] = in ? g.fi[4][n] : T(0);
-    h[2] = in ? g.fi[5][n] : T(0);
+    const unsigned n = n0 + sxy * (unsigned)(in ? k : 0);
+    h[0] = in ? ldg(g.fi[3], n) : T(0);
+    h[1] = in ? ldg(g.fi[4], n) : T(0);
+    h[2] = in ? ldg(g.fi[5], n) : T(0);
   };
-  auto ld_c = [&](bool ok, int k) -> int { return (ok && k >= 0 && k < nz) ? (int)cls[n0 + sxy * k] : 0; };
+  auto ld_c = [&](bool ok, int k) -> int { return (ok && k >= 0 && k < nz) ? (int)ldg(cls, n0 + sxy * (unsigned)k) : 0; };
 
   // pipeline registers of this thread's point
   T e0c[3], e0n[3], h0c[3];
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, 
     if (inB && kin && k >= k0 - 1) {
       int l[3] = {lx, ly, PML ? slab_pos(k, nz, g.npml) : -1};
       if (PML) psi_load(g, 0, l, x, y, k, psen);
-      e_core<T, PML>(g, l, n0 + sxy * k, coef(cc), h1c[0], h1c[1], h1c[2], sm.sh1[0][v - 1][u], h1p[0],
+      e_core<T, PML>(g, l, n0 + sxy * (unsigned)k, coef(cc), h1c[0], h1c[1], h1c[2], sm.sh1[0][v - 1][u], h1p[0],
                      sm.sh1[1][v][u - 1], h1p[1], sm.sh1[2][v][u - 1], sm.sh1[2][v - 1][u], e0c, step, psen, e1c);
     }
     const int s1 = (k + 2) & 1, s1m = s1 ^ 1;
@@ -562,10 +562,10 @@ __global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, 
                      sm.se1[s1m][1][v][u + 1], e1c[1], sm.se1[s1m][2][v][u + 1], sm.se1[s1m][2][v + 1][u], h1p, psh,
                      h2c);
       if (inD && km >= k0) {
-        const long long n = n0 + sxy * km;
-        g.fo[3][n] = h2c[0];
-        g.fo[4][n] = h2c[1];
-        g.fo[5][n] = h2c[2];
+        const unsigned n = n0 + sxy * (unsigned)km;
+        stg(g.fo[3], n, h2c[0]);
+        stg(g.fo[4], n, h2c[1]);
+        stg(g.fo[5], n, h2c[2]);
         if (PML) psi_store(g, 1, l, x, y, km, psh);
       }
     }
@@ -574,13 +574,13 @@ __global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, 
     // D: E^{n+2}, plane k-1 (the output tile)
     if (inD && k >= k0 + 1 && km < k1) {
       int l[3] = {lx, ly, PML ? slab_pos(km, nz, g.npml) : -1};
-      const long long n = n0 + sxy * km;
+      const unsigned n = n0 + sxy * (unsigned)km;
       T e2[3];
       e_core<T, PML>(g, l, n, coef(cp), h2c[0], h2c[1], h2c[2], sm.sh2[0][v - 1][u], h2p[0], sm.sh2[1][v][u - 1],
                      h2p[1], sm.sh2[2][v][u - 1], sm.sh2[2][v - 1][u], e1p, step + 1, pse, e2);
-      g.fo[0][n] = e2[0];
-      g.fo[1][n] = e2[1];
-      g.fo[2][n] = e2[2];
+      stg(g.fo[0], n, e2[0]);
+      stg(g.fo[1], n, e2[1]);
+      stg(g.fo[2], n, e2[2]);
       if (PML) psi_store(g, 0, l, x, y, km, pse);
     }
     // rotate the pipeline
@@ -613,16 +613,16 @@ template <typename T, typename CI, bool PML>
 __device__ __forceinline__ void h1_at(const GridView<T>& g, int x, int y, int k, T h[3]) {
   h[0] = h[1] = h[2] = T(0);
   if (x < 0 || y < 0 || k < 0 || x >= g.nx || y >= g.ny || k >= g.nz) return;
-  const long long n = x + (long long)g.nx * y + g.sxy * k;
-  const T* cf = g.ctab + (int)((const CI*)g.cls)[n] * K_STRIDE;
-  const T ex = g.fi[0][n], ey = g.fi[1][n], ez = g.fi[2][n];
-  const T ex_j = (y + 1 < g.ny) ? g.fi[0][n + g.nx] : T(0);
-  const T ex_k = (k + 1 < g.nz) ? g.fi[0][n + g.sxy] : T(0);
-  const T ey_i = (x + 1 < g.nx) ? g.fi[1][n + 1] : T(0);
-  const T ey_k = (k + 1 < g.nz) ? g.fi[1][n + g.sxy] : T(0);
-  const T ez_i = (x + 1 < g.nx) ? g.fi[2][n + 1] : T(0);
-  const T ez_j = (y + 1 < g.ny) ? g.fi[2][n + g.nx] : T(0);
-  const T hold[3] = {g.fi[3][n], g.fi[4][n], g.fi[5][n]};
+  const unsigned n = (unsigned)x + (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)k);
+  const T* cf = g.ctab + (int)ldg((const CI*)g.cls, n) * K_STRIDE;
+  const T ex = ldg(g.fi[0], n), ey = ldg(g.fi[1], n), ez = ldg(g.fi[2], n);
+  const T ex_j = (y + 1 < g.ny) ? ldg(g.fi[0], n + (unsigned)g.nx) : T(0);
+  const T ex_k = (k + 1 < g.nz) ? ldg(g.fi[0], n + (unsigned)g.sxy) : T(0);
+  const T ey_i = (x + 1 < g.nx) ? ldg(g.fi[1], n + 1) : T(0);
+  const T ey_k = (k + 1 < g.nz) ? ldg(g.fi[1], n + (unsigned)g.sxy) : T(0);
+  const T ez_i = (x + 1 < g.nx) ? ldg(g.fi[2], n + 1) : T(0);
+  const T ez_j = (y + 1 < g.ny) ? ldg(g.fi[2], n + (unsigned)g.nx) : T(0);
+  const T hold[3] = {ldg(g.fi[3], n), ldg(g.fi[4], n), ldg(g.fi[5], n)};
   int l[3] = {-1, -1, -1};
   T ps[3][2];
   if (PML) {
@@ -634,14 +634,14 @@ __device__ __forceinline__ void h1_at(const GridView<T>& g, int x, int y, int k,
 
 template <typename T, typename CI, bool PML>
 __device__ __forceinline__ void e1_at(const GridView<T>& g, int x, int y, int k, int step, T e[3]) {
-  const long long n = x + (long long)g.nx * y + g.sxy * k;
+  const unsigned n = (unsigned)x + (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)k);
   T h[3], hi[3], hj[3], hk[3];
   h1_at<T, CI, PML>(g, x, y, k, h);
   h1_at<T, CI, PML>(g, x - 1, y, k, hi);
   h1_at<T, CI, PML>(g, x, y - 1, k, hj);
   h1_at<T, CI, PML>(g, x, y, k - 1, hk);
-  const T* cf = g.ctab + (int)((const CI*)g.cls)[n] * K_STRIDE;
-  const T eold[3] = {g.fi[0][n], g.fi[1][n], g.fi[2][n]};
+  const T* cf = g.ctab + (int)ldg((const CI*)g.cls, n) * K_STRIDE;
+  const T eold[3] = {ldg(g.fi[0], n), ldg(g.fi[1], n), ldg(g.fi[2], n)};
   int l[3] = {-1, -1, -1};
   T ps[3][2];
   if (PML) {
@@ -659,7 +659,7 @@ __global__ __launch_bounds__(256) void k_probes_tb2(GridView<T> g, int step) {
   double a1 = 0.0, a2 = 0.0;
   for (int t = g.pr_off[p] + lane; t < g.pr_off[p + 1]; t += 64) {
     const int c = g.term_comp[t];
-    const long long n = g.term_idx[t];
+    const unsigned n = (unsigned)g.term_idx[t];
     const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), k = (int)(n / g.sxy);
     T v3[3];
     if (c < 3) e1_at<T, CI, PML>(g, x, y, k, step, v3);
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(256) void k_probes_tb2(GridView<T> g, int step) {
     const T v1 = cc == 0 ? v3[0] : cc == 1 ? v3[1] : v3[2];
     const T* f = c == 0 ? g.fo[0] : c == 1 ? g.fo[1] : c == 2 ? g.fo[2] : c == 3 ? g.fo[3] : c == 4 ? g.fo[4] : g.fo[5];
     a1 += g.term_w[t] * (double)v1;
-    a2 += g.term_w[t] * (double)f[n];
+    a2 += g.term_w[t] * (double)ldg((const T*)f, n);
   }
   for (int o = 32; o > 0; o >>= 1) {
     a1 += __shfl_down(a1, o, 64);

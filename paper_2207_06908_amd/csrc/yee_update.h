@@ -34,12 +34,24 @@ __device__ __forceinline__ int slab_pos(int pos, int n, int np) {
   return -1;
 }
 
-// Index of node (i, j, k) inside the psi slab of axis u at local position l.
-__device__ __forceinline__ long long psi_index(int u, int l, int i, int j, int k, int nx, int ny, int np) {
-  const int t = 2 * np;
-  if (u == 0) return (long long)l + (long long)t * (j + (long long)ny * k);
-  if (u == 1) return (long long)i + (long long)nx * (l + (long long)t * k);
-  return (long long)i + (long long)nx * (j + (long long)ny * l);
+// Index of node (i, j, k) inside the psi slab of axis u at local position l
+// (every array the kernels touch is below 4 GiB; the host checks).
+__device__ __forceinline__ unsigned psi_index(int u, int l, int i, int j, int k, int nx, int ny, int np) {
+  const unsigned t = 2u * np;
+  if (u == 0) return (unsigned)l + t * ((unsigned)j + (unsigned)ny * (unsigned)k);
+  if (u == 1) return (unsigned)i + (unsigned)nx * ((unsigned)l + t * (unsigned)k);
+  return (unsigned)i + (unsigned)nx * ((unsigned)j + (unsigned)ny * (unsigned)l);
+}
+
+// Element access through a uniform base pointer and a 32-bit byte offset, so
+// that loads and stores use the scalar-base + vector-offset address form.
+template <typename T>
+__device__ __forceinline__ T ldg(const T* base, unsigned idx) {
+  return *(const T*)((const char*)base + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* base, unsigned idx, T v) {
+  *(T*)((char*)base + idx * (unsigned)sizeof(T)) = v;
 }
 
 // H update of one node from raw E differences.
