@@ -20,6 +20,26 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
+# HBM bytes per launch of the dominant kernel from the profiler's FETCH_SIZE and
+# WRITE_SIZE counters, scaled by what they read for a plain 1 GiB copy (x2.0
+# and x1.0), keyed by the hash of the kernel sources they were taken with:
+# once the kernels change the figure no longer applies and is reported null.
+KERNEL_SOURCES = ("paper_2207_06908_amd/csrc/fdtd_kernels.hip", "paper_2207_06908_amd/csrc/yee_update.h",
+                  "paper_2207_06908_amd/csrc/fdtd_dev.h")
+MEASURED_TRAFFIC = {
+    # (source hash, kernel variant, tile_y, tile_z): bytes per launch
+    ("f83429f117a4ca15", "fused", 8, 32): 6.545e9,
+}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
 
 def cpu_baseline(steps: int):
     """Time the FP64 oracle on a bounded sample of the same workload: the
@@ -75,6 +95,22 @@ def bench_batch(warmup: int = 100, graph_steps: int = 100):
     return out
 
 
+def calibrate_copy(mib: int = 1024, reps: int = 3):
+    """Plain device-to-device copies of known size, run under the profiler's
+    FETCH_SIZE / WRITE_SIZE counters to scale them to true HBM bytes."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    for _ in range(reps):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy_ and neg", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                      "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,14 +119,20 @@ def main():
     ap.add_argument("--variant", default="auto", choices=["auto", "split", "fused", "tb2"])
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--tile-z", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-grid sweep measurement")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run plain copies of MIB MiB (profiler counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU "
               "decomposition is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
+
+    if a.calibrate_copy:
+        calibrate_copy(a.calibrate_copy)
+        return
 
     import torch
     from paper_2207_06908_amd import fdtd
@@ -116,6 +158,10 @@ def main():
 
     cells = sc.cells
     value = cells * a.steps / (ms / 1e3) / 1e6
+    vname = "fused" if a.variant == "auto" else a.variant
+    ty = a.tile_y or 8
+    tz = a.tile_z or (64 if vname == "tb2" else 32)
+    traffic = MEASURED_TRAFFIC.get((kernel_source_hash(), vname, ty, tz))
     bytes_step = g.algorithmic_bytes_per_step()
     k_avg_s = kms / max(kn, 1) / 1e3
     achieved = bytes_step / k_avg_s / 1e9
@@ -137,8 +183,10 @@ def main():
                    "cells": cells, "kernel_variant": a.variant, "tile_y": a.tile_y, "tile_z": a.tile_z,
                    "coefficient_classes": g.num_classes},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "update kernels of one step (event-timed)",
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_unit": "bytes per launch",
+                     "kernel": {"fused": "k_fused (one launch per step)", "tb2": "k_tb2 (one launch per two steps)",
+                                "split": "k_h_split + k_e_split (two launches per step)"}[vname],
                      "algorithmic_bytes_per_step": bytes_step,
                      "kernel_ms_per_step": round(kms / max(kn, 1), 5)},
     }
