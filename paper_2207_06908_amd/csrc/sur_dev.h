@@ -1,0 +1,62 @@
+// sur_dev.h -- host-side view of the surrogate kernels (launchers only).
+#pragma once
+#include <stdint.h>
+
+namespace mi355sur {
+
+enum Epi {
+  EPI_GELU_TRAIN = 0,  // o16 = bf16(gelu(z)), oT = its transpose, o32 = gelu'(z)
+  EPI_GELU_INFER = 1,  // o16 = bf16(gelu(z))
+  EPI_LINEAR = 2,      // o32 = z (rows < m_valid)
+  EPI_BWD = 3,         // dz = acc * aux; o16 = bf16(dz), oT = its transpose, o32 = dz
+  EPI_DW = 4,          // o32 = acc for columns < n_valid
+};
+
+// C[M x N] = A[M x K] B[N x K]^T (both operands K-contiguous bfloat16),
+// FP32 accumulation on the matrix cores, then the epilogue.  M and N are
+// multiples of 16, K a multiple of 32, leading dimensions multiples of 8.
+struct GemmArgs {
+  const uint16_t* A;
+  const uint16_t* B;
+  int lda, ldb, M, N, K;
+  const float* bias;  // [N], z = acc + bias
+  uint16_t* o16;
+  int ld16;
+  uint16_t* oT;
+  int ldT;
+  float* o32;
+  int ld32;
+  const float* aux;
+  int ldaux;
+  int n_valid;
+  int m_valid;
+};
+
+struct AdamLayer {
+  int off, n, k, kp;  // flat offset of W (bias follows), shape, padded K
+  long long w16, wt;  // element offsets of the bfloat16 copies W [n x kp], W^T [kp x n]
+};
+
+struct AdamArgs {
+  float* p;
+  float* m;
+  float* v;
+  const float* g;
+  uint16_t* bf;  // base of the bfloat16 copies of this net
+  int P, nl, update;
+  float lr, b1, b2, eps, c1, c2;
+  AdamLayer L[8];
+};
+
+int launch_gemm(int epi, const GemmArgs& a, void* stream);
+int launch_gather(const float* x, const float* t, const int* rows, int m_valid, int M, int kin, int W,
+                  uint16_t* X16, uint16_t* XT, float* T, void* stream);
+int launch_loss(const float* y, const float* t, int M, int m_valid, int W, uint16_t* g16, uint16_t* gT,
+                float* dz, float* part, float* loss_dev, void* stream);
+int launch_colsum(const float* dz, int M, int N, float* out, void* stream);
+int launch_adam(const AdamArgs& a, void* stream);
+int launch_route(const float* ys, int nets, int ld_net, int m, int W, float* ymean, float* spread, void* stream);
+int launch_compact(const float* spread, int n, float threshold, int* ids, int* count, void* stream);
+int loss_parts(int M, int W);
+
+}  // namespace mi355sur

@@ -1,0 +1,328 @@
+// sur_kernels.hip -- kernels of the surrogate network on gfx950.
+//
+// Products are C = A B^T with both operands bfloat16 and K-contiguous, on
+// the CDNA4 matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  The
+// producers of every operand write it in the layout its consumer wants: the
+// forward epilogue writes each activation both row-major (input of the next
+// layer) and transposed (input of the weight-gradient product), the backward
+// epilogue does the same for the output-side gradient, and Adam keeps W and
+// W^T copies.  So every product reads 16-byte vectors along K and no kernel
+// transposes through LDS.
+//
+// Fragment layout of the 16x16x32 instruction (64 lanes): lane l supplies
+// A[row l%16][k = 8(l/16) .. 8(l/16)+7] and B^T[col l%16][same k], and holds
+// D[rows 4(l/16) .. 4(l/16)+3][col l%16].
+//
+// Reductions (loss, bias gradients, routing) use a fixed order, so every
+// result is reproducible run to run.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "sur_dev.h"
+
+namespace mi355sur {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+// FP32 -> bfloat16, round to nearest, ties to even (inputs are finite).
+__device__ __forceinline__ uint32_t f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ bf16x8 ld_frag(const uint16_t* p) {
+  const uint4 q = *(const uint4*)p;
+  return __builtin_bit_cast(bf16x8, q);
+}
+
+constexpr float kInvSqrt2 = 0.70710678118654752f;
+constexpr float kInvSqrt2Pi = 0.39894228040143268f;
+
+// One 64x64 output tile per block of four waves; each wave owns a 32x32
+// quarter (2 x 2 fragments).  Fragments beyond M or N are skipped (the
+// conditions are uniform across the wave).
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int mw = blockIdx.y * 64 + (w >> 1) * 32;
+  const int nw = blockIdx.x * 64 + (w & 1) * 32;
+  if (mw >= g.M || nw >= g.N) return;
+  const bool vm1 = mw + 16 < g.M, vn1 = nw + 16 < g.N;
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
+  const uint16_t* pa0 = g.A + (size_t)(mw + r16) * g.lda + kq;
+  const uint16_t* pa1 = pa0 + (size_t)16 * g.lda;
+  const uint16_t* pb0 = g.B + (size_t)(nw + r16) * g.ldb + kq;
+  const uint16_t* pb1 = pb0 + (size_t)16 * g.ldb;
+  f32x4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
+  const bf16x8 zero = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+  for (int k0 = 0; k0 < g.K; k0 += 32) {
+    const bf16x8 a0 = ld_frag(pa0 + k0);
+    const bf16x8 a1 = vm1 ? ld_frag(pa1 + k0) : zero;
+    const bf16x8 b0 = ld_frag(pb0 + k0);
+    const bf16x8 b1 = vn1 ? ld_frag(pb1 + k0) : zero;
+    c00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, c00, 0, 0, 0);
+    c01 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, c01, 0, 0, 0);
+    c10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, c10, 0, 0, 0);
+    c11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, c11, 0, 0, 0);
+  }
+  const f32x4 acc[2][2] = {{c00, c01}, {c10, c11}};
+  const int rq = (lane >> 4) * 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (i == 1 && !vm1) continue;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (j == 1 && !vn1) continue;
+      const int m0 = mw + 16 * i + rq, n = nw + 16 * j + r16;
+      uint32_t t16[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + r;
+        const float v = acc[i][j][r];
+        if (EPI == EPI_GELU_TRAIN || EPI == EPI_GELU_INFER) {
+          const float z = v + g.bias[n];
+          const float e = erff(z * kInvSqrt2);
+          const float a = 0.5f * z * (1.0f + e);
+          t16[r] = f2bf(a);
+          g.o16[(size_t)m * g.ld16 + n] = (uint16_t)t16[r];
+          if (EPI == EPI_GELU_TRAIN)
+            g.o32[(size_t)m * g.ld32 + n] = 0.5f * (1.0f + e) + z * expf(-0.5f * z * z) * kInvSqrt2Pi;
+        } else if (EPI == EPI_LINEAR) {
+          if (m < g.m_valid) g.o32[(size_t)m * g.ld32 + n] = v + g.bias[n];
+        } else if (EPI == EPI_BWD) {
+          const float dz = v * g.aux[(size_t)m * g.ldaux + n];
+          t16[r] = f2bf(dz);
+          g.o16[(size_t)m * g.ld16 + n] = (uint16_t)t16[r];
+          g.o32[(size_t)m * g.ld32 + n] = dz;
+        } else {  // EPI_DW
+          if (n < g.n_valid) g.o32[(size_t)m * g.ld32 + n] = v;
+        }
+      }
+      if (EPI == EPI_GELU_TRAIN || EPI == EPI_BWD)
+        *(uint2*)(g.oT + (size_t)n * g.ldT + m0) = make_uint2(t16[0] | (t16[1] << 16), t16[2] | (t16[3] << 16));
+    }
+  }
+}
+
+// Batch assembly: inputs to bfloat16, zero-padded to 32 columns and to M rows
+// (row-major and transposed), targets to a dense FP32 block.
+__global__ void k_gather(const float* __restrict__ x, const float* __restrict__ t, const int* __restrict__ rows,
+                         int m_valid, int M, int kin, int W, uint16_t* X16, uint16_t* XT, float* T) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < M * 32; e += stride) {
+    const int m = e >> 5, c = e & 31;
+    float v = 0.0f;
+    if (m < m_valid && c < kin) {
+      const long long r = rows ? rows[m] : m;
+      v = x[r * kin + c];
+    }
+    const uint16_t b = (uint16_t)f2bf(v);
+    X16[e] = b;
+    if (XT) XT[(size_t)c * M + m] = b;
+  }
+  if (!T) return;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < M * W; e += stride) {
+    const int m = e / W, c = e - m * W;
+    float v = 0.0f;
+    if (m < m_valid) {
+      const long long r = rows ? rows[m] : m;
+      v = t[r * W + c];
+    }
+    T[e] = v;
+  }
+}
+
+// Mean squared error and its gradient dY = 2 (y - t) / (m_valid W), written
+// as FP32, bfloat16 and transposed bfloat16.  Each block covers 64 columns x
+// 16 rows and leaves the sum of its squared errors in part[].
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const float* __restrict__ t, int M,
+                                              int m_valid, int W, float scale, uint16_t* g16, uint16_t* gT,
+                                              float* dz, float* part) {
+  __shared__ float red[256];
+  const int n = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int m0 = blockIdx.y * 16 + (threadIdx.x >> 6) * 4;
+  float s = 0.0f;
+  uint32_t q[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int m = m0 + r;
+    const size_t e = (size_t)m * W + n;
+    const float d = m < m_valid ? y[e] - t[e] : 0.0f;
+    s += d * d;
+    const float gv = scale * d;
+    dz[e] = gv;
+    q[r] = f2bf(gv);
+    g16[e] = (uint16_t)q[r];
+  }
+  *(uint2*)(gT + (size_t)n * M + m0) = make_uint2(q[0] | (q[1] << 16), q[2] | (q[3] << 16));
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_loss_final(const float* part, int n, float inv, float* loss) {
+  __shared__ float red[256];
+  float s = 0.0f;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = red[0] * inv;
+}
+
+// Column sums of an M x N FP32 block (bias gradients): 64 columns x 4 row
+// slices per block, slices added in a fixed order.
+__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ dz, int M, int N, float* out) {
+  __shared__ float red[4][64];
+  const int c = threadIdx.x & 63, s = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
+  const int rows = (M + 3) / 4, r0 = s * rows, r1 = min(M, r0 + rows);
+  float acc = 0.0f;
+  if (n < N)
+    for (int m = r0; m < r1; ++m) acc += dz[(size_t)m * N + n];
+  red[s][c] = acc;
+  __syncthreads();
+  if (s == 0 && n < N) out[n] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+// Adam on the flat FP32 parameters of one net (update != 0), then refresh of
+// the bfloat16 copies W [n x kp] and W^T [kp x n] used by the products.
+__global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.P) return;
+  float p = a.p[e];
+  if (a.update) {
+    const float g = a.g[e];
+    const float m = a.b1 * a.m[e] + (1.0f - a.b1) * g;
+    const float v = a.b2 * a.v[e] + (1.0f - a.b2) * (g * g);
+    a.m[e] = m;
+    a.v[e] = v;
+    p = p - a.lr * (m / a.c1) / (sqrtf(v / a.c2) + a.eps);
+    a.p[e] = p;
+  }
+  int l = 0;
+  while (l + 1 < a.nl && e >= a.L[l + 1].off) ++l;
+  const AdamLayer& L = a.L[l];
+  const int i = e - L.off;
+  if (i < L.n * L.k) {
+    const int row = i / L.k, col = i - row * L.k;
+    const uint16_t b = (uint16_t)f2bf(p);
+    a.bf[L.w16 + (long long)row * L.kp + col] = b;
+    a.bf[L.wt + (long long)col * L.n + row] = b;
+  }
+}
+
+// Ensemble reduction of one chunk: one wave per row.  ys holds the nets'
+// outputs (net stride ld_net floats, rows of W).  Writes the mean waveform and
+// the spread (max - min) / |mean| of the nets' peaks.
+__global__ __launch_bounds__(256) void k_route(const float* __restrict__ ys, int nets, long long ld_net, int m, int W,
+                                               float* ymean, float* spread) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= m) return;
+  float pmax = -INFINITY, pmin = INFINITY, psum = 0.0f;
+  for (int c0 = 0; c0 < W; c0 += 64) {
+    const int c = c0 + lane;
+    float s = 0.0f;
+    for (int q = 0; q < nets; ++q) s += c < W ? ys[q * ld_net + (long long)row * W + c] : 0.0f;
+    if (c < W) ymean[(long long)row * W + c] = s / (float)nets;
+  }
+  for (int q = 0; q < nets; ++q) {
+    float pk = -INFINITY;
+    for (int c = lane; c < W; c += 64) pk = fmaxf(pk, ys[q * ld_net + (long long)row * W + c]);
+    for (int o = 32; o > 0; o >>= 1) pk = fmaxf(pk, __shfl_xor(pk, o, 64));
+    pmax = fmaxf(pmax, pk);
+    pmin = fminf(pmin, pk);
+    psum += pk;
+  }
+  if (lane == 0) spread[row] = (pmax - pmin) / fabsf(psum / (float)nets);
+}
+
+// Ordered list of the rows whose spread is above the threshold or not finite:
+// one block, each thread scans a contiguous segment, block-wide exclusive scan.
+__global__ __launch_bounds__(1024) void k_compact(const float* __restrict__ spread, int n, float thr, int* ids,
+                                                  int* count) {
+  __shared__ int cnt[1024];
+  const int per = (n + 1023) / 1024;
+  const int b = threadIdx.x * per, e = min(n, b + per);
+  int c = 0;
+  for (int i = b; i < e; ++i) c += !(spread[i] <= thr);
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele scan
+    const int v = threadIdx.x >= o ? cnt[threadIdx.x - o] : 0;
+    __syncthreads();
+    cnt[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int pos = cnt[threadIdx.x] - c;
+  for (int i = b; i < e; ++i)
+    if (!(spread[i] <= thr)) ids[pos++] = i;
+  if (threadIdx.x == 1023) *count = cnt[1023];
+}
+
+static int last() { return (int)hipGetLastError(); }
+
+int launch_gemm(int epi, const GemmArgs& a, void* stream) {
+  const dim3 grid((a.N + 63) / 64, (a.M + 63) / 64), block(256);
+  hipStream_t s = (hipStream_t)stream;
+  switch (epi) {
+    case EPI_GELU_TRAIN: k_gemm<EPI_GELU_TRAIN><<<grid, block, 0, s>>>(a); break;
+    case EPI_GELU_INFER: k_gemm<EPI_GELU_INFER><<<grid, block, 0, s>>>(a); break;
+    case EPI_LINEAR: k_gemm<EPI_LINEAR><<<grid, block, 0, s>>>(a); break;
+    case EPI_BWD: k_gemm<EPI_BWD><<<grid, block, 0, s>>>(a); break;
+    default: k_gemm<EPI_DW><<<grid, block, 0, s>>>(a); break;
+  }
+  return last();
+}
+
+int launch_gather(const float* x, const float* t, const int* rows, int m_valid, int M, int kin, int W,
+                  uint16_t* X16, uint16_t* XT, float* T, void* stream) {
+  const long long work = (long long)M * (T ? (W > 32 ? W : 32) : 32);
+  const int blocks = (int)((work + 255) / 256 < 4096 ? (work + 255) / 256 : 4096);
+  k_gather<<<blocks, 256, 0, (hipStream_t)stream>>>(x, t, rows, m_valid, M, kin, W, X16, XT, T);
+  return last();
+}
+
+int loss_parts(int M, int W) { return (W / 64) * (M / 16); }
+
+int launch_loss(const float* y, const float* t, int M, int m_valid, int W, uint16_t* g16, uint16_t* gT, float* dz,
+                float* part, float* loss_dev, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const double denom = (double)m_valid * W;
+  k_loss<<<dim3(W / 64, M / 16), 256, 0, s>>>(y, t, M, m_valid, W, (float)(2.0 / denom), g16, gT, dz, part);
+  if (loss_dev) k_loss_final<<<1, 256, 0, s>>>(part, loss_parts(M, W), (float)(1.0 / denom), loss_dev);
+  return last();
+}
+
+int launch_colsum(const float* dz, int M, int N, float* out, void* stream) {
+  k_colsum<<<(N + 63) / 64, 256, 0, (hipStream_t)stream>>>(dz, M, N, out);
+  return last();
+}
+
+int launch_adam(const AdamArgs& a, void* stream) {
+  k_adam<<<(a.P + 255) / 256, 256, 0, (hipStream_t)stream>>>(a);
+  return last();
+}
+
+int launch_route(const float* ys, int nets, int ld_net, int m, int W, float* ymean, float* spread, void* stream) {
+  if (m <= 0) return 0;
+  k_route<<<(m + 3) / 4, 256, 0, (hipStream_t)stream>>>(ys, nets, ld_net, m, W, ymean, spread);
+  return last();
+}
+
+int launch_compact(const float* spread, int n, float threshold, int* ids, int* count, void* stream) {
+  k_compact<<<1, 1024, 0, (hipStream_t)stream>>>(spread, n, threshold, ids, count);
+  return last();
+}
+
+}  // namespace mi355sur

@@ -28,6 +28,40 @@ def test_library_exports_every_declared_symbol():
     assert sorted(n for n, _r, _a in fdtd.SIGNATURES) == names
 
 
+def test_library_exports_every_surrogate_symbol():
+    from paper_2207_06908_amd import sur
+    L = sur.lib()
+    names = _declared("sur.h")
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(n for n, _r, _a in sur.SIGNATURES) == names
+
+
+def test_surrogate_create_validation():
+    import ctypes as C
+    from paper_2207_06908_amd import sur
+    L = sur.lib()
+
+    def create(widths, nets=1, rows=1024):
+        h = C.c_void_p()
+        arr = (C.c_int * len(widths))(*widths)
+        rc = L.sur_create(arr, len(widths), nets, rows, None, C.byref(h))
+        return rc, h
+
+    assert create([5, 100, 256])[0] == -1          # hidden width not a multiple of 64
+    assert create([33, 64, 64])[0] == -1           # more than 32 inputs
+    assert create([5, 64], nets=17)[0] == -1
+    assert create([5, 64], rows=1000)[0] == -1     # rows not a multiple of 64
+    rc, h = create([5, 512, 512, 512, 512, 256], nets=4, rows=1024)
+    assert rc == 0
+    assert L.sur_num_params(h) == 922368           # 5 -> 512 x4 -> 256
+    assert L.sur_workspace_bytes(h) > 4 * 922368 * 4 * 4
+    assert L.sur_train_step(h, 0, None, None, None, 64, 1e-3, 1, None) == -3   # no workspace
+    assert L.sur_init_params(h, 7, 1) == -1        # bad net index
+    L.sur_destroy(h)
+
+
 def _grid(**kw):
     base = dict(nx=12, ny=10, nz=9, dx=0.5, max_steps=10)
     base.update(kw)
