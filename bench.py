@@ -61,20 +61,29 @@ def cpu_baseline(steps: int):
             "sample": f"FP64 oracle, full 512x512x384 grid, {steps} steps after table build"}
 
 
-def bench_batch(warmup: int = 100, graph_steps: int = 100):
+def bench_batch(warmup: int = 100, graph_steps: int = 100, tune: bool = True):
     """The 256-grid electrode sweep (uneven 32-96^3 grids, dx 0.25 m, 8-cell
-    CPML, 2000 steps) in the batched engine with HIP-graph replay."""
+    CPML, 2000 steps) in the batched engine with HIP-graph replay; tile shape
+    from the autotuner (cached) unless tune is False."""
     import torch
+    from paper_2207_06908_amd import autotune
     from paper_2207_06908_amd import fdtd
     from paper_2207_06908_amd import scenarios as S
     steps = 2000
-    scs = S.config3(n_steps=warmup + steps)
+    tune_steps = autotune.tuning_steps(batch=True) if tune else 0
+    scs = S.config3(n_steps=tune_steps + warmup + steps)
     grids = []
     for sc in scs:
         g = fdtd.Grid.from_params(sc.params(), precision=32)
         S.apply(sc, g)
         grids.append(g)
-    b = fdtd.Batch(grids, tile=(32, 8, 32), graph_steps=graph_steps)
+    tile = (32, 8, 32)
+    b = fdtd.Batch(grids, tile=tile, graph_steps=graph_steps)
+    if tune:
+        b.bind()
+        c = autotune.tune_batch(b, autotune.batch_key([(s.nx, s.ny, s.nz) for s in scs], scs[0].npml))
+        tile = (c["tile_x"], c["tile_y"], c["tile_z"])
+        b.set_kernel(*tile, graph_steps)
     b.run(warmup)
     torch.cuda.synchronize()
     b.timing(True)
@@ -86,6 +95,7 @@ def bench_batch(warmup: int = 100, graph_steps: int = 100):
     out = {"workload": f"{len(scs)} independent electrode grids, 32-96^3 (x grown to fit the electrode), "
                        f"dx 0.25 m, 8-cell CPML, {steps} steps, one launch per step, HIP graph of "
                        f"{graph_steps} steps",
+           "tile": list(tile),
            "cells": cells, "value": round(cells * steps / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
            "cases_per_s": round(len(scs) / (ms / 1e3), 2), "ms_per_step": round(ms / steps, 5),
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -116,12 +126,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--variant", default="auto", choices=["auto", "split", "fused", "tb2"])
+    ap.add_argument("--variant", default="tuned", choices=["tuned", "auto", "split", "fused", "tb2"],
+                    help="tuned: launch shape from the autotuner (cached); auto: fused 64x8, TZ 32")
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--tile-z", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-grid sweep measurement")
+    ap.add_argument("--no-tune", action="store_true", help="batched leg: fixed 32x8 tiles, TZ 32")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run plain copies of MIB MiB (profiler counter calibration)")
     a = ap.parse_args()
@@ -138,12 +150,20 @@ def main():
     from paper_2207_06908_amd import fdtd
     from paper_2207_06908_amd import scenarios as S
 
-    variant = {"auto": 0, "split": 1, "fused": 2, "tb2": 3}[a.variant]
-    sc = S.config2(n_steps=a.warmup + a.steps)
+    from paper_2207_06908_amd import autotune
+    variant = {"auto": 0, "split": 1, "fused": 2, "tb2": 3, "tuned": 0}[a.variant]
+    tune_steps = autotune.tuning_steps() if a.variant == "tuned" else 0
+    sc = S.config2(n_steps=tune_steps + a.warmup + a.steps)
     g = fdtd.Grid.from_params(sc.params(), precision=32)
     S.apply(sc, g)
-    g.set_kernel(variant, a.tile_y, a.tile_z)
     g.bind()
+    if a.variant == "tuned":
+        choice = autotune.tune_grid(g, autotune.grid_key(sc.params()))
+        autotune.apply_grid(g, choice)
+        a.variant = {1: "split", 2: "fused", 3: "tb2"}[choice["variant"]]
+        a.tile_y, a.tile_z = choice["tile_y"], choice["tile_z"]
+    else:
+        g.set_kernel(variant, a.tile_y, a.tile_z)
     g.step(a.warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -193,7 +213,7 @@ def main():
     del g
     torch.cuda.empty_cache()
     if not a.no_batch:
-        out["batched"] = bench_batch()
+        out["batched"] = bench_batch(tune=not a.no_tune)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -74,6 +74,11 @@ namespace mi355fdtd {
 int launch_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, int tile_z,
                 void* stream);
 
+// Fused step of one grid over a tile list: `tiles` is a device array of int4
+// (i0, j0, k0, k1); the first n_int tiles (64 x tile_y, clear of the CPML)
+// run without CPML arithmetic, the next n_pml (32 x tile_y) with it.
+int launch_fused_lists(int prec, const void* view, int cls16, int step, int tile_y, const void* tiles, int n_int,
+                       int n_pml, void* stream);
 // Record the probes of step `step` from the view's output set.
 int launch_probes(int prec, const void* view, int step, void* stream);
 

@@ -76,6 +76,11 @@ struct fdtd_ctx {
   size_t off_src_comp = 0, off_src_idx = 0, off_amp = 0, off_pr_off = 0, off_term_comp = 0;
   size_t off_term_idx = 0, off_term_w = 0, off_out = 0, psi_elems[3] = {0, 0, 0};
   std::vector<uint8_t> cls8;          // staging for 1-byte class ids
+  // fused tile lists of a grid with a CPML (i0, j0, k0, k1 per tile): the
+  // interior tiles first, then the CPML tiles; rebuilt when TY or TZ change
+  size_t off_tiles = 0, max_tiles = 0;
+  std::vector<int> tl;
+  int tl_int = 0, tl_pml = 0, tl_ty = -1, tl_kz = -1;
 
   // bound state
   char* ws = nullptr;
@@ -461,6 +466,11 @@ void layout(fdtd_ctx* c) {
   c->off_term_idx = take(c->term_idx.size() * sizeof(long long));
   c->off_term_w = take(c->term_w.size() * sizeof(double));
   c->off_out = take(c->probes.size() * (size_t)c->P.max_steps * sizeof(double));
+  c->max_tiles = 0;
+  if (np > 0) {  // bound for 32-wide, 4-high tiles and chunks of >= 8 planes
+    c->max_tiles = (size_t)(c->N[0] / 32 + 2) * (c->N[1] / 4 + 2) * (c->N[2] / 8 + 4);
+    c->off_tiles = take(c->max_tiles * 4 * sizeof(int));
+  }
   bool psi_fits = true;
   for (int u = 0; u < 3; ++u) psi_fits = psi_fits && 4 * c->psi_elems[u] * ts < (size_t(1) << 32);
   c->ws_bytes = psi_fits ? o : 0;
@@ -715,6 +725,74 @@ int fdtd_set_kernel(fdtd_ctx* c, int variant, int tile_y, int tile_z) {
   return FDTD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+struct Seg {
+  int a, b;
+  bool in;
+};
+
+// Split [0, n) into the aligned run of `w`-wide pieces that stays clear of
+// the CPML (a piece [a, a + w) with a - 1 >= np and a + w <= n - np, a a
+// multiple of `align`), and `w_out`-wide pieces for the rest.
+std::vector<Seg> segments(int n, int np, int w, int align, int w_out) {
+  std::vector<Seg> s;
+  int a = (np + 1 + align - 1) / align * align, b = a;
+  while (b + w <= n - np) b += w;
+  if (b == a) a = b = n;
+  for (int x = 0; x < a; x += w_out) s.push_back({x, std::min(x + w_out, a), false});
+  for (int x = a; x < b; x += w) s.push_back({x, x + w, true});
+  for (int x = b; x < n; x += w_out) s.push_back({x, std::min(x + w_out, n), false});
+  return s;
+}
+
+// Tile lists of the fused variant for a grid with a CPML (see fdtd_ctx::tl).
+int ensure_tiles(fdtd_ctx* c, int ty, int kz) {
+  if (c->tl_ty == ty && c->tl_kz == kz) return FDTD_OK;
+  const int np = c->P.npml, nz = c->N[2];
+  const std::vector<Seg> xs = segments(c->N[0], np, 64, 32, 32);
+  const std::vector<Seg> ys = segments(c->N[1], np, ty, ty, ty);
+  std::vector<Seg> zs;
+  const int za = np + 1, zb = nz - np;
+  if (zb - za >= 1) {
+    zs.push_back({0, za, false});
+    for (int z = za; z < zb; z += kz) zs.push_back({z, std::min(z + kz, zb), true});
+    for (int z = zb; z < nz; z += kz) zs.push_back({z, std::min(z + kz, nz), false});
+  } else {
+    for (int z = 0; z < nz; z += kz) zs.push_back({z, std::min(z + kz, nz), false});
+  }
+  std::vector<int> in, pml;
+  for (const Seg& z : zs)
+    for (const Seg& y : ys)
+      for (const Seg& x : xs) {
+        if (x.in && y.in && z.in) {
+          in.insert(in.end(), {x.a, y.a, z.a, z.b});
+        } else {
+          for (int xx = x.a; xx < x.b; xx += 32) pml.insert(pml.end(), {xx, y.a, z.a, z.b});
+        }
+      }
+  const size_t nt = (in.size() + pml.size()) / 4;
+  if (nt > c->max_tiles) return fail(c, FDTD_EINVAL, "tile list larger than its reservation");
+  hipError_t e = hipStreamSynchronize(c->stream);  // a previous upload may still read c->tl
+  if (e != hipSuccess) return hip_fail(c, e, "tile list");
+  c->tl = in;
+  c->tl.insert(c->tl.end(), pml.begin(), pml.end());
+  e = hipMemcpyAsync(c->ws + c->off_tiles, c->tl.data(), c->tl.size() * sizeof(int), hipMemcpyHostToDevice,
+                     c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tile list upload");
+  c->tl_int = (int)(in.size() / 4);
+  c->tl_pml = (int)(pml.size() / 4);
+  c->tl_ty = ty;
+  c->tl_kz = kz;
+  return FDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int fdtd_step(fdtd_ctx* c, int n) {
   if (!c || n < 0) return fail(c, FDTD_EINVAL, "bad step count");
   if (!c->ws) return fail(c, FDTD_ESTATE, "no workspace bound");
@@ -727,6 +805,12 @@ int fdtd_step(fdtd_ctx* c, int n) {
     const int in = c->cur, out = variant == FDTD_KERNEL_SPLIT ? c->cur : 1 - c->cur;
     const void* view = c->P.precision == 64 ? (const void*)&c->v64[in][out] : (const void*)&c->v32[in][out];
     const void* pview = c->P.precision == 64 ? (const void*)&c->v64[out][out] : (const void*)&c->v32[out][out];
+    const bool lists = variant == FDTD_KERNEL_FUSED && c->P.npml > 0;
+    const int lty = c->tile_y == 4 ? 4 : 8, lkz = std::max(8, c->tile_z > 0 ? c->tile_z : 32);
+    if (lists) {
+      int rc = ensure_tiles(c, lty, lkz);
+      if (rc) return rc;
+    }
     int slot = -1;
     if (c->timing) {
       slot = c->ev_next;
@@ -742,8 +826,14 @@ int fdtd_step(fdtd_ctx* c, int n) {
       hipError_t er = hipEventRecord(c->ev0[slot], c->stream);
       if (er != hipSuccess) return hip_fail(c, er, "hipEventRecord");
     }
-    int e = launch_step(c->P.precision, view, c->cls16, variant, (int)c->steps_done, c->tile_y, c->tile_z,
-                        (void*)c->stream);
+    int e;
+    if (lists) {
+      e = launch_fused_lists(c->P.precision, view, c->cls16, (int)c->steps_done, lty, c->ws + c->off_tiles,
+                             c->tl_int, c->tl_pml, (void*)c->stream);
+    } else {
+      e = launch_step(c->P.precision, view, c->cls16, variant, (int)c->steps_done, c->tile_y, c->tile_z,
+                      (void*)c->stream);
+    }
     if (e) return fail(c, FDTD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString((hipError_t)e));
     if (variant != FDTD_KERNEL_SPLIT) c->cur ^= 1;
     if (slot >= 0) {

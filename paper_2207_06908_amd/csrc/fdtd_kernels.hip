@@ -420,6 +420,17 @@ __global__ __launch_bounds__(TX * TY) void k_fused(GridView<T> g, int step, int 
   fused_tile<T, CI, PML, TX, TY>(g, sm, tile_x * TX, (rest % nty) * TY, k0, min(k0 + kz, g.nz), step);
 }
 
+// One grid, tile list: block b takes tile (i0, j0, k0, k1).  The host splits
+// a grid with a CPML into tiles clear of every slab (including the recomputed
+// halo and the prologue plane), which run the lean instantiation, and the
+// rest, which runs the CPML one.
+template <typename T, typename CI, bool PML, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_fused_list(GridView<T> g, const int4* __restrict__ tiles, int step) {
+  __shared__ FusedSmem<T, TX, TY> sm;
+  const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+  fused_tile<T, CI, PML, TX, TY>(g, sm, t.x, t.y, t.z, t.w, step);
+}
+
 // Batched: one block per entry of a tile list spanning many grids; each
 // grid's view is read from a device table (one table per field-set parity).
 // The step index is a device counter (plus a per-launch offset) so that a
@@ -760,6 +771,28 @@ hipError_t step_fused(const GridView<T>& g, int step, int tile_y, int tile_z, hi
   return pml ? launch_fused<T, CI, true, 64, 8>(g, step, kz, st) : launch_fused<T, CI, false, 64, 8>(g, step, kz, st);
 }
 
+template <typename T, typename CI, int TY>
+hipError_t launch_lists(const GridView<T>& g, int step, const int4* tiles, int n_int, int n_pml, hipStream_t st) {
+  if (sizeof(CI) == 1 && g.ncls > 256) return hipErrorInvalidValue;
+  if (n_int > 0)
+    hipLaunchKernelGGL((k_fused_list<T, CI, false, 64, TY>), dim3((unsigned)n_int), dim3(64 * TY), 0, st, g,
+                       tiles, step);
+  if (n_pml > 0)
+    hipLaunchKernelGGL((k_fused_list<T, CI, true, 32, TY>), dim3((unsigned)n_pml), dim3(32 * TY), 0, st, g,
+                       tiles + n_int, step);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t lists_any(const GridView<T>& g, int cls16, int step, int ty, const int4* tiles, int n_int, int n_pml,
+                     hipStream_t st) {
+  if (ty == 4)
+    return cls16 ? launch_lists<T, uint16_t, 4>(g, step, tiles, n_int, n_pml, st)
+                 : launch_lists<T, uint8_t, 4>(g, step, tiles, n_int, n_pml, st);
+  return cls16 ? launch_lists<T, uint16_t, 8>(g, step, tiles, n_int, n_pml, st)
+               : launch_lists<T, uint8_t, 8>(g, step, tiles, n_int, n_pml, st);
+}
+
 template <typename T, typename CI, bool PML, int TY>
 hipError_t launch_tb2(const GridView<T>& g, int step, int kz, hipStream_t st) {
   const int ntx = (g.nx + 59) / 60, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + kz - 1) / kz;
@@ -789,6 +822,16 @@ hipError_t step_any(const GridView<T>& g, int cls16, int variant, int step, int 
     return cls16 ? step_fused<T, uint16_t>(g, step, tile_y, tile_z, st)
                  : step_fused<T, uint8_t>(g, step, tile_y, tile_z, st);
   return cls16 ? step_split<T, uint16_t>(g, step, st) : step_split<T, uint8_t>(g, step, st);
+}
+
+int launch_fused_lists(int prec, const void* view, int cls16, int step, int tile_y, const void* tiles, int n_int,
+                       int n_pml, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int4* t = (const int4*)tiles;
+  const int ty = tile_y == 4 ? 4 : 8;
+  hipError_t e = prec == 64 ? lists_any<double>(*(const GridView<double>*)view, cls16, step, ty, t, n_int, n_pml, st)
+                            : lists_any<float>(*(const GridView<float>*)view, cls16, step, ty, t, n_int, n_pml, st);
+  return (int)e;
 }
 
 int launch_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, int tile_z,

@@ -132,8 +132,11 @@ class Grid:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().fdtd_destroy(h)
+        if h and _lib is not None:
+            try:
+                _lib.fdtd_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
             self._h = None
 
     def _chk(self, rc):
@@ -261,8 +264,11 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().fdtd_batch_destroy(h)
+        if h and _lib is not None:
+            try:
+                _lib.fdtd_batch_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
             self._h = None
 
     def _chk(self, rc):

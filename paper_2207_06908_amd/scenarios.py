@@ -267,12 +267,13 @@ CONFIG3_RANGES = dict(log10_sigma=(-4.0, -1.0), eps_r=(4.0, 40.0), length=(5.0, 
 
 def electrode_grid(case: ElectrodeCase, dims: Tuple[int, int, int], dx: float = 0.25,
                    npml: int = 8, n_steps: int = 2000, T2: float = 10e-6,
-                   name: str = "electrode") -> Scenario:
+                   name: str = "electrode", amps: np.ndarray = None) -> Scenario:
     """Buried horizontal electrode fed like the ground-potential-rise model
     file of Section 4.1 (Fig. 3): a riser from the electrode to one cell above
     the surface, a current-source gap on a horizontal stub with a lead into
     the absorbing layer, and a voltage gap on a perpendicular stub with its own
-    lead (the remote reference)."""
+    lead (the remote reference).  ``amps`` (n_steps samples) replaces the
+    double-exponential current when given."""
     nx, ny, nz = dims
     dt = courant_dt(dx)
     n_w = int(round(case.length / dx))
@@ -295,7 +296,8 @@ def electrode_grid(case: ElectrodeCase, dims: Tuple[int, int, int], dx: float = 
         (AX_Y, i_f, jc - 2, kw, 2, a),          # voltage stub
         (AX_Y, i_f, 0, kw, jc - 3, a),          # voltage lead into the CPML
     ]
-    amps = double_exponential(n_steps, dt, 1.0, case.T1, T2)
+    if amps is None:
+        amps = double_exponential(n_steps, dt, 1.0, case.T1, T2)
     probes = [("V_gap", PR_VLINE, AX_Y, i_f, jc - 3, kw, 1),
               ("I_source", PR_ILOOP, AX_X, i_f - 3, jc, kw, 1)]
     return Scenario(name, nx, ny, nz, dx, dt, n_steps, cm, mats, npml=npml, wires=wires,
