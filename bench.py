@@ -121,6 +121,46 @@ def calibrate_copy(mib: int = 1024, reps: int = 3):
                       "reps": reps}), flush=True)
 
 
+def bench_surrogate(queries: int = 65536, threshold: float = 0.02, fdtd_cases: int = 256):
+    """Surrogate in the loop on the electrode sweep: queries from ranges 20%
+    wider than the training ranges, one batched inference of the 4-net
+    ensemble with spread routing, fallback queries priced at the batched FDTD
+    engine's measured cases/s on the same kind of case grids."""
+    import torch
+    from paper_2207_06908_amd import scenarios as S
+    from paper_2207_06908_amd import surrogate as U
+    weights = os.path.join(ROOT, "paper_2207_06908_amd", "data", "surrogate_weights.npz")
+    cases = S.draw_cases(queries, seed=5, widen=0.1)
+    X = torch.from_numpy(U.features(cases)).cuda()
+    sur = U.Surrogate(n_nets=4, max_rows=8192)
+    sur.load(weights)
+    sur.ens.infer_route(X[:8192], threshold)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    _ym, _sp, _ids, cnt = sur.ens.infer_route(X, threshold)
+    e1.record()
+    torch.cuda.synchronize()
+    infer_s = e0.elapsed_time(e1) / 1e3
+    n_fb = int(cnt.item())
+    run = U.run_fdtd(cases[:fdtd_cases])
+    fdtd_cps = fdtd_cases / (run.gpu_ms / 1e3)
+    loop_s = infer_s + n_fb / fdtd_cps
+    w = U.WIDTHS
+    flop = 2.0 * sur.n_nets * queries * sum(k * n for k, n in zip(w[:-1], w[1:]))
+    tf = flop / infer_s / 1e12
+    del sur
+    torch.cuda.empty_cache()
+    return {"workload": f"{queries} electrode queries (ranges 20% wider than training), 4-net ensemble "
+                        f"5-512x4-256, spread > {threshold:.0%} -> batched FDTD",
+            "inference_ms": round(infer_s * 1e3, 3), "inference_cases_per_s": round(queries / infer_s, 1),
+            "fallback_fraction": round(n_fb / queries, 5), "fdtd_cases_per_s": round(fdtd_cps, 2),
+            "surrogate_in_loop_cases_per_s": round(queries / loop_s, 1),
+            "gain_vs_fdtd": round((queries / loop_s) / fdtd_cps, 1),
+            "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": round(tf / 2500.0, 5), "kernel": "ensemble inference (bf16 MFMA products)"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +174,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-grid sweep measurement")
     ap.add_argument("--no-tune", action="store_true", help="batched leg: fixed 32x8 tiles, TZ 32")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-in-the-loop measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run plain copies of MIB MiB (profiler counter calibration)")
     a = ap.parse_args()
@@ -214,6 +255,8 @@ def main():
     torch.cuda.empty_cache()
     if not a.no_batch:
         out["batched"] = bench_batch(tune=not a.no_tune)
+    if not a.no_surrogate:
+        out["surrogate"] = bench_surrogate()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_steps)
     print(json.dumps(out), flush=True)

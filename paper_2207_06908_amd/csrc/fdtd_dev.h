@@ -74,11 +74,16 @@ namespace mi355fdtd {
 int launch_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, int tile_z,
                 void* stream);
 
-// Fused step of one grid over a tile list: `tiles` is a device array of int4
-// (i0, j0, k0, k1); the first n_int tiles (64 x tile_y, clear of the CPML)
-// run without CPML arithmetic, the next n_pml (32 x tile_y) with it.
-int launch_fused_lists(int prec, const void* view, int cls16, int step, int tile_y, const void* tiles, int n_int,
-                       int n_pml, void* stream);
+// Fused (variant 2) or two-step (variant 3) pass of one grid over a tile
+// list: `tiles` is a device array of int4 in 4 groups of counts[q] tiles, by
+// the CPML slabs a tile reaches (halo included): 0 neither x nor y slabs, 1 x
+// slabs only, 2 y slabs only, 3 both.  Every group carries z CPML code.
+//   variant 2: (i0, j0, k0, k1); 32 x tile_y tiles in groups 1 and 3,
+//              64 x tile_y in groups 0 and 2;
+//   variant 3: (i0 | iw << 16, j0 | jh << 16, k0, k1) with iw <= 60,
+//              jh <= tile_y.
+int launch_lists_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, const void* tiles,
+                      const int* counts, void* stream);
 // Record the probes of step `step` from the view's output set.
 int launch_probes(int prec, const void* view, int step, void* stream);
 

@@ -80,7 +80,7 @@ struct fdtd_ctx {
   // interior tiles first, then the CPML tiles; rebuilt when TY or TZ change
   size_t off_tiles = 0, max_tiles = 0;
   std::vector<int> tl;
-  int tl_int = 0, tl_pml = 0, tl_ty = -1, tl_kz = -1;
+  int tl_cnt[4] = {0, 0, 0, 0}, tl_var = -1, tl_ty = -1, tl_kz = -1;
 
   // bound state
   char* ws = nullptr;
@@ -468,7 +468,7 @@ void layout(fdtd_ctx* c) {
   c->off_out = take(c->probes.size() * (size_t)c->P.max_steps * sizeof(double));
   c->max_tiles = 0;
   if (np > 0) {  // bound for 32-wide, 4-high tiles and chunks of >= 8 planes
-    c->max_tiles = (size_t)(c->N[0] / 32 + 2) * (c->N[1] / 4 + 2) * (c->N[2] / 8 + 4);
+    c->max_tiles = (size_t)(c->N[0] / 32 + 6) * (c->N[1] / 4 + 6) * (c->N[2] / 8 + 6);
     c->off_tiles = take(c->max_tiles * 4 * sizeof(int));
   }
   bool psi_fits = true;
@@ -748,42 +748,66 @@ std::vector<Seg> segments(int n, int np, int w, int align, int w_out) {
   return s;
 }
 
-// Tile lists of the fused variant for a grid with a CPML (see fdtd_ctx::tl).
-int ensure_tiles(fdtd_ctx* c, int ty, int kz) {
-  if (c->tl_ty == ty && c->tl_kz == kz) return FDTD_OK;
+// Two-step pieces: [0, n) split into w-wide pieces, those in [a, b) clear
+// of the CPML including the h-cell halo (a - h >= np, piece end + h <= n - np);
+// a is a multiple of w so that the pieces below it are full width.
+std::vector<Seg> segments_tb2(int n, int np, int w, int h) {
+  std::vector<Seg> s;
+  int a = (np + h + w - 1) / w * w, b = a;
+  while (b + w <= n - np - h) b += w;
+  if (b == a) a = b = n;
+  for (int x = 0; x < a; x += w) s.push_back({x, std::min(x + w, a), false});
+  for (int x = a; x < b; x += w) s.push_back({x, x + w, true});
+  for (int x = b; x < n; x += w) s.push_back({x, std::min(x + w, n), false});
+  return s;
+}
+
+// Tile lists of the fused and two-step passes for a grid with a CPML (see
+// fdtd_ctx::tl and launch_lists_step).
+int ensure_tiles(fdtd_ctx* c, int variant, int ty, int kz) {
+  if (c->tl_var == variant && c->tl_ty == ty && c->tl_kz == kz) return FDTD_OK;
+  const bool tb2 = variant == FDTD_KERNEL_TB2;
   const int np = c->P.npml, nz = c->N[2];
-  const std::vector<Seg> xs = segments(c->N[0], np, 64, 32, 32);
-  const std::vector<Seg> ys = segments(c->N[1], np, ty, ty, ty);
-  std::vector<Seg> zs;
-  const int za = np + 1, zb = nz - np;
-  if (zb - za >= 1) {
-    zs.push_back({0, za, false});
-    for (int z = za; z < zb; z += kz) zs.push_back({z, std::min(z + kz, zb), true});
-    for (int z = zb; z < nz; z += kz) zs.push_back({z, std::min(z + kz, nz), false});
-  } else {
-    for (int z = 0; z < nz; z += kz) zs.push_back({z, std::min(z + kz, nz), false});
-  }
-  std::vector<int> in, pml;
-  for (const Seg& z : zs)
-    for (const Seg& y : ys)
-      for (const Seg& x : xs) {
-        if (x.in && y.in && z.in) {
-          in.insert(in.end(), {x.a, y.a, z.a, z.b});
-        } else {
-          for (int xx = x.a; xx < x.b; xx += 32) pml.insert(pml.end(), {xx, y.a, z.a, z.b});
+  const std::vector<Seg> xs = tb2 ? segments_tb2(c->N[0], np, 60, 2) : segments(c->N[0], np, 64, 32, 32);
+  const std::vector<Seg> ys = tb2 ? segments_tb2(c->N[1], np, ty, 2) : segments(c->N[1], np, ty, ty, ty);
+  // z chunks are not split at the slabs: the z CPML branch depends on the
+  // plane only, which every thread of a block shares, so the tiles clear of
+  // the x and y slabs carry z CPML code at little cost
+  // The CPML groups hold few tiles; shorter chunks give their launches
+  // enough blocks to fill the device.
+  std::vector<Seg> zs[2];
+  const int kzp = std::max(8, kz / 4);
+  for (int z = 0; z < nz; z += kz) zs[0].push_back({z, std::min(z + kz, nz), true});
+  for (int z = 0; z < nz; z += kzp) zs[1].push_back({z, std::min(z + kzp, nz), true});
+  std::vector<int> grp[4];
+  for (int pass = 0; pass < 2; ++pass)
+    for (const Seg& z : zs[pass])
+      for (const Seg& y : ys)
+        for (const Seg& x : xs) {
+          const int q = (x.in ? 0 : 1) | (y.in ? 0 : 2);
+          if ((q == 0) != (pass == 0)) continue;
+          if (tb2) {
+            grp[q].insert(grp[q].end(), {x.a | (x.b - x.a) << 16, y.a | (y.b - y.a) << 16, z.a, z.b});
+          } else if (q & 1) {
+            for (int xx = x.a; xx < x.b; xx += 32) grp[q].insert(grp[q].end(), {xx, y.a, z.a, z.b});
+          } else {
+            grp[q].insert(grp[q].end(), {x.a, y.a, z.a, z.b});
+          }
         }
-      }
-  const size_t nt = (in.size() + pml.size()) / 4;
+  size_t nt = 0;
+  for (int q = 0; q < 4; ++q) nt += grp[q].size() / 4;
   if (nt > c->max_tiles) return fail(c, FDTD_EINVAL, "tile list larger than its reservation");
   hipError_t e = hipStreamSynchronize(c->stream);  // a previous upload may still read c->tl
   if (e != hipSuccess) return hip_fail(c, e, "tile list");
-  c->tl = in;
-  c->tl.insert(c->tl.end(), pml.begin(), pml.end());
+  c->tl.clear();
+  for (int q = 0; q < 4; ++q) {
+    c->tl.insert(c->tl.end(), grp[q].begin(), grp[q].end());
+    c->tl_cnt[q] = (int)(grp[q].size() / 4);
+  }
   e = hipMemcpyAsync(c->ws + c->off_tiles, c->tl.data(), c->tl.size() * sizeof(int), hipMemcpyHostToDevice,
                      c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "tile list upload");
-  c->tl_int = (int)(in.size() / 4);
-  c->tl_pml = (int)(pml.size() / 4);
+  c->tl_var = variant;
   c->tl_ty = ty;
   c->tl_kz = kz;
   return FDTD_OK;
@@ -805,10 +829,13 @@ int fdtd_step(fdtd_ctx* c, int n) {
     const int in = c->cur, out = variant == FDTD_KERNEL_SPLIT ? c->cur : 1 - c->cur;
     const void* view = c->P.precision == 64 ? (const void*)&c->v64[in][out] : (const void*)&c->v32[in][out];
     const void* pview = c->P.precision == 64 ? (const void*)&c->v64[out][out] : (const void*)&c->v32[out][out];
-    const bool lists = variant == FDTD_KERNEL_FUSED && c->P.npml > 0;
-    const int lty = c->tile_y == 4 ? 4 : 8, lkz = std::max(8, c->tile_z > 0 ? c->tile_z : 32);
+    // grids with a CPML run the fused and two-step passes over tile lists
+    const bool lists = (variant == FDTD_KERNEL_FUSED || variant == FDTD_KERNEL_TB2) && c->P.npml > 0 &&
+                       c->N[0] < 65536 && c->N[1] < 65536;
+    const int lty = c->tile_y == 4 ? 4 : 8;
+    const int lkz = std::max(8, c->tile_z > 0 ? c->tile_z : (variant == FDTD_KERNEL_TB2 ? 64 : 32));
     if (lists) {
-      int rc = ensure_tiles(c, lty, lkz);
+      int rc = ensure_tiles(c, variant, lty, lkz);
       if (rc) return rc;
     }
     int slot = -1;
@@ -828,8 +855,8 @@ int fdtd_step(fdtd_ctx* c, int n) {
     }
     int e;
     if (lists) {
-      e = launch_fused_lists(c->P.precision, view, c->cls16, (int)c->steps_done, lty, c->ws + c->off_tiles,
-                             c->tl_int, c->tl_pml, (void*)c->stream);
+      e = launch_lists_step(c->P.precision, view, c->cls16, variant, (int)c->steps_done, lty, c->ws + c->off_tiles,
+                            c->tl_cnt, (void*)c->stream);
     } else {
       e = launch_step(c->P.precision, view, c->cls16, variant, (int)c->steps_done, c->tile_y, c->tile_z,
                       (void*)c->stream);

@@ -27,11 +27,13 @@ namespace mi355fdtd {
 // ---------------------------------------------------------------------------
 
 // Slab-local CPML positions of node (x, y, k) along each axis (-1 outside).
-template <typename T>
+// AX masks the axes whose slabs the caller can reach (bit 0 x, 1 y, 2 z); the
+// other positions are the constant -1, which removes their CPML code.
+template <typename T, int AX = 7>
 __device__ __forceinline__ void slabs(const GridView<T>& g, int x, int y, int k, int l[3]) {
-  l[0] = slab_pos(x, g.nx, g.npml);
-  l[1] = slab_pos(y, g.ny, g.npml);
-  l[2] = slab_pos(k, g.nz, g.npml);
+  l[0] = (AX & 1) ? slab_pos(x, g.nx, g.npml) : -1;
+  l[1] = (AX & 2) ? slab_pos(y, g.ny, g.npml) : -1;
+  l[2] = (AX & 4) ? slab_pos(k, g.nz, g.npml) : -1;
 }
 
 // CPML state of one node: ps[axis][q], q = 0 for the component along
@@ -131,28 +133,28 @@ __device__ __forceinline__ void e_core(const GridView<T>& g, const int l[3], uns
 
 // One-step wrappers: CPML state from the input set, written (optionally for
 // H) to the output set.
-template <typename T, bool PML>
+template <typename T, bool PML, int AX = 7>
 __device__ __forceinline__ void h_point(const GridView<T>& g, int x, int y, int k, const T* cf, T ex, T ey,
                                         T ez, T ex_j, T ex_k, T ey_i, T ey_k, T ez_i, T ez_j, const T hold[3],
                                         bool store_psi, T hnew[3]) {
   int l[3] = {-1, -1, -1};
   T ps[3][2];
   if (PML) {
-    slabs(g, x, y, k, l);
+    slabs<T, AX>(g, x, y, k, l);
     psi_load(g, 1, l, x, y, k, ps);
   }
   h_core<T, PML>(g, l, cf, ex, ey, ez, ex_j, ex_k, ey_i, ey_k, ez_i, ez_j, hold, ps, hnew);
   if (PML && store_psi) psi_store(g, 1, l, x, y, k, ps);
 }
 
-template <typename T, bool PML>
+template <typename T, bool PML, int AX = 7>
 __device__ __forceinline__ void e_point(const GridView<T>& g, int x, int y, int k, unsigned n, const T* cf,
                                         T hx, T hy, T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j,
                                         const T eold[3], int step, T enew[3]) {
   int l[3] = {-1, -1, -1};
   T ps[3][2];
   if (PML) {
-    slabs(g, x, y, k, l);
+    slabs<T, AX>(g, x, y, k, l);
     psi_load(g, 0, l, x, y, k, ps);
   }
   e_core<T, PML>(g, l, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, ps, enew);
@@ -252,7 +254,7 @@ struct FusedSmem {
 };
 
 // One tile [i0, i0+TX) x [j0, j0+TY) x [k0, k1) of one grid, one step.
-template <typename T, typename CI, bool PML, int TX, int TY>
+template <typename T, typename CI, bool PML, int TX, int TY, int AX = 7>
 __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX, TY>& sm, int i0, int j0,
                                            int k0, int k1, int step) {
   constexpr int NT = TX * TY, EW = TX + 2, EH = TY + 2, HW = TX + 1;
@@ -326,7 +328,7 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
     __syncthreads();
     if (own && kb >= 0) {
       T h[3];
-      h_point<T, PML>(g, i, j, kb, coef(cb), eb[0], eb[1], eb[2], se[sb][0][ty + 2][tx + 1], ecur[0],
+      h_point<T, PML, AX>(g, i, j, kb, coef(cb), eb[0], eb[1], eb[2], se[sb][0][ty + 2][tx + 1], ecur[0],
                       se[sb][1][ty + 1][tx + 2], ecur[1], se[sb][2][ty + 1][tx + 2], se[sb][2][ty + 2][tx + 1],
                       hb, false, h);
       hm[0] = h[0];
@@ -363,7 +365,7 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
     // (c) H(k): own column, then the low-side halo point
     T hown[3] = {T(0), T(0), T(0)};
     if (own) {
-      h_point<T, PML>(g, i, j, k, coef(cls_cur), ecur[0], ecur[1], ecur[2], se[s][0][ty + 2][tx + 1], enext[0],
+      h_point<T, PML, AX>(g, i, j, k, coef(cls_cur), ecur[0], ecur[1], ecur[2], se[s][0][ty + 2][tx + 1], enext[0],
                       se[s][1][ty + 1][tx + 2], enext[1], se[s][2][ty + 1][tx + 2], se[s][2][ty + 2][tx + 1],
                       hold, true, hown);
       const unsigned n = n0 + sxy * (unsigned)k;
@@ -377,7 +379,7 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
     if (hh) {
       T hx3[3] = {T(0), T(0), T(0)};
       if (hh_in) {
-        h_point<T, PML>(g, hx_x, hx_y, k, coef(xcls_cur), se[s][0][hr][hc], se[s][1][hr][hc], se[s][2][hr][hc],
+        h_point<T, PML, AX>(g, hx_x, hx_y, k, coef(xcls_cur), se[s][0][hr][hc], se[s][1][hr][hc], se[s][2][hr][hc],
                         se[s][0][hr + 1][hc], se[s1][0][hr][hc], se[s][1][hr][hc + 1], se[s1][1][hr][hc],
                         se[s][2][hr][hc + 1], se[s][2][hr + 1][hc], xh_old, false, hx3);
       }
@@ -390,7 +392,7 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
     if (own) {
       const unsigned n = n0 + sxy * (unsigned)k;
       T e[3];
-      e_point<T, PML>(g, i, j, k, n, coef(cls_cur), hown[0], hown[1], hown[2], sh[0][ty][tx + 1], hm[0],
+      e_point<T, PML, AX>(g, i, j, k, n, coef(cls_cur), hown[0], hown[1], hown[2], sh[0][ty][tx + 1], hm[0],
                       sh[1][ty + 1][tx], hm[1], sh[2][ty + 1][tx], sh[2][ty][tx + 1], ecur, step, e);
       stg(g.fo[0], n, e[0]);
       stg(g.fo[1], n, e[1]);
@@ -424,11 +426,11 @@ __global__ __launch_bounds__(TX * TY) void k_fused(GridView<T> g, int step, int 
 // a grid with a CPML into tiles clear of every slab (including the recomputed
 // halo and the prologue plane), which run the lean instantiation, and the
 // rest, which runs the CPML one.
-template <typename T, typename CI, bool PML, int TX, int TY>
+template <typename T, typename CI, bool PML, int TX, int TY, int AX>
 __global__ __launch_bounds__(TX * TY) void k_fused_list(GridView<T> g, const int4* __restrict__ tiles, int step) {
   __shared__ FusedSmem<T, TX, TY> sm;
   const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
-  fused_tile<T, CI, PML, TX, TY>(g, sm, t.x, t.y, t.z, t.w, step);
+  fused_tile<T, CI, PML, TX, TY, AX>(g, sm, t.x, t.y, t.z, t.w, step);
 }
 
 // Batched: one block per entry of a tile list spanning many grids; each
@@ -475,16 +477,14 @@ struct TB2Smem {
   T stab[256 * K_STRIDE];
 };
 
-template <typename T, typename CI, bool PML, int TY>
-__global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, int kz, int ntx, int nty) {
+// One two-step tile: outputs [i0, i0+iw) x [j0, j0+jh) x [k0, k1) with
+// iw <= 60, jh <= TY.  AX masks the axes whose CPML slabs the tile can reach.
+template <typename T, typename CI, bool PML, int TY, int AX>
+__device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& sm, int i0, int j0, int iw, int jh,
+                                         int k0, int k1, int step) {
   constexpr int TX = 60, NT = 64 * (TY + 4);
   constexpr bool LDS_TAB = sizeof(CI) == 1;
-  __shared__ TB2Smem<T, TY> sm;
   const int tid = threadIdx.x, u = tid & 63, v = tid >> 6;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tile_x = tile % ntx, rest = tile / ntx;
-  const int i0 = tile_x * TX, j0 = (rest % nty) * TY, k0 = (rest / nty) * kz;
-  const int k1 = min(k0 + kz, g.nz);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const unsigned sxy = (unsigned)g.sxy;
   const CI* cls = (const CI*)g.cls;
@@ -498,10 +498,11 @@ __global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, 
   const bool inA = dom && u <= TX + 2 && v <= TY + 2;
   const bool inB = inA && u >= 1 && v >= 1;
   const bool inC = inB && u <= TX + 1 && v <= TY + 1;
-  const bool inD = inC && u >= 2 && v >= 2;
+  const bool inD = inC && u >= 2 && v >= 2 && u < 2 + iw && v < 2 + jh;
   const unsigned n0 = dom ? (unsigned)x + (unsigned)nx * (unsigned)y : 0u;
-  const int lx = PML && dom ? slab_pos(x, nx, g.npml) : -1;
-  const int ly = PML && dom ? slab_pos(y, ny, g.npml) : -1;
+  const int lx = PML && (AX & 1) && dom ? slab_pos(x, nx, g.npml) : -1;
+  const int ly = PML && (AX & 2) && dom ? slab_pos(y, ny, g.npml) : -1;
+  constexpr bool PZ = PML && (AX & 4);
 
   auto ld_e = [&](bool ok, int k, T e[3]) {
     const bool in = ok && k >= 0 && k < nz;
@@ -545,7 +546,7 @@ __global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, 
     T h1c[3] = {T(0), T(0), T(0)};
     T pshn[3][2];
     if (inA && kin) {
-      int l[3] = {lx, ly, PML ? slab_pos(k, nz, g.npml) : -1};
+      int l[3] = {lx, ly, PZ ? slab_pos(k, nz, g.npml) : -1};
       if (PML) psi_load(g, 1, l, x, y, k, pshn);
       h_core<T, PML>(g, l, coef(cc), e0c[0], e0c[1], e0c[2], sm.se0[0][v + 1][u], e0n[0], sm.se0[1][v][u + 1],
                      e0n[1], sm.se0[2][v][u + 1], sm.se0[2][v + 1][u], h0c, pshn, h1c);
@@ -556,7 +557,7 @@ __global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, 
     T e1c[3] = {T(0), T(0), T(0)};
     T psen[3][2];
     if (inB && kin && k >= k0 - 1) {
-      int l[3] = {lx, ly, PML ? slab_pos(k, nz, g.npml) : -1};
+      int l[3] = {lx, ly, PZ ? slab_pos(k, nz, g.npml) : -1};
       if (PML) psi_load(g, 0, l, x, y, k, psen);
       e_core<T, PML>(g, l, n0 + sxy * (unsigned)k, coef(cc), h1c[0], h1c[1], h1c[2], sm.sh1[0][v - 1][u], h1p[0],
                      sm.sh1[1][v][u - 1], h1p[1], sm.sh1[2][v][u - 1], sm.sh1[2][v - 1][u], e0c, step, psen, e1c);
@@ -568,7 +569,7 @@ __global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, 
     const int km = k - 1;
     T h2c[3] = {T(0), T(0), T(0)};
     if (inC && k >= k0 && km >= 0 && km < nz) {
-      int l[3] = {lx, ly, PML ? slab_pos(km, nz, g.npml) : -1};
+      int l[3] = {lx, ly, PZ ? slab_pos(km, nz, g.npml) : -1};
       h_core<T, PML>(g, l, coef(cp), e1p[0], e1p[1], e1p[2], sm.se1[s1m][0][v + 1][u], e1c[0],
                      sm.se1[s1m][1][v][u + 1], e1c[1], sm.se1[s1m][2][v][u + 1], sm.se1[s1m][2][v + 1][u], h1p, psh,
                      h2c);
@@ -584,7 +585,7 @@ __global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, 
     __syncthreads();
     // D: E^{n+2}, plane k-1 (the output tile)
     if (inD && k >= k0 + 1 && km < k1) {
-      int l[3] = {lx, ly, PML ? slab_pos(km, nz, g.npml) : -1};
+      int l[3] = {lx, ly, PZ ? slab_pos(km, nz, g.npml) : -1};
       const unsigned n = n0 + sxy * (unsigned)km;
       T e2[3];
       e_core<T, PML>(g, l, n, coef(cp), h2c[0], h2c[1], h2c[2], sm.sh2[0][v - 1][u], h2p[0], sm.sh2[1][v][u - 1],
@@ -614,6 +615,27 @@ __global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, 
     cp = cc;
     cc = cf1;
   }
+}
+
+template <typename T, typename CI, bool PML, int TY>
+__global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, int kz, int ntx, int nty) {
+  __shared__ TB2Smem<T, TY> sm;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile_x = tile % ntx, rest = tile / ntx;
+  const int k0 = (rest / nty) * kz;
+  tb2_tile<T, CI, PML, TY, 7>(g, sm, tile_x * 60, (rest % nty) * TY, 60, TY, k0, min(k0 + kz, g.nz), step);
+}
+
+// Tile list: (i0 | iw << 16, j0 | jh << 16, k0, k1) per block.
+// Except for the all-axes corner instantiation, at most 80 VGPRs (6 waves
+// per SIMD), so that two blocks share a CU.
+template <typename T, typename CI, bool PML, int TY, int AX>
+__global__ __launch_bounds__(64 * (TY + 4), (AX == 7 ? 1 : 6)) void k_tb2_list(GridView<T> g,
+                                                                              const int4* __restrict__ tiles,
+                                                            int step) {
+  __shared__ TB2Smem<T, TY> sm;
+  const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+  tb2_tile<T, CI, PML, TY, AX>(g, sm, t.x & 0xffff, t.y & 0xffff, t.x >> 16, t.y >> 16, t.z, t.w, step);
 }
 
 // Probes of a two-step pass: the intermediate step's values are recomputed
@@ -771,26 +793,69 @@ hipError_t step_fused(const GridView<T>& g, int step, int tile_y, int tile_z, hi
   return pml ? launch_fused<T, CI, true, 64, 8>(g, step, kz, st) : launch_fused<T, CI, false, 64, 8>(g, step, kz, st);
 }
 
+// Tile groups of a grid with a CPML, by the slabs a tile (halo included)
+// reaches: 0 neither the x nor the y slabs (z CPML code only), 1 x slabs, 2
+// y slabs, 3 both (x-y corners).  Fused tiles are 32 wide in groups 1 and 3
+// and 64 wide otherwise; two-step tiles are 60 wide.  FP64 (a diagnostic
+// precision) keeps the all-axes instantiation for every group.
 template <typename T, typename CI, int TY>
-hipError_t launch_lists(const GridView<T>& g, int step, const int4* tiles, int n_int, int n_pml, hipStream_t st) {
+hipError_t launch_lists(const GridView<T>& g, int step, const int4* tiles, const int* counts, hipStream_t st) {
   if (sizeof(CI) == 1 && g.ncls > 256) return hipErrorInvalidValue;
-  if (n_int > 0)
-    hipLaunchKernelGGL((k_fused_list<T, CI, false, 64, TY>), dim3((unsigned)n_int), dim3(64 * TY), 0, st, g,
-                       tiles, step);
-  if (n_pml > 0)
-    hipLaunchKernelGGL((k_fused_list<T, CI, true, 32, TY>), dim3((unsigned)n_pml), dim3(32 * TY), 0, st, g,
-                       tiles + n_int, step);
+  constexpr bool D = sizeof(T) == 8;
+  const int4* t = tiles;
+  if (counts[0] > 0)
+    hipLaunchKernelGGL((k_fused_list<T, CI, true, 64, TY, D ? 7 : 4>), dim3((unsigned)counts[0]), dim3(64 * TY), 0,
+                       st, g, t, step);
+  t += counts[0];
+  if (counts[1] > 0)
+    hipLaunchKernelGGL((k_fused_list<T, CI, true, 32, TY, D ? 7 : 5>), dim3((unsigned)counts[1]), dim3(32 * TY), 0,
+                       st, g, t, step);
+  t += counts[1];
+  if (counts[2] > 0)
+    hipLaunchKernelGGL((k_fused_list<T, CI, true, 64, TY, D ? 7 : 6>), dim3((unsigned)counts[2]), dim3(64 * TY), 0,
+                       st, g, t, step);
+  t += counts[2];
+  if (counts[3] > 0)
+    hipLaunchKernelGGL((k_fused_list<T, CI, true, 32, TY, 7>), dim3((unsigned)counts[3]), dim3(32 * TY), 0, st, g, t,
+                       step);
+  return hipGetLastError();
+}
+
+template <typename T, typename CI, int TY>
+hipError_t launch_lists_tb2(const GridView<T>& g, int step, const int4* tiles, const int* counts, hipStream_t st) {
+  if (sizeof(CI) == 1 && g.ncls > 256) return hipErrorInvalidValue;
+  constexpr bool D = sizeof(T) == 8;
+  const dim3 blk(64 * (TY + 4));
+  const int4* t = tiles;
+  if (counts[0] > 0)
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 4>), dim3((unsigned)counts[0]), blk, 0, st, g, t, step);
+  t += counts[0];
+  if (counts[1] > 0)
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 5>), dim3((unsigned)counts[1]), blk, 0, st, g, t, step);
+  t += counts[1];
+  if (counts[2] > 0)
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 6>), dim3((unsigned)counts[2]), blk, 0, st, g, t, step);
+  t += counts[2];
+  if (counts[3] > 0)
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, 7>), dim3((unsigned)counts[3]), blk, 0, st, g, t, step);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t lists_any(const GridView<T>& g, int cls16, int step, int ty, const int4* tiles, int n_int, int n_pml,
-                     hipStream_t st) {
+hipError_t lists_any(const GridView<T>& g, int cls16, int variant, int step, int ty, const int4* tiles,
+                     const int* counts, hipStream_t st) {
+  if (variant == 3) {
+    if (ty == 4)
+      return cls16 ? launch_lists_tb2<T, uint16_t, 4>(g, step, tiles, counts, st)
+                   : launch_lists_tb2<T, uint8_t, 4>(g, step, tiles, counts, st);
+    return cls16 ? launch_lists_tb2<T, uint16_t, 8>(g, step, tiles, counts, st)
+                 : launch_lists_tb2<T, uint8_t, 8>(g, step, tiles, counts, st);
+  }
   if (ty == 4)
-    return cls16 ? launch_lists<T, uint16_t, 4>(g, step, tiles, n_int, n_pml, st)
-                 : launch_lists<T, uint8_t, 4>(g, step, tiles, n_int, n_pml, st);
-  return cls16 ? launch_lists<T, uint16_t, 8>(g, step, tiles, n_int, n_pml, st)
-               : launch_lists<T, uint8_t, 8>(g, step, tiles, n_int, n_pml, st);
+    return cls16 ? launch_lists<T, uint16_t, 4>(g, step, tiles, counts, st)
+                 : launch_lists<T, uint8_t, 4>(g, step, tiles, counts, st);
+  return cls16 ? launch_lists<T, uint16_t, 8>(g, step, tiles, counts, st)
+               : launch_lists<T, uint8_t, 8>(g, step, tiles, counts, st);
 }
 
 template <typename T, typename CI, bool PML, int TY>
@@ -824,13 +889,14 @@ hipError_t step_any(const GridView<T>& g, int cls16, int variant, int step, int 
   return cls16 ? step_split<T, uint16_t>(g, step, st) : step_split<T, uint8_t>(g, step, st);
 }
 
-int launch_fused_lists(int prec, const void* view, int cls16, int step, int tile_y, const void* tiles, int n_int,
-                       int n_pml, void* stream) {
+int launch_lists_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, const void* tiles,
+                      const int* counts, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const int4* t = (const int4*)tiles;
   const int ty = tile_y == 4 ? 4 : 8;
-  hipError_t e = prec == 64 ? lists_any<double>(*(const GridView<double>*)view, cls16, step, ty, t, n_int, n_pml, st)
-                            : lists_any<float>(*(const GridView<float>*)view, cls16, step, ty, t, n_int, n_pml, st);
+  hipError_t e = prec == 64
+                     ? lists_any<double>(*(const GridView<double>*)view, cls16, variant, step, ty, t, counts, st)
+                     : lists_any<float>(*(const GridView<float>*)view, cls16, variant, step, ty, t, counts, st);
   return (int)e;
 }
 

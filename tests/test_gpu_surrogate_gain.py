@@ -1,0 +1,71 @@
+"""What the trained surrogate gains over the method without it.
+
+Queries are drawn from ranges 20% wider than the training ranges.  The
+ensemble answers all of them in one batched inference; queries whose nets
+disagree on the GPR peak by more than 2% go to the batched FDTD engine.  The
+same queries also run through FDTD alone, which is both the reference for the
+errors and the throughput the surrogate is compared with.  The nets are the
+committed ones (paper_2207_06908_amd/data/surrogate_weights.npz, written by
+``surrogate_run train``)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2207_06908_amd import scenarios as S
+from paper_2207_06908_amd import surrogate as U
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(U.__file__), "data", "surrogate_weights.npz")
+
+
+def _loop_vs_fdtd(n, seed, widen):
+    cases = S.draw_cases(n, seed=seed, widen=widen)
+    X = torch.from_numpy(U.features(cases)).cuda()
+    sur = U.Surrogate(n_nets=4, max_rows=8192)
+    sur.load(WEIGHTS)
+    sur.route(X[:64], 0.02)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ym, sp, ids, cnt = sur.ens.infer_route(X, 0.02)
+    e1.record()
+    torch.cuda.synchronize()
+    infer_s = e0.elapsed_time(e1) / 1e3
+    fb = ids[:int(cnt.item())].cpu().numpy()
+    pred = U.gpr_from_prediction(ym.cpu().numpy(), cases)
+
+    run = U.run_fdtd(cases)                      # FDTD alone, every query
+    ref = U.resample(run.gpr)
+    fdtd_s = run.gpu_ms / 1e3
+    answer = pred.copy()
+    answer[fb] = ref[fb]                         # fallback rows are answered by the same engine
+    pe = U.peak_error(answer, ref)
+    loop_s = infer_s + fdtd_s * fb.size / n      # fallback cases at the engine's per-case cost
+    gain = (n / loop_s) / (n / fdtd_s)
+    print(f"widen {widen}: fallback {fb.size}/{n}; peak error median {np.median(pe):.4f} "
+          f"p95 {np.percentile(pe, 95):.4f} max {pe.max():.4f}; FDTD {n / fdtd_s:.1f} cases/s, "
+          f"surrogate in the loop {n / loop_s:.1f} cases/s, gain {gain:.1f}x")
+    return pe, fb, gain
+
+
+def test_surrogate_gain_inside_the_training_ranges():
+    """Unseen cases from the training ranges: the ensemble answers nearly all
+    of them within 2% of FDTD, hundreds of times faster."""
+    pe, fb, gain = _loop_vs_fdtd(256, 2024, 0.0)
+    assert np.mean(pe <= 0.02) >= 0.99
+    assert pe.max() <= 0.03
+    assert fb.size <= 0.02 * 256
+    assert gain >= 50.0
+
+
+def test_surrogate_gain_on_the_widened_sweep():
+    """Queries from ranges 20% wider than training (the surrogate-in-the-loop
+    sweep): routing sends the queries the nets disagree on to FDTD; most of
+    the rest stay within 2%."""
+    pe, fb, gain = _loop_vs_fdtd(256, 2025, 0.1)
+    assert np.mean(pe <= 0.02) >= 0.90
+    assert fb.size <= 0.06 * 256
+    assert gain >= 15.0
