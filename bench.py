@@ -27,8 +27,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 KERNEL_SOURCES = ("paper_2207_06908_amd/csrc/fdtd_kernels.hip", "paper_2207_06908_amd/csrc/yee_update.h",
                   "paper_2207_06908_amd/csrc/fdtd_dev.h")
 MEASURED_TRAFFIC = {
-    # (source hash, kernel variant, tile_y, tile_z): bytes per launch
+    # (source hash, kernel variant, tile_y, tile_z): HBM bytes per step (all
+    # launches of the step; a two-step pass counts half)
     ("f83429f117a4ca15", "fused", 8, 32): 6.545e9,
+    ("d56d7af9ae3d765f", "tb2", 8, 64): 3.298e9,
 }
 
 
@@ -245,8 +247,9 @@ def main():
                    "coefficient_classes": g.num_classes},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "traffic_unit": "bytes per launch",
-                     "kernel": {"fused": "k_fused (one launch per step)", "tb2": "k_tb2 (one launch per two steps)",
+                     "traffic_unit": "HBM bytes per step",
+                     "kernel": {"fused": "k_fused_list (one pass per step, launched per CPML tile group)",
+                                "tb2": "k_tb2_list (one pass per two steps, launched per CPML tile group)",
                                 "split": "k_h_split + k_e_split (two launches per step)"}[vname],
                      "algorithmic_bytes_per_step": bytes_step,
                      "kernel_ms_per_step": round(kms / max(kn, 1), 5)},

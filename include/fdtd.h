@@ -138,8 +138,11 @@ size_t fdtd_workspace_bytes(fdtd_ctx* c);
  * Errors: ENOMEM, ESTATE, EDEVICE. */
 int fdtd_bind_workspace(fdtd_ctx* c, void* dev_ptr, size_t bytes);
 
-/* Select a kernel variant (FDTD_KERNEL_*) and tile parameters (0 = default).
- * Results do not depend on the choice.  Errors: EINVAL. */
+/* Select a kernel variant (FDTD_KERNEL_*) and tile parameters (0 = default):
+ * tile_y (rows per tile) in {4, 8}, or 12 for FDTD_KERNEL_TB2; tile_z
+ * (planes per z chunk) >= 0.  Grids with a CPML run the fused and two-step
+ * passes over tile lists grouped by the CPML slabs each tile reaches.
+ * Results do not depend on the choice (bitwise).  Errors: EINVAL. */
 int fdtd_set_kernel(fdtd_ctx* c, int variant, int tile_y, int tile_z);
 
 /* Advance n_steps steps, asynchronously on the stream.  Errors: ESTATE (not

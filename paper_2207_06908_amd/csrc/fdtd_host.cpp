@@ -717,8 +717,9 @@ int fdtd_bind_workspace(fdtd_ctx* c, void* dev, size_t bytes) {
 
 int fdtd_set_kernel(fdtd_ctx* c, int variant, int tile_y, int tile_z) {
   if (!c || variant < FDTD_KERNEL_AUTO || variant > FDTD_KERNEL_TB2 || tile_z < 0 ||
-      (tile_y != 0 && tile_y != 4 && tile_y != 8))
-    return fail(c, FDTD_EINVAL, "bad kernel selection (tile_y in {0, 4, 8}, tile_z >= 0)");
+      (tile_y != 0 && tile_y != 4 && tile_y != 8 && tile_y != 12) ||
+      (tile_y == 12 && variant != FDTD_KERNEL_TB2))
+    return fail(c, FDTD_EINVAL, "bad kernel selection (tile_y in {0, 4, 8}, 12 for the two-step pass; tile_z >= 0)");
   c->variant = variant;
   c->tile_y = tile_y;
   c->tile_z = tile_z;
@@ -832,7 +833,7 @@ int fdtd_step(fdtd_ctx* c, int n) {
     // grids with a CPML run the fused and two-step passes over tile lists
     const bool lists = (variant == FDTD_KERNEL_FUSED || variant == FDTD_KERNEL_TB2) && c->P.npml > 0 &&
                        c->N[0] < 65536 && c->N[1] < 65536;
-    const int lty = c->tile_y == 4 ? 4 : 8;
+    const int lty = c->tile_y == 4 ? 4 : (c->tile_y == 12 && variant == FDTD_KERNEL_TB2) ? 12 : 8;
     const int lkz = std::max(8, c->tile_z > 0 ? c->tile_z : (variant == FDTD_KERNEL_TB2 ? 64 : 32));
     if (lists) {
       int rc = ensure_tiles(c, variant, lty, lkz);

@@ -848,6 +848,9 @@ hipError_t lists_any(const GridView<T>& g, int cls16, int variant, int step, int
     if (ty == 4)
       return cls16 ? launch_lists_tb2<T, uint16_t, 4>(g, step, tiles, counts, st)
                    : launch_lists_tb2<T, uint8_t, 4>(g, step, tiles, counts, st);
+    if (ty == 12)
+      return cls16 ? launch_lists_tb2<T, uint16_t, 12>(g, step, tiles, counts, st)
+                   : launch_lists_tb2<T, uint8_t, 12>(g, step, tiles, counts, st);
     return cls16 ? launch_lists_tb2<T, uint16_t, 8>(g, step, tiles, counts, st)
                  : launch_lists_tb2<T, uint8_t, 8>(g, step, tiles, counts, st);
   }
@@ -874,6 +877,8 @@ hipError_t step_tb2(const GridView<T>& g, int step, int tile_y, int tile_z, hipS
   const bool pml = g.npml > 0;
   if (tile_y == 4)
     return pml ? launch_tb2<T, CI, true, 4>(g, step, kz, st) : launch_tb2<T, CI, false, 4>(g, step, kz, st);
+  if (tile_y == 12)
+    return pml ? launch_tb2<T, CI, true, 12>(g, step, kz, st) : launch_tb2<T, CI, false, 12>(g, step, kz, st);
   return pml ? launch_tb2<T, CI, true, 8>(g, step, kz, st) : launch_tb2<T, CI, false, 8>(g, step, kz, st);
 }
 
@@ -893,7 +898,7 @@ int launch_lists_step(int prec, const void* view, int cls16, int variant, int st
                       const int* counts, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const int4* t = (const int4*)tiles;
-  const int ty = tile_y == 4 ? 4 : 8;
+  const int ty = tile_y == 4 ? 4 : (tile_y == 12 && variant == 3) ? 12 : 8;
   hipError_t e = prec == 64
                      ? lists_any<double>(*(const GridView<double>*)view, cls16, variant, step, ty, t, counts, st)
                      : lists_any<float>(*(const GridView<float>*)view, cls16, variant, step, ty, t, counts, st);

@@ -132,13 +132,16 @@ def test_config3_subset_against_stored_oracle(fd):
         assert_probes_close(got, ref, 1e-5)
 
 
-@pytest.mark.parametrize("dims,npml", [((77, 21, 15), 4), ((130, 19, 70), 6), ((61, 9, 9), 0)])
+@pytest.mark.parametrize("dims,npml", [((77, 21, 15), 4), ((130, 19, 70), 6), ((61, 9, 9), 0),
+                                       ((150, 70, 40), 6), ((190, 45, 33), 3)])
 def test_variants_bitwise_equal(fd, dims, npml):
     """All kernel variants and tile shapes give the same bits, also when the
-    steps come in odd chunks (the two-step pass then ends with one fused step)."""
+    steps come in odd chunks (the two-step pass then ends with one fused
+    step).  The larger grids have tiles in every CPML group of the tile
+    lists (clear of the x and y slabs, x only, y only, corners)."""
     sc = _random_case(*dims, npml, seed=3, nsteps=41, n_mats=3)
     runs = [(1, 0, 0, [41]), (2, 8, 32, [41]), (2, 4, 7, [41]), (3, 8, 64, [41]), (3, 4, 5, [3, 10, 1, 27]),
-            (3, 8, 16, [2, 39])]
+            (3, 8, 16, [2, 39]), (3, 12, 64, [41]), (3, 12, 8, [5, 36])]
     outs = []
     for variant, ty, kz, chunks in runs:
         g = fd.Grid.from_params(sc.params(), precision=32)
