@@ -41,6 +41,7 @@ struct GridView {
   T* pob[3];
   unsigned pel[3];
   int pad2;
+  const T* zpl;                  // nx * ny zeros: E of the planes outside [0, nz)
   const void* cls;               // class id per node (uint8 or uint16)
   const T* ctab;                 // [ncls][K_STRIDE]
   const T* prof[3];              // per axis [P_NROW][2*npml]

@@ -72,7 +72,7 @@ struct fdtd_ctx {
   std::vector<double> term_w;
   size_t ws_bytes = 0;
   // workspace offsets (bytes from the workspace base)
-  size_t off_f = 0, off_psi[2][3] = {{0, 0, 0}, {0, 0, 0}}, off_cls = 0, off_ctab = 0, off_prof = 0;
+  size_t off_f = 0, off_psi[2][3] = {{0, 0, 0}, {0, 0, 0}}, off_zpl = 0, off_cls = 0, off_ctab = 0, off_prof = 0;
   size_t off_src_comp = 0, off_src_idx = 0, off_amp = 0, off_pr_off = 0, off_term_comp = 0;
   size_t off_term_idx = 0, off_term_w = 0, off_out = 0, psi_elems[3] = {0, 0, 0};
   std::vector<uint8_t> cls8;          // staging for 1-byte class ids
@@ -455,6 +455,7 @@ void layout(fdtd_ctx* c) {
   }
   for (int s = 0; s < 2; ++s)
     for (int u = 0; u < 3; ++u) c->off_psi[s][u] = take(4 * c->psi_elems[u] * ts);
+  c->off_zpl = take((size_t)c->N[0] * c->N[1] * ts);  // zeroed with the fields, never written
   c->off_cls = take(N * (c->cls16 ? 2 : 1));
   c->off_ctab = take((size_t)c->ncls * K_STRIDE * ts);
   c->off_prof = take(3 * (size_t)P_NROW * 2 * np * ts);
@@ -501,6 +502,7 @@ void fill_view(fdtd_ctx* c, GridView<T>& g, int in, int out) {
     g.pob[u] = np ? (T*)(w + c->off_psi[out][u]) : nullptr;
     g.pel[u] = (unsigned)c->psi_elems[u];
   }
+  g.zpl = (const T*)(w + c->off_zpl);
   g.cls = w + c->off_cls;
   g.ctab = (const T*)(w + c->off_ctab);
   for (int u = 0; u < 3; ++u) g.prof[u] = (const T*)(w + c->off_prof) + (size_t)u * P_NROW * 2 * np;
@@ -532,7 +534,7 @@ int upload(fdtd_ctx* c) {
     for (int out = 0; out < 2; ++out) fill_view<T>(c, view_of<T>(c, in, out), in, out);
   const GridView<T>& g = view_of<T>(c, 0, 0);
   hipStream_t st = c->stream;
-  // zero fields and CPML state (both sets)
+  // zero fields, CPML state (both sets) and the zero plane
   hipError_t e = hipMemsetAsync(c->ws + c->off_f, 0, c->off_cls - c->off_f, st);
   if (e != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
   const void* cls_src = c->cls_id.data();

@@ -504,21 +504,47 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
   const int ly = PML && (AX & 2) && dom ? slab_pos(y, ny, g.npml) : -1;
   constexpr bool PZ = PML && (AX & 4);
 
-  auto ld_e = [&](bool ok, int k, T e[3]) {
-    const bool in = ok && k >= 0 && k < nz;
-    const unsigned n = n0 + sxy * (unsigned)(in ? k : 0);
-    e[0] = in ? ldg(g.fi[0], n) : T(0);
-    e[1] = in ? ldg(g.fi[1], n) : T(0);
-    e[2] = in ? ldg(g.fi[2], n) : T(0);
+  // Loads are unconditional, from uniform plane bases and the thread's
+  // column offset n0 (0 for points outside the grid): E planes outside
+  // [0, nz) read the zero plane, H and class planes are clamped (those values
+  // are never used).  E of points outside the grid is zeroed where it enters
+  // LDS.  No load then sits behind a branch, and none waits on a select.
+  // The x- and y-slab instantiations (AX 5, 6) keep predicated loads, which
+  // need fewer registers there.
+  constexpr bool UNC = AX == 4 || AX == 7;
+  auto ld_e = [&](int k, T e[3]) {
+    const bool in = k >= 0 && k < nz;
+    if (UNC) {
+      const size_t po = (size_t)sxy * (size_t)(in ? k : 0);
+      e[0] = ldg(in ? g.fi[0] + po : g.zpl, n0);
+      e[1] = ldg(in ? g.fi[1] + po : g.zpl, n0);
+      e[2] = ldg(in ? g.fi[2] + po : g.zpl, n0);
+    } else {
+      const bool ok = dom && in;
+      const unsigned n = n0 + sxy * (unsigned)(ok ? k : 0);
+      e[0] = ok ? ldg(g.fi[0], n) : T(0);
+      e[1] = ok ? ldg(g.fi[1], n) : T(0);
+      e[2] = ok ? ldg(g.fi[2], n) : T(0);
+    }
   };
-  auto ld_h = [&](bool ok, int k, T h[3]) {
-    const bool in = ok && k >= 0 && k < nz;
-    const unsigned n = n0 + sxy * (unsigned)(in ? k : 0);
-    h[0] = in ? ldg(g.fi[3], n) : T(0);
-    h[1] = in ? ldg(g.fi[4], n) : T(0);
-    h[2] = in ? ldg(g.fi[5], n) : T(0);
+  auto ld_h = [&](int k, T h[3]) {
+    if (UNC) {
+      const size_t po = (size_t)sxy * (size_t)min(max(k, 0), nz - 1);
+      h[0] = ldg(g.fi[3] + po, n0);
+      h[1] = ldg(g.fi[4] + po, n0);
+      h[2] = ldg(g.fi[5] + po, n0);
+    } else {
+      const bool ok = inA && k >= 0 && k < nz;
+      const unsigned n = n0 + sxy * (unsigned)(ok ? k : 0);
+      h[0] = ok ? ldg(g.fi[3], n) : T(0);
+      h[1] = ok ? ldg(g.fi[4], n) : T(0);
+      h[2] = ok ? ldg(g.fi[5], n) : T(0);
+    }
   };
-  auto ld_c = [&](bool ok, int k) -> int { return (ok && k >= 0 && k < nz) ? (int)ldg(cls, n0 + sxy * (unsigned)k) : 0; };
+  auto ld_c = [&](int k) -> int {
+    if (UNC) return (int)ldg(cls + (size_t)sxy * (size_t)min(max(k, 0), nz - 1), n0);
+    return (inA && k >= 0 && k < nz) ? (int)ldg(cls, n0 + sxy * (unsigned)k) : 0;
+  };
 
   // pipeline registers of this thread's point
   T e0c[3], e0n[3], h0c[3];
@@ -528,19 +554,19 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
   T psh[3][2], pse[3][2];          // CPML state after step n+1, plane k-1
   for (int a = 0; a < 3; ++a) psh[a][0] = psh[a][1] = pse[a][0] = pse[a][1] = T(0);
   const int kb = k0 - 2;
-  ld_e(dom, kb, e0c);
-  ld_e(dom, kb + 1, e0n);
-  ld_h(inA, kb, h0c);
-  int cc = ld_c(inA, kb), cp = 0;
+  ld_e(kb, e0c);
+  ld_e(kb + 1, e0n);
+  ld_h(kb, h0c);
+  int cc = ld_c(kb), cp = 0;
 
   for (int k = kb; k <= k1; ++k) {
     // prefetch: E^n of plane k+2, H^{n-1/2} and classes of plane k+1
     T e0f[3], h0f[3];
-    ld_e(dom, k + 2, e0f);
-    ld_h(inA, k + 1, h0f);
-    const int cf1 = ld_c(inA, k + 1);
+    ld_e(k + 2, e0f);
+    ld_h(k + 1, h0f);
+    const int cf1 = ld_c(k + 1);
     const bool kin = k >= 0 && k < nz;
-    for (int c = 0; c < 3; ++c) sm.se0[c][v][u] = e0c[c];
+    for (int c = 0; c < 3; ++c) sm.se0[c][v][u] = dom ? e0c[c] : T(0);
     __syncthreads();
     // A: H^{n+1/2}, plane k
     T h1c[3] = {T(0), T(0), T(0)};
