@@ -83,8 +83,10 @@ int launch_step(int prec, const void* view, int cls16, int variant, int step, in
 //              64 x tile_y in groups 0 and 2;
 //   variant 3: (i0 | iw << 16, j0 | jh << 16, k0, k1) with iw <= 60,
 //              jh <= tile_y.
+// Group 0 runs on `stream`, groups 1-3 on `stream2` (the caller orders the
+// two streams around the call; they write disjoint tiles).
 int launch_lists_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, const void* tiles,
-                      const int* counts, void* stream);
+                      const int* counts, void* stream, void* stream2);
 // Record the probes of step `step` from the view's output set.
 int launch_probes(int prec, const void* view, int step, void* stream);
 

@@ -81,6 +81,10 @@ struct fdtd_ctx {
   size_t off_tiles = 0, max_tiles = 0;
   std::vector<int> tl;
   int tl_cnt[4] = {0, 0, 0, 0}, tl_var = -1, tl_ty = -1, tl_kz = -1;
+  // the CPML tile groups run on a second stream, concurrently with the
+  // clear tiles: fork and join events around each pass
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   // bound state
   char* ws = nullptr;
@@ -779,7 +783,7 @@ int ensure_tiles(fdtd_ctx* c, int variant, int ty, int kz) {
   // The CPML groups hold few tiles; shorter chunks give their launches
   // enough blocks to fill the device.
   std::vector<Seg> zs[2];
-  const int kzp = std::max(8, kz / 4);
+  const int kzp = std::max(8, tb2 ? kz / 2 : kz / 4);
   for (int z = 0; z < nz; z += kz) zs[0].push_back({z, std::min(z + kz, nz), true});
   for (int z = 0; z < nz; z += kzp) zs[1].push_back({z, std::min(z + kzp, nz), true});
   std::vector<int> grp[4];
@@ -840,6 +844,12 @@ int fdtd_step(fdtd_ctx* c, int n) {
     if (lists) {
       int rc = ensure_tiles(c, variant, lty, lkz);
       if (rc) return rc;
+      if (!c->aux) {
+        hipError_t he = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+        if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+        if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+        if (he != hipSuccess) return hip_fail(c, he, "second stream");
+      }
     }
     int slot = -1;
     if (c->timing) {
@@ -858,8 +868,16 @@ int fdtd_step(fdtd_ctx* c, int n) {
     }
     int e;
     if (lists) {
+      hipError_t he = hipEventRecord(c->ev_fork, c->stream);
+      if (he == hipSuccess) he = hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+      if (he != hipSuccess) return hip_fail(c, he, "stream fork");
       e = launch_lists_step(c->P.precision, view, c->cls16, variant, (int)c->steps_done, lty, c->ws + c->off_tiles,
-                            c->tl_cnt, (void*)c->stream);
+                            c->tl_cnt, (void*)c->stream, (void*)c->aux);
+      if (!e) {
+        he = hipEventRecord(c->ev_join, c->aux);
+        if (he == hipSuccess) he = hipStreamWaitEvent(c->stream, c->ev_join, 0);
+        if (he != hipSuccess) return hip_fail(c, he, "stream join");
+      }
     } else {
       e = launch_step(c->P.precision, view, c->cls16, variant, (int)c->steps_done, c->tile_y, c->tile_z,
                       (void*)c->stream);
@@ -1325,6 +1343,10 @@ void fdtd_batch_destroy(fdtd_batch* b) {
 
 void fdtd_destroy(fdtd_ctx* c) {
   if (!c) return;
+  if (c->aux) (void)hipStreamSynchronize(c->aux);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   for (int q = 0; q < fdtd_ctx::kRing; ++q) {
     if (c->ev0[q]) (void)hipEventDestroy(c->ev0[q]);
     if (c->ev1[q]) (void)hipEventDestroy(c->ev1[q]);

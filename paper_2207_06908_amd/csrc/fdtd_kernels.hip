@@ -825,7 +825,8 @@ hipError_t step_fused(const GridView<T>& g, int step, int tile_y, int tile_z, hi
 // and 64 wide otherwise; two-step tiles are 60 wide.  FP64 (a diagnostic
 // precision) keeps the all-axes instantiation for every group.
 template <typename T, typename CI, int TY>
-hipError_t launch_lists(const GridView<T>& g, int step, const int4* tiles, const int* counts, hipStream_t st) {
+hipError_t launch_lists(const GridView<T>& g, int step, const int4* tiles, const int* counts, hipStream_t st,
+                        hipStream_t st2) {
   if (sizeof(CI) == 1 && g.ncls > 256) return hipErrorInvalidValue;
   constexpr bool D = sizeof(T) == 8;
   const int4* t = tiles;
@@ -835,20 +836,21 @@ hipError_t launch_lists(const GridView<T>& g, int step, const int4* tiles, const
   t += counts[0];
   if (counts[1] > 0)
     hipLaunchKernelGGL((k_fused_list<T, CI, true, 32, TY, D ? 7 : 5>), dim3((unsigned)counts[1]), dim3(32 * TY), 0,
-                       st, g, t, step);
+                       st2, g, t, step);
   t += counts[1];
   if (counts[2] > 0)
     hipLaunchKernelGGL((k_fused_list<T, CI, true, 64, TY, D ? 7 : 6>), dim3((unsigned)counts[2]), dim3(64 * TY), 0,
-                       st, g, t, step);
+                       st2, g, t, step);
   t += counts[2];
   if (counts[3] > 0)
-    hipLaunchKernelGGL((k_fused_list<T, CI, true, 32, TY, 7>), dim3((unsigned)counts[3]), dim3(32 * TY), 0, st, g, t,
+    hipLaunchKernelGGL((k_fused_list<T, CI, true, 32, TY, 7>), dim3((unsigned)counts[3]), dim3(32 * TY), 0, st2, g, t,
                        step);
   return hipGetLastError();
 }
 
 template <typename T, typename CI, int TY>
-hipError_t launch_lists_tb2(const GridView<T>& g, int step, const int4* tiles, const int* counts, hipStream_t st) {
+hipError_t launch_lists_tb2(const GridView<T>& g, int step, const int4* tiles, const int* counts, hipStream_t st,
+                            hipStream_t st2) {
   if (sizeof(CI) == 1 && g.ncls > 256) return hipErrorInvalidValue;
   constexpr bool D = sizeof(T) == 8;
   const dim3 blk(64 * (TY + 4));
@@ -857,34 +859,34 @@ hipError_t launch_lists_tb2(const GridView<T>& g, int step, const int4* tiles, c
     hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 4>), dim3((unsigned)counts[0]), blk, 0, st, g, t, step);
   t += counts[0];
   if (counts[1] > 0)
-    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 5>), dim3((unsigned)counts[1]), blk, 0, st, g, t, step);
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 5>), dim3((unsigned)counts[1]), blk, 0, st2, g, t, step);
   t += counts[1];
   if (counts[2] > 0)
-    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 6>), dim3((unsigned)counts[2]), blk, 0, st, g, t, step);
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 6>), dim3((unsigned)counts[2]), blk, 0, st2, g, t, step);
   t += counts[2];
   if (counts[3] > 0)
-    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, 7>), dim3((unsigned)counts[3]), blk, 0, st, g, t, step);
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, 7>), dim3((unsigned)counts[3]), blk, 0, st2, g, t, step);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t lists_any(const GridView<T>& g, int cls16, int variant, int step, int ty, const int4* tiles,
-                     const int* counts, hipStream_t st) {
+                     const int* counts, hipStream_t st, hipStream_t st2) {
   if (variant == 3) {
     if (ty == 4)
-      return cls16 ? launch_lists_tb2<T, uint16_t, 4>(g, step, tiles, counts, st)
-                   : launch_lists_tb2<T, uint8_t, 4>(g, step, tiles, counts, st);
+      return cls16 ? launch_lists_tb2<T, uint16_t, 4>(g, step, tiles, counts, st, st2)
+                   : launch_lists_tb2<T, uint8_t, 4>(g, step, tiles, counts, st, st2);
     if (ty == 12)
-      return cls16 ? launch_lists_tb2<T, uint16_t, 12>(g, step, tiles, counts, st)
-                   : launch_lists_tb2<T, uint8_t, 12>(g, step, tiles, counts, st);
-    return cls16 ? launch_lists_tb2<T, uint16_t, 8>(g, step, tiles, counts, st)
-                 : launch_lists_tb2<T, uint8_t, 8>(g, step, tiles, counts, st);
+      return cls16 ? launch_lists_tb2<T, uint16_t, 12>(g, step, tiles, counts, st, st2)
+                   : launch_lists_tb2<T, uint8_t, 12>(g, step, tiles, counts, st, st2);
+    return cls16 ? launch_lists_tb2<T, uint16_t, 8>(g, step, tiles, counts, st, st2)
+                 : launch_lists_tb2<T, uint8_t, 8>(g, step, tiles, counts, st, st2);
   }
   if (ty == 4)
-    return cls16 ? launch_lists<T, uint16_t, 4>(g, step, tiles, counts, st)
-                 : launch_lists<T, uint8_t, 4>(g, step, tiles, counts, st);
-  return cls16 ? launch_lists<T, uint16_t, 8>(g, step, tiles, counts, st)
-               : launch_lists<T, uint8_t, 8>(g, step, tiles, counts, st);
+    return cls16 ? launch_lists<T, uint16_t, 4>(g, step, tiles, counts, st, st2)
+                 : launch_lists<T, uint8_t, 4>(g, step, tiles, counts, st, st2);
+  return cls16 ? launch_lists<T, uint16_t, 8>(g, step, tiles, counts, st, st2)
+               : launch_lists<T, uint8_t, 8>(g, step, tiles, counts, st, st2);
 }
 
 template <typename T, typename CI, bool PML, int TY>
@@ -921,13 +923,14 @@ hipError_t step_any(const GridView<T>& g, int cls16, int variant, int step, int 
 }
 
 int launch_lists_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, const void* tiles,
-                      const int* counts, void* stream) {
-  hipStream_t st = (hipStream_t)stream;
+                      const int* counts, void* stream, void* stream2) {
+  hipStream_t st = (hipStream_t)stream, st2 = (hipStream_t)stream2;
   const int4* t = (const int4*)tiles;
   const int ty = tile_y == 4 ? 4 : (tile_y == 12 && variant == 3) ? 12 : 8;
-  hipError_t e = prec == 64
-                     ? lists_any<double>(*(const GridView<double>*)view, cls16, variant, step, ty, t, counts, st)
-                     : lists_any<float>(*(const GridView<float>*)view, cls16, variant, step, ty, t, counts, st);
+  hipError_t e = prec == 64 ? lists_any<double>(*(const GridView<double>*)view, cls16, variant, step, ty, t, counts,
+                                                st, st2)
+                            : lists_any<float>(*(const GridView<float>*)view, cls16, variant, step, ty, t, counts,
+                                               st, st2);
   return (int)e;
 }
 
