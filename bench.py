@@ -31,6 +31,7 @@ MEASURED_TRAFFIC = {
     # launches of the step; a two-step pass counts half)
     ("f83429f117a4ca15", "fused", 8, 32): 6.545e9,
     ("d56d7af9ae3d765f", "tb2", 8, 64): 3.298e9,
+    ("1b1a56f3d67cc8d6", "tb2", 8, 32): 3.508e9,
 }
 
 
