@@ -199,7 +199,11 @@ size_t fdtd_batch_workspace_bytes(const fdtd_batch* b);
 int fdtd_batch_bind_workspace(fdtd_batch* b, void* dev_ptr, size_t bytes);
 /* Tile shape (tile_x, tile_y) in {(32, 8), (32, 16), (64, 8)}, z-chunk
  * tile_z in [8, 4096]; graph_steps (even, 0 = off): steps captured in one
- * HIP graph and replayed.  Default (32, 8, 32, 0).  Errors: EINVAL. */
+ * HIP graph and replayed.  (60, 8) selects two-step passes (two time steps
+ * per launch sequence, tiles grouped by the CPML slabs they reach) with
+ * tile_z in [16, 4096] and graph_steps a multiple of 4; an odd step count
+ * ends with one single-step launch.  Results do not depend on the choice.
+ * Default (32, 8, 32, 0).  Errors: EINVAL. */
 int fdtd_batch_set_kernel(fdtd_batch* b, int tile_x, int tile_y, int tile_z, int graph_steps);
 /* Advance every grid n_steps steps.  Errors: ESTATE, ERANGE (beyond the
  * smallest max_steps), EDEVICE. */

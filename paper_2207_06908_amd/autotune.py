@@ -23,8 +23,9 @@ GRID_CANDIDATES: List[Tuple[int, int, int]] = (
     + [(fdtd.KERNEL_FUSED, ty, tz) for ty in (4, 8) for tz in (16, 32, 64)]
     + [(fdtd.KERNEL_TB2, 8, tz) for tz in (24, 32, 48, 64)] + [(fdtd.KERNEL_TB2, 12, 32)]
 )
-BATCH_CANDIDATES: List[Tuple[int, int, int]] = [
-    (tx, ty, tz) for (tx, ty) in ((32, 8), (32, 16), (64, 8)) for tz in (16, 32, 64)]
+BATCH_CANDIDATES: List[Tuple[int, int, int]] = (
+    [(tx, ty, tz) for (tx, ty) in ((32, 8), (32, 16), (64, 8)) for tz in (16, 32, 64)]
+    + [(60, 8, tz) for tz in (16, 32, 64)])
 
 
 def tuning_steps(batch: bool = False, warmup: int = 4, steps: int = None) -> int:

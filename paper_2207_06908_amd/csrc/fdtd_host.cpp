@@ -1031,6 +1031,14 @@ struct fdtd_batch {
   size_t off_views = 0, off_pviews = 0, off_tiles = 0, off_plist = 0, off_step = 0, ws_bytes = 0;
   std::vector<int> tiles;             // int4 entries (grid, i0, j0, k0 | kz << 16)
   std::vector<int> plist;             // int2 entries (grid, probe)
+  // two-step passes (set_kernel with tile_x 60): CPML-grouped tile list of
+  // (grid, i0 | iw << 16, j0 | jh << 16, k0 | kz << 16); an odd remainder of
+  // steps takes one fused step over `tiles` (32 x 8)
+  bool tb2 = false;
+  int tb2_kz = 32;
+  std::vector<int> tiles2;
+  int tcnt[4] = {0, 0, 0, 0};
+  size_t off_tiles2 = 0;
   char* ws = nullptr;
   int cur = 0;
   long long steps_done = 0;
@@ -1078,6 +1086,36 @@ void build_tiles(fdtd_batch* b) {
   }
 }
 
+// Two-step tile list of every grid, grouped by the CPML slabs the tiles reach
+// (as for a single grid), larger grids first within each group.
+void build_tiles_tb2(fdtd_batch* b) {
+  std::vector<int> order(b->grids.size());
+  for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) { return b->grids[a]->ncell > b->grids[c]->ncell; });
+  std::vector<int> grp[4];
+  const int kz = b->tb2_kz, kzp = std::max(8, kz / 2);
+  for (int g : order) {
+    const fdtd_ctx* c = b->grids[g];
+    const int np = c->P.npml, nz = c->N[2];
+    const std::vector<Seg> xs = segments_tb2(c->N[0], np, 60, 2);
+    const std::vector<Seg> ys = segments_tb2(c->N[1], np, 8, 2);
+    for (const Seg& y : ys)
+      for (const Seg& x : xs) {
+        const int q = (x.in ? 0 : 1) | (y.in ? 0 : 2);
+        const int d = q == 0 ? kz : kzp;
+        for (int z = 0; z < nz; z += d)
+          grp[q].insert(grp[q].end(), {g, x.a | (x.b - x.a) << 16, y.a | (y.b - y.a) << 16,
+                                       z | (std::min(d, nz - z) << 16)});
+      }
+  }
+  b->tiles2.clear();
+  for (int q = 0; q < 4; ++q) {
+    b->tiles2.insert(b->tiles2.end(), grp[q].begin(), grp[q].end());
+    b->tcnt[q] = (int)(grp[q].size() / 4);
+  }
+}
+
 template <typename T>
 int batch_upload(fdtd_batch* b) {
   const size_t nv = b->grids.size();
@@ -1108,6 +1146,11 @@ int upload_tiles(fdtd_batch* b) {
   build_tiles(b);
   hipError_t e = hipMemcpyAsync(b->ws + b->off_tiles, b->tiles.data(), b->tiles.size() * sizeof(int),
                                 hipMemcpyHostToDevice, b->stream);
+  if (b->tb2 && e == hipSuccess) {
+    build_tiles_tb2(b);
+    e = hipMemcpyAsync(b->ws + b->off_tiles2, b->tiles2.data(), b->tiles2.size() * sizeof(int),
+                       hipMemcpyHostToDevice, b->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, std::string("tile upload: ") + hipGetErrorString(e));
   b->tiles_dirty = false;
@@ -1119,6 +1162,24 @@ size_t max_tiles(const fdtd_batch* b) {  // upper bound over the allowed tile sh
   for (const fdtd_ctx* c : b->grids)
     n += (size_t)((c->N[0] + 31) / 32) * ((c->N[1] + 7) / 8) * ((c->N[2] + 7) / 8);
   return n;
+}
+
+size_t max_tiles_tb2(const fdtd_batch* b) {  // 60 x 8 pieces (3 extra per axis), chunks of >= 8 planes
+  size_t n = 0;
+  for (const fdtd_ctx* c : b->grids) n += (size_t)(c->N[0] / 60 + 3) * (c->N[1] / 8 + 3) * (c->N[2] / 8 + 1);
+  return n;
+}
+
+// One two-step pass (kernels + probes of both steps) on stream `st`, steps
+// *d_step + off and + 1; parity p selects the view tables.
+int batch_launch_pass(fdtd_batch* b, hipStream_t st, int p, int off) {
+  const size_t nv = b->grids.size();
+  const size_t vb = view_bytes(b->prec);
+  const int* d_step = (const int*)(b->ws + b->off_step);
+  int e = launch_batch_pass_tb2(b->prec, b->cls16, b->ws + b->off_views + p * nv * vb, b->ws + b->off_tiles2,
+                                b->tcnt, b->ws + b->off_plist, (int)(b->plist.size() / 2), d_step, off, (void*)st);
+  if (e) return bfail(b, FDTD_EDEVICE, std::string("batch pass: ") + hipGetErrorString((hipError_t)e));
+  return FDTD_OK;
 }
 
 // Launch one step (kernel + probes) on stream `st` with step offset `off`
@@ -1184,6 +1245,7 @@ int fdtd_batch_create(fdtd_ctx* const* grids, int n, void* hip_stream, fdtd_batc
   b->off_views = take(2 * b->grids.size() * view_bytes(b->prec));
   b->off_pviews = take(2 * b->grids.size() * view_bytes(b->prec));
   b->off_tiles = take(max_tiles(b) * 4 * sizeof(int));
+  b->off_tiles2 = take(max_tiles_tb2(b) * 4 * sizeof(int));
   b->off_plist = take(b->plist.size() * sizeof(int) + 8);
   b->off_step = take(sizeof(int));
   b->ws_bytes = o;
@@ -1213,9 +1275,23 @@ int fdtd_batch_bind_workspace(fdtd_batch* b, void* dev, size_t bytes) {
 
 int fdtd_batch_set_kernel(fdtd_batch* b, int tile_x, int tile_y, int tile_z, int graph_steps) {
   if (!b) return FDTD_EINVAL;
+  if (tile_x == 60) {  // two-step passes
+    if (tile_y != 8 || tile_z < 16 || tile_z > 4096 || graph_steps < 0 || (graph_steps % 4))
+      return bfail(b, FDTD_EINVAL, "two-step tiles (60, 8), tile_z in [16, 4096], graph_steps a multiple of 4");
+    b->tb2 = true;
+    b->tb2_kz = tile_z;
+    b->tx = 32;
+    b->ty = 8;
+    b->kz = 32;
+    b->graph_steps = graph_steps;
+    b->tiles_dirty = true;
+    drop_graph(b);
+    return FDTD_OK;
+  }
   const bool ok = (tile_x == 32 && (tile_y == 8 || tile_y == 16)) || (tile_x == 64 && tile_y == 8);
   if (!ok || tile_z < 8 || tile_z > 4096 || graph_steps < 0 || (graph_steps & 1))
-    return bfail(b, FDTD_EINVAL, "tiles (32, 8|16) or (64, 8), tile_z in [8, 4096], even graph_steps");
+    return bfail(b, FDTD_EINVAL, "tiles (32, 8|16), (64, 8) or (60, 8), tile_z in [8, 4096], even graph_steps");
+  b->tb2 = false;
   b->tx = tile_x;
   b->ty = tile_y;
   b->kz = tile_z;
@@ -1255,7 +1331,10 @@ int fdtd_batch_run(fdtd_batch* b, int n) {
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
         int rc = FDTD_OK;
-        for (int t = 0; t < G && rc == FDTD_OK; ++t) rc = batch_launch_step(b, cs, t & 1, t);
+        if (b->tb2)
+          for (int t = 0; t < G / 2 && rc == FDTD_OK; ++t) rc = batch_launch_pass(b, cs, t & 1, 2 * t);
+        else
+          for (int t = 0; t < G && rc == FDTD_OK; ++t) rc = batch_launch_step(b, cs, t & 1, t);
         if (rc == FDTD_OK && launch_add((int*)(b->ws + b->off_step), G, (void*)cs))
           rc = bfail(b, FDTD_EDEVICE, "capture: counter");
         hipGraph_t gr = nullptr;
@@ -1272,12 +1351,13 @@ int fdtd_batch_run(fdtd_batch* b, int n) {
       b->steps_done += G;
       continue;
     }
-    int rc = batch_launch_step(b, b->stream, b->cur, 0);
+    const int adv = (b->tb2 && left >= 2) ? 2 : 1;
+    int rc = adv == 2 ? batch_launch_pass(b, b->stream, b->cur, 0) : batch_launch_step(b, b->stream, b->cur, 0);
     if (rc) return rc;
-    if (launch_add((int*)(b->ws + b->off_step), 1, (void*)b->stream)) return bfail(b, FDTD_EDEVICE, "counter");
+    if (launch_add((int*)(b->ws + b->off_step), adv, (void*)b->stream)) return bfail(b, FDTD_EDEVICE, "counter");
     b->cur ^= 1;
-    ++b->steps_done;
-    --left;
+    b->steps_done += adv;
+    left -= adv;
   }
   if (b->timing) {
     float ms = 0;

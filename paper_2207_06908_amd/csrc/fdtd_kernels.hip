@@ -710,11 +710,10 @@ __device__ __forceinline__ void e1_at(const GridView<T>& g, int x, int y, int k,
   e_core<T, PML>(g, l, n, cf, h[0], h[1], h[2], hj[0], hk[0], hi[1], hk[1], hi[2], hj[2], eold, step, ps, e);
 }
 
+// Probe p of a two-step pass, one wave: samples `step` (recomputed) and
+// `step` + 1 (read).
 template <typename T, typename CI, bool PML>
-__global__ __launch_bounds__(256) void k_probes_tb2(GridView<T> g, int step) {
-  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (p >= g.n_probe) return;  // uniform per wave
+__device__ __forceinline__ void probe_tb2(const GridView<T>& g, int p, int step, int lane) {
   double a1 = 0.0, a2 = 0.0;
   for (int t = g.pr_off[p] + lane; t < g.pr_off[p + 1]; t += 64) {
     const int c = g.term_comp[t];
@@ -737,6 +736,39 @@ __global__ __launch_bounds__(256) void k_probes_tb2(GridView<T> g, int step) {
     g.pr_out[(long long)p * g.max_steps + step] = a1;
     g.pr_out[(long long)p * g.max_steps + step + 1] = a2;
   }
+}
+
+template <typename T, typename CI, bool PML>
+__global__ __launch_bounds__(256) void k_probes_tb2(GridView<T> g, int step) {
+  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= g.n_probe) return;  // uniform per wave
+  probe_tb2<T, CI, PML>(g, p, step, threadIdx.x & 63);
+}
+
+// Batched two-step probes: entry q of the list is (grid, probe).
+template <typename T, typename CI>
+__global__ __launch_bounds__(256) void k_probes_tb2_batch(const GridView<T>* __restrict__ views,
+                                                         const int2* __restrict__ plist, int n,
+                                                         const int* __restrict__ d_step, int offset) {
+  const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= n) return;  // uniform per wave
+  const int2 e = plist[q];
+  probe_tb2<T, CI, true>(views[e.x], e.y, *d_step + offset, threadIdx.x & 63);
+}
+
+// Batched two-step pass: tile (grid, i0 | iw << 16, j0 | jh << 16,
+// k0 | kz << 16) per block; step index *d_step + offset.
+template <typename T, typename CI, int TY, int AX>
+__global__ __launch_bounds__(64 * (TY + 4), (AX == 7 ? 1 : 6)) void k_tb2_batch(const GridView<T>* __restrict__ views,
+                                                                               const int4* __restrict__ tiles,
+                                                                               const int* __restrict__ d_step,
+                                                                               int offset) {
+  __shared__ TB2Smem<T, TY> sm;
+  const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+  const GridView<T>& g = views[t.x];
+  const int k0 = t.w & 0xffff;
+  tb2_tile<T, CI, true, TY, AX>(g, sm, t.y & 0xffff, t.z & 0xffff, t.y >> 16, t.z >> 16, k0, k0 + (t.w >> 16),
+                                *d_step + offset);
 }
 
 // ---------------------------------------------------------------------------
@@ -1025,6 +1057,60 @@ int launch_batch_probes(int prec, const void* views, const void* plist, int n, c
   else
     hipLaunchKernelGGL((k_probes_batch<float>), grd, blk, 0, st, (const GridView<float>*)views,
                        (const int2*)plist, n, d_step, offset);
+  return (int)hipGetLastError();
+}
+
+template <typename T, typename CI>
+hipError_t batch_pass_t(const void* views, const void* tiles, const int* counts, const int* d_step, int offset,
+                        hipStream_t st) {
+  constexpr bool D = sizeof(T) == 8;
+  const GridView<T>* v = (const GridView<T>*)views;
+  const int4* t = (const int4*)tiles;
+  const dim3 blk(64 * 12);
+  if (counts[0] > 0)
+    hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, D ? 7 : 4>), dim3((unsigned)counts[0]), blk, 0, st, v, t, d_step,
+                       offset);
+  t += counts[0];
+  if (counts[1] > 0)
+    hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, D ? 7 : 5>), dim3((unsigned)counts[1]), blk, 0, st, v, t, d_step,
+                       offset);
+  t += counts[1];
+  if (counts[2] > 0)
+    hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, D ? 7 : 6>), dim3((unsigned)counts[2]), blk, 0, st, v, t, d_step,
+                       offset);
+  t += counts[2];
+  if (counts[3] > 0)
+    hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, 7>), dim3((unsigned)counts[3]), blk, 0, st, v, t, d_step, offset);
+  return hipGetLastError();
+}
+
+int launch_batch_pass_tb2(int prec, int cls16, const void* views, const void* tiles, const int* counts,
+                          const void* plist, int n_probes, const int* d_step, int offset, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (prec == 64)
+    e = cls16 ? batch_pass_t<double, uint16_t>(views, tiles, counts, d_step, offset, st)
+              : batch_pass_t<double, uint8_t>(views, tiles, counts, d_step, offset, st);
+  else
+    e = cls16 ? batch_pass_t<float, uint16_t>(views, tiles, counts, d_step, offset, st)
+              : batch_pass_t<float, uint8_t>(views, tiles, counts, d_step, offset, st);
+  if (e != hipSuccess || n_probes <= 0) return (int)e;
+  const dim3 grd((n_probes + 3) / 4), blk(256);
+  if (prec == 64) {
+    if (cls16)
+      hipLaunchKernelGGL((k_probes_tb2_batch<double, uint16_t>), grd, blk, 0, st, (const GridView<double>*)views,
+                         (const int2*)plist, n_probes, d_step, offset);
+    else
+      hipLaunchKernelGGL((k_probes_tb2_batch<double, uint8_t>), grd, blk, 0, st, (const GridView<double>*)views,
+                         (const int2*)plist, n_probes, d_step, offset);
+  } else {
+    if (cls16)
+      hipLaunchKernelGGL((k_probes_tb2_batch<float, uint16_t>), grd, blk, 0, st, (const GridView<float>*)views,
+                         (const int2*)plist, n_probes, d_step, offset);
+    else
+      hipLaunchKernelGGL((k_probes_tb2_batch<float, uint8_t>), grd, blk, 0, st, (const GridView<float>*)views,
+                         (const int2*)plist, n_probes, d_step, offset);
+  }
   return (int)hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 """Batched engine on the GPU: many uneven grids in one launch per step.
 
 * every grid of a batch is bit-identical to the same grid run alone (the
-  solo path uses 64-wide tiles, the batch 32-wide ones);
+  solo path uses 64-wide tiles, the batch 32-wide ones or two-step passes
+  over 60 x 8 tiles);
 * replaying a captured HIP graph gives the same bits as eager launches,
   with eager work and synchronisations between replays;
 * the full 256-grid sweep (2000 steps) reproduces the stored FP64-oracle
@@ -62,7 +63,7 @@ def _batch(fd, scs, tile=(32, 8, 32), graph_steps=0, chunks=None, fields=True):
     return probes, fields
 
 
-@pytest.mark.parametrize("tile", [(32, 8, 32), (32, 16, 16), (64, 8, 64)])
+@pytest.mark.parametrize("tile", [(32, 8, 32), (32, 16, 16), (64, 8, 64), (60, 8, 32), (60, 8, 16)])
 def test_batch_bitwise_equals_solo(fd, tile):
     scs = _small_sweep()
     _say(f"batch vs solo tile={tile}: " + ", ".join(f"{s.nx}x{s.ny}x{s.nz}" for s in scs))
@@ -75,11 +76,14 @@ def test_batch_bitwise_equals_solo(fd, tile):
             assert np.array_equal(bf[gi][c], sf[c]), (gi, c)
 
 
-def test_batch_graph_replay_matches_eager(fd):
+@pytest.mark.parametrize("tile", [(32, 8, 32), (60, 8, 32)])
+def test_batch_graph_replay_matches_eager(fd, tile):
+    """(60, 8, ...) selects the two-step passes: odd chunks end with one fused
+    step, graphs hold whole passes."""
     scs = _small_sweep(n=5, steps=250)
     ep, ef = _batch(fd, scs)
     # 250 = 3 eager + 4 x 60 graph + 7 eager, in pieces with eager work between
-    gp, gf = _batch(fd, scs, graph_steps=20, chunks=[3, 60, 60, 1, 60, 59, 7])
+    gp, gf = _batch(fd, scs, tile=tile, graph_steps=20, chunks=[3, 60, 60, 1, 60, 59, 7])
     for gi in range(len(scs)):
         for k in ep[gi]:
             assert np.array_equal(ep[gi][k], gp[gi][k]), (gi, k)
@@ -87,7 +91,8 @@ def test_batch_graph_replay_matches_eager(fd):
             assert np.array_equal(ef[gi][c], gf[gi][c]), (gi, c)
 
 
-def test_full_sweep_against_stored_oracle_subset(fd):
+@pytest.mark.parametrize("tile", [(32, 8, 16), (60, 8, 32)])
+def test_full_sweep_against_stored_oracle_subset(fd, tile):
     path = os.path.join(GOLD, "config3_subset.npz")
     if not os.path.exists(path):
         pytest.skip("golden subset not generated")
@@ -95,7 +100,7 @@ def test_full_sweep_against_stored_oracle_subset(fd):
     gold = np.load(path)
     scs = S.config3()
     _say(f"full sweep: {len(scs)} grids, {sum(s.cells for s in scs)} cells, {scs[0].n_steps} steps")
-    probes, _fields = _batch(fd, scs, graph_steps=100, fields=False)
+    probes, _fields = _batch(fd, scs, tile=tile, graph_steps=100, fields=False)
     for gi in CONFIG3_SUBSET:
         sc = scs[gi]
         ref = {p[0]: gold[f"{sc.name}/{p[0]}"] for p in sc.probes}
