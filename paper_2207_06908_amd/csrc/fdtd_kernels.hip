@@ -98,7 +98,7 @@ __device__ __forceinline__ void h_core(const GridView<T>& g, const int l[3], con
 template <typename T, bool PML>
 __device__ __forceinline__ void e_core(const GridView<T>& g, const int l[3], unsigned n, const T* cf, T hx, T hy,
                                        T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j, const T eold[3],
-                                       int step, T ps[3][2], T enew[3]) {
+                                       int step, T ps[3][2], T enew[3], bool src) {
   T a_ex = hz - hz_j, b_ex = hy - hy_k;  // Ex: dHz/dy - dHy/dz
   T a_ey = hx - hx_k, b_ey = hz - hz_i;  // Ey: dHx/dz - dHz/dx
   T a_ez = hy - hy_i, b_ez = hx - hx_j;  // Ez: dHy/dx - dHx/dy
@@ -120,7 +120,9 @@ __device__ __forceinline__ void e_core(const GridView<T>& g, const int l[3], uns
   enew[0] = e_new(eold[0], cf[K_CAX], cf[K_CBX], a_ex, b_ex);
   enew[1] = e_new(eold[1], cf[K_CAY], cf[K_CBY], a_ey, b_ey);
   enew[2] = e_new(eold[2], cf[K_CAZ], cf[K_CBZ], a_ez, b_ez);
-  // ideal current sources: E -= Cb I / dx^2 (precomputed per step)
+  // ideal current sources: E -= Cb I / dx^2 (precomputed per step); src is
+  // false where the caller knows the node's column holds none
+  if (src)
   for (int s = 0; s < g.n_src; ++s) {
     if ((unsigned)g.src_idx[s] != n) continue;
     const T v = g.src_amp[(long long)s * g.max_steps + step];
@@ -129,6 +131,18 @@ __device__ __forceinline__ void e_core(const GridView<T>& g, const int l[3], uns
     enew[1] = comp == 1 ? enew[1] - v : enew[1];
     enew[2] = comp == 2 ? enew[2] - v : enew[2];
   }
+}
+
+// Whether column n0 (= x + nx*y) holds a source at any height.  The tile
+// kernels evaluate it once per tile, so that the per-plane source test, whose
+// global loads would make the wave wait for every load and store it has in
+// flight, runs only in waves that hold a source column.
+template <typename T>
+__device__ __forceinline__ bool src_column(const GridView<T>& g, unsigned n0, bool on) {
+  bool any = false;
+  if (on)
+    for (int s = 0; s < g.n_src; ++s) any |= (unsigned)g.src_idx[s] % (unsigned)g.sxy == n0;
+  return any;
 }
 
 // One-step wrappers: CPML state from the input set, written (optionally for
@@ -150,14 +164,14 @@ __device__ __forceinline__ void h_point(const GridView<T>& g, int x, int y, int 
 template <typename T, bool PML, int AX = 7>
 __device__ __forceinline__ void e_point(const GridView<T>& g, int x, int y, int k, unsigned n, const T* cf,
                                         T hx, T hy, T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j,
-                                        const T eold[3], int step, T enew[3]) {
+                                        const T eold[3], int step, T enew[3], bool src = true) {
   int l[3] = {-1, -1, -1};
   T ps[3][2];
   if (PML) {
     slabs<T, AX>(g, x, y, k, l);
     psi_load(g, 0, l, x, y, k, ps);
   }
-  e_core<T, PML>(g, l, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, ps, enew);
+  e_core<T, PML>(g, l, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, ps, enew, src);
   if (PML) psi_store(g, 0, l, x, y, k, ps);
 }
 
@@ -281,6 +295,7 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
   const int i = i0 + tx, j = j0 + ty;
   const bool own = i < nx && j < ny;
   const unsigned n0 = own ? (unsigned)i + (unsigned)nx * (unsigned)j : 0u;  // + sxy * k
+  const bool srcc = src_column(g, n0, own);
   // E halo point (threads NT-NHE .. NT-1)
   int er = 0, ec = 0;
   bool eh = false;
@@ -393,7 +408,7 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
       const unsigned n = n0 + sxy * (unsigned)k;
       T e[3];
       e_point<T, PML, AX>(g, i, j, k, n, coef(cls_cur), hown[0], hown[1], hown[2], sh[0][ty][tx + 1], hm[0],
-                      sh[1][ty + 1][tx], hm[1], sh[2][ty + 1][tx], sh[2][ty][tx + 1], ecur, step, e);
+                      sh[1][ty + 1][tx], hm[1], sh[2][ty + 1][tx], sh[2][ty][tx + 1], ecur, step, e, srcc);
       stg(g.fo[0], n, e[0]);
       stg(g.fo[1], n, e[1]);
       stg(g.fo[2], n, e[2]);
@@ -503,6 +518,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
   const int lx = PML && (AX & 1) && dom ? slab_pos(x, nx, g.npml) : -1;
   const int ly = PML && (AX & 2) && dom ? slab_pos(y, ny, g.npml) : -1;
   constexpr bool PZ = PML && (AX & 4);
+  const bool srcc = src_column(g, n0, inB);
 
   // Loads are unconditional, from uniform plane bases and the thread's
   // column offset n0 (0 for points outside the grid): E planes outside
@@ -559,23 +575,65 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
   ld_h(kb, h0c);
   int cc = ld_c(kb), cp = 0;
 
+  // The outputs of plane k-1 are written at the top of the next iteration,
+  // ahead of its prefetch: the vector-memory counter retires in order, so a
+  // wait for the prefetched values then never has to wait for stores issued
+  // after them.
+  T e2[3] = {T(0), T(0), T(0)};
+  T h2z = T(0);
+  unsigned nst = 0;
+  bool pend = false;
+  // (The x- and y-slab instantiations store at once: they have no registers
+  // to spare under their cap.)
+  constexpr bool DEFER = UNC && sizeof(T) == 4;
+  auto flush = [&]() {
+    if (DEFER && pend) {
+      stg(g.fo[0], nst, e2[0]);
+      stg(g.fo[1], nst, e2[1]);
+      stg(g.fo[2], nst, e2[2]);
+      stg(g.fo[3], nst, h2p[0]);
+      stg(g.fo[4], nst, h2p[1]);
+      stg(g.fo[5], nst, h2z);
+    }
+  };
+
+  // Let the prologue's loads land before the loop.  Otherwise the compiler,
+  // which merges the loop entry with the back edge, places the wait for them
+  // after the stores at the top of every iteration and so waits for those
+  // stores as well.  (vmcnt 0, expcnt and lgkmcnt unconstrained)
+  __builtin_amdgcn_s_waitcnt(0x0F70);
   for (int k = kb; k <= k1; ++k) {
-    // prefetch: E^n of plane k+2, H^{n-1/2} and classes of plane k+1
+    flush();
+    // prefetch: classes and H^{n-1/2} of plane k+1, E^n of plane k+2 (the
+    // classes first: the end of the iteration then waits for all of it)
     T e0f[3], h0f[3];
+    const int cf1 = ld_c(k + 1);
     ld_e(k + 2, e0f);
     ld_h(k + 1, h0f);
-    const int cf1 = ld_c(k + 1);
     const bool kin = k >= 0 && k < nz;
     for (int c = 0; c < 3; ++c) sm.se0[c][v][u] = dom ? e0c[c] : T(0);
     __syncthreads();
     // A: H^{n+1/2}, plane k
     T h1c[3] = {T(0), T(0), T(0)};
     T pshn[3][2];
+    // The z-slab planes take their own branch (lz is uniform), so that the
+    // CPML state loaded there is consumed inside it and no wait for it is
+    // left at the end of the iteration, where it would also wait for the
+    // prefetch and the stores.
+    const int lz = PZ ? slab_pos(k, nz, g.npml) : -1;
     if (inA && kin) {
-      int l[3] = {lx, ly, PZ ? slab_pos(k, nz, g.npml) : -1};
-      if (PML) psi_load(g, 1, l, x, y, k, pshn);
-      h_core<T, PML>(g, l, coef(cc), e0c[0], e0c[1], e0c[2], sm.se0[0][v + 1][u], e0n[0], sm.se0[1][v][u + 1],
-                     e0n[1], sm.se0[2][v][u + 1], sm.se0[2][v + 1][u], h0c, pshn, h1c);
+      auto stage_a = [&](const int l[3]) {
+        if (PML) psi_load(g, 1, l, x, y, k, pshn);
+        h_core<T, PML>(g, l, coef(cc), e0c[0], e0c[1], e0c[2], sm.se0[0][v + 1][u], e0n[0], sm.se0[1][v][u + 1],
+                       e0n[1], sm.se0[2][v][u + 1], sm.se0[2][v + 1][u], h0c, pshn, h1c);
+      };
+      if (lz >= 0) {
+        const int l[3] = {lx, ly, lz};
+        stage_a(l);
+      } else {
+        const int l[3] = {lx, ly, -1};
+        stage_a(l);
+      }
     }
     for (int c = 0; c < 3; ++c) sm.sh1[c][v][u] = h1c[c];
     __syncthreads();
@@ -583,10 +641,19 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
     T e1c[3] = {T(0), T(0), T(0)};
     T psen[3][2];
     if (inB && kin && k >= k0 - 1) {
-      int l[3] = {lx, ly, PZ ? slab_pos(k, nz, g.npml) : -1};
-      if (PML) psi_load(g, 0, l, x, y, k, psen);
-      e_core<T, PML>(g, l, n0 + sxy * (unsigned)k, coef(cc), h1c[0], h1c[1], h1c[2], sm.sh1[0][v - 1][u], h1p[0],
-                     sm.sh1[1][v][u - 1], h1p[1], sm.sh1[2][v][u - 1], sm.sh1[2][v - 1][u], e0c, step, psen, e1c);
+      auto stage_b = [&](const int l[3]) {
+        if (PML) psi_load(g, 0, l, x, y, k, psen);
+        e_core<T, PML>(g, l, n0 + sxy * (unsigned)k, coef(cc), h1c[0], h1c[1], h1c[2], sm.sh1[0][v - 1][u],
+                       h1p[0], sm.sh1[1][v][u - 1], h1p[1], sm.sh1[2][v][u - 1], sm.sh1[2][v - 1][u], e0c, step,
+                       psen, e1c, srcc);
+      };
+      if (lz >= 0) {
+        const int l[3] = {lx, ly, lz};
+        stage_b(l);
+      } else {
+        const int l[3] = {lx, ly, -1};
+        stage_b(l);
+      }
     }
     const int s1 = (k + 2) & 1, s1m = s1 ^ 1;
     for (int c = 0; c < 3; ++c) sm.se1[s1][c][v][u] = e1c[c];
@@ -600,30 +667,35 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
                      sm.se1[s1m][1][v][u + 1], e1c[1], sm.se1[s1m][2][v][u + 1], sm.se1[s1m][2][v + 1][u], h1p, psh,
                      h2c);
       if (inD && km >= k0) {
-        const unsigned n = n0 + sxy * (unsigned)km;
-        stg(g.fo[3], n, h2c[0]);
-        stg(g.fo[4], n, h2c[1]);
-        stg(g.fo[5], n, h2c[2]);
+        if (!DEFER) {
+          const unsigned n = n0 + sxy * (unsigned)km;
+          stg(g.fo[3], n, h2c[0]);
+          stg(g.fo[4], n, h2c[1]);
+          stg(g.fo[5], n, h2c[2]);
+        }
         if (PML) psi_store(g, 1, l, x, y, km, psh);
       }
     }
     for (int c = 0; c < 3; ++c) sm.sh2[c][v][u] = h2c[c];
     __syncthreads();
-    // D: E^{n+2}, plane k-1 (the output tile)
-    if (inD && k >= k0 + 1 && km < k1) {
+    // D: E^{n+2}, plane k-1 (the output tile; km < k1 always holds)
+    pend = inD && km >= k0;
+    nst = n0 + sxy * (unsigned)km;
+    if (pend) {
       int l[3] = {lx, ly, PZ ? slab_pos(km, nz, g.npml) : -1};
-      const unsigned n = n0 + sxy * (unsigned)km;
-      T e2[3];
-      e_core<T, PML>(g, l, n, coef(cp), h2c[0], h2c[1], h2c[2], sm.sh2[0][v - 1][u], h2p[0], sm.sh2[1][v][u - 1],
-                     h2p[1], sm.sh2[2][v][u - 1], sm.sh2[2][v - 1][u], e1p, step + 1, pse, e2);
-      stg(g.fo[0], n, e2[0]);
-      stg(g.fo[1], n, e2[1]);
-      stg(g.fo[2], n, e2[2]);
+      e_core<T, PML>(g, l, nst, coef(cp), h2c[0], h2c[1], h2c[2], sm.sh2[0][v - 1][u], h2p[0], sm.sh2[1][v][u - 1],
+                     h2p[1], sm.sh2[2][v][u - 1], sm.sh2[2][v - 1][u], e1p, step + 1, pse, e2, srcc);
+      if (!DEFER) {
+        stg(g.fo[0], nst, e2[0]);
+        stg(g.fo[1], nst, e2[1]);
+        stg(g.fo[2], nst, e2[2]);
+      }
       if (PML) psi_store(g, 0, l, x, y, km, pse);
     }
     // rotate the pipeline
     h2p[0] = h2c[0];
     h2p[1] = h2c[1];
+    h2z = h2c[2];
     for (int c = 0; c < 3; ++c) {
       h1p[c] = h1c[c];
       e1p[c] = e1c[c];
@@ -641,6 +713,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
     cp = cc;
     cc = cf1;
   }
+  flush();
 }
 
 template <typename T, typename CI, bool PML, int TY>
@@ -707,7 +780,7 @@ __device__ __forceinline__ void e1_at(const GridView<T>& g, int x, int y, int k,
     slabs(g, x, y, k, l);
     psi_load(g, 0, l, x, y, k, ps);
   }
-  e_core<T, PML>(g, l, n, cf, h[0], h[1], h[2], hj[0], hk[0], hi[1], hk[1], hi[2], hj[2], eold, step, ps, e);
+  e_core<T, PML>(g, l, n, cf, h[0], h[1], h[2], hj[0], hk[0], hi[1], hk[1], hi[2], hj[2], eold, step, ps, e, true);
 }
 
 // Probe p of a two-step pass, one wave: samples `step` (recomputed) and
