@@ -62,29 +62,48 @@ __device__ __forceinline__ void psi_store(const GridView<T>& g, int kind, const 
   }
 }
 
+// CPML profile values (b - 1, c, 1/kappa) of one axis at slab position l;
+// `row` is P_BE or P_BH.  ProfG reads the grid's tables in global memory.
+template <typename T>
+struct Prof3 {
+  T b, c, k;
+};
+template <typename T>
+struct ProfG {
+  const GridView<T>& g;
+  template <int U>
+  __device__ __forceinline__ Prof3<T> at(int row, int l) const {
+    const int tn = 2 * g.npml;
+    const T* p = g.prof[U] + row * tn + l;
+    return {p[0], p[tn], p[2 * tn]};
+  }
+};
+
 // H^{n+1/2} of one node from E^n at the node (ex, ey, ez), at x+1 (ey_i,
 // ez_i), y+1 (ex_j, ez_j) and k+1 (ex_k, ey_k); ps is the node's H-type CPML
 // state, advanced in place.
-template <typename T, bool PML>
-__device__ __forceinline__ void h_core(const GridView<T>& g, const int l[3], const T* cf, T ex, T ey, T ez,
-                                       T ex_j, T ex_k, T ey_i, T ey_k, T ez_i, T ez_j, const T hold[3],
-                                       T ps[3][2], T hnew[3]) {
+template <typename T, bool PML, typename PF>
+__device__ __forceinline__ void h_core_pf(const PF& pf, const int l[3], const T* cf, T ex, T ey, T ez, T ex_j,
+                                          T ex_k, T ey_i, T ey_k, T ez_i, T ez_j, const T hold[3], T ps[3][2],
+                                          T hnew[3]) {
   T a_hx = ey_k - ey, b_hx = ez_j - ez;  // Hx: dEy/dz - dEz/dy
   T a_hy = ez_i - ez, b_hy = ex_k - ex;  // Hy: dEz/dx - dEx/dz
   T a_hz = ex_j - ex, b_hz = ey_i - ey;  // Hz: dEx/dy - dEy/dx
   if (PML) {
-    const int tn = 2 * g.npml;
     if (l[0] >= 0) {  // Hy (dEz/dx), Hz (dEy/dx)
-      a_hy = pml_term(a_hy, ps[0][0], g.prof[0], l[0], tn, P_BH);
-      b_hz = pml_term(b_hz, ps[0][1], g.prof[0], l[0], tn, P_BH);
+      const Prof3<T> q = pf.template at<0>(P_BH, l[0]);
+      a_hy = pml_step(a_hy, ps[0][0], q.b, q.c, q.k);
+      b_hz = pml_step(b_hz, ps[0][1], q.b, q.c, q.k);
     }
     if (l[1] >= 0) {  // Hz (dEx/dy), Hx (dEz/dy)
-      a_hz = pml_term(a_hz, ps[1][0], g.prof[1], l[1], tn, P_BH);
-      b_hx = pml_term(b_hx, ps[1][1], g.prof[1], l[1], tn, P_BH);
+      const Prof3<T> q = pf.template at<1>(P_BH, l[1]);
+      a_hz = pml_step(a_hz, ps[1][0], q.b, q.c, q.k);
+      b_hx = pml_step(b_hx, ps[1][1], q.b, q.c, q.k);
     }
     if (l[2] >= 0) {  // Hx (dEy/dz), Hy (dEx/dz)
-      a_hx = pml_term(a_hx, ps[2][0], g.prof[2], l[2], tn, P_BH);
-      b_hy = pml_term(b_hy, ps[2][1], g.prof[2], l[2], tn, P_BH);
+      const Prof3<T> q = pf.template at<2>(P_BH, l[2]);
+      a_hx = pml_step(a_hx, ps[2][0], q.b, q.c, q.k);
+      b_hy = pml_step(b_hy, ps[2][1], q.b, q.c, q.k);
     }
   }
   hnew[0] = h_new(hold[0], cf[K_DBX], a_hx, b_hx);
@@ -95,26 +114,28 @@ __device__ __forceinline__ void h_core(const GridView<T>& g, const int l[3], con
 // E^{n+1} of node n from H^{n+1/2} at the node (hx, hy, hz), at x-1 (hy_i,
 // hz_i), y-1 (hx_j, hz_j) and k-1 (hx_k, hy_k), then the sources of `step`;
 // ps is the node's E-type CPML state, advanced in place.
-template <typename T, bool PML>
-__device__ __forceinline__ void e_core(const GridView<T>& g, const int l[3], unsigned n, const T* cf, T hx, T hy,
-                                       T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j, const T eold[3],
-                                       int step, T ps[3][2], T enew[3], bool src) {
+template <typename T, bool PML, typename PF>
+__device__ __forceinline__ void e_core_pf(const PF& pf, const GridView<T>& g, const int l[3], unsigned n,
+                                          const T* cf, T hx, T hy, T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i,
+                                          T hz_j, const T eold[3], int step, T ps[3][2], T enew[3], bool src) {
   T a_ex = hz - hz_j, b_ex = hy - hy_k;  // Ex: dHz/dy - dHy/dz
   T a_ey = hx - hx_k, b_ey = hz - hz_i;  // Ey: dHx/dz - dHz/dx
   T a_ez = hy - hy_i, b_ez = hx - hx_j;  // Ez: dHy/dx - dHx/dy
   if (PML) {
-    const int tn = 2 * g.npml;
     if (l[0] >= 0) {  // Ey (dHz/dx), Ez (dHy/dx)
-      b_ey = pml_term(b_ey, ps[0][0], g.prof[0], l[0], tn, P_BE);
-      a_ez = pml_term(a_ez, ps[0][1], g.prof[0], l[0], tn, P_BE);
+      const Prof3<T> q = pf.template at<0>(P_BE, l[0]);
+      b_ey = pml_step(b_ey, ps[0][0], q.b, q.c, q.k);
+      a_ez = pml_step(a_ez, ps[0][1], q.b, q.c, q.k);
     }
     if (l[1] >= 0) {  // Ez (dHx/dy), Ex (dHz/dy)
-      b_ez = pml_term(b_ez, ps[1][0], g.prof[1], l[1], tn, P_BE);
-      a_ex = pml_term(a_ex, ps[1][1], g.prof[1], l[1], tn, P_BE);
+      const Prof3<T> q = pf.template at<1>(P_BE, l[1]);
+      b_ez = pml_step(b_ez, ps[1][0], q.b, q.c, q.k);
+      a_ex = pml_step(a_ex, ps[1][1], q.b, q.c, q.k);
     }
     if (l[2] >= 0) {  // Ex (dHy/dz), Ey (dHx/dz)
-      b_ex = pml_term(b_ex, ps[2][0], g.prof[2], l[2], tn, P_BE);
-      a_ey = pml_term(a_ey, ps[2][1], g.prof[2], l[2], tn, P_BE);
+      const Prof3<T> q = pf.template at<2>(P_BE, l[2]);
+      b_ex = pml_step(b_ex, ps[2][0], q.b, q.c, q.k);
+      a_ey = pml_step(a_ey, ps[2][1], q.b, q.c, q.k);
     }
   }
   enew[0] = e_new(eold[0], cf[K_CAX], cf[K_CBX], a_ex, b_ex);
@@ -131,6 +152,20 @@ __device__ __forceinline__ void e_core(const GridView<T>& g, const int l[3], uns
     enew[1] = comp == 1 ? enew[1] - v : enew[1];
     enew[2] = comp == 2 ? enew[2] - v : enew[2];
   }
+}
+
+template <typename T, bool PML>
+__device__ __forceinline__ void h_core(const GridView<T>& g, const int l[3], const T* cf, T ex, T ey, T ez,
+                                       T ex_j, T ex_k, T ey_i, T ey_k, T ez_i, T ez_j, const T hold[3],
+                                       T ps[3][2], T hnew[3]) {
+  h_core_pf<T, PML>(ProfG<T>{g}, l, cf, ex, ey, ez, ex_j, ex_k, ey_i, ey_k, ez_i, ez_j, hold, ps, hnew);
+}
+template <typename T, bool PML>
+__device__ __forceinline__ void e_core(const GridView<T>& g, const int l[3], unsigned n, const T* cf, T hx, T hy,
+                                       T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j, const T eold[3],
+                                       int step, T ps[3][2], T enew[3], bool src) {
+  e_core_pf<T, PML>(ProfG<T>{g}, g, l, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, ps, enew,
+                    src);
 }
 
 // Whether column n0 (= x + nx*y) holds a source at any height.  The tile
@@ -485,16 +520,43 @@ __global__ __launch_bounds__(TX * TY) void k_fused_batch(const GridView<T>* __re
 template <typename T, int TY>
 struct TB2Smem {
   static constexpr int R = TY + 4;
+  static constexpr int PZ = 512 / sizeof(T);  // longest z profile row held here (2 npml)
   T se0[3][R][64];      // E^n, plane k
   T sh1[3][R][64];      // H^{n+1/2}, plane k
   T se1[2][3][R][64];   // E^{n+1}, planes k and k-1
   T sh2[3][R][64];      // H^{n+3/2}, plane k-1
   T stab[256 * K_STRIDE];
+  T px[P_NROW][64];     // CPML profile at each lane's x
+  T py[P_NROW][R];      // ... at each wave's y
+  T pz[P_NROW * PZ];    // the z table
+};
+
+// CPML profile values of a two-step tile from the LDS copies made at the
+// tile start (the z table from global memory when it is longer than its
+// copy).  Reading them from global memory in every plane would make the
+// wave wait for its whole prefetch at each CPML term.
+template <typename T, int TY>
+struct ProfTB2 {
+  const GridView<T>& g;
+  const TB2Smem<T, TY>& sm;
+  int u, v;
+  template <int U>
+  __device__ __forceinline__ Prof3<T> at(int row, int l) const {
+    if (U == 0) return {sm.px[row][u], sm.px[row + 1][u], sm.px[row + 2][u]};
+    if (U == 1) return {sm.py[row][v], sm.py[row + 1][v], sm.py[row + 2][v]};
+    const int tn = 2 * g.npml;
+    if (tn <= TB2Smem<T, TY>::PZ) {
+      const T* p = sm.pz + row * tn + l;
+      return {p[0], p[tn], p[2 * tn]};
+    }
+    const T* p = g.prof[2] + row * tn + l;
+    return {p[0], p[tn], p[2 * tn]};
+  }
 };
 
 // One two-step tile: outputs [i0, i0+iw) x [j0, j0+jh) x [k0, k1) with
 // iw <= 60, jh <= TY.  AX masks the axes whose CPML slabs the tile can reach.
-template <typename T, typename CI, bool PML, int TY, int AX>
+template <typename T, typename CI, bool PML, int TY, int AX, bool USLAB = false>
 __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& sm, int i0, int j0, int iw, int jh,
                                          int k0, int k1, int step) {
   constexpr int TX = 60, NT = 64 * (TY + 4);
@@ -519,15 +581,30 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
   const int ly = PML && (AX & 2) && dom ? slab_pos(y, ny, g.npml) : -1;
   constexpr bool PZ = PML && (AX & 4);
   const bool srcc = src_column(g, n0, inB);
+  if (PML) {
+    const int tn = 2 * g.npml;
+    if ((AX & 1) && v == 0) {
+      const int xl = x >= 0 && x < nx ? slab_pos(x, nx, g.npml) : -1;
+      for (int r = 0; r < P_NROW; ++r) sm.px[r][u] = xl >= 0 ? g.prof[0][r * tn + xl] : T(0);
+    }
+    if ((AX & 2) && u == 0) {
+      const int yl = y >= 0 && y < ny ? slab_pos(y, ny, g.npml) : -1;
+      for (int r = 0; r < P_NROW; ++r) sm.py[r][v] = yl >= 0 ? g.prof[1][r * tn + yl] : T(0);
+    }
+    if ((AX & 4) && tn <= TB2Smem<T, TY>::PZ)
+      for (int q = tid; q < P_NROW * tn; q += NT) sm.pz[q] = g.prof[2][q];
+  }
+  const ProfTB2<T, TY> pf{g, sm, u, v};
 
   // Loads are unconditional, from uniform plane bases and the thread's
   // column offset n0 (0 for points outside the grid): E planes outside
   // [0, nz) read the zero plane, H and class planes are clamped (those values
   // are never used).  E of points outside the grid is zeroed where it enters
   // LDS.  No load then sits behind a branch, and none waits on a select.
-  // The x- and y-slab instantiations (AX 5, 6) keep predicated loads, which
-  // need fewer registers there.
-  constexpr bool UNC = AX == 4 || AX == 7;
+  // The x- and y-slab instantiations (AX 5, 6) keep predicated loads unless
+  // USLAB: the batched kernels, which read their grid's view from memory,
+  // have no registers to spare for them there.
+  constexpr bool UNC = AX == 4 || AX == 7 || USLAB;
   auto ld_e = [&](int k, T e[3]) {
     const bool in = k >= 0 && k < nz;
     if (UNC) {
@@ -585,7 +662,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
   bool pend = false;
   // (The x- and y-slab instantiations store at once: they have no registers
   // to spare under their cap.)
-  constexpr bool DEFER = UNC && sizeof(T) == 4;
+  constexpr bool DEFER = (AX == 4 || AX == 7) && sizeof(T) == 4;
   auto flush = [&]() {
     if (DEFER && pend) {
       stg(g.fo[0], nst, e2[0]);
@@ -624,7 +701,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
     if (inA && kin) {
       auto stage_a = [&](const int l[3]) {
         if (PML) psi_load(g, 1, l, x, y, k, pshn);
-        h_core<T, PML>(g, l, coef(cc), e0c[0], e0c[1], e0c[2], sm.se0[0][v + 1][u], e0n[0], sm.se0[1][v][u + 1],
+        h_core_pf<T, PML>(pf, l, coef(cc), e0c[0], e0c[1], e0c[2], sm.se0[0][v + 1][u], e0n[0], sm.se0[1][v][u + 1],
                        e0n[1], sm.se0[2][v][u + 1], sm.se0[2][v + 1][u], h0c, pshn, h1c);
       };
       if (lz >= 0) {
@@ -643,7 +720,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
     if (inB && kin && k >= k0 - 1) {
       auto stage_b = [&](const int l[3]) {
         if (PML) psi_load(g, 0, l, x, y, k, psen);
-        e_core<T, PML>(g, l, n0 + sxy * (unsigned)k, coef(cc), h1c[0], h1c[1], h1c[2], sm.sh1[0][v - 1][u],
+        e_core_pf<T, PML>(pf, g, l, n0 + sxy * (unsigned)k, coef(cc), h1c[0], h1c[1], h1c[2], sm.sh1[0][v - 1][u],
                        h1p[0], sm.sh1[1][v][u - 1], h1p[1], sm.sh1[2][v][u - 1], sm.sh1[2][v - 1][u], e0c, step,
                        psen, e1c, srcc);
       };
@@ -663,7 +740,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
     T h2c[3] = {T(0), T(0), T(0)};
     if (inC && k >= k0 && km >= 0 && km < nz) {
       int l[3] = {lx, ly, PZ ? slab_pos(km, nz, g.npml) : -1};
-      h_core<T, PML>(g, l, coef(cp), e1p[0], e1p[1], e1p[2], sm.se1[s1m][0][v + 1][u], e1c[0],
+      h_core_pf<T, PML>(pf, l, coef(cp), e1p[0], e1p[1], e1p[2], sm.se1[s1m][0][v + 1][u], e1c[0],
                      sm.se1[s1m][1][v][u + 1], e1c[1], sm.se1[s1m][2][v][u + 1], sm.se1[s1m][2][v + 1][u], h1p, psh,
                      h2c);
       if (inD && km >= k0) {
@@ -683,7 +760,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
     nst = n0 + sxy * (unsigned)km;
     if (pend) {
       int l[3] = {lx, ly, PZ ? slab_pos(km, nz, g.npml) : -1};
-      e_core<T, PML>(g, l, nst, coef(cp), h2c[0], h2c[1], h2c[2], sm.sh2[0][v - 1][u], h2p[0], sm.sh2[1][v][u - 1],
+      e_core_pf<T, PML>(pf, g, l, nst, coef(cp), h2c[0], h2c[1], h2c[2], sm.sh2[0][v - 1][u], h2p[0], sm.sh2[1][v][u - 1],
                      h2p[1], sm.sh2[2][v][u - 1], sm.sh2[2][v - 1][u], e1p, step + 1, pse, e2, srcc);
       if (!DEFER) {
         stg(g.fo[0], nst, e2[0]);
@@ -734,7 +811,7 @@ __global__ __launch_bounds__(64 * (TY + 4), (AX == 7 ? 1 : 6)) void k_tb2_list(G
                                                             int step) {
   __shared__ TB2Smem<T, TY> sm;
   const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
-  tb2_tile<T, CI, PML, TY, AX>(g, sm, t.x & 0xffff, t.y & 0xffff, t.x >> 16, t.y >> 16, t.z, t.w, step);
+  tb2_tile<T, CI, PML, TY, AX, true>(g, sm, t.x & 0xffff, t.y & 0xffff, t.x >> 16, t.y >> 16, t.z, t.w, step);
 }
 
 // Probes of a two-step pass: the intermediate step's values are recomputed

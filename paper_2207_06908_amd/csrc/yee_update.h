@@ -19,12 +19,13 @@ namespace mi355fdtd {
 // table holds b - 1, so the recursion psi <- b psi + c d is evaluated as
 // psi + ((b - 1) psi + c d), which keeps FP32 accurate where b is near 1.
 template <typename T>
-__device__ __forceinline__ T pml_term(T d, T& psi, const T* prof, int l, int two_np, int row) {
-  const T bm1 = prof[(row + 0) * two_np + l];
-  const T c = prof[(row + 1) * two_np + l];
-  const T ik = prof[(row + 2) * two_np + l];
+__device__ __forceinline__ T pml_step(T d, T& psi, T bm1, T c, T ik) {
   psi = psi + fma(bm1, psi, c * d);
   return fma(d, ik, psi);
+}
+template <typename T>
+__device__ __forceinline__ T pml_term(T d, T& psi, const T* prof, int l, int two_np, int row) {
+  return pml_step(d, psi, prof[(row + 0) * two_np + l], prof[(row + 1) * two_np + l], prof[(row + 2) * two_np + l]);
 }
 
 // Slab-local position of node index `pos` along an axis of n cells, or -1.

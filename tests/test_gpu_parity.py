@@ -157,6 +157,44 @@ def test_variants_bitwise_equal(fd, dims, npml):
             assert np.array_equal(a, b), runs[r]
 
 
+def test_sources_on_tile_seams(fd, oracle_mod):
+    """Sources on the seams of every tile shape (the tile kernels test for
+    sources once per column), two sources in one column at heights in
+    different z chunks, and two on one node (same and different component):
+    each variant and tile shape against the oracle element by element, and
+    all of them bit for bit against the split variant."""
+    nx, ny, nz, npml, nsteps = 150, 40, 35, 6, 30
+    sc = _random_case(nx, ny, nz, npml, seed=11, nsteps=nsteps, n_mats=3)
+    amps = S.gaussian(nsteps, sc.dt, 10 * sc.dt, 4 * sc.dt, 2.0)
+    spots = [(2, 7, 8, 9), (0, 8, 15, 16), (1, 67, 16, 17), (2, 68, 23, 8), (2, 69, 24, 24), (0, 127, 7, 12),
+             (1, 128, 31, 20), (2, 63, 12, 16), (2, 64, 13, 31), (0, 65, 32, 7),
+             (2, 40, 20, 5), (2, 40, 20, 30),            # one column, two z chunks
+             (0, 90, 17, 17), (2, 90, 17, 17),           # one node, two components
+             (1, 100, 25, 10), (1, 100, 25, 10)]         # one node, one component twice
+    sc.sources = [(c, i, j, k, amps * (1.0 + 0.1 * q)) for q, (c, i, j, k) in enumerate(spots)]
+    _say("sources on tile seams")
+    o = oracle_mod.Oracle.from_params(sc.params())
+    S.apply(sc, o)
+    o.step(nsteps)
+    ref = [o.get_field(c) for c in range(6)]
+    runs = [(1, 0, 0), (2, 8, 32), (2, 4, 8), (3, 8, 64), (3, 8, 8), (3, 12, 16), (3, 4, 5)]
+    base = None
+    for variant, ty, kz in runs:
+        g = fd.Grid.from_params(sc.params(), precision=32)
+        S.apply(sc, g)
+        g.set_kernel(variant, ty, kz)
+        g.step(nsteps)
+        got = [g.get_field(c) for c in range(6)]
+        for c in range(6):
+            err = float(np.abs(got[c] - ref[c]).max()) / max(float(np.abs(ref[c]).max()), 1e-300)
+            assert err <= 2e-5, (variant, ty, kz, c, err)
+        if base is None:
+            base = got
+        else:
+            for c in range(6):
+                assert np.array_equal(base[c], got[c]), (variant, ty, kz, c)
+
+
 def test_edge_cases(fd):
     # smallest grid: every E edge lies on a wall, so everything stays zero
     g = fd.Grid(2, 2, 2, 0.5, max_steps=5)
