@@ -29,9 +29,10 @@ KERNEL_SOURCES = ("paper_2207_06908_amd/csrc/fdtd_kernels.hip", "paper_2207_0690
 MEASURED_TRAFFIC = {
     # (source hash, kernel variant, tile_y, tile_z): HBM bytes per step (all
     # launches of the step; a two-step pass counts half)
-    ("f83429f117a4ca15", "fused", 8, 32): 6.545e9,
-    ("d56d7af9ae3d765f", "tb2", 8, 64): 3.298e9,
-    ("1b1a56f3d67cc8d6", "tb2", 8, 32): 3.508e9,
+    ("e685cc69844de716", "tb2", 8, 20): 4.095e9,
+    ("e685cc69844de716", "tb2", 8, 24): 4.063e9,
+    ("e685cc69844de716", "tb2", 8, 28): 4.042e9,
+    ("e685cc69844de716", "tb2", 8, 32): 4.032e9,
 }
 
 

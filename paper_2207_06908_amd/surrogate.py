@@ -113,13 +113,36 @@ def case_scenario(case: S.ElectrodeCase, n_steps: int = N_STEPS, name: str = "ca
 # Features and targets
 # ---------------------------------------------------------------------------
 
+def _conductance(log10_sigma: float, eps_r: float, T1: float) -> float:
+    """Conduction plus displacement conductivity at the front time scale,
+    sigma + eps0 eps_r / T1 (S/m)."""
+    return 10.0 ** log10_sigma + EPS0 * eps_r / T1
+
+
+def _feature_box():
+    """Ranges of the five inputs over the corners of the training box."""
+    (s0, s1), (e0, e1), (t0, t1) = RANGES["log10_sigma"], RANGES["eps_r"], RANGES["T1"]
+    return [(math.log10(_conductance(s0, e0, t1)), math.log10(_conductance(s1, e1, t0))),
+            (10.0 ** s0 / _conductance(s0, e1, t0), 10.0 ** s1 / _conductance(s1, e0, t1)),
+            RANGES["length"], RANGES["depth"], RANGES["T1"]]
+
+
+FEATURE_BOX = _feature_box()
+
+
 def features(cases: Sequence[S.ElectrodeCase]) -> np.ndarray:
-    """Inputs scaled so that the training ranges map to [-1, 1]."""
+    """The network inputs of (quantized) cases: log10 of the conductance
+    g = sigma + eps0 eps_r / T1, the conduction fraction sigma / g, length,
+    depth and T1, each scaled so that the training box maps into [-1, 1].
+    (sigma, eps_r) and (g, sigma / g) carry the same information for a given
+    T1; the second pair keeps queries outside the training ranges of sigma
+    and eps_r nearer the box, where the nets of the ensemble agree better.)"""
     out = np.empty((len(cases), 5), np.float32)
     for n, c in enumerate(map(quantize, cases)):
-        for q, key in enumerate(RANGES):
-            lo, hi = RANGES[key]
-            out[n, q] = 2.0 * (getattr(c, key) - lo) / (hi - lo) - 1.0
+        g = _conductance(c.log10_sigma, c.eps_r, c.T1)
+        vals = (math.log10(g), 10.0 ** c.log10_sigma / g, c.length, c.depth, c.T1)
+        for q, (v, (lo, hi)) in enumerate(zip(vals, FEATURE_BOX)):
+            out[n, q] = 2.0 * (v - lo) / (hi - lo) - 1.0
     return out
 
 
@@ -172,14 +195,18 @@ class FdtdRun:
     cells: int
 
 
-def run_fdtd(cases: Sequence[S.ElectrodeCase], n_steps: int = N_STEPS, chunk: int = 512,
+def run_fdtd(cases: Sequence[S.ElectrodeCase], n_steps: int = N_STEPS, chunk: int = 2048,
              graph_steps: int = 100, log=None) -> FdtdRun:
-    """GPR of every case from the batched FDTD engine, `chunk` grids per batch."""
+    """GPR of every case from the batched FDTD engine: at most `chunk` grids
+    per batch, the batches of equal size (a small last batch would leave
+    the device half idle)."""
     import torch
     from . import fdtd
     out = np.zeros((len(cases), n_steps))
     gpu_ms, cells = 0.0, 0
     t0 = time.perf_counter()
+    n_chunks = max(1, -(-len(cases) // chunk))
+    chunk = -(-len(cases) // n_chunks) if cases else chunk
     for c0 in range(0, len(cases), chunk):
         part = cases[c0:c0 + chunk]
         grids, pids = [], []
@@ -189,7 +216,7 @@ def run_fdtd(cases: Sequence[S.ElectrodeCase], n_steps: int = N_STEPS, chunk: in
             ids = S.apply(sc, g)
             pids.append(ids[[p[0] for p in sc.probes].index("V_gap")])
             grids.append(g)
-        b = fdtd.Batch(grids, tile=(32, 8, 32), graph_steps=graph_steps if n_steps % graph_steps == 0 else 0)
+        b = fdtd.Batch(grids, tile=(32, 8, 16), graph_steps=graph_steps if n_steps % graph_steps == 0 else 0)
         b.bind()
         b.timing(True)
         b.run(n_steps)

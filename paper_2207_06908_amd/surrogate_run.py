@@ -50,7 +50,7 @@ def train(a):
     scale = U.resistance_scale(cases)
     if a.dataset:   # waveforms of the same seeded cases from an earlier run
         d = np.load(a.dataset)
-        assert np.array_equal(d["X"], X), "dataset was made from other cases"
+        assert np.array_equal(d["scale"], scale), "dataset was made from other cases"
         Y = d["Y"]
         gpr = Y.astype(np.float64) * scale[:, None]
         fd = json.load(open(os.path.join(os.path.dirname(a.dataset), "train.json")))["fdtd"]
@@ -174,7 +174,7 @@ def main(argv=None):
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--lr-min", type=float, default=1e-5)
     t.add_argument("--dataset", default="", help="reuse the FDTD waveforms of an earlier run (same seed/sizes)")
-    t.add_argument("--chunk", type=int, default=512)
+    t.add_argument("--chunk", type=int, default=2048)
     t.add_argument("--threshold", type=float, default=0.02)
     s = sub.add_parser("sweep")
     s.add_argument("--weights", required=True)
@@ -183,7 +183,7 @@ def main(argv=None):
     s.add_argument("--seed", type=int, default=5)
     s.add_argument("--nets", type=int, default=4)
     s.add_argument("--threshold", type=float, default=0.02)
-    s.add_argument("--chunk", type=int, default=512)
+    s.add_argument("--chunk", type=int, default=2048)
     s.add_argument("--json", default="")
     a = ap.parse_args(argv)
     {"train": train, "sweep": sweep}[a.cmd](a)
