@@ -556,7 +556,7 @@ struct ProfTB2 {
 
 // One two-step tile: outputs [i0, i0+iw) x [j0, j0+jh) x [k0, k1) with
 // iw <= 60, jh <= TY.  AX masks the axes whose CPML slabs the tile can reach.
-template <typename T, typename CI, bool PML, int TY, int AX, bool USLAB = false>
+template <typename T, typename CI, bool PML, int TY, int AX, bool USLAB = false, bool BATCH = false>
 __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& sm, int i0, int j0, int iw, int jh,
                                          int k0, int k1, int step) {
   constexpr int TX = 60, NT = 64 * (TY + 4);
@@ -603,8 +603,11 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
   // LDS.  No load then sits behind a branch, and none waits on a select.
   // The x- and y-slab instantiations (AX 5, 6) keep predicated loads unless
   // USLAB: the batched kernels, which read their grid's view from memory,
-  // have no registers to spare for them there.
-  constexpr bool UNC = AX == 4 || AX == 7 || USLAB;
+  // have no registers to spare for them there.  In the batch (BATCH) the
+  // corner instantiation carries most of the work (the grids are small), so
+  // it too keeps predicated loads and stores at once, to fit two blocks per
+  // CU.
+  constexpr bool UNC = AX == 4 || (AX == 7 && !BATCH) || USLAB;
   auto ld_e = [&](int k, T e[3]) {
     const bool in = k >= 0 && k < nz;
     if (UNC) {
@@ -662,7 +665,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
   bool pend = false;
   // (The x- and y-slab instantiations store at once: they have no registers
   // to spare under their cap.)
-  constexpr bool DEFER = (AX == 4 || AX == 7) && sizeof(T) == 4;
+  constexpr bool DEFER = (AX == 4 || (AX == 7 && !BATCH)) && sizeof(T) == 4;
   auto flush = [&]() {
     if (DEFER && pend) {
       stg(g.fo[0], nst, e2[0]);
@@ -907,9 +910,10 @@ __global__ __launch_bounds__(256) void k_probes_tb2_batch(const GridView<T>* __r
 }
 
 // Batched two-step pass: tile (grid, i0 | iw << 16, j0 | jh << 16,
-// k0 | kz << 16) per block; step index *d_step + offset.
+// k0 | kz << 16) per block; step index *d_step + offset.  FP32: at most 80
+// VGPRs, so that two blocks share a CU.
 template <typename T, typename CI, int TY, int AX>
-__global__ __launch_bounds__(64 * (TY + 4), (AX == 7 ? 1 : 6)) void k_tb2_batch(const GridView<T>* __restrict__ views,
+__global__ __launch_bounds__(64 * (TY + 4), (sizeof(T) == 8 ? 1 : 6)) void k_tb2_batch(const GridView<T>* __restrict__ views,
                                                                                const int4* __restrict__ tiles,
                                                                                const int* __restrict__ d_step,
                                                                                int offset) {
@@ -917,8 +921,9 @@ __global__ __launch_bounds__(64 * (TY + 4), (AX == 7 ? 1 : 6)) void k_tb2_batch(
   const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const GridView<T>& g = views[t.x];
   const int k0 = t.w & 0xffff;
-  tb2_tile<T, CI, true, TY, AX>(g, sm, t.y & 0xffff, t.z & 0xffff, t.y >> 16, t.z >> 16, k0, k0 + (t.w >> 16),
-                                *d_step + offset);
+  tb2_tile<T, CI, true, TY, AX, false, true>(g, sm, t.y & 0xffff, t.z & 0xffff, t.y >> 16, t.z >> 16, k0,
+                                             k0 + (t.w >> 16),
+                                             *d_step + offset);
 }
 
 // ---------------------------------------------------------------------------
