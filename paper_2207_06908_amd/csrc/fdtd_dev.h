@@ -107,9 +107,12 @@ int launch_batch_probes(int prec, const void* views, const void* plist, int n, c
 // pass's input), `tiles` a device array of int4 (grid, i0 | iw << 16,
 // j0 | jh << 16, k0 | kz << 16) in 4 CPML groups of counts[q] tiles (as for
 // launch_lists_step), 60 x 8 tiles; then the probes of both steps for the
-// (grid, probe) pairs of `plist`.  Steps *d_step + offset and + 1.
+// (grid, probe) pairs of `plist`.  Steps *d_step + offset and + 1.  With a
+// second stream (and two events), group 1 runs on it beside the others,
+// forked from and joined back to `stream` before the probes.
 int launch_batch_pass_tb2(int prec, int cls16, const void* views, const void* tiles, const int* counts,
-                          const void* plist, int n_probes, const int* d_step, int offset, void* stream);
+                          const void* plist, int n_probes, const int* d_step, int offset, void* stream,
+                          void* stream2, void* ev_fork, void* ev_join);
 // *d += v on the stream (advances the device step counter).
 int launch_add(int* d, int v, void* stream);
 }  // namespace mi355fdtd

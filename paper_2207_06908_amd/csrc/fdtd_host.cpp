@@ -1045,6 +1045,9 @@ struct fdtd_batch {
   bool tiles_dirty = true;
   // graph replay (captured on a private stream, launched on `stream`)
   hipStream_t cap_stream = nullptr;
+  // second stream of the two-step pass (the x-slab tile group beside the rest)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int graph_steps = 0;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -1176,8 +1179,15 @@ int batch_launch_pass(fdtd_batch* b, hipStream_t st, int p, int off) {
   const size_t nv = b->grids.size();
   const size_t vb = view_bytes(b->prec);
   const int* d_step = (const int*)(b->ws + b->off_step);
+  if (!b->aux) {
+    hipError_t he = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+    if (he != hipSuccess) return bfail(b, FDTD_EDEVICE, std::string("second stream: ") + hipGetErrorString(he));
+  }
   int e = launch_batch_pass_tb2(b->prec, b->cls16, b->ws + b->off_views + p * nv * vb, b->ws + b->off_tiles2,
-                                b->tcnt, b->ws + b->off_plist, (int)(b->plist.size() / 2), d_step, off, (void*)st);
+                                b->tcnt, b->ws + b->off_plist, (int)(b->plist.size() / 2), d_step, off, (void*)st,
+                                (void*)b->aux, (void*)b->ev_fork, (void*)b->ev_join);
   if (e) return bfail(b, FDTD_EDEVICE, std::string("batch pass: ") + hipGetErrorString((hipError_t)e));
   return FDTD_OK;
 }
@@ -1414,6 +1424,10 @@ const char* fdtd_batch_last_error(const fdtd_batch* b) { return b ? b->err.c_str
 void fdtd_batch_destroy(fdtd_batch* b) {
   if (!b) return;
   drop_graph(b);
+  if (b->aux) (void)hipStreamSynchronize(b->aux);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->aux) (void)hipStreamDestroy(b->aux);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->t0) (void)hipEventDestroy(b->t0);
   if (b->t1) (void)hipEventDestroy(b->t1);

@@ -1215,40 +1215,47 @@ int launch_batch_probes(int prec, const void* views, const void* plist, int n, c
   return (int)hipGetLastError();
 }
 
+// Group q of the pass's tile list runs the instantiation for the slabs its
+// tiles reach (FP64: the all-axes one).
 template <typename T, typename CI>
-hipError_t batch_pass_t(const void* views, const void* tiles, const int* counts, const int* d_step, int offset,
-                        hipStream_t st) {
+hipError_t batch_group_t(int q, const void* views, const int4* t, int count, const int* d_step, int offset,
+                         hipStream_t st) {
   constexpr bool D = sizeof(T) == 8;
   const GridView<T>* v = (const GridView<T>*)views;
-  const int4* t = (const int4*)tiles;
-  const dim3 blk(64 * 12);
-  if (counts[0] > 0)
-    hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, D ? 7 : 4>), dim3((unsigned)counts[0]), blk, 0, st, v, t, d_step,
-                       offset);
-  t += counts[0];
-  if (counts[1] > 0)
-    hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, D ? 7 : 5>), dim3((unsigned)counts[1]), blk, 0, st, v, t, d_step,
-                       offset);
-  t += counts[1];
-  if (counts[2] > 0)
-    hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, D ? 7 : 6>), dim3((unsigned)counts[2]), blk, 0, st, v, t, d_step,
-                       offset);
-  t += counts[2];
-  if (counts[3] > 0)
-    hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, 7>), dim3((unsigned)counts[3]), blk, 0, st, v, t, d_step, offset);
+  const dim3 blk(64 * 12), grd((unsigned)count);
+  if (q == 0) hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, D ? 7 : 4>), grd, blk, 0, st, v, t, d_step, offset);
+  if (q == 1) hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, D ? 7 : 5>), grd, blk, 0, st, v, t, d_step, offset);
+  if (q == 2) hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, D ? 7 : 6>), grd, blk, 0, st, v, t, d_step, offset);
+  if (q == 3) hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, 7>), grd, blk, 0, st, v, t, d_step, offset);
   return hipGetLastError();
 }
 
 int launch_batch_pass_tb2(int prec, int cls16, const void* views, const void* tiles, const int* counts,
-                          const void* plist, int n_probes, const int* d_step, int offset, void* stream) {
-  hipStream_t st = (hipStream_t)stream;
-  hipError_t e;
-  if (prec == 64)
-    e = cls16 ? batch_pass_t<double, uint16_t>(views, tiles, counts, d_step, offset, st)
-              : batch_pass_t<double, uint8_t>(views, tiles, counts, d_step, offset, st);
-  else
-    e = cls16 ? batch_pass_t<float, uint16_t>(views, tiles, counts, d_step, offset, st)
-              : batch_pass_t<float, uint8_t>(views, tiles, counts, d_step, offset, st);
+                          const void* plist, int n_probes, const int* d_step, int offset, void* stream,
+                          void* stream2, void* ev_fork, void* ev_join) {
+  hipStream_t st = (hipStream_t)stream, st2 = (hipStream_t)stream2;
+  hipError_t e = hipSuccess;
+  // group 1 on the second stream beside the others, when both are there
+  const bool fork = st2 && counts[1] > 0 && counts[0] + counts[2] + counts[3] > 0;
+  if (fork) {
+    e = hipEventRecord((hipEvent_t)ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st2, (hipEvent_t)ev_fork, 0);
+  }
+  const int4* t = (const int4*)tiles;
+  for (int q = 0; q < 4 && e == hipSuccess; t += counts[q], ++q) {
+    if (counts[q] <= 0) continue;
+    hipStream_t s = fork && q == 1 ? st2 : st;
+    if (prec == 64)
+      e = cls16 ? batch_group_t<double, uint16_t>(q, views, t, counts[q], d_step, offset, s)
+                : batch_group_t<double, uint8_t>(q, views, t, counts[q], d_step, offset, s);
+    else
+      e = cls16 ? batch_group_t<float, uint16_t>(q, views, t, counts[q], d_step, offset, s)
+                : batch_group_t<float, uint8_t>(q, views, t, counts[q], d_step, offset, s);
+  }
+  if (fork && e == hipSuccess) {
+    e = hipEventRecord((hipEvent_t)ev_join, st2);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, (hipEvent_t)ev_join, 0);
+  }
   if (e != hipSuccess || n_probes <= 0) return (int)e;
   const dim3 grd((n_probes + 3) / 4), blk(256);
   if (prec == 64) {
