@@ -193,14 +193,15 @@ typedef struct fdtd_batch fdtd_batch;
  * the batch before them.  After binding, fdtd_probe / fdtd_get_field on a
  * member context read its part of the batch workspace.  Errors: EINVAL,
  * ESTATE (a context already bound), and fdtd_finalize's errors. */
-int fdtd_batch_create(fdtd_ctx* const* grids, int n, void* hip_stream, fdtd_batch** out);
+int fdtd_batch_pack(fdtd_ctx* const* grids, int n, void* hip_stream, fdtd_batch** out);
 size_t fdtd_batch_workspace_bytes(const fdtd_batch* b);
 /* Caller-owned device memory, 256-byte aligned.  Errors: ENOMEM, ESTATE, EDEVICE. */
 int fdtd_batch_bind_workspace(fdtd_batch* b, void* dev_ptr, size_t bytes);
 /* Tile shape (tile_x, tile_y) in {(32, 8), (32, 16), (64, 8)}, z-chunk
  * tile_z in [8, 4096]; graph_steps (even, 0 = off): steps captured in one
  * HIP graph and replayed.  (60, 8) selects two-step passes (two time steps
- * per launch sequence, tiles grouped by the CPML slabs they reach) with
+ * per launch sequence, tiles grouped by the CPML slabs they reach, the
+ * x-slab group on a second stream of the library's beside the others) with
  * tile_z in [16, 4096] and graph_steps a multiple of 4; an odd step count
  * ends with one single-step launch.  Results do not depend on the choice.
  * Default (32, 8, 32, 0).  Errors: EINVAL. */
@@ -208,6 +209,10 @@ int fdtd_batch_set_kernel(fdtd_batch* b, int tile_x, int tile_y, int tile_z, int
 /* Advance every grid n_steps steps.  Errors: ESTATE, ERANGE (beyond the
  * smallest max_steps), EDEVICE. */
 int fdtd_batch_run(fdtd_batch* b, int n_steps);
+/* Samples of probe probe_id of member grid `grid` (its index in the packed
+ * array), as fdtd_probe: syncs the stream, copies min(n_max, steps run)
+ * FP64 samples to the caller's host buffer.  Errors: EINVAL (no such grid
+ * or probe, null pointers), ESTATE (not bound), EDEVICE. */
 int fdtd_batch_probe(fdtd_batch* b, int grid, int probe_id, double* out, int n_max, int* n_written);
 /* Wall time of fdtd_batch_run calls made while timing is enabled (HIP
  * events on the stream); fdtd_batch_time returns and resets the totals. */

@@ -1218,7 +1218,7 @@ void drop_graph(fdtd_batch* b) {
 
 extern "C" {
 
-int fdtd_batch_create(fdtd_ctx* const* grids, int n, void* hip_stream, fdtd_batch** out) {
+int fdtd_batch_pack(fdtd_ctx* const* grids, int n, void* hip_stream, fdtd_batch** out) {
   if (!grids || n < 1 || !out) return FDTD_EINVAL;
   *out = nullptr;
   fdtd_batch* b = new fdtd_batch;

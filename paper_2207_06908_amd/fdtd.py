@@ -60,7 +60,7 @@ SIGNATURES = [
     ("fdtd_kernel_time", C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
     ("fdtd_last_error", C.c_char_p, [_vp]),
     ("fdtd_destroy", None, [_vp]),
-    ("fdtd_batch_create", C.c_int, [C.POINTER(_vp), C.c_int, _vp, C.POINTER(_vp)]),
+    ("fdtd_batch_pack", C.c_int, [C.POINTER(_vp), C.c_int, _vp, C.POINTER(_vp)]),
     ("fdtd_batch_workspace_bytes", C.c_size_t, [_vp]),
     ("fdtd_batch_bind_workspace", C.c_int, [_vp, _vp, C.c_size_t]),
     ("fdtd_batch_set_kernel", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int]),
@@ -255,9 +255,9 @@ class Batch:
         arr = (C.c_void_p * len(self.grids))(*[g._h for g in self.grids])
         h = C.c_void_p()
         st = stream if stream is not None else _stream_handle(device)
-        rc = lib().fdtd_batch_create(arr, len(self.grids), st, C.byref(h))
+        rc = lib().fdtd_batch_pack(arr, len(self.grids), st, C.byref(h))
         if rc:
-            raise FdtdError(rc, "fdtd_batch_create rejected the grids")
+            raise FdtdError(rc, "fdtd_batch_pack rejected the grids")
         self._h = h
         self._ws = None
         self.set_kernel(*tile, graph_steps)
