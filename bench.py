@@ -136,9 +136,9 @@ def bench_surrogate(queries: int = 65536, threshold: float = 0.02, fdtd_cases: i
     weights = os.path.join(ROOT, "paper_2207_06908_amd", "data", "surrogate_weights.npz")
     cases = S.draw_cases(queries, seed=5, widen=0.1)
     X = torch.from_numpy(U.features(cases)).cuda()
-    sur = U.Surrogate(n_nets=4, max_rows=8192)
+    sur = U.Surrogate(n_nets=4, max_rows=queries)   # one chunk: the products take 128 x 128 tiles
     sur.load(weights)
-    sur.ens.infer_route(X[:8192], threshold)
+    sur.ens.infer_route(X, threshold)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()

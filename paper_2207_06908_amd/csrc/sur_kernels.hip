@@ -19,6 +19,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sur_dev.h"
 
 namespace mi355sur {
@@ -40,47 +42,71 @@ __device__ __forceinline__ bf16x8 ld_frag(const uint16_t* p) {
 constexpr float kInvSqrt2 = 0.70710678118654752f;
 constexpr float kInvSqrt2Pi = 0.39894228040143268f;
 
-// One 64x64 output tile per block of four waves; each wave owns a 32x32
-// quarter (2 x 2 fragments).  Fragments beyond M or N are skipped (the
-// conditions are uniform across the wave).
-template <int EPI>
+// One (32 F) x (32 F) output tile per block of four waves; each wave owns a
+// (16 F) x (16 F) quarter, F x F fragments.  F = 2 for small products (the
+// training batches: more blocks), F = 4 for large ones (twice the reuse of
+// every fragment loaded).  Fragments beyond M or N are skipped (the
+// conditions are uniform across the wave).  Each accumulator takes its K
+// steps in order, so the result does not depend on F.
+template <int EPI, int F>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int mw = blockIdx.y * 64 + (w >> 1) * 32;
-  const int nw = blockIdx.x * 64 + (w & 1) * 32;
+  const int mw = blockIdx.y * (32 * F) + (w >> 1) * (16 * F);
+  const int nw = blockIdx.x * (32 * F) + (w & 1) * (16 * F);
   if (mw >= g.M || nw >= g.N) return;
-  const bool vm1 = mw + 16 < g.M, vn1 = nw + 16 < g.N;
-  const int r16 = lane & 15, kq = (lane >> 4) * 8;
-  const uint16_t* pa0 = g.A + (size_t)(mw + r16) * g.lda + kq;
-  const uint16_t* pa1 = pa0 + (size_t)16 * g.lda;
-  const uint16_t* pb0 = g.B + (size_t)(nw + r16) * g.ldb + kq;
-  const uint16_t* pb1 = pb0 + (size_t)16 * g.ldb;
-  f32x4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
-  const bf16x8 zero = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
-  for (int k0 = 0; k0 < g.K; k0 += 32) {
-    const bf16x8 a0 = ld_frag(pa0 + k0);
-    const bf16x8 a1 = vm1 ? ld_frag(pa1 + k0) : zero;
-    const bf16x8 b0 = ld_frag(pb0 + k0);
-    const bf16x8 b1 = vn1 ? ld_frag(pb1 + k0) : zero;
-    c00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, c00, 0, 0, 0);
-    c01 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, c01, 0, 0, 0);
-    c10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, c10, 0, 0, 0);
-    c11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, c11, 0, 0, 0);
+  bool vm[F], vn[F];
+#pragma unroll
+  for (int i = 0; i < F; ++i) {
+    vm[i] = i == 0 || mw + 16 * i < g.M;
+    vn[i] = i == 0 || nw + 16 * i < g.N;
   }
-  const f32x4 acc[2][2] = {{c00, c01}, {c10, c11}};
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
+  const uint16_t* pa = g.A + (size_t)(mw + r16) * g.lda + kq;
+  const uint16_t* pb = g.B + (size_t)(nw + r16) * g.ldb + kq;
+  const size_t sa = (size_t)16 * g.lda, sb = (size_t)16 * g.ldb;
+  f32x4 c[F][F];
+#pragma unroll
+  for (int i = 0; i < F; ++i)
+#pragma unroll
+    for (int j = 0; j < F; ++j) c[i][j] = f32x4{0, 0, 0, 0};
+  const bf16x8 zero = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+  // U K steps at a time: all their fragment loads first, then the products,
+  // so a wave waits for memory once per U steps.
+  auto steps = [&](int k0, auto u_tag) {
+    constexpr int U = decltype(u_tag)::value;
+    bf16x8 fa[U][F], fb[U][F];
+#pragma unroll
+    for (int s = 0; s < U; ++s)
+#pragma unroll
+      for (int i = 0; i < F; ++i) {
+        fa[s][i] = vm[i] ? ld_frag(pa + i * sa + k0 + 32 * s) : zero;
+        fb[s][i] = vn[i] ? ld_frag(pb + i * sb + k0 + 32 * s) : zero;
+      }
+#pragma unroll
+    for (int s = 0; s < U; ++s)
+#pragma unroll
+      for (int i = 0; i < F; ++i)
+#pragma unroll
+        for (int j = 0; j < F; ++j)
+          c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[s][i], fb[s][j], c[i][j], 0, 0, 0);
+  };
+  constexpr int KU = F == 2 ? 4 : 2;
+  int k0 = 0;
+  for (; k0 + 32 * KU <= g.K; k0 += 32 * KU) steps(k0, std::integral_constant<int, KU>());
+  for (; k0 < g.K; k0 += 32) steps(k0, std::integral_constant<int, 1>());
   const int rq = (lane >> 4) * 4;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    if (i == 1 && !vm1) continue;
+  for (int i = 0; i < F; ++i) {
+    if (!vm[i]) continue;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      if (j == 1 && !vn1) continue;
+    for (int j = 0; j < F; ++j) {
+      if (!vn[j]) continue;
       const int m0 = mw + 16 * i + rq, n = nw + 16 * j + r16;
       uint32_t t16[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + r;
-        const float v = acc[i][j][r];
+        const float v = c[i][j][r];
         if (EPI == EPI_GELU_TRAIN || EPI == EPI_GELU_INFER) {
           const float z = v + g.bias[n];
           const float e = erff(z * kInvSqrt2);
@@ -272,16 +298,24 @@ __global__ __launch_bounds__(1024) void k_compact(const float* __restrict__ spre
 
 static int last() { return (int)hipGetLastError(); }
 
-int launch_gemm(int epi, const GemmArgs& a, void* stream) {
-  const dim3 grid((a.N + 63) / 64, (a.M + 63) / 64), block(256);
-  hipStream_t s = (hipStream_t)stream;
+template <int F>
+void launch_gemm_f(int epi, const GemmArgs& a, hipStream_t s) {
+  const dim3 grid((a.N + 32 * F - 1) / (32 * F), (a.M + 32 * F - 1) / (32 * F)), block(256);
   switch (epi) {
-    case EPI_GELU_TRAIN: k_gemm<EPI_GELU_TRAIN><<<grid, block, 0, s>>>(a); break;
-    case EPI_GELU_INFER: k_gemm<EPI_GELU_INFER><<<grid, block, 0, s>>>(a); break;
-    case EPI_LINEAR: k_gemm<EPI_LINEAR><<<grid, block, 0, s>>>(a); break;
-    case EPI_BWD: k_gemm<EPI_BWD><<<grid, block, 0, s>>>(a); break;
-    default: k_gemm<EPI_DW><<<grid, block, 0, s>>>(a); break;
+    case EPI_GELU_TRAIN: k_gemm<EPI_GELU_TRAIN, F><<<grid, block, 0, s>>>(a); break;
+    case EPI_GELU_INFER: k_gemm<EPI_GELU_INFER, F><<<grid, block, 0, s>>>(a); break;
+    case EPI_LINEAR: k_gemm<EPI_LINEAR, F><<<grid, block, 0, s>>>(a); break;
+    case EPI_BWD: k_gemm<EPI_BWD, F><<<grid, block, 0, s>>>(a); break;
+    default: k_gemm<EPI_DW, F><<<grid, block, 0, s>>>(a); break;
   }
+}
+
+int launch_gemm(int epi, const GemmArgs& a, void* stream) {
+  // 128 x 128 block tiles once they still give every CU a few blocks
+  if ((long long)((a.M + 127) / 128) * ((a.N + 127) / 128) >= 1024)
+    launch_gemm_f<4>(epi, a, (hipStream_t)stream);
+  else
+    launch_gemm_f<2>(epi, a, (hipStream_t)stream);
   return last();
 }
 

@@ -110,7 +110,7 @@ def sweep(a):
     from . import surrogate as U
     cases = S.draw_cases(a.queries, a.seed, widen=0.1)
     X = U.features(cases)
-    sur = U.Surrogate(n_nets=a.nets)
+    sur = U.Surrogate(n_nets=a.nets, max_rows=a.queries)  # one inference chunk
     sur.load(a.weights)
     xd = torch.from_numpy(X).cuda()
     sur.route(xd[:1024], a.threshold)                       # warm-up
