@@ -154,3 +154,23 @@ def test_infer_route_empty_and_chunked():
         a, _s, _i, _c = e.infer_route(_dev(X[c0:c0 + 64]), 0.02)
         ym2.append(a.cpu().numpy())
     assert np.array_equal(ym.cpu().numpy(), np.concatenate(ym2))
+
+
+def test_large_and_small_product_tiles_give_the_same_bits():
+    """Products with at least 1024 blocks of 128 x 128 use 4 x 4 fragments per
+    wave, smaller ones 2 x 2; every output still accumulates its K steps in
+    the same order, so a 65,536-row inference (128 x 128 tiles) must equal
+    the same rows run in 8,192-row chunks (64 x 64 tiles) bit for bit."""
+    from paper_2207_06908_amd import sur
+    big, ps, X, _T = _setup(FULL, nets=2, rows=65536, n=65536, seed=3)
+    small = sur.Ensemble(FULL, n_nets=2, max_rows=8192)
+    for q in range(2):
+        small.set_params(q, M.flat(ps[q]))
+    xd = _dev(X)
+    ym_big, sp_big, _i, _c = big.infer_route(xd, 0.02)
+    ym_small, sp_small, _i2, _c2 = small.infer_route(xd, 0.02)
+    assert np.array_equal(ym_big.cpu().numpy(), ym_small.cpu().numpy())
+    assert np.array_equal(sp_big.cpu().numpy(), sp_small.cpu().numpy())
+    y0 = big.forward(0, xd[:4096]).cpu().numpy()
+    y1 = small.forward(0, xd[:4096]).cpu().numpy()
+    assert np.array_equal(y0, y1)
