@@ -12,9 +12,13 @@
 //   split  two passes (H over the grid, then E), in place;
 //   fused  one pass per step over x-y tiles marching up z; each block
 //          recomputes the H it needs on a one-node low-side halo; reads one
-//          field set and writes the other.
-// Both evaluate every component through h_point / e_point below and are
-// compiled with FP contraction off, so they agree bit for bit.
+//          field set and writes the other;
+//   tb2    one pass per two steps (temporal blocking): 60 x TY output tiles
+//          in 64 x (TY+4) regions, four stages per plane;
+// each also as tile lists grouped by the CPML slabs the tiles reach, and
+// batched over many grids.  All evaluate every component through h_core /
+// e_core below (with the arithmetic of yee_update.h) and are compiled with FP
+// contraction off, so they agree bit for bit.
 #include <hip/hip_runtime.h>
 
 #include "fdtd_dev.h"
