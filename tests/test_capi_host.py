@@ -85,6 +85,17 @@ def test_create_validation():
     assert g.dt == pytest.approx(0.99 * 0.5 / (299792458.0 * math.sqrt(3)), rel=1e-15)
 
 
+def test_largest_grid_accepted_and_the_next_rejected():
+    """Every field component must stay below 4 GiB (the kernels use 32-bit
+    element offsets): 1024 x 1024 x 1023 FP32 cells are accepted, 1024^3
+    (exactly 4 GiB per component) are not; FP64 halves the limit.  Creation
+    allocates nothing per cell, so this runs on any host."""
+    _grid(nx=1024, ny=1024, nz=1023)
+    assert _code(lambda: _grid(nx=1024, ny=1024, nz=1024)) == -1
+    _grid(nx=1024, ny=1024, nz=511, precision=64)
+    assert _code(lambda: _grid(nx=1024, ny=1024, nz=512, precision=64)) == -1
+
+
 def test_setup_validation():
     g = _grid()
     cm = np.zeros(g.shape, np.uint8)
