@@ -1179,12 +1179,6 @@ int batch_launch_pass(fdtd_batch* b, hipStream_t st, int p, int off) {
   const size_t nv = b->grids.size();
   const size_t vb = view_bytes(b->prec);
   const int* d_step = (const int*)(b->ws + b->off_step);
-  if (!b->aux) {
-    hipError_t he = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking);
-    if (he == hipSuccess) he = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
-    if (he == hipSuccess) he = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
-    if (he != hipSuccess) return bfail(b, FDTD_EDEVICE, std::string("second stream: ") + hipGetErrorString(he));
-  }
   int e = launch_batch_pass_tb2(b->prec, b->cls16, b->ws + b->off_views + p * nv * vb, b->ws + b->off_tiles2,
                                 b->tcnt, b->ws + b->off_plist, (int)(b->plist.size() / 2), d_step, off, (void*)st,
                                 (void*)b->aux, (void*)b->ev_fork, (void*)b->ev_join);
@@ -1320,6 +1314,12 @@ int fdtd_batch_run(fdtd_batch* b, int n) {
     if (rc) return rc;
   }
   hipError_t e = hipSuccess;
+  if (b->tb2 && !b->aux) {  // the two-step pass's second stream, made outside any capture
+    e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, std::string("second stream: ") + hipGetErrorString(e));
+  }
   if (b->timing) {
     if (!b->t0) {
       e = hipEventCreate(&b->t0);
