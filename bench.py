@@ -51,24 +51,72 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(steps: int):
     """Time the FP64 oracle on a bounded sample of the same workload: the
-    full grid for a few steps (set-up excluded)."""
+    full grid for a few steps (set-up excluded), on all the threads it is
+    given and on one thread (a sixteenth of the steps)."""
     from oracle import orc
     from paper_2207_06908_amd import scenarios as S
     orc.build(force=False)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    orc.set_threads(threads)
-    sc = S.config2(n_steps=steps + 1)
+    steps1 = max(3, steps // 16)
+    sc = S.config2(n_steps=steps + steps1 + 1)
     o = orc.Oracle.from_params(sc.params())
     S.apply(sc, o)
+    orc.set_threads(threads)
     o.step(1)  # builds the tables; not timed
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
+    orc.set_threads(1)
+    t0 = time.perf_counter()
+    o.step(steps1)
+    dt1 = time.perf_counter() - t0
+    orc.set_threads(threads)
     return {"value": sc.cells * steps / dt / 1e6, "unit": "Mcell-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"FP64 oracle, full 512x512x384 grid, {steps} steps after table build"}
+            "sample": f"FP64 oracle, full 512x512x384 grid, {steps} steps after table build",
+            "cpu": _cpu_model(), "value_1_thread": sc.cells * steps1 / dt1 / 1e6,
+            "sample_1_thread": f"the next {steps1} steps on one thread"}
+
+
+def stream_ceiling(mib: int = 2048, reps: int = 10):
+    """Practical HBM ceiling on this GPU: best of `reps` device copies
+    (read + write) and triads a = b + s c (two reads, one write) of `mib` MiB
+    arrays, timed with events."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.ones(n, dtype=torch.float32, device="cuda")
+    c = torch.ones(n, dtype=torch.float32, device="cuda")
+    def best(fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1))
+        return nbytes / (min(t) / 1e3) / 1e9
+    copy = best(lambda: a.copy_(b), 8 * n)
+    triad = best(lambda: torch.add(b, c, alpha=0.5, out=a), 12 * n)
+    del a, b, c
+    torch.cuda.empty_cache()
+    return round(copy, 1), round(triad, 1)
 
 
 def bench_batch(warmup: int = 100, graph_steps: int = 100, tune: bool = True):
@@ -264,6 +312,12 @@ def main():
     }
     del g
     torch.cuda.empty_cache()
+    # actual HBM rate of the pass (counter traffic) and the practical ceiling
+    copy_gbs, triad_gbs = stream_ceiling()
+    if traffic:
+        out["roofline"]["traffic_GBs"] = round(traffic / k_avg_s / 1e9, 1)
+    out["roofline"]["stream_copy_GBs"] = copy_gbs
+    out["roofline"]["stream_triad_GBs"] = triad_gbs
     if not a.no_batch:
         out["batched"] = bench_batch(tune=not a.no_tune)
     if not a.no_surrogate:
