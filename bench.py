@@ -237,8 +237,8 @@ def main():
                     help="only run plain copies of MIB MiB (profiler counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU "
-              "decomposition is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}): the multi-GPU "
+              "decomposition of the grid is designed but not built.", file=sys.stderr)
         sys.exit(2)
 
     if a.calibrate_copy:

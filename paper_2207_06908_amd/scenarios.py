@@ -17,8 +17,9 @@ Geometry conventions (shared by every backend):
 
 The three workloads follow the paper's model-file templates (Section 4.1,
 Fig. 3 for the feed topology of a buried electrode) scaled to the sizes of
-the three FDTD benchmark configurations.  Readings of points the paper does
-not fix (waveform definitions, electrode placement) are listed in the design doc.
+the three FDTD benchmark configurations.  Where the paper does not fix a
+point (waveform definitions, electrode placement), the choice made is stated
+at the function that makes it.
 """
 from __future__ import annotations
 

@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
 the same seeded inputs.  FP32 waveforms must agree to relative L2 1e-5
-(spec tolerance); the FP64 instantiation of the same kernels to 1e-11.
+per probe; the FP64 instantiation of the same kernels to 1e-11.
 Stored expected waveforms under tests/golden/ were written by
 tests/golden/make_golden.py, which calls only the oracle."""
 import os
