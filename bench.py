@@ -225,7 +225,8 @@ def main():
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--variant", default="tuned", choices=["tuned", "auto", "split", "fused", "tb2"],
-                    help="tuned: launch shape from the autotuner (cached); auto: fused 64x8, TZ 32")
+                    help="tuned: launch shape from the autotuner (cached); auto: the library default "
+                         "(two-step pass, 60x8 tiles, TZ 28, on this grid with a CPML)")
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--tile-z", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=100)
@@ -277,9 +278,9 @@ def main():
 
     cells = sc.cells
     value = cells * a.steps / (ms / 1e3) / 1e6
-    vname = "fused" if a.variant == "auto" else a.variant
+    vname = "tb2" if a.variant == "auto" else a.variant
     ty = a.tile_y or 8
-    tz = a.tile_z or (64 if vname == "tb2" else 32)
+    tz = a.tile_z or (28 if vname == "tb2" else 32)
     traffic = MEASURED_TRAFFIC.get((kernel_source_hash(), vname, ty, tz))
     bytes_step = g.algorithmic_bytes_per_step()
     k_avg_s = kms / max(kn, 1) / 1e3

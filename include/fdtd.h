@@ -59,7 +59,8 @@ enum { FDTD_LOSS_SEMI = 0, FDTD_LOSS_EXPLICIT = 1 };
 enum { FDTD_SRC_CURRENT = 0 };
 /* Kernel variants for fdtd_set_kernel: two passes per step (H, then E), one
  * fused pass per step, or one temporally blocked pass per two steps (an odd
- * remaining step takes one fused pass). */
+ * remaining step takes one fused pass).  FDTD_KERNEL_AUTO (the default) is
+ * the two-step pass for grids with a CPML and the fused pass otherwise. */
 enum { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_SPLIT = 1, FDTD_KERNEL_FUSED = 2, FDTD_KERNEL_TB2 = 3 };
 
 typedef struct fdtd_ctx fdtd_ctx;
@@ -138,9 +139,10 @@ size_t fdtd_workspace_bytes(fdtd_ctx* c);
  * Errors: ENOMEM, ESTATE, EDEVICE. */
 int fdtd_bind_workspace(fdtd_ctx* c, void* dev_ptr, size_t bytes);
 
-/* Select a kernel variant (FDTD_KERNEL_*) and tile parameters (0 = default):
- * tile_y (rows per tile) in {4, 8}, or 12 for FDTD_KERNEL_TB2; tile_z
- * (planes per z chunk) >= 0.  Grids with a CPML run the fused and two-step
+/* Select a kernel variant (FDTD_KERNEL_*) and tile parameters (0 = default:
+ * 8 rows; 28 planes for the two-step pass, 32 otherwise): tile_y (rows per
+ * tile) in {4, 8}, or 12 for FDTD_KERNEL_TB2; tile_z (planes per z chunk)
+ * >= 0.  Grids with a CPML run the fused and two-step
  * passes over tile lists grouped by the CPML slabs each tile reaches.
  * Results do not depend on the choice (bitwise).  Errors: EINVAL. */
 int fdtd_set_kernel(fdtd_ctx* c, int variant, int tile_y, int tile_z);

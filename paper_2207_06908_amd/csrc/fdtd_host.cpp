@@ -828,7 +828,10 @@ int fdtd_step(fdtd_ctx* c, int n) {
   if (!c || n < 0) return fail(c, FDTD_EINVAL, "bad step count");
   if (!c->ws) return fail(c, FDTD_ESTATE, "no workspace bound");
   if (c->steps_done + n > c->P.max_steps) return fail(c, FDTD_ERANGE, "beyond max_steps");
-  const int chosen = c->variant == FDTD_KERNEL_AUTO ? FDTD_KERNEL_FUSED : c->variant;
+  // AUTO: the two-step pass over CPML tile lists for grids with a CPML (the
+  // fastest on such grids), the fused pass otherwise
+  const bool listable = c->P.npml > 0 && c->N[0] < 65536 && c->N[1] < 65536;
+  const int chosen = c->variant != FDTD_KERNEL_AUTO ? c->variant : listable ? FDTD_KERNEL_TB2 : FDTD_KERNEL_FUSED;
   for (int t = 0; t < n;) {
     // the two-step pass needs two steps; an odd remainder takes one fused step
     const int variant = (chosen == FDTD_KERNEL_TB2 && n - t < 2) ? FDTD_KERNEL_FUSED : chosen;
@@ -837,10 +840,9 @@ int fdtd_step(fdtd_ctx* c, int n) {
     const void* view = c->P.precision == 64 ? (const void*)&c->v64[in][out] : (const void*)&c->v32[in][out];
     const void* pview = c->P.precision == 64 ? (const void*)&c->v64[out][out] : (const void*)&c->v32[out][out];
     // grids with a CPML run the fused and two-step passes over tile lists
-    const bool lists = (variant == FDTD_KERNEL_FUSED || variant == FDTD_KERNEL_TB2) && c->P.npml > 0 &&
-                       c->N[0] < 65536 && c->N[1] < 65536;
+    const bool lists = (variant == FDTD_KERNEL_FUSED || variant == FDTD_KERNEL_TB2) && listable;
     const int lty = c->tile_y == 4 ? 4 : (c->tile_y == 12 && variant == FDTD_KERNEL_TB2) ? 12 : 8;
-    const int lkz = std::max(8, c->tile_z > 0 ? c->tile_z : (variant == FDTD_KERNEL_TB2 ? 64 : 32));
+    const int lkz = std::max(8, c->tile_z > 0 ? c->tile_z : (variant == FDTD_KERNEL_TB2 ? 28 : 32));
     if (lists) {
       int rc = ensure_tiles(c, variant, lty, lkz);
       if (rc) return rc;
