@@ -60,7 +60,9 @@ enum { FDTD_SRC_CURRENT = 0 };
 /* Kernel variants for fdtd_set_kernel: two passes per step (H, then E), one
  * fused pass per step, or one temporally blocked pass per two steps (an odd
  * remaining step takes one fused pass).  FDTD_KERNEL_AUTO (the default) is
- * the two-step pass for grids with a CPML and the fused pass otherwise. */
+ * the two-step pass for grids with a CPML and the fused pass otherwise.  The
+ * two-step pass needs 2 npml <= 128 (FP32) or 64 (FP64); thicker CPMLs take
+ * the fused pass. */
 enum { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_SPLIT = 1, FDTD_KERNEL_FUSED = 2, FDTD_KERNEL_TB2 = 3 };
 
 typedef struct fdtd_ctx fdtd_ctx;
@@ -204,8 +206,9 @@ int fdtd_batch_bind_workspace(fdtd_batch* b, void* dev_ptr, size_t bytes);
  * HIP graph and replayed.  (60, 8) selects two-step passes (two time steps
  * per launch sequence, tiles grouped by the CPML slabs they reach, the
  * x-slab group on a second stream of the library's beside the others) with
- * tile_z in [16, 4096] and graph_steps a multiple of 4; an odd step count
- * ends with one single-step launch.  Results do not depend on the choice.
+ * tile_z in [16, 4096] and graph_steps a multiple of 4 (every grid with
+ * 2 npml <= 128 in FP32, 64 in FP64); an odd step count ends with one
+ * single-step launch.  Results do not depend on the choice.
  * Default (32, 8, 32, 0).  Errors: EINVAL. */
 int fdtd_batch_set_kernel(fdtd_batch* b, int tile_x, int tile_y, int tile_z, int graph_steps);
 /* Advance every grid n_steps steps.  Errors: ESTATE, ERANGE (beyond the

@@ -758,6 +758,10 @@ std::vector<Seg> segments(int n, int np, int w, int align, int w_out) {
 // Two-step pieces: [0, n) split into w-wide pieces, those in [a, b) clear
 // of the CPML including the h-cell halo (a - h >= np, piece end + h <= n - np);
 // a is a multiple of w so that the pieces below it are full width.
+// The two-step tiles keep the z CPML table (P_NROW rows of 2 npml values)
+// in LDS, room for 2 npml <= 128 values (FP32) or 64 (FP64).
+bool tb2_cpml_fits(int npml, int precision) { return 2 * npml <= (precision == 64 ? 64 : 128); }
+
 std::vector<Seg> segments_tb2(int n, int np, int w, int h) {
   std::vector<Seg> s;
   int a = (np + h + w - 1) / w * w, b = a;
@@ -829,9 +833,12 @@ int fdtd_step(fdtd_ctx* c, int n) {
   if (!c->ws) return fail(c, FDTD_ESTATE, "no workspace bound");
   if (c->steps_done + n > c->P.max_steps) return fail(c, FDTD_ERANGE, "beyond max_steps");
   // AUTO: the two-step pass over CPML tile lists for grids with a CPML (the
-  // fastest on such grids), the fused pass otherwise
+  // fastest on such grids), the fused pass otherwise.  The two-step tiles hold
+  // the z CPML table in LDS: thicker layers take the fused pass.
   const bool listable = c->P.npml > 0 && c->N[0] < 65536 && c->N[1] < 65536;
-  const int chosen = c->variant != FDTD_KERNEL_AUTO ? c->variant : listable ? FDTD_KERNEL_TB2 : FDTD_KERNEL_FUSED;
+  const bool tb2_ok = tb2_cpml_fits(c->P.npml, c->P.precision);
+  int chosen = c->variant != FDTD_KERNEL_AUTO ? c->variant : listable ? FDTD_KERNEL_TB2 : FDTD_KERNEL_FUSED;
+  if (chosen == FDTD_KERNEL_TB2 && !tb2_ok) chosen = FDTD_KERNEL_FUSED;
   for (int t = 0; t < n;) {
     // the two-step pass needs two steps; an odd remainder takes one fused step
     const int variant = (chosen == FDTD_KERNEL_TB2 && n - t < 2) ? FDTD_KERNEL_FUSED : chosen;
@@ -1284,6 +1291,9 @@ int fdtd_batch_set_kernel(fdtd_batch* b, int tile_x, int tile_y, int tile_z, int
   if (tile_x == 60) {  // two-step passes
     if (tile_y != 8 || tile_z < 16 || tile_z > 4096 || graph_steps < 0 || (graph_steps % 4))
       return bfail(b, FDTD_EINVAL, "two-step tiles (60, 8), tile_z in [16, 4096], graph_steps a multiple of 4");
+    for (const fdtd_ctx* c : b->grids)
+      if (!tb2_cpml_fits(c->P.npml, c->P.precision))
+        return bfail(b, FDTD_EINVAL, "two-step tiles need 2 npml <= 128 (FP32) or 64 (FP64)");
     b->tb2 = true;
     b->tb2_kz = tile_z;
     b->tx = 32;

@@ -536,9 +536,9 @@ struct TB2Smem {
 };
 
 // CPML profile values of a two-step tile from the LDS copies made at the
-// tile start (the z table from global memory when it is longer than its
-// copy).  Reading them from global memory in every plane would make the
-// wave wait for its whole prefetch at each CPML term.
+// tile start.  Reading them from global memory in every plane would make the
+// wave wait for its whole prefetch at each CPML term.  (The host runs the
+// two-step pass only on grids whose z table fits its copy: 2 npml <= PZ.)
 template <typename T, int TY>
 struct ProfTB2 {
   const GridView<T>& g;
@@ -548,13 +548,8 @@ struct ProfTB2 {
   __device__ __forceinline__ Prof3<T> at(int row, int l) const {
     if (U == 0) return {sm.px[row][u], sm.px[row + 1][u], sm.px[row + 2][u]};
     if (U == 1) return {sm.py[row][v], sm.py[row + 1][v], sm.py[row + 2][v]};
-    const int tn = 2 * g.npml;
-    if (tn <= TB2Smem<T, TY>::PZ) {
-      const T* p = sm.pz + row * tn + l;
-      return {p[0], p[tn], p[2 * tn]};
-    }
-    const T* p = g.prof[2] + row * tn + l;
-    return {p[0], p[tn], p[2 * tn]};
+    const int tn = 2 * g.npml, q = row * tn + l;
+    return {sm.pz[q], sm.pz[q + tn], sm.pz[q + 2 * tn]};
   }
 };
 
@@ -595,7 +590,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
       const int yl = y >= 0 && y < ny ? slab_pos(y, ny, g.npml) : -1;
       for (int r = 0; r < P_NROW; ++r) sm.py[r][v] = yl >= 0 ? g.prof[1][r * tn + yl] : T(0);
     }
-    if ((AX & 4) && tn <= TB2Smem<T, TY>::PZ)
+    if (AX & 4)
       for (int q = tid; q < P_NROW * tn; q += NT) sm.pz[q] = g.prof[2][q];
   }
   const ProfTB2<T, TY> pf{g, sm, u, v};

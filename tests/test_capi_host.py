@@ -96,6 +96,17 @@ def test_largest_grid_accepted_and_the_next_rejected():
     assert _code(lambda: _grid(nx=1024, ny=1024, nz=512, precision=64)) == -1
 
 
+def test_two_step_batch_tiles_need_the_z_cpml_table_to_fit_lds():
+    """The two-step tiles keep the z CPML table (2 npml values per row) in LDS:
+    a batch with a thicker CPML rejects them, and keeps its previous tiles."""
+    thick = [fdtd.Grid(150, 150, 150, 0.5, npml=70, max_steps=8) for _ in range(2)]
+    b = fdtd.Batch(thick, tile=(32, 8, 32))
+    assert _code(lambda: b.set_kernel(60, 8, 32, 0)) == -1
+    b.set_kernel(32, 8, 16, 0)
+    ok = [fdtd.Grid(40, 40, 40, 0.5, npml=8, max_steps=8) for _ in range(2)]
+    fdtd.Batch(ok, tile=(60, 8, 32))
+
+
 def test_setup_validation():
     g = _grid()
     cm = np.zeros(g.shape, np.uint8)

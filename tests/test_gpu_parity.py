@@ -198,6 +198,22 @@ def test_sources_on_tile_seams(fd, oracle_mod):
                 assert np.array_equal(base[c], got[c]), (variant, ty, kz, c)
 
 
+def test_thick_cpml_two_step_request_takes_the_fused_pass(fd):
+    """With 2 npml above what the two-step tiles hold in LDS, a two-step (or
+    default) request runs the fused pass: same bits as the split pass."""
+    sc = _random_case(150, 150, 146, 70, seed=5, nsteps=9, n_mats=2)
+    outs = []
+    for variant in (1, 3, 0):
+        g = fd.Grid.from_params(sc.params(), precision=32)
+        S.apply(sc, g)
+        g.set_kernel(variant)
+        g.step(9)
+        outs.append([g.get_field(c) for c in range(6)])
+    for r in (1, 2):
+        for c in range(6):
+            assert np.array_equal(outs[0][c], outs[r][c]), (r, c)
+
+
 def test_edge_cases(fd):
     # smallest grid: every E edge lies on a wall, so everything stays zero
     g = fd.Grid(2, 2, 2, 0.5, max_steps=5)
