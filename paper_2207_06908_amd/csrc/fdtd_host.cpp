@@ -476,7 +476,8 @@ void layout(fdtd_ctx* c) {
     c->max_tiles = (size_t)(c->N[0] / 32 + 6) * (c->N[1] / 4 + 6) * (c->N[2] / 8 + 6);
     c->off_tiles = take(c->max_tiles * 4 * sizeof(int));
   }
-  bool psi_fits = true;
+  // the kernels address every array with 32-bit byte offsets
+  bool psi_fits = c->src_amp.size() * ts < (size_t(1) << 32);
   for (int u = 0; u < 3; ++u) psi_fits = psi_fits && 4 * c->psi_elems[u] * ts < (size_t(1) << 32);
   c->ws_bytes = psi_fits ? o : 0;
 }
@@ -586,7 +587,7 @@ int freeze(fdtd_ctx* c) {
   build_cpml(c);
   build_sources_probes(c);
   layout(c);
-  if (c->ws_bytes == 0) return fail(c, FDTD_EINVAL, "a CPML state array exceeds 4 GiB");
+  if (c->ws_bytes == 0) return fail(c, FDTD_EINVAL, "a CPML state array or the source table exceeds 4 GiB");
   c->frozen = true;
   return FDTD_OK;
 }

@@ -78,8 +78,8 @@ struct ProfG {
   template <int U>
   __device__ __forceinline__ Prof3<T> at(int row, int l) const {
     const int tn = 2 * g.npml;
-    const T* p = g.prof[U] + row * tn + l;
-    return {p[0], p[tn], p[2 * tn]};
+    const unsigned q = (unsigned)(row * tn + l);
+    return {ldg(g.prof[U], q), ldg(g.prof[U], q + tn), ldg(g.prof[U], q + 2 * tn)};
   }
 };
 
@@ -149,9 +149,9 @@ __device__ __forceinline__ void e_core_pf(const PF& pf, const GridView<T>& g, co
   // false where the caller knows the node's column holds none
   if (src)
   for (int s = 0; s < g.n_src; ++s) {
-    if ((unsigned)g.src_idx[s] != n) continue;
-    const T v = g.src_amp[(long long)s * g.max_steps + step];
-    const int comp = g.src_comp[s];
+    if ((unsigned)ldg(g.src_idx, (unsigned)s) != n) continue;
+    const T v = ldg(g.src_amp, (unsigned)s * (unsigned)g.max_steps + (unsigned)step);
+    const int comp = ldg(g.src_comp, (unsigned)s);
     enew[0] = comp == 0 ? enew[0] - v : enew[0];
     enew[1] = comp == 1 ? enew[1] - v : enew[1];
     enew[2] = comp == 2 ? enew[2] - v : enew[2];
@@ -180,7 +180,7 @@ template <typename T>
 __device__ __forceinline__ bool src_column(const GridView<T>& g, unsigned n0, bool on) {
   bool any = false;
   if (on)
-    for (int s = 0; s < g.n_src; ++s) any |= (unsigned)g.src_idx[s] % (unsigned)g.sxy == n0;
+    for (int s = 0; s < g.n_src; ++s) any |= (unsigned)ldg(g.src_idx, (unsigned)s) % (unsigned)g.sxy == n0;
   return any;
 }
 
@@ -326,7 +326,7 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
   const CI* cls = (const CI*)g.cls;
 
   if (LDS_TAB) {
-    for (int q = tid; q < g.ncls * K_STRIDE; q += NT) stab[q] = g.ctab[q];
+    for (int q = tid; q < g.ncls * K_STRIDE; q += NT) stab[q] = ldg(g.ctab, (unsigned)q);
   }
   auto coef = [&](int c) -> const T* { return LDS_TAB ? stab + c * K_STRIDE : g.ctab + c * K_STRIDE; };
 
@@ -565,7 +565,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
   const unsigned sxy = (unsigned)g.sxy;
   const CI* cls = (const CI*)g.cls;
   if (LDS_TAB) {
-    for (int q = tid; q < g.ncls * K_STRIDE; q += NT) sm.stab[q] = g.ctab[q];
+    for (int q = tid; q < g.ncls * K_STRIDE; q += NT) sm.stab[q] = ldg(g.ctab, (unsigned)q);
   }
   auto coef = [&](int c) -> const T* { return LDS_TAB ? sm.stab + c * K_STRIDE : g.ctab + c * K_STRIDE; };
 
@@ -584,14 +584,14 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
     const int tn = 2 * g.npml;
     if ((AX & 1) && v == 0) {
       const int xl = x >= 0 && x < nx ? slab_pos(x, nx, g.npml) : -1;
-      for (int r = 0; r < P_NROW; ++r) sm.px[r][u] = xl >= 0 ? g.prof[0][r * tn + xl] : T(0);
+      for (int r = 0; r < P_NROW; ++r) sm.px[r][u] = xl >= 0 ? ldg(g.prof[0], (unsigned)(r * tn + xl)) : T(0);
     }
     if ((AX & 2) && u == 0) {
       const int yl = y >= 0 && y < ny ? slab_pos(y, ny, g.npml) : -1;
-      for (int r = 0; r < P_NROW; ++r) sm.py[r][v] = yl >= 0 ? g.prof[1][r * tn + yl] : T(0);
+      for (int r = 0; r < P_NROW; ++r) sm.py[r][v] = yl >= 0 ? ldg(g.prof[1], (unsigned)(r * tn + yl)) : T(0);
     }
     if (AX & 4)
-      for (int q = tid; q < P_NROW * tn; q += NT) sm.pz[q] = g.prof[2][q];
+      for (int q = tid; q < P_NROW * tn; q += NT) sm.pz[q] = ldg(g.prof[2], (unsigned)q);
   }
   const ProfTB2<T, TY> pf{g, sm, u, v};
 

@@ -48,11 +48,16 @@ __device__ __forceinline__ unsigned psi_index(int u, int l, int i, int j, int k,
 // that loads and stores use the scalar-base + vector-offset address form.
 template <typename T>
 __device__ __forceinline__ T ldg(const T* base, unsigned idx) {
-  return *(const T*)((const char*)base + idx * (unsigned)sizeof(T));
+  // every array read this way lives in global memory; saying so keeps the
+  // access a global (not generic) one where the pointer itself was read from
+  // memory, e.g. a batched grid's view
+  typedef __attribute__((address_space(1))) const T GT;
+  return *(GT*)((const __attribute__((address_space(1))) char*)base + idx * (unsigned)sizeof(T));
 }
 template <typename T>
 __device__ __forceinline__ void stg(T* base, unsigned idx, T v) {
-  *(T*)((char*)base + idx * (unsigned)sizeof(T)) = v;
+  typedef __attribute__((address_space(1))) T GT;
+  *(GT*)((__attribute__((address_space(1))) char*)base + idx * (unsigned)sizeof(T)) = v;
 }
 
 // H update of one node from raw E differences.
