@@ -555,7 +555,7 @@ struct ProfTB2 {
 
 // One two-step tile: outputs [i0, i0+iw) x [j0, j0+jh) x [k0, k1) with
 // iw <= 60, jh <= TY.  AX masks the axes whose CPML slabs the tile can reach.
-template <typename T, typename CI, bool PML, int TY, int AX, bool USLAB = false, bool BATCH = false>
+template <typename T, typename CI, bool PML, int TY, int AX, bool USLAB = false, bool LEAN = false>
 __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& sm, int i0, int j0, int iw, int jh,
                                          int k0, int k1, int step) {
   constexpr int TX = 60, NT = 64 * (TY + 4);
@@ -602,11 +602,11 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
   // LDS.  No load then sits behind a branch, and none waits on a select.
   // The x- and y-slab instantiations (AX 5, 6) keep predicated loads unless
   // USLAB: the batched kernels, which read their grid's view from memory,
-  // have no registers to spare for them there.  In the batch (BATCH) the
-  // corner instantiation carries most of the work (the grids are small), so
-  // it too keeps predicated loads and stores at once, to fit two blocks per
-  // CU.
-  constexpr bool UNC = AX == 4 || (AX == 7 && !BATCH) || USLAB;
+  // have no registers to spare for them there.  LEAN corner tiles keep
+  // predicated loads too and store at once, to fit two blocks per CU: the
+  // batch's corner tiles (its grids are small, so they carry much of the
+  // work) and the FP32 single-grid ones.
+  constexpr bool UNC = AX == 4 || (AX == 7 && !LEAN) || USLAB;
   auto ld_e = [&](int k, T e[3]) {
     const bool in = k >= 0 && k < nz;
     if (UNC) {
@@ -664,7 +664,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
   bool pend = false;
   // (The x- and y-slab instantiations store at once: they have no registers
   // to spare under their cap.)
-  constexpr bool DEFER = (AX == 4 || (AX == 7 && !BATCH)) && sizeof(T) == 4;
+  constexpr bool DEFER = (AX == 4 || (AX == 7 && !LEAN)) && sizeof(T) == 4;
   auto flush = [&]() {
     if (DEFER && pend) {
       stg(g.fo[0], nst, e2[0]);
@@ -804,16 +804,19 @@ __global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, 
   tb2_tile<T, CI, PML, TY, 7>(g, sm, tile_x * 60, (rest % nty) * TY, 60, TY, k0, min(k0 + kz, g.nz), step);
 }
 
-// Tile list: (i0 | iw << 16, j0 | jh << 16, k0, k1) per block.
-// Except for the all-axes corner instantiation, at most 80 VGPRs (6 waves
-// per SIMD), so that two blocks share a CU.
+// Tile list: (i0 | iw << 16, j0 | jh << 16, k0, k1) per block.  FP32: at
+// most 80 VGPRs (6 waves per SIMD), so that two blocks share a CU.  The
+// corner tiles get there as LEAN tiles, which also lets them run beside the
+// z-only tiles rather than wait for a free CU.
 template <typename T, typename CI, bool PML, int TY, int AX>
-__global__ __launch_bounds__(64 * (TY + 4), (AX == 7 ? 1 : 6)) void k_tb2_list(GridView<T> g,
-                                                                              const int4* __restrict__ tiles,
-                                                            int step) {
+__global__ __launch_bounds__(64 * (TY + 4), (sizeof(T) == 8 ? 1 : 6)) void k_tb2_list(GridView<T> g,
+                                                                                      const int4* __restrict__ tiles,
+                                                                                      int step) {
   __shared__ TB2Smem<T, TY> sm;
   const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
-  tb2_tile<T, CI, PML, TY, AX, true>(g, sm, t.x & 0xffff, t.y & 0xffff, t.x >> 16, t.y >> 16, t.z, t.w, step);
+  constexpr bool LEAN = AX == 7 && sizeof(T) == 4;
+  tb2_tile<T, CI, PML, TY, AX, !LEAN, LEAN>(g, sm, t.x & 0xffff, t.y & 0xffff, t.x >> 16, t.y >> 16, t.z, t.w,
+                                           step);
 }
 
 // Probes of a two-step pass: the intermediate step's values are recomputed
@@ -862,12 +865,28 @@ __device__ __forceinline__ void e1_at(const GridView<T>& g, int x, int y, int k,
   e_core<T, PML>(g, l, n, cf, h[0], h[1], h[2], hj[0], hk[0], hi[1], hk[1], hi[2], hj[2], eold, step, ps, e, true);
 }
 
-// Probe p of a two-step pass, one wave: samples `step` (recomputed) and
-// `step` + 1 (read).
+// Probes: one block of PR_NT threads per probe.  Thread `tid` sums terms
+// tid, tid + PR_NT, ... of the probe in order; the lanes of each wave are
+// then summed by a shuffle tree and the four wave sums in order.  Every probe
+// kernel sums in this one FP64 order, so that all variants, and a batch and
+// its grids run alone, agree bit for bit.
+constexpr int PR_NT = 256;
+
+// Block sum of `a` in the fixed order; `red` holds 4 doubles of LDS.  The
+// total is returned to every thread.
+__device__ __forceinline__ double probe_block_sum(double a, double* red) {
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  return ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Probe p of a two-step pass, one block: samples `step` (recomputed) and
+// `step` + 1 (read).  `red` holds 8 doubles of LDS.
 template <typename T, typename CI, bool PML>
-__device__ __forceinline__ void probe_tb2(const GridView<T>& g, int p, int step, int lane) {
+__device__ __forceinline__ void probe_tb2(const GridView<T>& g, int p, int step, double* red) {
   double a1 = 0.0, a2 = 0.0;
-  for (int t = g.pr_off[p] + lane; t < g.pr_off[p + 1]; t += 64) {
+  for (int t = g.pr_off[p] + (int)threadIdx.x; t < g.pr_off[p + 1]; t += PR_NT) {
     const int c = g.term_comp[t];
     const unsigned n = (unsigned)g.term_idx[t];
     const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), k = (int)(n / g.sxy);
@@ -880,32 +899,30 @@ __device__ __forceinline__ void probe_tb2(const GridView<T>& g, int p, int step,
     a1 += g.term_w[t] * (double)v1;
     a2 += g.term_w[t] * (double)ldg((const T*)f, n);
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    a1 += __shfl_down(a1, o, 64);
-    a2 += __shfl_down(a2, o, 64);
-  }
-  if (lane == 0) {
+  a1 = probe_block_sum(a1, red);
+  a2 = probe_block_sum(a2, red + 4);
+  if (threadIdx.x == 0) {
     g.pr_out[(long long)p * g.max_steps + step] = a1;
     g.pr_out[(long long)p * g.max_steps + step + 1] = a2;
   }
 }
 
 template <typename T, typename CI, bool PML>
-__global__ __launch_bounds__(256) void k_probes_tb2(GridView<T> g, int step) {
-  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (p >= g.n_probe) return;  // uniform per wave
-  probe_tb2<T, CI, PML>(g, p, step, threadIdx.x & 63);
+__global__ __launch_bounds__(PR_NT) void k_probes_tb2(GridView<T> g, int step) {
+  __shared__ double red[8];
+  if ((int)blockIdx.x >= g.n_probe) return;  // uniform per block
+  probe_tb2<T, CI, PML>(g, blockIdx.x, step, red);
 }
 
 // Batched two-step probes: entry q of the list is (grid, probe).
 template <typename T, typename CI>
-__global__ __launch_bounds__(256) void k_probes_tb2_batch(const GridView<T>* __restrict__ views,
-                                                         const int2* __restrict__ plist, int n,
-                                                         const int* __restrict__ d_step, int offset) {
-  const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (q >= n) return;  // uniform per wave
-  const int2 e = plist[q];
-  probe_tb2<T, CI, true>(views[e.x], e.y, *d_step + offset, threadIdx.x & 63);
+__global__ __launch_bounds__(PR_NT) void k_probes_tb2_batch(const GridView<T>* __restrict__ views,
+                                                           const int2* __restrict__ plist, int n,
+                                                           const int* __restrict__ d_step, int offset) {
+  __shared__ double red[8];
+  if ((int)blockIdx.x >= n) return;  // uniform per block
+  const int2 e = plist[blockIdx.x];
+  probe_tb2<T, CI, true>(views[e.x], e.y, *d_step + offset, red);
 }
 
 // Batched two-step pass: tile (grid, i0 | iw << 16, j0 | jh << 16,
@@ -926,43 +943,38 @@ __global__ __launch_bounds__(64 * (TY + 4), (sizeof(T) == 8 ? 1 : 6)) void k_tb2
 }
 
 // ---------------------------------------------------------------------------
-// probes: one wave per probe, FP64 sum in a fixed order (deterministic)
+// probes of a one-step pass: one block per probe, the fixed FP64 order of
+// probe_block_sum
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_probes(GridView<T> g, int step) {
-  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (p >= g.n_probe) return;  // uniform per wave
+__device__ __forceinline__ void probe_one(const GridView<T>& g, int p, int step, double* red) {
   double acc = 0.0;
-  for (int t = g.pr_off[p] + lane; t < g.pr_off[p + 1]; t += 64) {
+  for (int t = g.pr_off[p] + (int)threadIdx.x; t < g.pr_off[p + 1]; t += PR_NT) {
     const int c = g.term_comp[t];
     const T* f = c == 0 ? g.fi[0] : c == 1 ? g.fi[1] : c == 2 ? g.fi[2] : c == 3 ? g.fi[3] : c == 4 ? g.fi[4] : g.fi[5];
-    acc += g.term_w[t] * (double)f[g.term_idx[t]];
+    acc += g.term_w[t] * (double)ldg(f, (unsigned)g.term_idx[t]);
   }
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-  if (lane == 0) g.pr_out[(long long)p * g.max_steps + step] = acc;
+  acc = probe_block_sum(acc, red);
+  if (threadIdx.x == 0) g.pr_out[(long long)p * g.max_steps + step] = acc;
 }
 
-// Batched probes: entry q of the list is (grid, probe); one wave each.
 template <typename T>
-__global__ __launch_bounds__(256) void k_probes_batch(const GridView<T>* __restrict__ views,
-                                                     const int2* __restrict__ plist, int n,
-                                                     const int* __restrict__ d_step, int offset) {
-  const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (q >= n) return;  // uniform per wave
-  const int2 e = plist[q];
-  const GridView<T>& g = views[e.x];
-  const int p = e.y, step = *d_step + offset;
-  double acc = 0.0;
-  for (int t = g.pr_off[p] + lane; t < g.pr_off[p + 1]; t += 64) {
-    const int c = g.term_comp[t];
-    const T* f = c == 0 ? g.fi[0] : c == 1 ? g.fi[1] : c == 2 ? g.fi[2] : c == 3 ? g.fi[3] : c == 4 ? g.fi[4] : g.fi[5];
-    acc += g.term_w[t] * (double)f[g.term_idx[t]];
-  }
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-  if (lane == 0) g.pr_out[(long long)p * g.max_steps + step] = acc;
+__global__ __launch_bounds__(PR_NT) void k_probes(GridView<T> g, int step) {
+  __shared__ double red[4];
+  if ((int)blockIdx.x >= g.n_probe) return;  // uniform per block
+  probe_one(g, blockIdx.x, step, red);
+}
+
+// Batched probes: entry q of the list is (grid, probe); one block each.
+template <typename T>
+__global__ __launch_bounds__(PR_NT) void k_probes_batch(const GridView<T>* __restrict__ views,
+                                                       const int2* __restrict__ plist, int n,
+                                                       const int* __restrict__ d_step, int offset) {
+  __shared__ double red[4];
+  if ((int)blockIdx.x >= n) return;  // uniform per block
+  const int2 e = plist[blockIdx.x];
+  probe_one(views[e.x], e.y, *d_step + offset, red);
 }
 
 __global__ void k_add(int* p, int v) {
@@ -1040,18 +1052,20 @@ hipError_t launch_lists_tb2(const GridView<T>& g, int step, const int4* tiles, c
   if (sizeof(CI) == 1 && g.ncls > 256) return hipErrorInvalidValue;
   constexpr bool D = sizeof(T) == 8;
   const dim3 blk(64 * (TY + 4));
-  const int4* t = tiles;
+  const int4* t1 = tiles + counts[0];
+  const int4* t2 = t1 + counts[1];
+  const int4* t3 = t2 + counts[2];
   if (counts[0] > 0)
-    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 4>), dim3((unsigned)counts[0]), blk, 0, st, g, t, step);
-  t += counts[0];
-  if (counts[1] > 0)
-    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 5>), dim3((unsigned)counts[1]), blk, 0, st2, g, t, step);
-  t += counts[1];
-  if (counts[2] > 0)
-    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 6>), dim3((unsigned)counts[2]), blk, 0, st2, g, t, step);
-  t += counts[2];
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 4>), dim3((unsigned)counts[0]), blk, 0, st, g, tiles,
+                       step);
+  // Second stream: the few corner tiles first, beside the z-only ones; the
+  // y-slab tiles last, to fill the end of the pass.
   if (counts[3] > 0)
-    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, 7>), dim3((unsigned)counts[3]), blk, 0, st2, g, t, step);
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, 7>), dim3((unsigned)counts[3]), blk, 0, st2, g, t3, step);
+  if (counts[1] > 0)
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 5>), dim3((unsigned)counts[1]), blk, 0, st2, g, t1, step);
+  if (counts[2] > 0)
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 6>), dim3((unsigned)counts[2]), blk, 0, st2, g, t2, step);
   return hipGetLastError();
 }
 
@@ -1134,14 +1148,14 @@ int launch_step(int prec, const void* view, int cls16, int variant, int step, in
 template <typename T>
 hipError_t probes_any(const GridView<T>& g, int step, hipStream_t st) {
   if (g.n_probe <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_probes<T>), dim3((g.n_probe + 3) / 4), dim3(256), 0, st, g, step);
+  hipLaunchKernelGGL((k_probes<T>), dim3((unsigned)g.n_probe), dim3(PR_NT), 0, st, g, step);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t probes2_any(const GridView<T>& g, int cls16, int step, hipStream_t st) {
   if (g.n_probe <= 0) return hipSuccess;
-  const dim3 grd((g.n_probe + 3) / 4), blk(256);
+  const dim3 grd((unsigned)g.n_probe), blk(PR_NT);
   const bool pml = g.npml > 0;
   if (cls16) {
     if (pml) hipLaunchKernelGGL((k_probes_tb2<T, uint16_t, true>), grd, blk, 0, st, g, step);
@@ -1204,7 +1218,7 @@ int launch_batch_probes(int prec, const void* views, const void* plist, int n, c
                         void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (n <= 0) return 0;
-  const dim3 grd((n + 3) / 4), blk(256);
+  const dim3 grd((unsigned)n), blk(PR_NT);
   if (prec == 64)
     hipLaunchKernelGGL((k_probes_batch<double>), grd, blk, 0, st, (const GridView<double>*)views,
                        (const int2*)plist, n, d_step, offset);
@@ -1256,7 +1270,7 @@ int launch_batch_pass_tb2(int prec, int cls16, const void* views, const void* ti
     if (e == hipSuccess) e = hipStreamWaitEvent(st, (hipEvent_t)ev_join, 0);
   }
   if (e != hipSuccess || n_probes <= 0) return (int)e;
-  const dim3 grd((n_probes + 3) / 4), blk(256);
+  const dim3 grd((unsigned)n_probes), blk(PR_NT);
   if (prec == 64) {
     if (cls16)
       hipLaunchKernelGGL((k_probes_tb2_batch<double, uint16_t>), grd, blk, 0, st, (const GridView<double>*)views,
