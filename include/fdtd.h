@@ -142,10 +142,12 @@ size_t fdtd_workspace_bytes(fdtd_ctx* c);
 int fdtd_bind_workspace(fdtd_ctx* c, void* dev_ptr, size_t bytes);
 
 /* Select a kernel variant (FDTD_KERNEL_*) and tile parameters (0 = default:
- * 8 rows; 28 planes for the two-step pass, 32 otherwise): tile_y (rows per
+ * 8 rows; 20 planes for the two-step pass, 32 otherwise): tile_y (rows per
  * tile) in {4, 8}, or 12 for FDTD_KERNEL_TB2; tile_z (planes per z chunk)
- * >= 0.  Grids with a CPML run the fused and two-step
- * passes over tile lists grouped by the CPML slabs each tile reaches.
+ * >= 0.  Grids with a CPML run the fused and two-step passes over tile
+ * lists grouped by the CPML slabs each tile reaches; tile_z applies to the
+ * tiles clear of the x and y slabs, the slab groups take chunks of
+ * min(tile_z, 20) planes (two-step) or max(8, tile_z / 4) (fused).
  * Results do not depend on the choice (bitwise).  Errors: EINVAL. */
 int fdtd_set_kernel(fdtd_ctx* c, int variant, int tile_y, int tile_z);
 

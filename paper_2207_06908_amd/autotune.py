@@ -21,7 +21,7 @@ from . import fdtd
 GRID_CANDIDATES: List[Tuple[int, int, int]] = (
     [(fdtd.KERNEL_SPLIT, 0, 0)]
     + [(fdtd.KERNEL_FUSED, ty, tz) for ty in (4, 8) for tz in (16, 32, 64)]
-    + [(fdtd.KERNEL_TB2, 8, tz) for tz in (20, 24, 28, 32, 48)] + [(fdtd.KERNEL_TB2, 12, 24)]
+    + [(fdtd.KERNEL_TB2, 8, tz) for tz in (18, 20, 22, 28)] + [(fdtd.KERNEL_TB2, 12, 24)]
 )
 BATCH_CANDIDATES: List[Tuple[int, int, int]] = (
     [(tx, ty, tz) for (tx, ty) in ((32, 8), (32, 16), (64, 8)) for tz in (16, 32, 64)]

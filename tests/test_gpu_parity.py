@@ -114,8 +114,8 @@ def test_config2_small_against_stored_oracle(fd, variant):
 @pytest.mark.parametrize("variant,ty,tz", [(0, 0, 0), (2, 8, 32)])
 def test_config2_full_against_stored_oracle(fd, variant, ty, tz):
     """Full 512 x 512 x 384, 4000 steps: the default launch, which is the
-    two-step pass with the tile shape the benchmark's autotuner picks (60 x 8
-    tiles, 28-plane chunks; the other two-step shapes give the same bits, see
+    two-step pass with its default tile shape (60 x 8 tiles, 20-plane chunks;
+    the other two-step shapes give the same bits, see
     test_variants_bitwise_equal), and the fused pass."""
     sc = S.config2()
     ref = _golden("config2_full", [sc])[0]
