@@ -84,15 +84,18 @@ int launch_step(int prec, const void* view, int cls16, int variant, int step, in
 //   variant 3: (i0 | iw << 16, j0 | jh << 16, k0, k1) with iw <= 60,
 //              jh <= tile_y.
 // Group 0 runs on `stream`, groups 1-3 on `stream2` (the caller orders the
-// two streams around the call; they write disjoint tiles).
+// two streams around the call; they write disjoint tiles).  Variant 3 also
+// records the probes of `step` on `stream2`.
 int launch_lists_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, const void* tiles,
                       const int* counts, void* stream, void* stream2);
 // Record the probes of step `step` from the view's output set.
 int launch_probes(int prec, const void* view, int step, void* stream);
 
 // After a two-step pass (variant 3) from view.fi to view.fo: record the
-// probes of steps `step` (recomputed from the input set) and `step` + 1.
-int launch_probes2(int prec, const void* view, int cls16, int step, void* stream);
+// probes of steps `step` (recomputed from the input set; only if `first`)
+// and `step` + 1.  A two-step pass over tile lists records `step` itself
+// (launch_lists_step), so the caller passes first = 0 after it.
+int launch_probes2(int prec, const void* view, int cls16, int step, int first, void* stream);
 
 // Batched step over a tile list.  `views` is a device array of GridView (one
 // per grid, already resolved for this step's field-set parity), `tiles` a

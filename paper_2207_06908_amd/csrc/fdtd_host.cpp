@@ -905,7 +905,7 @@ int fdtd_step(fdtd_ctx* c, int n) {
       ++c->ev_pending;
     }
     if (variant == FDTD_KERNEL_TB2)
-      e = launch_probes2(c->P.precision, view, c->cls16, (int)c->steps_done, (void*)c->stream);
+      e = launch_probes2(c->P.precision, view, c->cls16, (int)c->steps_done, lists ? 0 : 1, (void*)c->stream);
     else
       e = launch_probes(c->P.precision, pview, (int)c->steps_done, (void*)c->stream);
     if (e) return fail(c, FDTD_EDEVICE, std::string("probe launch: ") + hipGetErrorString((hipError_t)e));

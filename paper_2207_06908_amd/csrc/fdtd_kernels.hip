@@ -881,37 +881,42 @@ __device__ __forceinline__ double probe_block_sum(double a, double* red) {
   return ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-// Probe p of a two-step pass, one block: samples `step` (recomputed) and
-// `step` + 1 (read).  `red` holds 8 doubles of LDS.
-template <typename T, typename CI, bool PML>
+// Probe p of a two-step pass, one block: sample `step` (S1: recomputed from
+// the input set, which the pass leaves untouched) and sample `step` + 1 (S2:
+// read from the output set).  `red` holds 8 doubles of LDS.
+template <typename T, typename CI, bool PML, bool S1 = true, bool S2 = true>
 __device__ __forceinline__ void probe_tb2(const GridView<T>& g, int p, int step, double* red) {
   double a1 = 0.0, a2 = 0.0;
   for (int t = g.pr_off[p] + (int)threadIdx.x; t < g.pr_off[p + 1]; t += PR_NT) {
     const int c = g.term_comp[t];
     const unsigned n = (unsigned)g.term_idx[t];
-    const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), k = (int)(n / g.sxy);
-    T v3[3];
-    if (c < 3) e1_at<T, CI, PML>(g, x, y, k, step, v3);
-    else h1_at<T, CI, PML>(g, x, y, k, v3);
-    const int cc = c < 3 ? c : c - 3;
-    const T v1 = cc == 0 ? v3[0] : cc == 1 ? v3[1] : v3[2];
-    const T* f = c == 0 ? g.fo[0] : c == 1 ? g.fo[1] : c == 2 ? g.fo[2] : c == 3 ? g.fo[3] : c == 4 ? g.fo[4] : g.fo[5];
-    a1 += g.term_w[t] * (double)v1;
-    a2 += g.term_w[t] * (double)ldg((const T*)f, n);
+    if (S1) {
+      const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), k = (int)(n / g.sxy);
+      T v3[3];
+      if (c < 3) e1_at<T, CI, PML>(g, x, y, k, step, v3);
+      else h1_at<T, CI, PML>(g, x, y, k, v3);
+      const int cc = c < 3 ? c : c - 3;
+      const T v1 = cc == 0 ? v3[0] : cc == 1 ? v3[1] : v3[2];
+      a1 += g.term_w[t] * (double)v1;
+    }
+    if (S2) {
+      const T* f = c == 0 ? g.fo[0] : c == 1 ? g.fo[1] : c == 2 ? g.fo[2] : c == 3 ? g.fo[3] : c == 4 ? g.fo[4] : g.fo[5];
+      a2 += g.term_w[t] * (double)ldg((const T*)f, n);
+    }
   }
-  a1 = probe_block_sum(a1, red);
-  a2 = probe_block_sum(a2, red + 4);
+  if (S1) a1 = probe_block_sum(a1, red);
+  if (S2) a2 = probe_block_sum(a2, red + 4);
   if (threadIdx.x == 0) {
-    g.pr_out[(long long)p * g.max_steps + step] = a1;
-    g.pr_out[(long long)p * g.max_steps + step + 1] = a2;
+    if (S1) g.pr_out[(long long)p * g.max_steps + step] = a1;
+    if (S2) g.pr_out[(long long)p * g.max_steps + step + 1] = a2;
   }
 }
 
-template <typename T, typename CI, bool PML>
+template <typename T, typename CI, bool PML, bool S1 = true, bool S2 = true>
 __global__ __launch_bounds__(PR_NT) void k_probes_tb2(GridView<T> g, int step) {
   __shared__ double red[8];
   if ((int)blockIdx.x >= g.n_probe) return;  // uniform per block
-  probe_tb2<T, CI, PML>(g, blockIdx.x, step, red);
+  probe_tb2<T, CI, PML, S1, S2>(g, blockIdx.x, step, red);
 }
 
 // Batched two-step probes: entry q of the list is (grid, probe).
@@ -1066,6 +1071,12 @@ hipError_t launch_lists_tb2(const GridView<T>& g, int step, const int4* tiles, c
     hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 5>), dim3((unsigned)counts[1]), blk, 0, st2, g, t1, step);
   if (counts[2] > 0)
     hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 6>), dim3((unsigned)counts[2]), blk, 0, st2, g, t2, step);
+  // The probes' first sample, recomputed from the input set (which no group
+  // writes), runs on the second stream beside the clear tiles; the caller
+  // reads the second sample after the join (launch_probes2 with first = 0).
+  if (g.n_probe > 0)
+    hipLaunchKernelGGL((k_probes_tb2<T, CI, true, true, false>), dim3((unsigned)g.n_probe), dim3(PR_NT), 0, st2, g,
+                       step);
   return hipGetLastError();
 }
 
@@ -1153,11 +1164,14 @@ hipError_t probes_any(const GridView<T>& g, int step, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t probes2_any(const GridView<T>& g, int cls16, int step, hipStream_t st) {
+hipError_t probes2_any(const GridView<T>& g, int cls16, int step, bool first, hipStream_t st) {
   if (g.n_probe <= 0) return hipSuccess;
   const dim3 grd((unsigned)g.n_probe), blk(PR_NT);
   const bool pml = g.npml > 0;
-  if (cls16) {
+  if (!first) {  // the second sample only (two-step tile lists, which have a CPML)
+    if (cls16) hipLaunchKernelGGL((k_probes_tb2<T, uint16_t, true, false, true>), grd, blk, 0, st, g, step);
+    else hipLaunchKernelGGL((k_probes_tb2<T, uint8_t, true, false, true>), grd, blk, 0, st, g, step);
+  } else if (cls16) {
     if (pml) hipLaunchKernelGGL((k_probes_tb2<T, uint16_t, true>), grd, blk, 0, st, g, step);
     else hipLaunchKernelGGL((k_probes_tb2<T, uint16_t, false>), grd, blk, 0, st, g, step);
   } else {
@@ -1167,10 +1181,10 @@ hipError_t probes2_any(const GridView<T>& g, int cls16, int step, hipStream_t st
   return hipGetLastError();
 }
 
-int launch_probes2(int prec, const void* view, int cls16, int step, void* stream) {
+int launch_probes2(int prec, const void* view, int cls16, int step, int first, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  if (prec == 64) return (int)probes2_any<double>(*(const GridView<double>*)view, cls16, step, st);
-  return (int)probes2_any<float>(*(const GridView<float>*)view, cls16, step, st);
+  if (prec == 64) return (int)probes2_any<double>(*(const GridView<double>*)view, cls16, step, first != 0, st);
+  return (int)probes2_any<float>(*(const GridView<float>*)view, cls16, step, first != 0, st);
 }
 
 int launch_probes(int prec, const void* view, int step, void* stream) {
