@@ -64,6 +64,14 @@ struct orc_sim {
   std::vector<char> emod[3], hmod[3];  // already modified by an earlier wire
   // CPML: psi[c][u] for component c (0..2 E, 3..5 H) and derivative axis u
   A3 psi[6][3];
+  // Debye media (ADE): pole time constants, eps0 * delta-eps per cell and
+  // pole (set-up), per E edge (built, then freed), and per E edge the
+  // polarisation current J, its update factor beta, the factor gam of J in
+  // the E update, and E before the step (for the J update)
+  int npole = 0;
+  double tau[4] = {0, 0, 0, 0}, kp[4] = {0, 0, 0, 0};
+  std::vector<double> c_deps;       // [cell * npole + p]
+  A3 deps[3][4], J[3][4], Jbeta[3][4], Jgam[3][4], Eprev[3];
   std::vector<double> be[3], ce[3], ike[3], bh[3], ch[3], ikh[3];
 };
 
@@ -117,12 +125,13 @@ void build_materials(orc_sim* s) {
     e_extent(s, a, ext);
     s->eps[a].init(ext[0], ext[1], ext[2], kEps0);
     s->sig[a].init(ext[0], ext[1], ext[2], 0.0);
+    for (int d = 0; d < s->npole; ++d) s->deps[a][d].init(ext[0], ext[1], ext[2], 0.0);
     const int b = (a + 1) % 3, c = (a + 2) % 3;
     for (int k = 0; k < ext[2]; ++k)
       for (int j = 0; j < ext[1]; ++j)
         for (int i = 0; i < ext[0]; ++i) {
           const int p[3] = {i, j, k};
-          double se = 0, ss = 0;
+          double se = 0, ss = 0, sd[4] = {0, 0, 0, 0};
           int cnt = 0;
           for (int db = -1; db <= 0; ++db)
             for (int dc = -1; dc <= 0; ++dc) {
@@ -133,11 +142,13 @@ void build_materials(orc_sim* s) {
               const size_t ci = cell_index(s, q[0], q[1], q[2]);
               se += s->c_eps[ci];
               ss += s->c_sig[ci];
+              for (int d = 0; d < s->npole; ++d) sd[d] += s->c_deps[ci * s->npole + d];
               ++cnt;
             }
           if (cnt) {
             s->eps[a](i, j, k) = se / cnt;
             s->sig[a](i, j, k) = ss / cnt;
+            for (int d = 0; d < s->npole; ++d) s->deps[a][d](i, j, k) = sd[d] / cnt;
           }
         }
     h_extent(s, a, ext);
@@ -179,7 +190,10 @@ void build_materials(orc_sim* s) {
 // stability limit at 0.99 of the Courant step.  All changes are material
 // changes, so the discrete energy identity of the Yee scheme still holds.
 // A perfect-conductor edge ignores any modification; a component next to two
-// wires keeps the factor of the first wire added.
+// wires keeps the factor of the first wire added.  In Debye media the radial
+// edges scale the whole permittivity function by m (eps_inf, sigma and each
+// pole's increment), a reading of the paper's note that the wire models are
+// adapted to Debye media.
 void scale_mu(orc_sim* s, int a, const int p[3], double m) {
   A3& h = s->mu[a];
   if (!h.in(p[0], p[1], p[2])) return;
@@ -214,6 +228,7 @@ void apply_wires(orc_sim* s) {
           s->emod[a][li] = 1;
           s->eps[a].v[li] *= m;
           s->sig[a].v[li] *= m;
+          for (int dd = 0; dd < s->npole; ++dd) s->deps[a][dd].v[li] *= m;
         }
       }
     }
@@ -247,12 +262,29 @@ void apply_wires(orc_sim* s) {
 // n + 1/2 as the mean of n and n + 1, the modification the paper points to
 // for better accuracy): Ca = (1 - x) / (1 + x), Cb = (dt / eps) / (1 + x),
 // x = sigma dt / (2 eps).  H: Db = dt / mu (eq. 5).
+//
+// Debye media (Section 2.4: auxiliary differential equation).  Each pole p
+// adds a polarisation current with tau_p dJ_p/dt + J_p = eps0 de_p dE/dt.
+// Taken at n + 1/2 with the trapezoidal rule, like sigma E:
+//   J_p^{n+1} = k_p J_p^n + beta_p (E^{n+1} - E^n),
+//   k_p = (2 tau_p - dt) / (2 tau_p + dt),  beta_p = 2 eps0 de_p / (2 tau_p + dt),
+// and Ampere's law eps dE/dt + sigma E + sum_p J_p = curl H (eps = eps0
+// eps_inf) at n + 1/2 with J_p as the mean of n and n + 1 gives
+//   E^{n+1} = Ca E^n + Cb curl H - sum_p gam_p J_p^n,  gam_p = Cb (1 + k_p) / 2,
+//   Ca = (1 - x + y) / (1 + x + y),  Cb = (dt / eps) / (1 + x + y),
+// y = sum_p beta_p dt / (2 eps).  With no pole increments y = 0 and the
+// semi-implicit lossy coefficients come out unchanged.
 int build_coefficients(orc_sim* s) {
   const double dt = s->dt;
+  for (int d = 0; d < s->npole; ++d) s->kp[d] = (2.0 * s->tau[d] - dt) / (2.0 * s->tau[d] + dt);
   for (int a = 0; a < 3; ++a) {
     const A3& e = s->eps[a];
     s->Ca[a].init(e.n0, e.n1, e.n2, 0.0);
     s->Cb[a].init(e.n0, e.n1, e.n2, 0.0);
+    for (int d = 0; d < s->npole; ++d) {
+      s->Jbeta[a][d].init(e.n0, e.n1, e.n2, 0.0);
+      s->Jgam[a][d].init(e.n0, e.n1, e.n2, 0.0);
+    }
     for (size_t li = 0; li < e.v.size(); ++li) {
       const double ep = s->eps[a].v[li], sg = s->sig[a].v[li];
       if (s->P.loss_mode == ORC_LOSS_EXPLICIT) {
@@ -261,8 +293,15 @@ int build_coefficients(orc_sim* s) {
         s->Cb[a].v[li] = dt / ep;
       } else {
         const double x = sg * dt / (2.0 * ep);
-        s->Ca[a].v[li] = (1.0 - x) / (1.0 + x);
-        s->Cb[a].v[li] = (dt / ep) / (1.0 + x);
+        double bsum = 0;
+        for (int d = 0; d < s->npole; ++d) {
+          s->Jbeta[a][d].v[li] = 2.0 * s->deps[a][d].v[li] / (2.0 * s->tau[d] + dt);
+          bsum += s->Jbeta[a][d].v[li];
+        }
+        const double y = bsum * dt / (2.0 * ep);
+        s->Ca[a].v[li] = (1.0 - x + y) / (1.0 + x + y);
+        s->Cb[a].v[li] = (dt / ep) / (1.0 + x + y);
+        for (int d = 0; d < s->npole; ++d) s->Jgam[a][d].v[li] = s->Cb[a].v[li] * (1.0 + s->kp[d]) / 2.0;
       }
     }
     const A3& m = s->mu[a];
@@ -341,6 +380,11 @@ int finalize(orc_sim* s) {
   if (rc) return rc;
   for (int a = 0; a < 3; ++a) {  // the update needs only the coefficients
     s->eps[a] = A3(); s->sig[a] = A3(); s->mu[a] = A3();
+    for (int d = 0; d < s->npole; ++d) {
+      s->deps[a][d] = A3();
+      s->J[a][d].init(s->E[a].n0, s->E[a].n1, s->E[a].n2, 0.0);
+    }
+    if (s->npole) s->Eprev[a].init(s->E[a].n0, s->E[a].n1, s->E[a].n2, 0.0);
     std::vector<char>().swap(s->emod[a]);
     std::vector<char>().swap(s->hmod[a]);
   }
@@ -348,6 +392,13 @@ int finalize(orc_sim* s) {
   for (Probe& pr : s->probes) pr.rec.assign(s->P.max_steps, 0.0);
   s->finalized = true;
   return ORC_OK;
+}
+
+// sum_p gam_p J_p^n of E edge li of component a (0 without poles)
+double debye_term(const orc_sim* s, int a, size_t li) {
+  double t = 0;
+  for (int d = 0; d < s->npole; ++d) t += s->Jgam[a][d].v[li] * s->J[a][d].v[li];
+  return t;
 }
 
 void update_h(orc_sim* s) {
@@ -415,7 +466,8 @@ void update_e(orc_sim* s) {
         py = s->be[1][j] * py + s->ce[1][j] * dy;
         pz = s->be[2][k] * pz + s->ce[2][k] * dz;
         Ex(i, j, k) = s->Ca[0](i, j, k) * Ex(i, j, k) +
-                      s->Cb[0](i, j, k) * ((dy * s->ike[1][j] + py) - (dz * s->ike[2][k] + pz));
+                      s->Cb[0](i, j, k) * ((dy * s->ike[1][j] + py) - (dz * s->ike[2][k] + pz)) -
+                      debye_term(s, 0, li);
       }
   // Ey at (i, j+1/2, k): dEy/dt = ((dHx/dz - dHz/dx) - sigma Ey) / eps.
 #pragma omp parallel for schedule(static)
@@ -431,7 +483,8 @@ void update_e(orc_sim* s) {
         pz = s->be[2][k] * pz + s->ce[2][k] * dz;
         px = s->be[0][i] * px + s->ce[0][i] * dxv;
         Ey(i, j, k) = s->Ca[1](i, j, k) * Ey(i, j, k) +
-                      s->Cb[1](i, j, k) * ((dz * s->ike[2][k] + pz) - (dxv * s->ike[0][i] + px));
+                      s->Cb[1](i, j, k) * ((dz * s->ike[2][k] + pz) - (dxv * s->ike[0][i] + px)) -
+                      debye_term(s, 1, li);
       }
   // Ez at (i, j, k+1/2): dEz/dt = ((dHy/dx - dHx/dy) - sigma Ez) / eps.
 #pragma omp parallel for schedule(static)
@@ -447,7 +500,8 @@ void update_e(orc_sim* s) {
         px = s->be[0][i] * px + s->ce[0][i] * dxv;
         py = s->be[1][j] * py + s->ce[1][j] * dy;
         Ez(i, j, k) = s->Ca[2](i, j, k) * Ez(i, j, k) +
-                      s->Cb[2](i, j, k) * ((dxv * s->ike[0][i] + px) - (dy * s->ike[1][j] + py));
+                      s->Cb[2](i, j, k) * ((dxv * s->ike[0][i] + px) - (dy * s->ike[1][j] + py)) -
+                      debye_term(s, 2, li);
       }
 }
 
@@ -461,6 +515,20 @@ void inject_sources(orc_sim* s) {
     const int a = q.axis;
     s->E[a](q.p[0], q.p[1], q.p[2]) -= s->Cb[a](q.p[0], q.p[1], q.p[2]) * I / area;
   }
+}
+
+// Debye polarisation currents, after the E update and the sources of the
+// step: J_p^{n+1} = k_p J_p^n + beta_p (E^{n+1} - E^n).
+void update_j(orc_sim* s) {
+  for (int a = 0; a < 3; ++a)
+    for (int d = 0; d < s->npole; ++d) {
+      std::vector<double>& j = s->J[a][d].v;
+      const std::vector<double>& b = s->Jbeta[a][d].v;
+      const std::vector<double>& e = s->E[a].v;
+      const std::vector<double>& e0 = s->Eprev[a].v;
+#pragma omp parallel for schedule(static)
+      for (size_t li = 0; li < j.size(); ++li) j[li] = s->kp[d] * j[li] + b[li] * (e[li] - e0[li]);
+    }
 }
 
 // Probe record n: E and line voltage at (n + 1) dt (after the E update of
@@ -545,6 +613,26 @@ int orc_set_materials(orc_sim* s, const uint8_t* cm, const orc_material* tab, in
   return ORC_OK;
 }
 
+int orc_set_debye(orc_sim* s, const uint8_t* cm, int n_mat, int n_poles, const double* tau, const double* d_eps) {
+  if (!s || !cm || !tau || !d_eps || n_mat < 1 || n_mat > 256 || n_poles < 1 || n_poles > 4) return ORC_EINVAL;
+  if (s->finalized) return fail(s, ORC_ESTATE, "setup after finalize");
+  if (s->P.loss_mode != ORC_LOSS_SEMI) return fail(s, ORC_EINVAL, "Debye media need the semi-implicit loss form");
+  for (int d = 0; d < n_poles; ++d)
+    if (!(tau[d] > 0) || !std::isfinite(tau[d])) return fail(s, ORC_EINVAL, "bad pole time constant");
+  for (int m = 0; m < n_mat * n_poles; ++m)
+    if (!(d_eps[m] >= 0) || !std::isfinite(d_eps[m])) return fail(s, ORC_EINVAL, "bad pole increment");
+  const size_t nc = s->c_eps.size();
+  std::vector<double> cd(nc * n_poles);
+  for (size_t c = 0; c < nc; ++c) {
+    if (cm[c] >= n_mat) return fail(s, ORC_ERANGE, "material id out of table");
+    for (int d = 0; d < n_poles; ++d) cd[c * n_poles + d] = kEps0 * d_eps[cm[c] * n_poles + d];
+  }
+  s->npole = n_poles;
+  for (int d = 0; d < n_poles; ++d) s->tau[d] = tau[d];
+  s->c_deps.swap(cd);
+  return ORC_OK;
+}
+
 int orc_add_wire(orc_sim* s, int axis, int i, int j, int k, int n, double radius) {
   if (!s || axis < 0 || axis > 2 || n < 1) return ORC_EINVAL;
   if (s->finalized) return fail(s, ORC_ESTATE, "setup after finalize");
@@ -597,8 +685,11 @@ int orc_step(orc_sim* s, int n_steps) {
   if (s->step + n_steps > s->P.max_steps) return fail(s, ORC_ERANGE, "beyond max_steps");
   for (int t = 0; t < n_steps; ++t) {
     update_h(s);
+    if (s->npole)
+      for (int a = 0; a < 3; ++a) s->Eprev[a].v = s->E[a].v;
     update_e(s);
     inject_sources(s);
+    if (s->npole) update_j(s);
     for (Probe& pr : s->probes) pr.rec[s->step] = probe_value(s, pr);
     ++s->step;
   }

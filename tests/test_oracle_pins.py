@@ -601,3 +601,93 @@ def test_validation_errors():
     o3.step(1)
     with pytest.raises(OracleError):
         o3.add_wire(0, 2, 2, 2, 3, 0.01)                    # setup after finalize
+
+
+# --- Debye media (Section 2.4, ADE) ---------------------------------------
+
+def _debye_relax(er, sg, tau, de, nsteps, dt_scale=1.0):
+    """Curl-free E^0 = -grad phi in a uniform Debye medium: H stays 0 and
+    every E edge follows the same scalar recurrence.  Returns (E^n / E^0 on
+    the edges, dt)."""
+    nx, ny, nz, dx = 8, 7, 6, 0.5
+    dt = 0.99 * dx / (C0 * math.sqrt(3.0)) * dt_scale
+    o = _orc()(nx, ny, nz, dx, dt=dt, max_steps=nsteps)
+    cm = np.zeros((nz, ny, nx), np.uint8)
+    o.set_materials(cm, [(er, sg, 1.0)])
+    o.set_debye(cm, tau, [de])
+    rng = np.random.default_rng(3)
+    phi = np.zeros((nz + 1, ny + 1, nx + 1))
+    phi[1:-1, 1:-1, 1:-1] = rng.integers(-50, 50, size=(nz - 1, ny - 1, nx - 1))
+    Ex = -(phi[:-1, :-1, 1:] - phi[:-1, :-1, :-1]) / dx
+    o.set_field(EX, Ex)
+    o.set_field(EY, -(phi[:-1, 1:, :-1] - phi[:-1, :-1, :-1]) / dx)
+    o.set_field(EZ, -(phi[1:, :-1, :-1] - phi[:-1, :-1, :-1]) / dx)
+    o.step(nsteps)
+    for c in range(3):
+        assert np.abs(o.get_field(3 + c)).max() <= 1e-12 * np.abs(Ex).max() / ETA0
+    mask = np.abs(Ex) > 0
+    r = o.get_field(EX)[mask] / Ex[mask]
+    assert np.ptp(r) <= 1e-12 * max(abs(r).max(), 1e-300)
+    return float(r.mean()), dt
+
+
+def _debye_matrix(er, sg, tau, de):
+    """d/dt (E, J_1..J_P) of a uniform field with no curl:
+    eps0 er dE/dt = -sigma E - sum J_p and tau_p dJ_p/dt = eps0 de_p dE/dt - J_p."""
+    P = len(tau)
+    A = np.zeros((P + 1, P + 1))
+    e = EPS0 * er
+    A[0, 0] = -sg / e
+    A[0, 1:] = -1.0 / e
+    for p in range(P):
+        A[p + 1, :] = EPS0 * de[p] * A[0, :] / tau[p]
+        A[p + 1, p + 1] -= 1.0 / tau[p]
+    return A
+
+
+DEBYE = dict(er=4.0, sg=2e-3, tau=[3e-9, 2e-8, 1.5e-10], de=[6.0, 20.0, 1.5])
+
+
+def test_debye_relaxation_is_the_trapezoidal_rule():
+    """The ADE update of a curl-free field is the trapezoidal rule applied to
+    the relaxation ODE of E and the pole currents: E^n / E^0 equals the first
+    entry of ((I - A dt/2)^-1 (I + A dt/2))^n (1, 0, ...), A built from the
+    material parameters alone."""
+    n = 300
+    r, dt = _debye_relax(DEBYE["er"], DEBYE["sg"], DEBYE["tau"], DEBYE["de"], n)
+    A = _debye_matrix(**DEBYE)
+    I = np.eye(A.shape[0])
+    M = np.linalg.solve(I - A * dt / 2, I + A * dt / 2)
+    x = np.linalg.matrix_power(M, n) @ np.eye(A.shape[0])[:, 0]
+    assert r == pytest.approx(x[0], rel=1e-11, abs=1e-14)
+
+
+def test_debye_relaxation_converges_to_the_ode_at_second_order():
+    """Against the exact solution expm(A t) of the same ODE: the error at a
+    fixed time falls about 4x when dt is halved."""
+    from scipy.linalg import expm
+    A = _debye_matrix(**DEBYE)
+    errs = []
+    for scale, n in ((1.0, 150), (0.5, 300)):
+        r, dt = _debye_relax(DEBYE["er"], DEBYE["sg"], DEBYE["tau"], DEBYE["de"], n, dt_scale=scale)
+        exact = expm(A * n * dt)[0, 0]
+        errs.append(abs(r - exact))
+    assert 0 < errs[0] < 1e-3
+    assert 3.5 <= errs[0] / errs[1] <= 4.5
+
+
+def test_debye_with_zero_increments_is_plain_media():
+    """Declaring poles whose increments are all zero changes no bit of the
+    fields (CPML, wires, sources, every material kind)."""
+    import tests.test_gpu_parity as tp
+    sc = tp._random_case(23, 17, 15, 3, seed=4, nsteps=40)
+    runs = []
+    for debye in (False, True):
+        o = _orc().from_params(sc.params())
+        S.apply(sc, o)
+        if debye:
+            o.set_debye(sc.cell_mat, [1e-9, 5e-8], np.zeros((len(sc.materials), 2)))
+        o.step(sc.n_steps)
+        runs.append([o.get_field(c) for c in range(6)])
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
