@@ -99,6 +99,21 @@ int fdtd_create(const fdtd_params* p, void* hip_stream, fdtd_ctx** out);
  * face.  Errors: EINVAL, ERANGE (id >= n_mat), ENONFINITE, ESTATE. */
 int fdtd_set_materials(fdtd_ctx* c, const uint8_t* cell_mat, const fdtd_material* tab, int n_mat);
 
+/* Debye media (Section 2.4, auxiliary differential equation), after
+ * fdtd_set_materials (which drops earlier poles): n_poles in 1..4 time
+ * constants tau [s] shared by the grid, and for each material m of that
+ * table the pole increments d_eps[m * n_poles + p] (dimensionless, >= 0; 0
+ * for non-dispersive materials).  A material's eps_r is then its eps_inf and
+ * its sigma the static conductivity.  Edges average the increments like eps;
+ * the radial edges of a thin wire scale them by the wire's factor like eps.
+ * Each pole adds a polarisation current per E component,
+ *   tau_p dJ_p/dt + J_p = eps0 d_eps_p dE/dt,
+ * taken at n + 1/2 with the trapezoidal rule, like sigma E; J_p lives in the
+ * workspace (3 n_poles extra arrays of nx*ny*nz values).  Such a grid runs
+ * the split pass whatever fdtd_set_kernel selects, and cannot join a batch.
+ * Needs the semi-implicit loss form.  Errors: EINVAL, ENONFINITE, ESTATE. */
+int fdtd_set_debye(fdtd_ctx* c, int n_poles, const double* tau, const double* d_eps);
+
 /* Perfect-conductor thin wire of the given radius along +axis from node
  * (i, j, k) over n_cells edges (Section 2.3).  The wire's edges are held at
  * zero; eps and sigma of the radial edges at its nodes are multiplied by

@@ -52,6 +52,8 @@ struct orc_sim {
 
   // per-cell materials (x fastest)
   std::vector<double> c_eps, c_sig, c_mu;
+  std::vector<uint8_t> c_mat;       // material ids of the last set_materials
+  int n_mat = 0;
   std::vector<Wire> wires;
   std::vector<Source> srcs;
   std::vector<Probe> probes;
@@ -610,12 +612,17 @@ int orc_set_materials(orc_sim* s, const uint8_t* cm, const orc_material* tab, in
     s->c_sig[c] = m.sigma;
     s->c_mu[c] = m.mu_r * kMu0;
   }
+  s->c_mat.assign(cm, cm + nc);
+  s->n_mat = n_mat;
   return ORC_OK;
 }
 
-int orc_set_debye(orc_sim* s, const uint8_t* cm, int n_mat, int n_poles, const double* tau, const double* d_eps) {
-  if (!s || !cm || !tau || !d_eps || n_mat < 1 || n_mat > 256 || n_poles < 1 || n_poles > 4) return ORC_EINVAL;
+int orc_set_debye(orc_sim* s, int n_poles, const double* tau, const double* d_eps) {
+  if (!s || !tau || !d_eps || n_poles < 1 || n_poles > 4) return ORC_EINVAL;
   if (s->finalized) return fail(s, ORC_ESTATE, "setup after finalize");
+  if (s->n_mat < 1) return fail(s, ORC_ESTATE, "Debye poles before the materials");
+  const int n_mat = s->n_mat;
+  const uint8_t* cm = s->c_mat.data();
   if (s->P.loss_mode != ORC_LOSS_SEMI) return fail(s, ORC_EINVAL, "Debye media need the semi-implicit loss form");
   for (int d = 0; d < n_poles; ++d)
     if (!(tau[d] > 0) || !std::isfinite(tau[d])) return fail(s, ORC_EINVAL, "bad pole time constant");

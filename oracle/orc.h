@@ -55,13 +55,12 @@ int  orc_create(const orc_params* p, orc_sim** out);
 void orc_destroy(orc_sim* s);
 int  orc_set_threads(int n);
 int  orc_set_materials(orc_sim* s, const uint8_t* cell_mat, const orc_material* tab, int n_mat);
-/* Debye media (Section 2.4): n_poles (1..4) time constants tau [s] shared by
- * the grid and, per material, the pole increments d_eps[m * n_poles + p]
- * (dimensionless, >= 0); the material's eps_r is then eps_inf and its sigma
- * the static conductivity.  cell_mat as for orc_set_materials.  Needs the
- * semi-implicit loss form. */
-int  orc_set_debye(orc_sim* s, const uint8_t* cell_mat, int n_mat, int n_poles, const double* tau,
-                   const double* d_eps);
+/* Debye media (Section 2.4), after orc_set_materials: n_poles (1..4) time
+ * constants tau [s] shared by the grid and, per material of that table, the
+ * pole increments d_eps[m * n_poles + p] (dimensionless, >= 0); the
+ * material's eps_r is then eps_inf and its sigma the static conductivity.
+ * Needs the semi-implicit loss form. */
+int  orc_set_debye(orc_sim* s, int n_poles, const double* tau, const double* d_eps);
 int  orc_add_wire(orc_sim* s, int axis, int i, int j, int k, int n_cells, double radius);
 int  orc_add_source(orc_sim* s, int axis, int i, int j, int k, const double* amps, int n);
 int  orc_add_probe(orc_sim* s, int kind, int axis, int i, int j, int k, int n_cells, int* id);

@@ -54,7 +54,7 @@ def lib():
         L.orc_destroy.restype = None
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_set_materials.argtypes = [vp, C.c_void_p, C.POINTER(_Mat), C.c_int]
-        L.orc_set_debye.argtypes = [vp, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+        L.orc_set_debye.argtypes = [vp, C.c_int, C.c_void_p, C.c_void_p]
         L.orc_add_wire.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]
         L.orc_add_source.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int]
         L.orc_add_probe.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -122,16 +122,14 @@ class Oracle:
         tab = (_Mat * len(materials))(*[_Mat(*m) for m in materials])
         self._chk(lib().orc_set_materials(self._h, cm.ctypes.data, tab, len(materials)))
 
-    def set_debye(self, cell_mat, tau, d_eps):
-        """Debye poles: time constants tau[p] [s] and per-material increments
-        d_eps[m][p]; the materials' eps_r is eps_inf (Section 2.4, ADE)."""
-        cm = np.ascontiguousarray(cell_mat, dtype=np.uint8)
-        assert cm.shape == self.shape
+    def set_debye(self, tau, d_eps):
+        """Debye poles, after set_materials: time constants tau[p] [s] and,
+        per material, increments d_eps[m][p]; the materials' eps_r is eps_inf
+        (Section 2.4, ADE)."""
         t = np.ascontiguousarray(tau, dtype=np.float64)
         d = np.ascontiguousarray(d_eps, dtype=np.float64)
         assert d.ndim == 2 and d.shape[1] == t.size
-        self._chk(lib().orc_set_debye(self._h, cm.ctypes.data, d.shape[0], t.size, t.ctypes.data,
-                                      d.ctypes.data))
+        self._chk(lib().orc_set_debye(self._h, t.size, t.ctypes.data, d.ctypes.data))
 
     def add_wire(self, axis, i, j, k, n, radius):
         self._chk(lib().orc_add_wire(self._h, axis, i, j, k, n, radius))

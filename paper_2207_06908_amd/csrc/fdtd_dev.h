@@ -62,6 +62,23 @@ struct GridView {
   double* pr_out;                // [n_probe][max_steps]
 };
 
+// Debye media (auxiliary differential equation), for the split E update:
+// per E component a and pole p the polarisation current J (one array of
+// ncell values each, j[a * 4 + p]), per class and component the pole
+// factors dtab[(class * 3 + a) * 8 + 2 p] = beta_p and [.. + 1] = gam_p,
+// a per-class flag (any pole term), and the decay factors kp.  The update:
+//   E^{n+1} = Ca E^n + Cb curl H - sources - sum_p gam_p J_p^n,
+//   J_p^{n+1} = kp_p J_p^n + beta_p (E^{n+1} - E^n).
+enum { D_MAXPOLE = 4, D_STRIDE = 3 * 2 * D_MAXPOLE };
+template <typename T>
+struct DebyeView {
+  T* j[3 * D_MAXPOLE];
+  const T* dtab;                 // [ncls][3][D_MAXPOLE][2]
+  const unsigned char* dflag;    // [ncls]
+  T kp[D_MAXPOLE];
+  int npole;
+};
+
 }  // namespace mi355fdtd
 
 namespace mi355fdtd {
@@ -74,6 +91,9 @@ namespace mi355fdtd {
 // the (first) source sample.  Returns 0 or a hipError_t value.
 int launch_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, int tile_z,
                 void* stream);
+// Split step (H then E, in place) of a grid with Debye poles: `dview` is a
+// DebyeView<float> or DebyeView<double>.
+int launch_step_debye(int prec, const void* view, const void* dview, int cls16, int step, void* stream);
 
 // Fused (variant 2) or two-step (variant 3) pass of one grid over a tile
 // list: `tiles` is a device array of int4 in 4 groups of counts[q] tiles, by

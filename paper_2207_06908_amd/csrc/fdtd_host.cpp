@@ -53,6 +53,17 @@ struct fdtd_ctx {
   // set-up inputs
   std::vector<uint8_t> cell_mat;
   std::vector<fdtd_material> mats;
+  // Debye media: pole time constants shared by the grid, eps0 * increment
+  // per material and pole; per class the pole factors (dtab, D_STRIDE values)
+  int npole = 0;
+  double tau[D_MAXPOLE] = {0, 0, 0, 0};
+  std::vector<double> mat_deps;       // [material * npole + p]
+  std::vector<double> dtab;           // [ncls][D_STRIDE]
+  std::vector<uint8_t> dflag;         // [ncls]
+  long long debye_nodes = 0;          // nodes whose class has a pole term
+  size_t off_j = 0, off_dtab = 0, off_dflag = 0;
+  DebyeView<float> d32 = {};
+  DebyeView<double> d64 = {};
   std::vector<WireRec> wires;
   std::vector<SrcRec> srcs;
   std::vector<ProbeRec> probes;
@@ -138,6 +149,10 @@ bool edge_updated(const fdtd_ctx* c, int a, const int p[3]) {
 // Coefficient classes
 // -------------------------------------------------------------------------
 
+// A class: the K_NCOEF coefficients, then the D_STRIDE pole factors.
+constexpr int K_ALL = K_NCOEF + D_STRIDE;
+using Coefs = std::array<double, K_ALL>;
+
 // Material id of cell (i, j, k), or 0xFF outside the grid.
 inline uint8_t cell_id(const fdtd_ctx* c, int i, int j, int k) {
   if (i < 0 || j < 0 || k < 0 || i >= c->N[0] || j >= c->N[1] || k >= c->N[2]) return 0xFF;
@@ -159,12 +174,13 @@ inline uint64_t node_key(const fdtd_ctx* c, int i, int j, int k) {
 // E_a: eps, sigma = arithmetic mean over the 4 cells sharing the edge (all
 // must be inside the grid, else the edge lies on a wall and is held at 0).
 // H_a: mu = harmonic mean over the (1 or 2) in-grid cells sharing the face.
-int node_coefs(fdtd_ctx* c, uint64_t key, const NodeMod* mod, std::array<double, K_NCOEF>& out) {
+int node_coefs(fdtd_ctx* c, uint64_t key, const NodeMod* mod, Coefs& out) {
   const double dt = c->dt, dx = c->P.dx;
   auto cell = [&](int q) -> int { return (int)((key >> (8 * q)) & 0xFF); };
+  for (int q = K_NCOEF; q < K_ALL; ++q) out[q] = 0.0;
   for (int a = 0; a < 3; ++a) {
     // cells sharing E_a: index along a fixed at +0 (bit a set), others vary
-    double eps = 0, sig = 0;
+    double eps = 0, sig = 0, de[D_MAXPOLE] = {0, 0, 0, 0};
     bool wall = false;
     for (int s = 0; s < 4; ++s) {
       int bits[3];
@@ -174,24 +190,43 @@ int node_coefs(fdtd_ctx* c, uint64_t key, const NodeMod* mod, std::array<double,
       if (id == 0xFF) { wall = true; break; }
       eps += c->mats[id].eps_r * kEps0;
       sig += c->mats[id].sigma;
+      for (int p = 0; p < c->npole; ++p) de[p] += c->mat_deps[(size_t)id * c->npole + p];
     }
     // The table stores ca - 1, not ca: in a conductor ca is close to 1 and an
     // FP32 ca would keep only a few bits of 1 - ca (the loss per step); the
     // kernels evaluate E + ((ca - 1) E + cb curl), the same update.
+    // Debye poles (auxiliary differential equation, trapezoidal in time):
+    // J_p' = kp J_p + beta_p (E' - E) with beta_p = 2 eps0 de_p / (2 tau_p + dt)
+    // enters Ampere's law as the mean of J_p and J_p', which adds
+    // y = sum_p beta_p dt / (2 eps) to the denominator of ca and cb and the
+    // term -gam_p J_p, gam_p = cb (1 + kp) / 2, to the update.  y = 0 without
+    // poles.
     double cam1 = -1.0, cb = 0;  // perfect conductor: E stays 0
     const bool pec = wall || (mod && (mod->pec >> a) & 1);
     if (!pec) {
       eps *= 0.25;
       sig *= 0.25;
+      double beta[D_MAXPOLE] = {0, 0, 0, 0}, bsum = 0;
+      for (int p = 0; p < c->npole; ++p) {
+        de[p] *= 0.25;
+        if (mod) de[p] *= mod->em[a];
+        beta[p] = 2.0 * de[p] / (2.0 * c->tau[p] + dt);
+        bsum += beta[p];
+      }
       if (mod) { eps *= mod->em[a]; sig *= mod->em[a]; }
       if (c->P.loss_mode == FDTD_LOSS_EXPLICIT) {
         if (sig * dt / eps >= 2.0) return fail(c, FDTD_EUNSTABLE, "literal eq. 4 loss factor below -1");
         cam1 = -sig * dt / eps;             // ca = 1 - sigma dt / eps
         cb = dt / eps;
       } else {
-        const double x = 0.5 * sig * dt / eps;
-        cam1 = -2.0 * x / (1.0 + x);         // ca = (1 - x) / (1 + x)
-        cb = (dt / eps) / (1.0 + x);
+        const double x = 0.5 * sig * dt / eps, y = 0.5 * bsum * dt / eps;
+        cam1 = -2.0 * x / (1.0 + x + y);     // ca = (1 - x + y) / (1 + x + y)
+        cb = (dt / eps) / (1.0 + x + y);
+      }
+      for (int p = 0; p < c->npole; ++p) {
+        const double kp = (2.0 * c->tau[p] - dt) / (2.0 * c->tau[p] + dt);
+        out[K_NCOEF + a * 2 * D_MAXPOLE + 2 * p] = beta[p];
+        out[K_NCOEF + a * 2 * D_MAXPOLE + 2 * p + 1] = cb * (1.0 + kp) / 2.0;
       }
     }
     out[2 * a] = cam1;
@@ -278,13 +313,13 @@ void collect_wire_mods(fdtd_ctx* c, std::unordered_map<long long, NodeMod>& mods
 }
 
 struct TupleKey {
-  std::array<uint64_t, K_NCOEF> b;
+  std::array<uint64_t, K_ALL> b;
   bool operator<(const TupleKey& o) const { return b < o.b; }
 };
 
-TupleKey tuple_key(const fdtd_ctx* c, const std::array<double, K_NCOEF>& v) {
+TupleKey tuple_key(const fdtd_ctx* c, const Coefs& v) {
   TupleKey k;
-  for (int q = 0; q < K_NCOEF; ++q) {
+  for (int q = 0; q < K_ALL; ++q) {
     if (c->P.precision == 64) {
       std::memcpy(&k.b[q], &v[q], 8);
     } else {
@@ -303,17 +338,25 @@ int build_classes(fdtd_ctx* c) {
   std::map<TupleKey, int> by_tuple;
   std::unordered_map<uint64_t, int> by_key;
   c->ctab.clear();
-  auto intern = [&](const std::array<double, K_NCOEF>& v) -> int {
+  c->dtab.clear();
+  c->dflag.clear();
+  auto intern = [&](const Coefs& v) -> int {
     const TupleKey k = tuple_key(c, v);
     auto it = by_tuple.find(k);
     if (it != by_tuple.end()) return it->second;
     const int id = (int)by_tuple.size();
     by_tuple.emplace(k, id);
-    c->ctab.insert(c->ctab.end(), v.begin(), v.end());
+    c->ctab.insert(c->ctab.end(), v.begin(), v.begin() + K_NCOEF);
+    if (c->npole) {
+      c->dtab.insert(c->dtab.end(), v.begin() + K_NCOEF, v.end());
+      bool any = false;
+      for (int q = K_NCOEF; q < K_ALL; ++q) any = any || v[q] != 0.0;
+      c->dflag.push_back(any ? 1 : 0);
+    }
     return id;
   };
   c->cls_id.assign((size_t)c->ncell, 0);
-  std::array<double, K_NCOEF> v;
+  Coefs v;
   for (int k = 0; k < c->N[2]; ++k)
     for (int j = 0; j < c->N[1]; ++j) {
       uint64_t last = ~0ull;
@@ -347,6 +390,9 @@ int build_classes(fdtd_ctx* c) {
   }
   c->ncls = (int)by_tuple.size();
   c->cls16 = c->ncls > 256 ? 1 : 0;
+  c->debye_nodes = 0;
+  if (c->npole)
+    for (long long n = 0; n < c->ncell; ++n) c->debye_nodes += c->dflag[c->cls_id[n]];
   // a source must not sit on a wire edge
   for (const SrcRec& s : c->srcs) {
     auto it = mods.find(node_index(c, s.p[0], s.p[1], s.p[2]));
@@ -460,8 +506,11 @@ void layout(fdtd_ctx* c) {
   for (int s = 0; s < 2; ++s)
     for (int u = 0; u < 3; ++u) c->off_psi[s][u] = take(4 * c->psi_elems[u] * ts);
   c->off_zpl = take((size_t)c->N[0] * c->N[1] * ts);  // zeroed with the fields, never written
+  c->off_j = take((size_t)3 * c->npole * N * ts);     // Debye currents, zeroed with the fields
   c->off_cls = take(N * (c->cls16 ? 2 : 1));
   c->off_ctab = take((size_t)c->ncls * K_STRIDE * ts);
+  c->off_dtab = take(c->npole ? (size_t)c->ncls * D_STRIDE * ts : 0);
+  c->off_dflag = take(c->npole ? (size_t)c->ncls : 0);
   c->off_prof = take(3 * (size_t)P_NROW * 2 * np * ts);
   c->off_src_comp = take(c->srcs.size() * sizeof(int));
   c->off_src_idx = take(c->srcs.size() * sizeof(long long));
@@ -488,6 +537,13 @@ template <>
 GridView<float>& view_of<float>(fdtd_ctx* c, int in, int out) { return c->v32[in][out]; }
 template <>
 GridView<double>& view_of<double>(fdtd_ctx* c, int in, int out) { return c->v64[in][out]; }
+
+template <typename T>
+DebyeView<T>& debye_view_of(fdtd_ctx* c);
+template <>
+DebyeView<float>& debye_view_of<float>(fdtd_ctx* c) { return c->d32; }
+template <>
+DebyeView<double>& debye_view_of<double>(fdtd_ctx* c) { return c->d64; }
 
 template <typename T>
 void fill_view(fdtd_ctx* c, GridView<T>& g, int in, int out) {
@@ -571,6 +627,23 @@ int upload(fdtd_ctx* c) {
     if (!u.n) continue;
     e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(c, e, "upload tables");
+  }
+  std::vector<T> dt;
+  if (c->npole) {
+    DebyeView<T>& d = debye_view_of<T>(c);
+    d = DebyeView<T>{};
+    for (int a = 0; a < 3; ++a)
+      for (int p = 0; p < c->npole; ++p)
+        d.j[a * D_MAXPOLE + p] = (T*)(c->ws + c->off_j) + (size_t)(a * c->npole + p) * (size_t)c->ncell;
+    d.dtab = (const T*)(c->ws + c->off_dtab);
+    d.dflag = (const unsigned char*)(c->ws + c->off_dflag);
+    for (int p = 0; p < c->npole; ++p) d.kp[p] = (T)((2.0 * c->tau[p] - c->dt) / (2.0 * c->tau[p] + c->dt));
+    d.npole = c->npole;
+    dt = convert<T>(c->dtab);
+    e = hipMemcpyAsync((void*)d.dtab, dt.data(), dt.size() * sizeof(T), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void*)d.dflag, c->dflag.data(), c->dflag.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(c, e, "upload Debye tables");
   }
   e = hipMemsetAsync(g.pr_out, 0, c->probes.size() * (size_t)c->P.max_steps * sizeof(double), st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);  // staging buffers are freed on return
@@ -658,6 +731,29 @@ int fdtd_set_materials(fdtd_ctx* c, const uint8_t* cm, const fdtd_material* tab,
     if (cm[n] >= n_mat) return fail(c, FDTD_ERANGE, "material id outside the table");
   c->cell_mat.assign(cm, cm + c->ncell);
   c->mats.assign(tab, tab + n_mat);
+  c->npole = 0;  // pole increments refer to a material table: set them again
+  c->mat_deps.clear();
+  return FDTD_OK;
+}
+
+int fdtd_set_debye(fdtd_ctx* c, int n_poles, const double* tau, const double* d_eps) {
+  if (!c || !tau || !d_eps || n_poles < 1 || n_poles > D_MAXPOLE) return fail(c, FDTD_EINVAL, "bad Debye arguments");
+  if (c->frozen) return fail(c, FDTD_ESTATE, "set-up after the workspace size was taken");
+  if (c->mats.empty()) return fail(c, FDTD_ESTATE, "Debye poles before the materials");
+  if (c->P.loss_mode != FDTD_LOSS_SEMI) return fail(c, FDTD_EINVAL, "Debye media need the semi-implicit loss form");
+  const size_t nm = c->mats.size();
+  for (int p = 0; p < n_poles; ++p)
+    if (!std::isfinite(tau[p])) return fail(c, FDTD_ENONFINITE, "non-finite pole time constant");
+  for (size_t q = 0; q < nm * n_poles; ++q)
+    if (!std::isfinite(d_eps[q])) return fail(c, FDTD_ENONFINITE, "non-finite pole increment");
+  for (int p = 0; p < n_poles; ++p)
+    if (!(tau[p] > 0)) return fail(c, FDTD_EINVAL, "pole time constant not positive");
+  for (size_t q = 0; q < nm * n_poles; ++q)
+    if (!(d_eps[q] >= 0)) return fail(c, FDTD_EINVAL, "negative pole increment");
+  c->npole = n_poles;
+  for (int p = 0; p < n_poles; ++p) c->tau[p] = tau[p];
+  c->mat_deps.assign(nm * n_poles, 0.0);
+  for (size_t q = 0; q < nm * n_poles; ++q) c->mat_deps[q] = kEps0 * d_eps[q];
   return FDTD_OK;
 }
 
@@ -843,6 +939,7 @@ int fdtd_step(fdtd_ctx* c, int n) {
   const bool tb2_ok = tb2_cpml_fits(c->P.npml, c->P.precision);
   int chosen = c->variant != FDTD_KERNEL_AUTO ? c->variant : listable ? FDTD_KERNEL_TB2 : FDTD_KERNEL_FUSED;
   if (chosen == FDTD_KERNEL_TB2 && !tb2_ok) chosen = FDTD_KERNEL_FUSED;
+  if (c->npole) chosen = FDTD_KERNEL_SPLIT;  // Debye media: the split pass only
   for (int t = 0; t < n;) {
     // the two-step pass needs two steps; an odd remainder takes one fused step
     const int variant = (chosen == FDTD_KERNEL_TB2 && n - t < 2) ? FDTD_KERNEL_FUSED : chosen;
@@ -891,6 +988,9 @@ int fdtd_step(fdtd_ctx* c, int n) {
         if (he == hipSuccess) he = hipStreamWaitEvent(c->stream, c->ev_join, 0);
         if (he != hipSuccess) return hip_fail(c, he, "stream join");
       }
+    } else if (c->npole) {
+      const void* dview = c->P.precision == 64 ? (const void*)&c->d64 : (const void*)&c->d32;
+      e = launch_step_debye(c->P.precision, view, dview, c->cls16, (int)c->steps_done, (void*)c->stream);
     } else {
       e = launch_step(c->P.precision, view, c->cls16, variant, (int)c->steps_done, c->tile_y, c->tile_z,
                       (void*)c->stream);
@@ -1021,6 +1121,8 @@ double fdtd_algorithmic_bytes_per_step(const fdtd_ctx* c) {
   // each CPML slab cell reads and writes 4 psi values per axis it lies in
   for (int u = 0; u < 3; ++u) b += (double)c->psi_elems[u] * 4.0 * 2.0 * ts;
   // (psi_elems counts the whole 2 npml slab pair of an axis)
+  // a node with Debye poles reads and writes one current per component and pole
+  b += (double)c->debye_nodes * 3.0 * c->npole * 2.0 * ts;
   return b;
 }
 
@@ -1237,6 +1339,7 @@ int fdtd_batch_pack(fdtd_ctx* const* grids, int n, void* hip_stream, fdtd_batch*
     int rc = freeze(c);
     if (rc) { delete b; return rc; }
     if (c->ws) { delete b; return FDTD_ESTATE; }  // already bound on its own
+    if (c->npole) { delete b; return FDTD_EINVAL; }  // Debye media run on their own (split pass)
     if (g == 0) {
       b->prec = c->P.precision;
       b->cls16 = c->cls16;

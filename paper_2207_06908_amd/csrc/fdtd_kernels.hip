@@ -264,6 +264,49 @@ __global__ __launch_bounds__(256) void k_e_split(GridView<T> g, int step) {
   stg(g.fo[2], n, e[2]);
 }
 
+// Split E update in Debye media: the plain update, then the pole currents.
+// Nodes whose class has no pole term (air, walls, wire edges) skip them, so
+// their J stays 0 without traffic.
+template <typename T, typename CI, bool PML>
+__global__ __launch_bounds__(256) void k_e_split_debye(GridView<T> g, DebyeView<T> d, int step) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const unsigned n = (unsigned)i + (unsigned)g.nx * ((unsigned)j + (unsigned)g.ny * (unsigned)k);
+  const int cid = (int)ldg((const CI*)g.cls, n);
+  const T* cf = g.ctab + cid * K_STRIDE;
+  const T hx = ldg(g.fi[3], n), hy = ldg(g.fi[4], n), hz = ldg(g.fi[5], n);
+  const T hx_j = (j > 0) ? ldg(g.fi[3], n - (unsigned)g.nx) : T(0);
+  const T hx_k = (k > 0) ? ldg(g.fi[3], n - (unsigned)g.sxy) : T(0);
+  const T hy_i = (i > 0) ? ldg(g.fi[4], n - 1) : T(0);
+  const T hy_k = (k > 0) ? ldg(g.fi[4], n - (unsigned)g.sxy) : T(0);
+  const T hz_i = (i > 0) ? ldg(g.fi[5], n - 1) : T(0);
+  const T hz_j = (j > 0) ? ldg(g.fi[5], n - (unsigned)g.nx) : T(0);
+  const T eold[3] = {ldg(g.fi[0], n), ldg(g.fi[1], n), ldg(g.fi[2], n)};
+  T e[3];
+  e_point<T, PML>(g, i, j, k, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, e);
+  if (ldg(d.dflag, (unsigned)cid)) {
+    const T* dt = d.dtab + cid * D_STRIDE;
+    for (int a = 0; a < 3; ++a) {
+      T jo[D_MAXPOLE];
+      T sum = T(0);
+      for (int p = 0; p < D_MAXPOLE; ++p) {
+        jo[p] = p < d.npole ? ldg(d.j[a * D_MAXPOLE + p], n) : T(0);
+        sum += ldg(dt, (unsigned)(a * 2 * D_MAXPOLE + 2 * p + 1)) * jo[p];
+      }
+      e[a] -= sum;
+      const T de = e[a] - eold[a];
+      for (int p = 0; p < D_MAXPOLE; ++p)
+        if (p < d.npole)
+          stg(d.j[a * D_MAXPOLE + p], n, d.kp[p] * jo[p] + ldg(dt, (unsigned)(a * 2 * D_MAXPOLE + 2 * p)) * de);
+    }
+  }
+  stg(g.fo[0], n, e[0]);
+  stg(g.fo[1], n, e[1]);
+  stg(g.fo[2], n, e[2]);
+}
+
 // ---------------------------------------------------------------------------
 // fused variant
 //
@@ -1001,6 +1044,34 @@ hipError_t step_split(const GridView<T>& g, int step, hipStream_t st) {
     hipLaunchKernelGGL((k_e_split<T, CI, false>), grd, blk, 0, st, g, step);
   }
   return hipGetLastError();
+}
+
+template <typename T, typename CI>
+hipError_t step_split_debye(const GridView<T>& g, const DebyeView<T>& d, int step, hipStream_t st) {
+  const dim3 blk(64, 4, 1), grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+  if (g.npml > 0) {
+    hipLaunchKernelGGL((k_h_split<T, CI, true>), grd, blk, 0, st, g);
+    hipLaunchKernelGGL((k_e_split_debye<T, CI, true>), grd, blk, 0, st, g, d, step);
+  } else {
+    hipLaunchKernelGGL((k_h_split<T, CI, false>), grd, blk, 0, st, g);
+    hipLaunchKernelGGL((k_e_split_debye<T, CI, false>), grd, blk, 0, st, g, d, step);
+  }
+  return hipGetLastError();
+}
+
+int launch_step_debye(int prec, const void* view, const void* dview, int cls16, int step, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (prec == 64) {
+    const GridView<double>& g = *(const GridView<double>*)view;
+    const DebyeView<double>& d = *(const DebyeView<double>*)dview;
+    e = cls16 ? step_split_debye<double, uint16_t>(g, d, step, st) : step_split_debye<double, uint8_t>(g, d, step, st);
+  } else {
+    const GridView<float>& g = *(const GridView<float>*)view;
+    const DebyeView<float>& d = *(const DebyeView<float>*)dview;
+    e = cls16 ? step_split_debye<float, uint16_t>(g, d, step, st) : step_split_debye<float, uint8_t>(g, d, step, st);
+  }
+  return (int)e;
 }
 
 template <typename T, typename CI, bool PML, int TX, int TY>

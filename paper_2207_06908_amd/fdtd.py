@@ -40,6 +40,7 @@ SIGNATURES = [
     ("fdtd_default_params", None, [C.POINTER(Params)]),
     ("fdtd_create", C.c_int, [C.POINTER(Params), _vp, C.POINTER(_vp)]),
     ("fdtd_set_materials", C.c_int, [_vp, _vp, C.POINTER(Material), C.c_int]),
+    ("fdtd_set_debye", C.c_int, [_vp, C.c_int, _vp, _vp]),
     ("fdtd_add_wire", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]),
     ("fdtd_add_source", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int]),
     ("fdtd_add_probe", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -150,6 +151,15 @@ class Grid:
             raise ValueError(f"cell_mat shape {cm.shape} != {self.shape}")
         tab = (Material * len(materials))(*[Material(*m) for m in materials])
         self._chk(lib().fdtd_set_materials(self._h, cm.ctypes.data, tab, len(materials)))
+
+    def set_debye(self, tau, d_eps):
+        """Debye poles, after set_materials: time constants tau[p] [s] and,
+        per material, increments d_eps[m][p]; the materials' eps_r is eps_inf."""
+        t = np.ascontiguousarray(tau, dtype=np.float64)
+        d = np.ascontiguousarray(d_eps, dtype=np.float64)
+        if d.ndim != 2 or d.shape[1] != t.size:
+            raise ValueError("d_eps must be [n_materials][n_poles]")
+        self._chk(lib().fdtd_set_debye(self._h, t.size, t.ctypes.data, d.ctypes.data))
 
     def add_wire(self, axis, i, j, k, n, radius):
         self._chk(lib().fdtd_add_wire(self._h, axis, i, j, k, n, radius))

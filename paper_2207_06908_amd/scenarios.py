@@ -25,7 +25,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import List, Tuple
+from typing import List, Tuple, Optional
 
 import numpy as np
 
@@ -147,6 +147,9 @@ class Scenario:
     wires: List[Tuple[int, int, int, int, int, float]] = field(default_factory=list)   # axis, i, j, k, n_cells, radius
     sources: List[Tuple[int, int, int, int, np.ndarray]] = field(default_factory=list)  # axis, i, j, k, amps
     probes: List[Tuple[str, int, int, int, int, int, int]] = field(default_factory=list)  # name, kind, axis, i, j, k, n_cells
+    # Debye poles: (tau [s] per pole, increments [material][pole]); the
+    # materials' eps_r is then eps_inf
+    debye: Optional[Tuple[List[float], np.ndarray]] = None
     meta: dict = field(default_factory=dict)
 
     @property
@@ -165,6 +168,8 @@ def apply(sc: Scenario, sim) -> List[int]:
     """Feed a scenario into any backend exposing set_materials / add_wire /
     add_source / add_probe (duck-typed).  Returns the probe ids in order."""
     sim.set_materials(sc.cell_mat, sc.materials)
+    if sc.debye is not None:
+        sim.set_debye(*sc.debye)
     for w in sc.wires:
         sim.add_wire(*w)
     for (ax, i, j, k, amps) in sc.sources:
@@ -244,6 +249,26 @@ def config2(nx: int = 512, ny: int = 512, nz: int = 384, dx: float = 0.5, npml: 
     return Scenario(f"config2_{nx}x{ny}x{nz}_cpml{npml}", nx, ny, nz, dx, dt, n_steps, cm, mats,
                     npml=npml, wires=wires, sources=[(AX_Z, ic, jc, kg, amps)], probes=probes,
                     meta=dict(ks=ks, kg=kg))
+
+
+# Measured soil of the paper's buried-wire example (Section 3, four-term
+# Debye expansion): eps_inf, static conductivity [S/m], and per pole
+# (delta eps, tau [s]).
+DEBYE_SOIL_EPS_INF = 16.381
+DEBYE_SOIL_SIGMA0 = 2.684e-3
+DEBYE_SOIL_POLES = ((92.103, 7.404e-6), (20.825, 1.062e-6), (374.768, 2.162e-5), (10.387, 1.008e-8))
+
+
+def config2_debye(**kw) -> Scenario:
+    """The config-2 scene (any of config2's size arguments) with both soil
+    layers replaced by the paper's measured four-pole Debye soil."""
+    sc = config2(**kw)
+    sc.name = sc.name.replace("config2", "config2_debye")
+    soil = (DEBYE_SOIL_EPS_INF, DEBYE_SOIL_SIGMA0, 1.0)
+    sc.materials = [AIR, soil, soil]
+    de = np.array([[0.0] * 4] + [[p[0] for p in DEBYE_SOIL_POLES]] * 2)
+    sc.debye = ([p[1] for p in DEBYE_SOIL_POLES], de)
+    return sc
 
 
 def config2_small(n_steps: int = 1200) -> Scenario:

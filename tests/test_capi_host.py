@@ -167,3 +167,36 @@ def test_classes_config2_small_with_cpml():
     n, npml = sc.nx, sc.npml
     slab = 2 * npml * (sc.ny * sc.nz + sc.nx * sc.nz + sc.nx * sc.ny)
     assert g.algorithmic_bytes_per_step() == pytest.approx(sc.cells * 49.0 + slab * 32.0)
+
+
+def test_debye_validation_and_workspace():
+    """fdtd_set_debye: tau > 0, increments >= 0 and finite, at most 4
+    poles, before the set-up freezes, the semi-implicit loss form only; the currents add 3 n_poles
+    arrays to the workspace; a Debye grid cannot join a batch."""
+    cm = np.zeros((9, 10, 12), np.uint8)
+    cm[:4] = 1
+    mats = [(1.0, 0.0, 1.0), (10.0, 0.01, 1.0)]
+    d_eps = [[0.0, 0.0], [5.0, 20.0]]
+    g = _grid()
+    g.set_materials(cm, mats)
+    assert _code(lambda: g.set_debye([1e-9, -1e-8], d_eps)) == -1
+    assert _code(lambda: g.set_debye([1e-9, 1e-8], [[0.0, 0.0], [5.0, -1.0]])) == -1
+    assert _code(lambda: g.set_debye([1e-9, float("nan")], d_eps)) == -7
+    assert _code(lambda: g.set_debye([1e-9] * 5, [[0.0] * 5, [1.0] * 5])) == -1
+    with pytest.raises(ValueError):
+        g.set_debye([1e-9], d_eps)
+    plain = _grid()
+    plain.set_materials(cm, mats)
+    g.set_debye([1e-9, 1e-8], d_eps)
+    extra = g.workspace_bytes() - plain.workspace_bytes()
+    n = 12 * 10 * 9
+    assert 3 * 2 * n * 4 <= extra <= 3 * 2 * n * 4 + 4096
+    assert g.algorithmic_bytes_per_step() > plain.algorithmic_bytes_per_step()
+    assert _code(lambda: g.set_debye([1e-9], [[0.0], [1.0]])) == -3  # frozen
+    lit = _grid(loss_mode=1)
+    lit.set_materials(cm, mats)
+    assert _code(lambda: lit.set_debye([1e-9, 1e-8], d_eps)) == -1
+    b = _grid()
+    b.set_materials(cm, mats)
+    b.set_debye([1e-9, 1e-8], d_eps)
+    assert _code(lambda: fdtd.Batch([b], tile=(32, 8, 32))) == -1

@@ -1,0 +1,126 @@
+"""GPU parity for Debye media (Section 2.4, auxiliary differential equation):
+the split pass with polarisation currents against the FP64 oracle on the
+same seeded inputs, element by element (FP64 1e-11, FP32 2e-5 of the largest
+value), and the special cases that must reproduce other runs bit for bit."""
+import numpy as np
+import pytest
+
+from paper_2207_06908_amd import scenarios as S
+from tests.test_gpu_parity import _random_case
+
+pytestmark = pytest.mark.gpu
+
+TAU = [2e-10, 3e-9, 4e-8]
+
+
+@pytest.fixture(scope="module")
+def fd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2207_06908_amd import fdtd
+    fdtd.lib()
+    return fdtd
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _debye_case(nx, ny, nz, npml, seed, nsteps=60):
+    """The random case (CPML, wires along all axes, sources, every probe
+    kind) with pole increments on half of its materials."""
+    sc = _random_case(nx, ny, nz, npml, seed=seed, nsteps=nsteps)
+    rng = np.random.default_rng(seed + 100)
+    de = rng.uniform(0.5, 30.0, size=(len(sc.materials), len(TAU)))
+    de[::2] = 0.0
+    sc.debye = (TAU, de)
+    return sc
+
+
+@pytest.mark.parametrize("dims,npml", [((70, 13, 11), 3), ((33, 41, 17), 4), ((64, 8, 8), 0)])
+def test_debye_fields_elementwise(fd, oracle_mod, dims, npml):
+    sc = _debye_case(*dims, npml, seed=dims[0] + dims[2])
+    _say(f"debye fields {dims} npml={npml}")
+    o = oracle_mod.Oracle.from_params(sc.params())
+    ids_o = S.apply(sc, o)
+    o.step(sc.n_steps)
+    for prec, tol in ((64, 1e-11), (32, 2e-5)):
+        g = fd.Grid.from_params(sc.params(), precision=prec)
+        ids = S.apply(sc, g)
+        g.step(sc.n_steps)
+        for c in range(6):
+            ref, got = o.get_field(c), g.get_field(c)
+            scale = max(float(np.abs(ref).max()), 1e-300)
+            assert np.isfinite(got).all()
+            err = float(np.abs(got - ref).max()) / scale
+            assert err <= tol, (prec, c, err)
+        for a, b in zip(ids_o, ids):
+            ref, got = o.probe(a), g.probe(b)
+            scale = max(float(np.abs(ref).max()), 1e-300)
+            assert float(np.abs(got - ref).max()) / scale <= tol * 10, prec
+
+
+def test_debye_changes_the_fields(fd):
+    """The pole terms are not a no-op: with increments the fields differ from
+    the same grid without them by far more than rounding."""
+    sc = _debye_case(40, 20, 16, 3, seed=7)
+    runs = []
+    for debye in (True, False):
+        s2 = _debye_case(40, 20, 16, 3, seed=7)
+        if not debye:
+            s2.debye = None
+        g = fd.Grid.from_params(s2.params(), precision=32)
+        S.apply(s2, g)
+        g.step(sc.n_steps)
+        runs.append(g.get_field(2))
+    scale = float(np.abs(runs[1]).max())
+    assert float(np.abs(runs[0] - runs[1]).max()) > 1e-3 * scale
+
+
+def test_debye_zero_increments_bitwise_split(fd):
+    """Poles whose increments are all zero give the bits of the plain split
+    pass (classes, coefficients and the update reduce exactly)."""
+    outs = []
+    for debye in (True, False):
+        sc = _random_case(45, 21, 13, 3, seed=9, nsteps=40)
+        if debye:
+            sc.debye = (TAU, np.zeros((len(sc.materials), len(TAU))))
+        g = fd.Grid.from_params(sc.params(), precision=32)
+        ids = S.apply(sc, g)
+        g.set_kernel(1)
+        g.step(sc.n_steps)
+        outs.append(([g.get_field(c) for c in range(6)], [g.probe(i) for i in ids]))
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(a, b)
+    for a, b in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("variant,ty,tz", [(0, 0, 0), (2, 8, 32), (3, 8, 20)])
+def test_debye_grid_takes_the_split_pass(fd, variant, ty, tz):
+    """Whatever variant is asked for, a Debye grid runs the split pass: the
+    same bits as an explicit split request, in odd step chunks."""
+    outs = []
+    for v, y, z in ((1, 0, 0), (variant, ty, tz)):
+        sc = _debye_case(50, 19, 15, 3, seed=12, nsteps=41)
+        g = fd.Grid.from_params(sc.params(), precision=32)
+        S.apply(sc, g)
+        g.set_kernel(v, y, z)
+        for c in (3, 20, 18):
+            g.step(c)
+        outs.append([g.get_field(c) for c in range(6)])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_config2_debye_small_probes(fd, oracle_mod):
+    """The config-2 scene on a 96 x 96 x 80 grid with the paper's measured
+    four-pole Debye soil in both layers, 600 steps: every probe within
+    relative L2 1e-5 of the oracle."""
+    from tests.parity import assert_probes_close
+    sc = S.config2_debye(nx=96, ny=96, nz=80, dx=0.5, npml=10, wire_cells=12, n_steps=600,
+                         e_probe_offsets=(5, 10, 20, 30))
+    _say("config2 debye small")
+    ref = oracle_mod.run_scenario(sc, S.apply)
+    got = fd.run_scenario(sc, S.apply, precision=32)
+    assert_probes_close(got, ref, 1e-5)

@@ -614,7 +614,7 @@ def _debye_relax(er, sg, tau, de, nsteps, dt_scale=1.0):
     o = _orc()(nx, ny, nz, dx, dt=dt, max_steps=nsteps)
     cm = np.zeros((nz, ny, nx), np.uint8)
     o.set_materials(cm, [(er, sg, 1.0)])
-    o.set_debye(cm, tau, [de])
+    o.set_debye(tau, [de])
     rng = np.random.default_rng(3)
     phi = np.zeros((nz + 1, ny + 1, nx + 1))
     phi[1:-1, 1:-1, 1:-1] = rng.integers(-50, 50, size=(nz - 1, ny - 1, nx - 1))
@@ -686,7 +686,7 @@ def test_debye_with_zero_increments_is_plain_media():
         o = _orc().from_params(sc.params())
         S.apply(sc, o)
         if debye:
-            o.set_debye(sc.cell_mat, [1e-9, 5e-8], np.zeros((len(sc.materials), 2)))
+            o.set_debye([1e-9, 5e-8], np.zeros((len(sc.materials), 2)))
         o.step(sc.n_steps)
         runs.append([o.get_field(c) for c in range(6)])
     for a, b in zip(*runs):
