@@ -165,6 +165,42 @@ def bench_batch(warmup: int = 100, graph_steps: int = 100, tune: bool = True):
     return out
 
 
+def bench_debye(steps: int = 400, warmup: int = 20):
+    """The 512 x 512 x 384 scene with the paper's measured four-pole Debye
+    soil in both layers: the split pass with polarisation currents."""
+    import torch
+    from paper_2207_06908_amd import fdtd
+    from paper_2207_06908_amd import scenarios as S
+    sc = S.config2_debye(n_steps=warmup + steps)
+    g = fdtd.Grid.from_params(sc.params(), precision=32)
+    S.apply(sc, g)
+    g.bind()
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g.timing(True)
+    e0.record()
+    g.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kms, kn = g.kernel_time()
+    bytes_step = g.algorithmic_bytes_per_step()
+    achieved = bytes_step / (kms / max(kn, 1) / 1e3) / 1e9
+    out = {"workload": "512x512x384 Yee FDTD as above, both soil layers four-pole Debye soil "
+                       "(eps_inf 16.381, sigma0 2.684 mS/m), ADE currents",
+           "kernel": "k_h_split + k_e_split_debye (two launches per step)",
+           "cells": sc.cells, "steps": steps,
+           "value": round(sc.cells * steps / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
+           "ms_per_step": round(ms / steps, 5),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_step": bytes_step,
+                        "kernel_ms_per_step": round(kms / max(kn, 1), 5)}}
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 def calibrate_copy(mib: int = 1024, reps: int = 3):
     """Plain device-to-device copies of known size, run under the profiler's
     FETCH_SIZE / WRITE_SIZE counters to scale them to true HBM bytes."""
@@ -236,6 +272,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-grid sweep measurement")
     ap.add_argument("--no-tune", action="store_true", help="batched leg: fixed 32x8 tiles, TZ 32")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-in-the-loop measurement")
+    ap.add_argument("--no-debye", action="store_true", help="skip the Debye-soil measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run plain copies of MIB MiB (profiler counter calibration)")
     a = ap.parse_args()
@@ -323,6 +360,8 @@ def main():
     out["roofline"]["stream_triad_GBs"] = triad_gbs
     if not a.no_batch:
         out["batched"] = bench_batch(tune=not a.no_tune)
+    if not a.no_debye:
+        out["debye"] = bench_debye()
     if not a.no_surrogate:
         out["surrogate"] = bench_surrogate()
     if not a.no_cpu_baseline:

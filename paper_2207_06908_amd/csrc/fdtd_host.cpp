@@ -223,10 +223,12 @@ int node_coefs(fdtd_ctx* c, uint64_t key, const NodeMod* mod, Coefs& out) {
         cam1 = -2.0 * x / (1.0 + x + y);     // ca = (1 - x + y) / (1 + x + y)
         cb = (dt / eps) / (1.0 + x + y);
       }
+      // (a pole with no increment keeps J = 0: its factors stay 0, so that
+      // the class carries no pole term)
       for (int p = 0; p < c->npole; ++p) {
         const double kp = (2.0 * c->tau[p] - dt) / (2.0 * c->tau[p] + dt);
         out[K_NCOEF + a * 2 * D_MAXPOLE + 2 * p] = beta[p];
-        out[K_NCOEF + a * 2 * D_MAXPOLE + 2 * p + 1] = cb * (1.0 + kp) / 2.0;
+        out[K_NCOEF + a * 2 * D_MAXPOLE + 2 * p + 1] = beta[p] != 0.0 ? cb * (1.0 + kp) / 2.0 : 0.0;
       }
     }
     out[2 * a] = cam1;
