@@ -1,11 +1,17 @@
 // orc.cpp -- FP64 CPU reference for the Yee FDTD hot path (test infrastructure).
 //
 // Plain triple loops, one per field component, written from the equations of
-// Section 2.1 of the paper (eqs. 2-5) and the readings stated below.  No
+// Section 2.1 of the paper (eqs. 2-5), the CPML and thin wire of Sections
+// 2.2-2.3, the Debye media of Section 2.4, and the readings stated below.  No
 // tiling, no fusion, no reordering beyond "all H, then all E, then the
-// sources, then the probes" within a step.  OpenMP splits the outer k loop of
-// each component update; every update reads only values that the same loop
-// does not write, so the result is independent of the thread count.
+// sources, then the Debye currents, then the probes" within a step.  OpenMP
+// splits the outer k loop of each component update; every update reads only
+// values that the same loop does not write, so the result is independent of
+// the thread count.
+//
+// Parity unpinned (no closed form or published value to check against): the
+// interface averaging of eps, sigma, mu and pole increments, and the thin-wire
+// scaling of pole increments in Debye media.
 #include "orc.h"
 
 #include <cmath>
@@ -195,7 +201,8 @@ void build_materials(orc_sim* s) {
 // wires keeps the factor of the first wire added.  In Debye media the radial
 // edges scale the whole permittivity function by m (eps_inf, sigma and each
 // pole's increment), a reading of the paper's note that the wire models are
-// adapted to Debye media.
+// adapted to Debye media (parity unpinned: the adaptation it cites is not
+// available).
 void scale_mu(orc_sim* s, int a, const int p[3], double m) {
   A3& h = s->mu[a];
   if (!h.in(p[0], p[1], p[2])) return;
