@@ -44,6 +44,7 @@ struct A3 {
 
 struct Wire { int axis, p[3], n; double radius; };
 struct Source { int axis, p[3]; std::vector<double> amps; };
+struct Lumped { int kind, axis, p[3]; double value; };
 struct Probe { int kind, axis, p[3], n; std::vector<double> rec; };
 
 }  // namespace
@@ -62,6 +63,7 @@ struct orc_sim {
   int n_mat = 0;
   std::vector<Wire> wires;
   std::vector<Source> srcs;
+  std::vector<Lumped> lumped;
   std::vector<Probe> probes;
 
   // fields at their natural Yee extents
@@ -266,6 +268,17 @@ void apply_wires(orc_sim* s) {
   }
 }
 
+// Lumped elements (Section 2.1, lumped circuit elements): a resistor R or a
+// capacitor C across one E edge of length dx in a cell of cross-section dx^2
+// is the conductivity dx / (R dx^2) = 1 / (R dx) or the permittivity
+// C dx / dx^2 = C / dx, added to the edge's own after the wire changes.
+void apply_lumped(orc_sim* s) {
+  for (const Lumped& l : s->lumped) {
+    A3& target = l.kind == ORC_LUMPED_R ? s->sig[l.axis] : s->eps[l.axis];
+    target(l.p[0], l.p[1], l.p[2]) += l.kind == ORC_LUMPED_R ? 1.0 / (l.value * s->dx) : l.value / s->dx;
+  }
+}
+
 // Lossy coefficients for E = Ca E + Cb curl H.  Literal eq. 4:
 // Ca = 1 - sigma dt / eps, Cb = dt / eps.  Semi-implicit (sigma E taken at
 // n + 1/2 as the mean of n and n + 1, the modification the paper points to
@@ -385,6 +398,12 @@ int finalize(orc_sim* s) {
       }
   build_materials(s);
   apply_wires(s);
+  for (const Lumped& l : s->lumped) {
+    const A3& e = s->E[l.axis];
+    if (s->pec[l.axis][((size_t)l.p[2] * e.n1 + l.p[1]) * e.n0 + l.p[0]])
+      return fail(s, ORC_ERANGE, "lumped element on a wire (perfect-conductor) edge");
+  }
+  apply_lumped(s);
   int rc = build_coefficients(s);
   if (rc) return rc;
   for (int a = 0; a < 3; ++a) {  // the update needs only the coefficients
@@ -660,6 +679,33 @@ int orc_add_wire(orc_sim* s, int axis, int i, int j, int k, int n, double radius
   Wire w{axis, {i, j, k}, n, radius};
   s->wires.push_back(w);
   return ORC_OK;
+}
+
+int orc_add_lumped(orc_sim* s, int kind, int axis, int i, int j, int k, double value) {
+  if (!s || axis < 0 || axis > 2 || (kind != ORC_LUMPED_R && kind != ORC_LUMPED_C)) return ORC_EINVAL;
+  if (s->finalized) return fail(s, ORC_ESTATE, "setup after finalize");
+  if (!(value > 0) || !std::isfinite(value)) return fail(s, ORC_EINVAL, "lumped value not positive");
+  const int p[3] = {i, j, k};
+  if (!e_interior(s, axis, p)) return fail(s, ORC_ERANGE, "lumped edge outside the updated edges");
+  s->lumped.push_back({kind, axis, {i, j, k}, value});
+  return ORC_OK;
+}
+
+// Non-ideal sources as their Norton equivalents: a current source I with a
+// shunt resistance r (r <= 0: ideal), or a voltage source V with a series
+// resistance r > 0, which is the current V / r in parallel with r.  Positive
+// values drive current toward +axis inside the source (the +axis end is the
+// positive terminal of a voltage source).
+int orc_add_source_r(orc_sim* s, int kind, int axis, int i, int j, int k, const double* amps, int n, double r) {
+  if (!s || !amps || n < 1 || (kind != ORC_SRC_CURRENT && kind != ORC_SRC_VOLTAGE)) return ORC_EINVAL;
+  if (kind == ORC_SRC_VOLTAGE && !(r > 0)) return fail(s, ORC_EINVAL, "a voltage source needs r > 0");
+  if (!std::isfinite(r)) return fail(s, ORC_EINVAL, "non-finite internal resistance");
+  std::vector<double> cur(amps, amps + n);
+  if (kind == ORC_SRC_VOLTAGE)
+    for (double& v : cur) v /= r;
+  int rc = orc_add_source(s, axis, i, j, k, cur.data(), n);
+  if (rc || !(r > 0)) return rc;
+  return orc_add_lumped(s, ORC_LUMPED_R, axis, i, j, k, r);
 }
 
 int orc_add_source(orc_sim* s, int axis, int i, int j, int k, const double* amps, int n) {

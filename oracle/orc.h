@@ -37,6 +37,8 @@ enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ERANGE = -2, ORC_ESTATE = -3, ORC_EUNSTA
 enum { ORC_EX = 0, ORC_EY, ORC_EZ, ORC_HX, ORC_HY, ORC_HZ };
 enum { ORC_PR_E = 0, ORC_PR_VLINE = 1, ORC_PR_ILOOP = 2 };
 enum { ORC_LOSS_SEMI = 0, ORC_LOSS_EXPLICIT = 1 };
+enum { ORC_SRC_CURRENT = 0, ORC_SRC_VOLTAGE = 1 };
+enum { ORC_LUMPED_R = 0, ORC_LUMPED_C = 1 };
 
 typedef struct orc_sim orc_sim;
 typedef struct { double eps_r, sigma, mu_r; } orc_material;
@@ -63,6 +65,12 @@ int  orc_set_materials(orc_sim* s, const uint8_t* cell_mat, const orc_material* 
 int  orc_set_debye(orc_sim* s, int n_poles, const double* tau, const double* d_eps);
 int  orc_add_wire(orc_sim* s, int axis, int i, int j, int k, int n_cells, double radius);
 int  orc_add_source(orc_sim* s, int axis, int i, int j, int k, const double* amps, int n);
+/* Lumped resistor (R [ohm]) or capacitor (C [F]) on an updated E edge:
+ * sigma += 1 / (R dx), eps += C / dx on that edge. */
+int  orc_add_lumped(orc_sim* s, int kind, int axis, int i, int j, int k, double value);
+/* Non-ideal source: current source with shunt resistance r (r <= 0 ideal),
+ * or voltage source [V] with series resistance r > 0 (Norton equivalent). */
+int  orc_add_source_r(orc_sim* s, int kind, int axis, int i, int j, int k, const double* amps, int n, double r);
 int  orc_add_probe(orc_sim* s, int kind, int axis, int i, int j, int k, int n_cells, int* id);
 int  orc_step(orc_sim* s, int n_steps);
 int  orc_probe(orc_sim* s, int id, double* out, int n_max, int* n_written);

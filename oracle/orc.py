@@ -57,6 +57,9 @@ def lib():
         L.orc_set_debye.argtypes = [vp, C.c_int, C.c_void_p, C.c_void_p]
         L.orc_add_wire.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]
         L.orc_add_source.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int]
+        L.orc_add_lumped.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]
+        L.orc_add_source_r.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int,
+                                       C.c_double]
         L.orc_add_probe.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                     C.POINTER(C.c_int)]
         L.orc_step.argtypes = [vp, C.c_int]
@@ -137,6 +140,16 @@ class Oracle:
     def add_source(self, axis, i, j, k, amps):
         a = np.ascontiguousarray(amps, dtype=np.float64)
         self._chk(lib().orc_add_source(self._h, axis, i, j, k, a.ctypes.data, a.size))
+
+    def add_lumped(self, kind, axis, i, j, k, value):
+        """Lumped resistor (kind 0, ohm) or capacitor (kind 1, F) on an E edge."""
+        self._chk(lib().orc_add_lumped(self._h, kind, axis, i, j, k, float(value)))
+
+    def add_source_r(self, kind, axis, i, j, k, amps, r):
+        """Non-ideal source: current (kind 0) with shunt r, or voltage (kind 1)
+        with series r > 0."""
+        a = np.ascontiguousarray(amps, dtype=np.float64)
+        self._chk(lib().orc_add_source_r(self._h, kind, axis, i, j, k, a.ctypes.data, a.size, float(r)))
 
     def add_probe(self, kind, axis, i, j, k, n=1) -> int:
         pid = C.c_int(-1)

@@ -691,3 +691,58 @@ def test_debye_with_zero_increments_is_plain_media():
         runs.append([o.get_field(c) for c in range(6)])
     for a, b in zip(*runs):
         assert np.array_equal(a, b)
+
+
+# --- lumped elements and non-ideal sources (Section 2.1) -------------------
+
+def _lumped_box(nsteps, setup):
+    """A 24^3 vacuum box (dx 0.1 m) with a 6-cell CPML; `setup` places
+    elements on the Ez edge at the centre; returns the edge voltage
+    V = -Ez dx over time and dt."""
+    n, dx = 24, 0.1
+    o = _orc()(n, n, n, dx, npml=6, max_steps=nsteps)
+    o.set_materials(np.zeros((n, n, n), np.uint8), [(1.0, 0.0, 1.0)])
+    dt = o.dt
+    setup(o, dt)
+    pid = o.add_probe(0, EZ, n // 2, n // 2, n // 2)
+    o.step(nsteps)
+    return -o.probe(pid) * dx, dt
+
+
+def _ramp(nsteps, dt, tau_steps=100.0):
+    t = (np.arange(nsteps) + 0.5) * dt
+    return 1.0 - np.exp(-t / (tau_steps * dt))
+
+
+def test_lumped_resistor_obeys_ohms_law_at_dc():
+    """A current source with a shunt resistor on one edge: once the current
+    has settled, the edge carries all of it, so V = I R (discrete charge
+    conservation leaves it no other path)."""
+    n, R, I0 = 3000, 50.0, 0.2
+    V, dt = _lumped_box(n, lambda o, dt: o.add_source_r(0, EZ, 12, 12, 12, I0 * _ramp(n, dt), R))
+    assert V[-1] == pytest.approx(I0 * R, rel=1e-3)
+
+
+def test_lumped_capacitor_charges_with_the_rc_time_constant():
+    """A step current into R parallel to a lumped C (large against the
+    edge's own capacitance eps0 dx): V = I R (1 - exp(-t / (R C)))."""
+    n, R, C, I0 = 1200, 50.0, 1e-9, 0.1
+    def setup(o, dt):
+        o.add_source_r(0, EZ, 12, 12, 12, np.full(n, I0), R)
+        o.add_lumped(1, EZ, 12, 12, 12, C)
+    V, dt = _lumped_box(n, setup)
+    t = (np.arange(n) + 1.0) * dt
+    want = I0 * R * (1.0 - np.exp(-t / (R * C)))
+    for q in (100, 300, 600, 1199):
+        assert V[q] == pytest.approx(want[q], rel=1e-2), q
+
+
+def test_resistive_voltage_source_divides_with_a_load():
+    """A voltage source V0 with series R_s across a load R_L on the same edge
+    settles at V0 R_L / (R_s + R_L)."""
+    n, Rs, RL, V0 = 3000, 50.0, 150.0, 1.0
+    def setup(o, dt):
+        o.add_source_r(1, EZ, 12, 12, 12, V0 * _ramp(n, dt), Rs)
+        o.add_lumped(0, EZ, 12, 12, 12, RL)
+    V, _ = _lumped_box(n, setup)
+    assert V[-1] == pytest.approx(V0 * RL / (Rs + RL), rel=1e-3)
