@@ -56,7 +56,8 @@ enum {
 enum { FDTD_EX = 0, FDTD_EY, FDTD_EZ, FDTD_HX, FDTD_HY, FDTD_HZ };
 enum { FDTD_PR_E = 0, FDTD_PR_VLINE = 1, FDTD_PR_ILOOP = 2 };
 enum { FDTD_LOSS_SEMI = 0, FDTD_LOSS_EXPLICIT = 1 };
-enum { FDTD_SRC_CURRENT = 0 };
+enum { FDTD_SRC_CURRENT = 0, FDTD_SRC_VOLTAGE = 1 };
+enum { FDTD_LUMPED_R = 0, FDTD_LUMPED_C = 1 };
 /* Kernel variants for fdtd_set_kernel: two passes per step (H, then E), one
  * fused pass per step, or one temporally blocked pass per two steps (an odd
  * remaining step takes one fused pass).  FDTD_KERNEL_AUTO (the default) is
@@ -131,6 +132,24 @@ int fdtd_add_wire(fdtd_ctx* c, int axis, int i, int j, int k, int n_cells, doubl
  * ESTATE. */
 int fdtd_add_source(fdtd_ctx* c, int kind, int axis, int i, int j, int k,
                     const double* amps, int n_samples);
+
+/* Lumped resistor (kind FDTD_LUMPED_R, value R [ohm] > 0) or capacitor
+ * (FDTD_LUMPED_C, value C [F] > 0) across the E edge (axis, i, j, k)
+ * (Section 2.1, lumped circuit elements): the edge's conductivity grows by
+ * 1 / (R dx), its permittivity by C / dx, after any thin-wire change.
+ * Elements on one edge add up.  Same edge rules as a source.  Errors:
+ * EINVAL, ERANGE, ENONFINITE, ESTATE. */
+int fdtd_add_lumped(fdtd_ctx* c, int kind, int axis, int i, int j, int k, double value);
+
+/* Non-ideal source (Section 2.1), as its Norton equivalent: FDTD_SRC_CURRENT
+ * is a current source (amps in A) with a shunt resistance r_internal [ohm]
+ * (r_internal <= 0: ideal, as fdtd_add_source); FDTD_SRC_VOLTAGE is a voltage
+ * source (amps in V, positive when the +axis end is the positive terminal)
+ * with a series resistance r_internal > 0, i.e. the current V / r_internal
+ * in parallel with r_internal.  Errors: as fdtd_add_source and
+ * fdtd_add_lumped. */
+int fdtd_add_source_r(fdtd_ctx* c, int kind, int axis, int i, int j, int k, const double* amps, int n_samples,
+                      double r_internal);
 
 /* Probe (recorded every step, FP64):
  *   FDTD_PR_E      value of the edge (axis, i, j, k) (n_cells = 1);

@@ -28,6 +28,7 @@ const double kEta0 = std::sqrt(kMu0 / kEps0);     // free-space impedance [ohm]
 
 struct WireRec { int axis, p[3], n; double radius; };
 struct SrcRec { int axis, p[3]; std::vector<double> amps; };
+struct LumpedRec { int kind, axis, p[3]; double value; };
 struct ProbeRec { int kind, axis, p[3], n; };
 
 // Per-node modifications made by thin wires.
@@ -36,6 +37,8 @@ struct NodeMod {
   uint8_t emod = 0, hmod = 0; // bit a: E_a / H_a parameter already scaled
   double em[3] = {1, 1, 1};   // eps and sigma factor of E_a
   double hm[3] = {1, 1, 1};   // mu divisor of H_a
+  double deps[3] = {0, 0, 0}; // lumped capacitance of E_a, as permittivity
+  double dsig[3] = {0, 0, 0}; // lumped resistance of E_a, as conductivity
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -66,6 +69,7 @@ struct fdtd_ctx {
   DebyeView<double> d64 = {};
   std::vector<WireRec> wires;
   std::vector<SrcRec> srcs;
+  std::vector<LumpedRec> lumped;
   std::vector<ProbeRec> probes;
 
   // frozen tables (host copies)
@@ -214,6 +218,7 @@ int node_coefs(fdtd_ctx* c, uint64_t key, const NodeMod* mod, Coefs& out) {
         bsum += beta[p];
       }
       if (mod) { eps *= mod->em[a]; sig *= mod->em[a]; }
+      if (mod) { eps += mod->deps[a]; sig += mod->dsig[a]; }  // lumped R and C
       if (c->P.loss_mode == FDTD_LOSS_EXPLICIT) {
         if (sig * dt / eps >= 2.0) return fail(c, FDTD_EUNSTABLE, "literal eq. 4 loss factor below -1");
         cam1 = -sig * dt / eps;             // ca = 1 - sigma dt / eps
@@ -312,6 +317,14 @@ void collect_wire_mods(fdtd_ctx* c, std::unordered_map<long long, NodeMod>& mods
           scale_h(q, u);
         }
   }
+  // Lumped elements (Section 2.1): R across an edge of length dx and
+  // cross-section dx^2 is the conductivity 1 / (R dx); C the permittivity
+  // C / dx; both add to the edge's own after the wire changes.
+  for (const LumpedRec& l : c->lumped) {
+    NodeMod& nm = mods[node_index(c, l.p[0], l.p[1], l.p[2])];
+    if (l.kind == FDTD_LUMPED_R) nm.dsig[l.axis] += 1.0 / (l.value * c->P.dx);
+    else nm.deps[l.axis] += l.value / c->P.dx;
+  }
 }
 
 struct TupleKey {
@@ -395,11 +408,16 @@ int build_classes(fdtd_ctx* c) {
   c->debye_nodes = 0;
   if (c->npole)
     for (long long n = 0; n < c->ncell; ++n) c->debye_nodes += c->dflag[c->cls_id[n]];
-  // a source must not sit on a wire edge
+  // a source or lumped element must not sit on a wire edge
   for (const SrcRec& s : c->srcs) {
     auto it = mods.find(node_index(c, s.p[0], s.p[1], s.p[2]));
     if (it != mods.end() && ((it->second.pec >> s.axis) & 1))
       return fail(c, FDTD_ERANGE, "source on a wire (perfect-conductor) edge");
+  }
+  for (const LumpedRec& l : c->lumped) {
+    auto it = mods.find(node_index(c, l.p[0], l.p[1], l.p[2]));
+    if (it != mods.end() && ((it->second.pec >> l.axis) & 1))
+      return fail(c, FDTD_ERANGE, "lumped element on a wire (perfect-conductor) edge");
   }
   return FDTD_OK;
 }
@@ -780,6 +798,34 @@ int fdtd_add_source(fdtd_ctx* c, int kind, int axis, int i, int j, int k, const 
   if (!finite_all(amps, (size_t)n)) return fail(c, FDTD_ENONFINITE, "non-finite source sample");
   c->srcs.push_back({axis, {i, j, k}, std::vector<double>(amps, amps + n)});
   return FDTD_OK;
+}
+
+int fdtd_add_lumped(fdtd_ctx* c, int kind, int axis, int i, int j, int k, double value) {
+  if (!c || (kind != FDTD_LUMPED_R && kind != FDTD_LUMPED_C) || axis < 0 || axis > 2)
+    return fail(c, FDTD_EINVAL, "bad lumped-element arguments");
+  if (c->frozen) return fail(c, FDTD_ESTATE, "set-up after the workspace size was taken");
+  if (!std::isfinite(value)) return fail(c, FDTD_ENONFINITE, "non-finite lumped value");
+  if (!(value > 0)) return fail(c, FDTD_EINVAL, "lumped value not positive");
+  const int p[3] = {i, j, k};
+  if (!edge_updated(c, axis, p)) return fail(c, FDTD_ERANGE, "lumped edge outside the updated edges");
+  c->lumped.push_back({kind, axis, {i, j, k}, value});
+  return FDTD_OK;
+}
+
+int fdtd_add_source_r(fdtd_ctx* c, int kind, int axis, int i, int j, int k, const double* amps, int n,
+                      double r_internal) {
+  if (!c || (kind != FDTD_SRC_CURRENT && kind != FDTD_SRC_VOLTAGE) || !amps || n < 1)
+    return fail(c, FDTD_EINVAL, "bad source arguments");
+  if (!std::isfinite(r_internal)) return fail(c, FDTD_ENONFINITE, "non-finite internal resistance");
+  if (kind == FDTD_SRC_VOLTAGE && !(r_internal > 0))
+    return fail(c, FDTD_EINVAL, "a voltage source needs a series resistance > 0");
+  // Norton equivalent: the current (V / r for a voltage source) in parallel with r
+  std::vector<double> cur(amps, amps + n);
+  if (kind == FDTD_SRC_VOLTAGE)
+    for (double& v : cur) v /= r_internal;
+  int rc = fdtd_add_source(c, FDTD_SRC_CURRENT, axis, i, j, k, cur.data(), n);
+  if (rc || !(r_internal > 0)) return rc;
+  return fdtd_add_lumped(c, FDTD_LUMPED_R, axis, i, j, k, r_internal);
 }
 
 int fdtd_add_probe(fdtd_ctx* c, int kind, int axis, int i, int j, int k, int n, int* id) {

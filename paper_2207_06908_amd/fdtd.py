@@ -41,6 +41,8 @@ SIGNATURES = [
     ("fdtd_create", C.c_int, [C.POINTER(Params), _vp, C.POINTER(_vp)]),
     ("fdtd_set_materials", C.c_int, [_vp, _vp, C.POINTER(Material), C.c_int]),
     ("fdtd_set_debye", C.c_int, [_vp, C.c_int, _vp, _vp]),
+    ("fdtd_add_lumped", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]),
+    ("fdtd_add_source_r", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int, C.c_double]),
     ("fdtd_add_wire", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]),
     ("fdtd_add_source", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int]),
     ("fdtd_add_probe", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -160,6 +162,16 @@ class Grid:
         if d.ndim != 2 or d.shape[1] != t.size:
             raise ValueError("d_eps must be [n_materials][n_poles]")
         self._chk(lib().fdtd_set_debye(self._h, t.size, t.ctypes.data, d.ctypes.data))
+
+    def add_lumped(self, kind, axis, i, j, k, value):
+        """Lumped resistor (kind 0, ohm) or capacitor (kind 1, F) on an E edge."""
+        self._chk(lib().fdtd_add_lumped(self._h, kind, axis, i, j, k, float(value)))
+
+    def add_source_r(self, kind, axis, i, j, k, amps, r):
+        """Non-ideal source: current (kind 0) with shunt r, or voltage (kind 1)
+        with series r > 0."""
+        a = np.ascontiguousarray(amps, dtype=np.float64)
+        self._chk(lib().fdtd_add_source_r(self._h, kind, axis, i, j, k, a.ctypes.data, a.size, float(r)))
 
     def add_wire(self, axis, i, j, k, n, radius):
         self._chk(lib().fdtd_add_wire(self._h, axis, i, j, k, n, radius))

@@ -150,6 +150,10 @@ class Scenario:
     # Debye poles: (tau [s] per pole, increments [material][pole]); the
     # materials' eps_r is then eps_inf
     debye: Optional[Tuple[List[float], np.ndarray]] = None
+    # lumped elements (kind 0 R [ohm], 1 C [F], axis, i, j, k, value) and
+    # non-ideal sources (kind 0 current / 1 voltage, axis, i, j, k, amps, r)
+    lumped: List[Tuple[int, int, int, int, int, float]] = field(default_factory=list)
+    sources_r: List[Tuple[int, int, int, int, int, np.ndarray, float]] = field(default_factory=list)
     meta: dict = field(default_factory=dict)
 
     @property
@@ -174,6 +178,10 @@ def apply(sc: Scenario, sim) -> List[int]:
         sim.add_wire(*w)
     for (ax, i, j, k, amps) in sc.sources:
         sim.add_source(ax, i, j, k, amps)
+    for (kind, ax, i, j, k, amps, r) in sc.sources_r:
+        sim.add_source_r(kind, ax, i, j, k, amps, r)
+    for (kind, ax, i, j, k, v) in sc.lumped:
+        sim.add_lumped(kind, ax, i, j, k, v)
     ids = []
     for (_name, kind, ax, i, j, k, n) in sc.probes:
         ids.append(sim.add_probe(kind, ax, i, j, k, n))

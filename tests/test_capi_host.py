@@ -203,3 +203,28 @@ def test_debye_validation_and_workspace():
     b.set_materials(cm, mats)
     b.set_debye([1e-9, 1e-8], d_eps)
     assert _code(lambda: fdtd.Batch([b], tile=(32, 8, 32))) == -1
+
+
+def test_lumped_and_nonideal_source_validation():
+    """Lumped values > 0 and finite on an updated edge; a voltage source needs
+    a series resistance; both add to the coefficient classes."""
+    g = _grid()
+    amps = np.ones(10)
+    assert _code(lambda: g.add_lumped(2, 2, 5, 5, 4, 50.0)) == -1       # kind
+    assert _code(lambda: g.add_lumped(0, 2, 5, 5, 4, -50.0)) == -1
+    assert _code(lambda: g.add_lumped(0, 2, 5, 5, 4, float("inf"))) == -7
+    assert _code(lambda: g.add_lumped(0, 2, 0, 5, 4, 50.0)) == -2       # Ez on the x = 0 wall
+    assert _code(lambda: g.add_source_r(1, 2, 5, 5, 4, amps, 0.0)) == -1
+    assert _code(lambda: g.add_source_r(2, 2, 5, 5, 4, amps, 50.0)) == -1
+    plain = _grid()
+    g.add_lumped(0, 2, 5, 5, 4, 50.0)
+    g.add_lumped(1, 0, 3, 3, 3, 1e-9)
+    g.add_source_r(1, 1, 6, 4, 4, amps, 75.0)
+    g.add_source_r(0, 1, 7, 4, 4, amps, 0.0)   # ideal
+    g.workspace_bytes()
+    plain.workspace_bytes()
+    assert g.num_classes >= plain.num_classes + 3
+    w = _grid()
+    w.add_wire(2, 5, 5, 2, 4, 0.01)
+    w.add_lumped(0, 2, 5, 5, 3, 50.0)            # on the wire's axial edge
+    assert _code(lambda: w.workspace_bytes() or w.finalize()) == -2
