@@ -201,6 +201,33 @@ def bench_debye(steps: int = 400, warmup: int = 20):
     return out
 
 
+def bench_lumped(steps: int = 1000, warmup: int = 20):
+    """The 512 x 512 x 384 scene with a resistive voltage source and a lumped
+    R and C: the same two-step pass (the elements are coefficient classes)."""
+    import torch
+    from paper_2207_06908_amd import fdtd
+    from paper_2207_06908_amd import scenarios as S
+    sc = S.config2_lumped(n_steps=warmup + steps)
+    g = fdtd.Grid.from_params(sc.params(), precision=32)
+    S.apply(sc, g)
+    g.bind()
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    out = {"workload": "512x512x384 Yee FDTD as above, source gap as a 400-ohm resistive voltage source, "
+                       "1 kohm + 100 pF lumped at the wire base",
+           "steps": steps, "value": round(sc.cells * steps / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
+           "ms_per_step": round(ms / steps, 5), "coefficient_classes": g.num_classes}
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 def calibrate_copy(mib: int = 1024, reps: int = 3):
     """Plain device-to-device copies of known size, run under the profiler's
     FETCH_SIZE / WRITE_SIZE counters to scale them to true HBM bytes."""
@@ -362,6 +389,7 @@ def main():
         out["batched"] = bench_batch(tune=not a.no_tune)
     if not a.no_debye:
         out["debye"] = bench_debye()
+        out["lumped"] = bench_lumped()
     if not a.no_surrogate:
         out["surrogate"] = bench_surrogate()
     if not a.no_cpu_baseline:

@@ -279,6 +279,20 @@ def config2_debye(**kw) -> Scenario:
     return sc
 
 
+def config2_lumped(**kw) -> Scenario:
+    """The config-2 scene (any of config2's size arguments) with its ideal
+    source gap replaced by a 10 kV-class resistive voltage source (series
+    400 ohm) and a 1 kohm, 100 pF load across the wire's base edge."""
+    sc = config2(**kw)
+    sc.name = sc.name.replace("config2", "config2_lumped")
+    ax, i, j, k, amps = sc.sources[0]
+    sc.sources = []
+    sc.sources_r = [(1, ax, i, j, k, amps * 400.0, 400.0)]
+    ks = sc.meta["ks"]
+    sc.lumped = [(0, AX_X, i, j, ks, 1000.0), (1, AX_X, i, j, ks, 1e-10)]
+    return sc
+
+
 def config2_small(n_steps: int = 1200) -> Scenario:
     """The config-2 structure on a 96 x 96 x 80 grid (oracle-sized)."""
     return config2(nx=96, ny=96, nz=80, dx=0.5, npml=10, wire_cells=12, n_steps=n_steps,
