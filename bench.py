@@ -228,6 +228,35 @@ def bench_lumped(steps: int = 1000, warmup: int = 20):
     return out
 
 
+def bench_array(steps: int = 20000, warmup: int = 2000):
+    """The apparent-resistivity array (100 x 100 x 80 cells, three Debye soil
+    layers, Heidler source): a bounded window of its 4.2M-step run."""
+    import torch
+    from paper_2207_06908_amd import fdtd
+    from paper_2207_06908_amd import scenarios as S
+    sc = S.config_array(n_steps=warmup + steps)
+    g = fdtd.Grid.from_params(sc.params(), precision=32)
+    S.apply(sc, g)
+    g.bind()
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    full = sc.meta["full_steps"]
+    out = {"workload": "apparent-resistivity array, 100x100x80 cells, dx 0.05 m, three 4-pole Debye layers, "
+                       "8 thin wires, Heidler source; steps 2000-22000 of the 400 us run",
+           "steps": steps, "value": round(sc.cells * steps / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
+           "ms_per_step": round(ms / steps, 6), "full_run_steps": full,
+           "full_run_s": round(full * ms / steps / 1e3, 1)}
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 def calibrate_copy(mib: int = 1024, reps: int = 3):
     """Plain device-to-device copies of known size, run under the profiler's
     FETCH_SIZE / WRITE_SIZE counters to scale them to true HBM bytes."""
@@ -390,6 +419,7 @@ def main():
     if not a.no_debye:
         out["debye"] = bench_debye()
         out["lumped"] = bench_lumped()
+        out["array"] = bench_array()
     if not a.no_surrogate:
         out["surrogate"] = bench_surrogate()
     if not a.no_cpu_baseline:

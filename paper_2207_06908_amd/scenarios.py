@@ -125,6 +125,16 @@ def double_exponential(n_steps: int, dt: float, I0: float, T1: float, T2: float)
     return I0 * k * (np.exp(-a * t) - np.exp(-b * t))
 
 
+def heidler(n_steps: int, dt: float, I0: float, tau1: float, tau2: float, n: float, eta: float = 1.0,
+            t_delay: float = 0.0) -> np.ndarray:
+    """Heidler current (I0 / eta) x^n / (1 + x^n) exp(-t' / tau2), x = t' / tau1,
+    t' = t - t_delay (0 before the delay), sampled at (n + 1/2) dt."""
+    t = sample_times(n_steps, dt) - t_delay
+    tp = np.maximum(t, 0.0)
+    x = (tp / tau1) ** n
+    return np.where(t > 0, (I0 / eta) * x / (1.0 + x) * np.exp(-tp / tau2), 0.0)
+
+
 # ---------------------------------------------------------------------------
 # Scenario container
 # ---------------------------------------------------------------------------
@@ -291,6 +301,53 @@ def config2_lumped(**kw) -> Scenario:
     ks = sc.meta["ks"]
     sc.lumped = [(0, AX_X, i, j, ks, 1000.0), (1, AX_X, i, j, ks, 1e-10)]
     return sc
+
+
+# The apparent-resistivity array of the paper's second example (Section 3):
+# three soil layers, each a four-pole Debye expansion of its Messier-model
+# properties (eps_inf, sigma0 [S/m], (delta eps, tau [s]) per pole).
+ARRAY_LAYERS = (
+    (15.767, 5.0e-3, ((839.441, 3.096e-5), (143.901, 4.068e-6), (66.971, 7.217e-7), (31.515, 9.141e-8))),
+    (13.488, 2.5e-3, ((593.525, 3.096e-5), (101.748, 4.066e-6), (47.348, 7.212e-7), (22.273, 9.132e-8))),
+    (11.884, 1.25e-3, ((419.744, 3.097e-5), (71.960, 4.069e-6), (33.494, 7.218e-7), (15.757, 9.140e-8))),
+)
+
+
+def config_array(dx: float = 0.05, n_steps: int = 4000) -> Scenario:
+    """The four-electrode array of the paper's apparent-soil example on its
+    5 x 5 x 4 m volume (100 x 100 x 80 cells at dx 0.05 m): soil layers of
+    1 m (z 2-3 m, 1-2 m, 0-1 m) under 1 m of air, a 0.5 m CPML; current
+    electrodes at (1, 1) and (2, 1) m and potential electrodes at (4, 3) and
+    (4, 4) m, 8 mm rods from z 2.95 to 3.15 m joined by 3 mm leads at
+    3.15 m; a Heidler current (tau1 0.37 us, tau2 14 us, n 10, delayed
+    0.185 us) in the gap of the current leads; probes: the source current and
+    the voltage across the gap of the potential leads.  The full run is
+    400 us.  Readings: the three layers' pole time constants agree to 0.1%
+    and the grid shares one set, their per-pole mean; the CPML tuple reads as
+    (thickness 0.5 m, sigma factor 1, kappa_max 1, alpha_max 1e-3, m 3, m_a 1);
+    the Heidler arguments as (tau1, tau2, I0, n, eta, delay)."""
+    m = lambda v: int(round(v / dx))
+    nx, ny, nz = m(5.0), m(5.0), m(4.0)
+    dt = courant_dt(dx)
+    cm = np.zeros((nz, ny, nx), np.uint8)
+    cm[m(2.0):m(3.0)] = 1
+    cm[m(1.0):m(2.0)] = 2
+    cm[:m(1.0)] = 3
+    mats = [AIR] + [(L[0], L[1], 1.0) for L in ARRAY_LAYERS]
+    tau = [float(np.mean([L[2][p][1] for L in ARRAY_LAYERS])) for p in range(4)]
+    de = np.array([[0.0] * 4] + [[pole[0] for pole in L[2]] for L in ARRAY_LAYERS])
+    k0, k1 = m(2.95), m(3.15)
+    rod, lead = 0.008, 0.003
+    wires = [(AX_Z, m(1.0), m(1.0), k0, k1 - k0, rod), (AX_Z, m(2.0), m(1.0), k0, k1 - k0, rod),
+             (AX_X, m(1.0), m(1.0), k1, m(1.45) - m(1.0), lead), (AX_X, m(1.5), m(1.0), k1, m(2.0) - m(1.5), lead),
+             (AX_Z, m(4.0), m(3.0), k0, k1 - k0, rod), (AX_Z, m(4.0), m(4.0), k0, k1 - k0, rod),
+             (AX_Y, m(4.0), m(3.0), k1, m(3.45) - m(3.0), lead), (AX_Y, m(4.0), m(3.5), k1, m(4.0) - m(3.5), lead)]
+    amps = heidler(n_steps, dt, 1.0, 3.7e-7, 1.4e-5, 10.0, 1.0, 1.85e-7)
+    probes = [("I_source", PR_ILOOP, AX_X, m(1.45), m(1.0), k1, 1),
+              ("V_potential", PR_VLINE, AX_Y, m(4.0), m(3.45), k1, 1)]
+    return Scenario(f"array_{nx}x{ny}x{nz}", nx, ny, nz, dx, dt, n_steps, cm, mats, npml=m(0.5),
+                    pml=(3.0, 1.0, 1.0, 1e-3, 1.0), wires=wires, sources=[(AX_X, m(1.45), m(1.0), k1, amps)],
+                    probes=probes, debye=(tau, de), meta=dict(full_steps=int(math.ceil(400e-6 / dt))))
 
 
 def config2_small(n_steps: int = 1200) -> Scenario:

@@ -57,3 +57,22 @@ def test_config2_full_geometry():
     assert sc.wires[0][:5] == (2, 256, 256, 192, 60)
     names = [p[0] for p in sc.probes]
     assert "V_Ex(k=192)" in names and "V_Ex(k=252)" in names and "I_source" in names
+
+
+def test_heidler_waveform_closed_forms():
+    """Heidler current: zero before the delay, (I0 / eta) e^(-tau1 / tau2) / 2
+    one tau1 after it, and at (1/2) tau1 the x^n factor 2^-n / (1 + 2^-n)."""
+    import math
+    import numpy as np
+    from paper_2207_06908_amd import scenarios as S
+    dt, tau1, tau2, n, t_d = 1e-9, 3.7e-7, 1.4e-5, 10.0, 1.85e-7
+    w = S.heidler(2000, dt, 2.0, tau1, tau2, n, 1.5, t_d)
+    t = (np.arange(2000) + 0.5) * dt
+    assert np.all(w[t <= t_d] == 0.0)
+    for frac in (0.5, 1.0):
+        tq = t_d + frac * tau1
+        idx = int(round(tq / dt - 0.5))
+        x = (((idx + 0.5) * dt - t_d) / tau1) ** n
+        want = 2.0 / 1.5 * x / (1 + x) * math.exp(-((idx + 0.5) * dt - t_d) / tau2)
+        assert w[idx] == pytest.approx(want, rel=1e-12)
+    assert np.argmax(w) > (t_d + tau1) / dt
