@@ -2,16 +2,21 @@
 //
 // Plain triple loops, one per field component, written from the equations of
 // Section 2.1 of the paper (eqs. 2-5), the CPML and thin wire of Sections
-// 2.2-2.3, the Debye media of Section 2.4, and the readings stated below.  No
-// tiling, no fusion, no reordering beyond "all H, then all E, then the
-// sources, then the Debye currents, then the probes" within a step.  OpenMP
+// 2.2-2.3, the Debye media of Section 2.4, the oblique thin wire the paper
+// names in Section 2.3, and the readings stated below.  No tiling, no fusion,
+// no reordering beyond "all H, then the oblique-wire currents, then all E,
+// then the sources and oblique-wire injection, then the Debye currents, then
+// the probes" within a step.  OpenMP
 // splits the outer k loop of each component update; every update reads only
 // values that the same loop does not write, so the result is independent of
 // the thread count.
 //
 // Parity unpinned (no closed form or published value to check against): the
 // interface averaging of eps, sigma, mu and pole increments, and the thin-wire
-// scaling of pole increments in Debye media.
+// scaling of pole increments in Debye media.  The oblique wire's equivalent
+// radius (the same r0 as the axis wires) and its vacuum L' and C' are a
+// reading (the paper names the model, not its equations); its transfer
+// weights, telegraph step and charge bookkeeping are pinned.
 #include "orc.h"
 
 #include <cmath>
@@ -46,6 +51,15 @@ struct Wire { int axis, p[3], n; double radius; };
 struct Source { int axis, p[3]; std::vector<double> amps; };
 struct Lumped { int kind, axis, p[3]; double value; };
 struct Probe { int kind, axis, p[3], n; std::vector<double> rec; };
+// Oblique thin wire: end points A, B in cells, unit direction t, segment
+// length dl (cells), n segments; per-unit-length inductance and capacitance;
+// segment currents I (n), end-point charges per unit length q (n + 1), an
+// optional hard-driven segment and an optional recorded segment.
+struct OWire {
+  double A[3], t[3], dl, Lp, Cp;
+  int n, src, rec;
+  std::vector<double> amps, I, q, rec_v;
+};
 
 }  // namespace
 
@@ -65,6 +79,7 @@ struct orc_sim {
   std::vector<Source> srcs;
   std::vector<Lumped> lumped;
   std::vector<Probe> probes;
+  std::vector<OWire> owires;
 
   // fields at their natural Yee extents
   A3 E[3], H[3];
@@ -378,6 +393,7 @@ void build_cpml(orc_sim* s) {
 }
 
 int finalize(orc_sim* s) {
+  if (s->npole && !s->owires.empty()) return fail(s, ORC_EINVAL, "oblique wires in a grid with Debye media");
   if (s->finalized) return ORC_OK;
   for (int a = 0; a < 3; ++a) {
     int ext[3];
@@ -542,6 +558,96 @@ void inject_sources(orc_sim* s) {
     const double I = (s->step < (long)q.amps.size()) ? q.amps[s->step] : 0.0;
     const int a = q.axis;
     s->E[a](q.p[0], q.p[1], q.p[2]) -= s->Cb[a](q.p[0], q.p[1], q.p[2]) * I / area;
+  }
+}
+
+// ---- Oblique thin wire (Section 2.4: the arbitrarily oriented wire model
+// the paper takes from the literature; the formulation here is this
+// oracle's reading of that model, see the header) ----
+//
+// Each wire owns a 1D grid along its axis.  Segment k (midpoint
+// m_k = A + (k + 1/2) dl t) carries the current I_k at times n + 1/2; the end
+// points of the segments carry the charge per unit length q_k at integer
+// times.  Telegraph equations with the in-cell inductance and capacitance
+//   L' dI_k/dt = E_t(m_k) - (q_{k+1} - q_k) / (C' dl)
+//   dq_k/dt    = -(I_k - I_{k-1}) / len_k    (I_{-1} = I_n = 0, len_k = dl / 2 at the two ends)
+// with L' = mu0 ln(r0/a) / (2 pi), C' = 2 pi eps0 / ln(r0/a), r0 = wire_r0_factor dx.
+// E_t is the field along t, each E component interpolated trilinearly from
+// its own Yee lattice; the segment's current moment I_k dl t goes back to the
+// same samples with the same weights as a current density over dx^3.
+
+// Trilinear weights of the point p (cells) on the lattice of E component a,
+// whose samples sit at integer positions moved half a cell along a.
+static void owire_weights(const double p[3], int a, int base[3], double w[8]) {
+  double f[3];
+  for (int u = 0; u < 3; ++u) {
+    const double x = p[u] - (u == a ? 0.5 : 0.0);
+    base[u] = (int)std::floor(x);
+    f[u] = x - base[u];
+  }
+  for (int c = 0; c < 8; ++c)
+    w[c] = ((c & 1) ? f[0] : 1.0 - f[0]) * ((c & 2) ? f[1] : 1.0 - f[1]) * ((c & 4) ? f[2] : 1.0 - f[2]);
+}
+
+static void owire_mid(const OWire& w, int k, double m[3]) {
+  for (int u = 0; u < 3; ++u) m[u] = w.A[u] + (k + 0.5) * w.dl * w.t[u];
+}
+
+// I^{n+1/2} from E^n and q^n, then q^{n+1} from I^{n+1/2} (before the E update).
+void owire_currents(orc_sim* s) {
+  const double dlm_of = s->dx;
+  for (OWire& w : s->owires) {
+    const double dlm = w.dl * dlm_of;
+    for (int k = 0; k < w.n; ++k) {
+      if (k == w.src) {
+        w.I[k] = s->step < (long)w.amps.size() ? w.amps[s->step] : 0.0;
+        continue;
+      }
+      double m[3];
+      owire_mid(w, k, m);
+      double et = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        if (w.t[a] == 0.0) continue;
+        int b[3];
+        double wt[8];
+        owire_weights(m, a, b, wt);
+        double v = 0.0;
+        for (int c = 0; c < 8; ++c) v += wt[c] * s->E[a](b[0] + (c & 1), b[1] + ((c >> 1) & 1), b[2] + ((c >> 2) & 1));
+        et += w.t[a] * v;
+      }
+      w.I[k] += s->dt / w.Lp * (et - (w.q[k + 1] - w.q[k]) / (w.Cp * dlm));
+    }
+    for (int j = 0; j <= w.n; ++j) {
+      const double il = j > 0 ? w.I[j - 1] : 0.0, ir = j < w.n ? w.I[j] : 0.0;
+      const double len = (j == 0 || j == w.n) ? 0.5 * dlm : dlm;
+      w.q[j] -= s->dt * (ir - il) / len;
+    }
+    if (w.rec >= 0) w.rec_v[s->step] = w.I[w.rec];
+  }
+}
+
+// After the E update and the lumped sources: E -= Cb J, J = I dl t w / dx^3;
+// perfectly conducting edges keep E = 0.
+void owire_inject(orc_sim* s) {
+  const double vol = s->dx * s->dx * s->dx;
+  for (const OWire& w : s->owires) {
+    const double dlm = w.dl * s->dx;
+    for (int k = 0; k < w.n; ++k) {
+      double m[3];
+      owire_mid(w, k, m);
+      for (int a = 0; a < 3; ++a) {
+        if (w.t[a] == 0.0) continue;
+        int b[3];
+        double wt[8];
+        owire_weights(m, a, b, wt);
+        for (int c = 0; c < 8; ++c) {
+          const int i = b[0] + (c & 1), j = b[1] + ((c >> 1) & 1), kk = b[2] + ((c >> 2) & 1);
+          const size_t li = ((size_t)kk * s->E[a].n1 + j) * s->E[a].n0 + i;
+          if (s->pec[a][li]) continue;
+          s->E[a](i, j, kk) -= s->Cb[a](i, j, kk) * w.I[k] * w.t[a] * wt[c] * dlm / vol;
+        }
+      }
+    }
   }
 }
 
@@ -738,6 +844,54 @@ int orc_add_probe(orc_sim* s, int kind, int axis, int i, int j, int k, int n, in
   return ORC_OK;
 }
 
+int orc_add_oblique_wire(orc_sim* s, const double* a, const double* b, double radius, int src_seg,
+                         const double* amps, int n_amps, int rec_seg, int* id) {
+  if (!s || !a || !b || n_amps < 0 || (n_amps > 0 && !amps)) return ORC_EINVAL;
+  if (s->finalized) return fail(s, ORC_ESTATE, "grid already stepped");
+  double d[3], len2 = 0.0;
+  for (int u = 0; u < 3; ++u) {
+    if (!std::isfinite(a[u]) || !std::isfinite(b[u])) return fail(s, ORC_EINVAL, "end point not finite");
+    const double lo = s->P.npml + 1.0, hi = s->N[u] - s->P.npml - 2.0;
+    if (a[u] < lo || a[u] > hi || b[u] < lo || b[u] > hi) return fail(s, ORC_ERANGE, "wire reaches the CPML or the wall");
+    d[u] = b[u] - a[u];
+    len2 += d[u] * d[u];
+  }
+  const double len = std::sqrt(len2);
+  if (!(len >= 1.0)) return fail(s, ORC_EINVAL, "wire shorter than one cell");
+  const double r0 = s->P.wire_r0_factor * s->dx;
+  if (!(radius > 0) || !(radius < r0)) return fail(s, ORC_EINVAL, "radius out of (0, r0)");
+  OWire w;
+  w.n = (int)std::floor(len);
+  w.dl = len / w.n;
+  for (int u = 0; u < 3; ++u) { w.A[u] = a[u]; w.t[u] = d[u] / len; }
+  if (src_seg < -1 || src_seg >= w.n || rec_seg < -1 || rec_seg >= w.n) return fail(s, ORC_ERANGE, "segment index");
+  const double lg = std::log(r0 / radius);
+  w.Lp = kMu0 * lg / (2.0 * kPi);
+  w.Cp = 2.0 * kPi * kEps0 / lg;
+  w.src = src_seg;
+  w.rec = rec_seg;
+  w.amps.assign(amps, amps + n_amps);
+  w.I.assign(w.n, 0.0);
+  w.q.assign(w.n + 1, 0.0);
+  w.rec_v.assign(rec_seg >= 0 ? s->P.max_steps : 0, 0.0);
+  s->owires.push_back(w);
+  if (id) *id = (int)s->owires.size() - 1;
+  return ORC_OK;
+}
+
+int orc_oblique_wire_read(orc_sim* s, int id, double* cur, double* q, double* rec, int n_rec_max, int* n_seg,
+                          int* n_written) {
+  if (!s || id < 0 || id >= (int)s->owires.size() || n_rec_max < 0) return ORC_EINVAL;
+  const OWire& w = s->owires[id];
+  if (n_seg) *n_seg = w.n;
+  if (cur) std::memcpy(cur, w.I.data(), sizeof(double) * w.n);
+  if (q) std::memcpy(q, w.q.data(), sizeof(double) * (w.n + 1));
+  const int n = w.rec >= 0 ? (int)std::min<long>(s->step, n_rec_max) : 0;
+  if (rec && n) std::memcpy(rec, w.rec_v.data(), sizeof(double) * n);
+  if (n_written) *n_written = n;
+  return ORC_OK;
+}
+
 int orc_step(orc_sim* s, int n_steps) {
   if (!s || n_steps < 0) return ORC_EINVAL;
   int rc = finalize(s);
@@ -745,10 +899,12 @@ int orc_step(orc_sim* s, int n_steps) {
   if (s->step + n_steps > s->P.max_steps) return fail(s, ORC_ERANGE, "beyond max_steps");
   for (int t = 0; t < n_steps; ++t) {
     update_h(s);
+    owire_currents(s);
     if (s->npole)
       for (int a = 0; a < 3; ++a) s->Eprev[a].v = s->E[a].v;
     update_e(s);
     inject_sources(s);
+    owire_inject(s);
     if (s->npole) update_j(s);
     for (Probe& pr : s->probes) pr.rec[s->step] = probe_value(s, pr);
     ++s->step;

@@ -72,6 +72,17 @@ int  orc_add_lumped(orc_sim* s, int kind, int axis, int i, int j, int k, double 
  * or voltage source [V] with series resistance r > 0 (Norton equivalent). */
 int  orc_add_source_r(orc_sim* s, int kind, int axis, int i, int j, int k, const double* amps, int n, double r);
 int  orc_add_probe(orc_sim* s, int kind, int axis, int i, int j, int k, int n_cells, int* id);
+/* Oblique thin wire from a to b (cell units, node (0,0,0) at the origin,
+ * at least one cell long, clear of the CPML and the walls by one cell),
+ * radius < wire_r0_factor dx; src_seg >= 0 drives that segment's current
+ * with amps (A, sampled at (n + 1/2) dt); rec_seg >= 0 records that
+ * segment's current each step.  Not with Debye media. */
+int  orc_add_oblique_wire(orc_sim* s, const double* a, const double* b, double radius, int src_seg,
+                          const double* amps, int n_amps, int rec_seg, int* id);
+/* Segment currents (n_seg), end-point charges per unit length (n_seg + 1),
+ * and the record (any pointer may be NULL). */
+int  orc_oblique_wire_read(orc_sim* s, int id, double* cur, double* q, double* rec, int n_rec_max,
+                           int* n_seg, int* n_written);
 int  orc_step(orc_sim* s, int n_steps);
 int  orc_probe(orc_sim* s, int id, double* out, int n_max, int* n_written);
 int  orc_set_field(orc_sim* s, int comp, const double* v);

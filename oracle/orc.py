@@ -62,6 +62,10 @@ def lib():
                                        C.c_double]
         L.orc_add_probe.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                     C.POINTER(C.c_int)]
+        L.orc_add_oblique_wire.argtypes = [vp, C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_void_p, C.c_int,
+                                           C.c_int, C.POINTER(C.c_int)]
+        L.orc_oblique_wire_read.argtypes = [vp, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                            C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_step.argtypes = [vp, C.c_int]
         L.orc_probe.argtypes = [vp, C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_int)]
         L.orc_set_field.argtypes = [vp, C.c_int, C.c_void_p]
@@ -155,6 +159,29 @@ class Oracle:
         pid = C.c_int(-1)
         self._chk(lib().orc_add_probe(self._h, kind, axis, i, j, k, n, C.byref(pid)))
         return pid.value
+
+    def add_oblique_wire(self, a, b, radius, src_seg=-1, amps=None, rec_seg=-1) -> int:
+        """Oblique thin wire from a to b (cell units); src_seg drives that
+        segment's current with amps, rec_seg records that segment's current."""
+        pa = np.ascontiguousarray(a, dtype=np.float64)
+        pb = np.ascontiguousarray(b, dtype=np.float64)
+        am = np.ascontiguousarray([] if amps is None else amps, dtype=np.float64)
+        wid = C.c_int(-1)
+        self._chk(lib().orc_add_oblique_wire(self._h, pa.ctypes.data, pb.ctypes.data, float(radius), int(src_seg),
+                                             am.ctypes.data, am.size, int(rec_seg), C.byref(wid)))
+        return wid.value
+
+    def oblique_wire(self, wid):
+        """(segment currents, end-point charges per unit length, record)."""
+        ns = C.c_int(0)
+        self._chk(lib().orc_oblique_wire_read(self._h, wid, None, None, None, 0, C.byref(ns), None))
+        cur = np.zeros(ns.value, np.float64)
+        q = np.zeros(ns.value + 1, np.float64)
+        rec = np.zeros(self.max_steps, np.float64)
+        nw = C.c_int(0)
+        self._chk(lib().orc_oblique_wire_read(self._h, wid, cur.ctypes.data, q.ctypes.data, rec.ctypes.data,
+                                              rec.size, C.byref(ns), C.byref(nw)))
+        return cur, q, rec[:nw.value].copy()
 
     def step(self, n):
         self._chk(lib().orc_step(self._h, int(n)))

@@ -746,3 +746,95 @@ def test_resistive_voltage_source_divides_with_a_load():
         o.add_lumped(0, EZ, 12, 12, 12, RL)
     V, _ = _lumped_box(n, setup)
     assert V[-1] == pytest.approx(V0 * RL / (Rs + RL), rel=1e-3)
+
+
+# ---- Oblique thin wire (Section 2.4) ----
+
+def _owire_box(n=20, npml=4, steps=4):
+    o = _orc()(n, n, n, 0.1, npml=npml, max_steps=steps)
+    o.set_materials(np.zeros((n, n, n), np.uint8), [(1.0, 0.0, 1.0)])
+    return o
+
+
+def test_oblique_wire_on_a_grid_edge_first_step_equals_a_lumped_source():
+    """A z-directed wire whose segment midpoints sit on Ez samples: with its
+    segment 3 driven, the first step leaves exactly the fields of an ideal
+    lumped current source on that Ez edge (interpolation weights 1 and 0,
+    current moment I dx over dx^3)."""
+    I0 = 2.0
+    a = _owire_box()
+    a.add_oblique_wire((10, 10, 6), (10, 10, 13), 0.002, src_seg=3, amps=[I0, I0])
+    a.step(1)
+    b = _owire_box()
+    b.add_source(EZ, 10, 10, 9, [I0, I0])
+    b.step(1)
+    for comp in range(6):
+        np.testing.assert_allclose(a.get_field(comp), b.get_field(comp), rtol=1e-13, atol=1e-300)
+    assert np.abs(a.get_field(EZ)).max() > 0
+
+
+def test_oblique_wire_neighbour_current_follows_the_telegraph_step():
+    """Driving segment 3 with I0 puts -/+ dt I0 / dl of charge on its ends;
+    one step later segment 2 (whose midpoint field is still zero) carries
+    I = dt^2 I0 / (L' C' dl^2) = (c dt / dl)^2 I0, since L' C' = mu0 eps0."""
+    I0 = 1.5
+    o = _owire_box()
+    w = o.add_oblique_wire((10, 10, 6), (10, 10, 13), 0.002, src_seg=3, amps=[I0] * 4, rec_seg=2)
+    o.step(2)
+    _, q, rec = o.oblique_wire(w)
+    c0 = 299792458.0
+    assert rec[0] == 0.0
+    assert rec[1] == pytest.approx((c0 * o.dt / 0.1) ** 2 * I0, rel=1e-12)
+    assert q[3] + q[4] == pytest.approx(0.0, abs=1e-12 * abs(q[3]))
+
+
+def test_oblique_wire_in_a_uniform_field_takes_the_projected_field():
+    """In a uniform E (each component different), trilinear interpolation is
+    exact, so after one step every segment carries I = dt (t . E) / L' with
+    L' = mu0 ln(r0 / a) / (2 pi)."""
+    n, a_r = 20, 0.003
+    o = _owire_box(n)
+    A, B = np.array([6.3, 7.9, 5.6]), np.array([13.1, 12.2, 13.7])
+    w = o.add_oblique_wire(A, B, a_r)
+    E = (3.0, -2.0, 5.0)
+    for comp in range(3):
+        o.set_field(comp, np.full((n, n, n), E[comp]))
+    o.step(1)
+    cur, _, _ = o.oblique_wire(w)
+    t = (B - A) / np.linalg.norm(B - A)
+    mu0 = 4e-7 * math.pi
+    Lp = mu0 * math.log(0.20787957635076193 * 0.1 / a_r) / (2 * math.pi)
+    assert cur.size == int(np.floor(np.linalg.norm(B - A)))
+    np.testing.assert_allclose(cur, o.dt * float(t @ np.array(E)) / Lp, rtol=1e-12)
+
+
+def test_oblique_wire_conserves_charge():
+    """With open ends the charge on the wire only moves: the sum of q_k over
+    the segment-end lengths (half a segment at each end) stays zero while a
+    driven segment pumps charge along a skew wire for 300 steps."""
+    o = _owire_box(steps=300)
+    amps = np.exp(-(((np.arange(300) - 60.0) / 20.0) ** 2))
+    w = o.add_oblique_wire((6.2, 6.8, 7.5), (13.4, 12.9, 11.1), 0.002, src_seg=2, amps=amps)
+    o.step(300)
+    cur, q, _ = o.oblique_wire(w)
+    wt = np.ones(q.size)
+    wt[0] = wt[-1] = 0.5
+    assert np.abs(q).max() > 0 and np.abs(cur).max() > 0
+    assert abs(float(q @ wt)) <= 1e-12 * float(np.abs(q) @ wt)
+
+
+def test_oblique_wire_swapping_x_and_y_swaps_the_fields():
+    """Mirror symmetry x <-> y of a cubic vacuum box: the mirrored skew wire
+    carries the same current and its Ez is the mirror image (catches a
+    component or lattice offset applied to the wrong axis)."""
+    res = []
+    for A, B in (((6.3, 8.7, 7.1), (13.2, 11.4, 12.6)), ((8.7, 6.3, 7.1), (11.4, 13.2, 12.6))):
+        o = _owire_box(steps=150)
+        w = o.add_oblique_wire(A, B, 0.002, src_seg=1, amps=np.sin(np.arange(150) * 0.05), rec_seg=4)
+        o.step(150)
+        res.append((o.oblique_wire(w)[2], o.get_field(EZ), o.get_field(EX), o.get_field(EY)))
+    (r1, z1, x1, y1), (r2, z2, x2, y2) = res
+    assert np.abs(r1).max() > 0
+    np.testing.assert_allclose(r1, r2, rtol=1e-9, atol=1e-12 * np.abs(r1).max())
+    np.testing.assert_allclose(z1, z2.swapaxes(1, 2), rtol=1e-9, atol=1e-12 * np.abs(z1).max())
+    np.testing.assert_allclose(x1, y2.swapaxes(1, 2), rtol=1e-9, atol=1e-12 * np.abs(x1).max())
