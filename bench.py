@@ -228,6 +228,34 @@ def bench_lumped(steps: int = 1000, warmup: int = 20):
     return out
 
 
+def bench_oblique(steps: int = 400, warmup: int = 20):
+    """The 512 x 512 x 384 scene with a slanted 37-segment conductor: the
+    split pass plus the wire's current/charge kernel and its injection."""
+    import torch
+    from paper_2207_06908_amd import fdtd
+    from paper_2207_06908_amd import scenarios as S
+    sc = S.config2_oblique(n_steps=warmup + steps)
+    g = fdtd.Grid.from_params(sc.params(), precision=32)
+    S.apply(sc, g)
+    g.bind()
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    out = {"workload": "512x512x384 Yee FDTD as above plus a slanted 5 cm conductor (20 x 12 x 30 cells, "
+                       "37 segments), driven at its base",
+           "kernel": "k_h_split, k_owire_iq, k_e_split, k_owire_inject (four launches per step)",
+           "steps": steps, "value": round(sc.cells * steps / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
+           "ms_per_step": round(ms / steps, 5)}
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_array(steps: int = 20000, warmup: int = 2000):
     """The apparent-resistivity array (100 x 100 x 80 cells, three Debye soil
     layers, Heidler source): a bounded window of its 4.2M-step run."""
@@ -328,7 +356,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-grid sweep measurement")
     ap.add_argument("--no-tune", action="store_true", help="batched leg: fixed 32x8 tiles, TZ 32")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-in-the-loop measurement")
-    ap.add_argument("--no-debye", action="store_true", help="skip the Debye-soil measurement")
+    ap.add_argument("--no-debye", action="store_true", help="skip the Debye-soil, lumped-element, oblique-wire and array measurements")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run plain copies of MIB MiB (profiler counter calibration)")
     a = ap.parse_args()
@@ -419,6 +447,7 @@ def main():
     if not a.no_debye:
         out["debye"] = bench_debye()
         out["lumped"] = bench_lumped()
+        out["oblique"] = bench_oblique()
         out["array"] = bench_array()
     if not a.no_surrogate:
         out["surrogate"] = bench_surrogate()

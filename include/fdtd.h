@@ -133,6 +133,40 @@ int fdtd_add_wire(fdtd_ctx* c, int axis, int i, int j, int k, int n_cells, doubl
 int fdtd_add_source(fdtd_ctx* c, int kind, int axis, int i, int j, int k,
                     const double* amps, int n_samples);
 
+/* Oblique thin wire (Section 2.3: the arbitrarily located wire model the
+ * paper lists beside the axis-aligned ones).  A straight wire from a to b
+ * (x, y, z in cells, node (0,0,0) at the origin; both ends at least one cell
+ * clear of the CPML and the walls; at least one cell long) of radius
+ * 0 < radius < wire_r0_factor dx.  It gets floor(length) segments of equal
+ * length dl with currents I_k at the segment midpoints and charges per unit
+ * length q_k at their ends (open ends), stepped by the telegraph equations
+ *   L' dI_k/dt = E_t(mid_k) - (q_{k+1} - q_k) / (C' dl),  dq_k/dt = -dI/dl,
+ * L' = mu0 ln(r0/radius) / (2 pi), C' = 2 pi eps0 / ln(r0/radius),
+ * r0 = wire_r0_factor dx.  E_t is each E component interpolated trilinearly
+ * at the midpoint and projected on the wire; the current moment I_k dl goes
+ * back to the same samples with the same weights as a current density
+ * over dx^3 (E -= Cb J after the E update).
+ * src_seg >= 0 drives that segment's current with amps[n] (A, at
+ * (n + 1/2) dt; 0 after the last sample; n_amps may be 0); rec_seg >= 0
+ * records that segment's current every step.  Grids with oblique wires run
+ * the split pass, cannot take Debye media (FDTD_EINVAL either way round)
+ * and cannot join a batch.  id (may be NULL) receives the wire's index.
+ * FDTD_ERANGE for an end point out of range or a segment index outside
+ * [-1, n_seg), FDTD_ENONFINITE for a non-finite end point or sample,
+ * FDTD_ESTATE after the workspace size was taken. */
+int fdtd_add_oblique_wire(fdtd_ctx* ctx, const double* a, const double* b, double radius, int src_seg,
+                          const double* amps, int n_amps, int rec_seg, int* id);
+
+/* State of oblique wire id: segment currents (n_seg values, A), end-point
+ * charges per unit length (n_seg + 1, C/m) and the recorded current
+ * (min(steps done, n_rec_max) values) into host arrays; any of cur, q, rec
+ * may be NULL (then nothing is copied for it, and with all three NULL only
+ * n_seg is set, also before a workspace is bound).  Waits for the
+ * library's stream.  n_written (may be NULL) receives the record length,
+ * 0 without rec or a recorded segment. */
+int fdtd_oblique_wire_read(fdtd_ctx* ctx, int id, double* cur, double* q, double* rec, int n_rec_max, int* n_seg,
+                           int* n_written);
+
 /* Lumped resistor (kind FDTD_LUMPED_R, value R [ohm] > 0) or capacitor
  * (FDTD_LUMPED_C, value C [F] > 0) across the E edge (axis, i, j, k)
  * (Section 2.1, lumped circuit elements): the edge's conductivity grows by

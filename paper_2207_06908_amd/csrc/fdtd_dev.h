@@ -83,6 +83,31 @@ struct DebyeView {
 
 namespace mi355fdtd {
 
+// Oblique thin wires, for the split pass.  Wire w has nseg segments
+// starting at seg0 in the segment arrays and nseg + 1 end-point charges
+// starting at seg0 + w.  Segment s samples and feeds E through 24 entries
+// e = s * 24 + a * 8 + corner (a the E component): node index idx[e], sample
+// weight ws[e] = t_a * (trilinear weight) and injection weight
+// wj[e] = ws[e] * dl / dx^2, so that E_a[idx] -= (Cb / dx) * I_s * wj.
+struct OWireParam {
+  int seg0, nseg, src, rec;   // first segment, count, driven and recorded segment (-1: none)
+  double dtL;                 // dt / L'
+  double invCdl;              // 1 / (C' dl)
+  double dtdl;                // dt / dl (interior end points; twice that at the two ends)
+  double pad;
+};
+struct OWireView {
+  int n_wire, max_steps;
+  const OWireParam* par;
+  const long long* idx;
+  const double* ws;
+  const double* wj;
+  const double* amp;          // [n_wire][max_steps] driven-segment current (A)
+  double* cur;                // segment currents (A)
+  double* q;                  // end-point charges per unit length (C/m)
+  double* rec;                // [n_wire][max_steps] recorded segment current
+};
+
 // Kernel launchers (fdtd_kernels.hip).  `view` points to a GridView<float>
 // (prec 32) or GridView<double> (prec 64) whose in/out pointers are already
 // resolved: the split variant (1) updates in place (in == out), the fused
@@ -93,6 +118,9 @@ int launch_step(int prec, const void* view, int cls16, int variant, int step, in
                 void* stream);
 // Split step (H then E, in place) of a grid with Debye poles: `dview` is a
 // DebyeView<float> or DebyeView<double>.
+// One split step with oblique wires: H, the wire currents and charges, E,
+// then the wires' currents onto E (n_seg segments over all wires).
+int launch_step_owire(int prec, const void* view, int cls16, const OWireView* ow, int n_seg, int step, void* stream);
 int launch_step_debye(int prec, const void* view, const void* dview, int cls16, int step, void* stream);
 
 // Fused (variant 2) or two-step (variant 3) pass of one grid over a tile

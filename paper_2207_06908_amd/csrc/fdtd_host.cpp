@@ -28,6 +28,9 @@ const double kEta0 = std::sqrt(kMu0 / kEps0);     // free-space impedance [ohm]
 
 struct WireRec { int axis, p[3], n; double radius; };
 struct SrcRec { int axis, p[3]; std::vector<double> amps; };
+// oblique thin wire as given: end points in cells, radius, driven and
+// recorded segment, driving current
+struct OWireRec { double a[3], b[3], radius; int src, rec; std::vector<double> amps; };
 struct LumpedRec { int kind, axis, p[3]; double value; };
 struct ProbeRec { int kind, axis, p[3], n; };
 
@@ -69,6 +72,14 @@ struct fdtd_ctx {
   DebyeView<double> d64 = {};
   std::vector<WireRec> wires;
   std::vector<SrcRec> srcs;
+  std::vector<OWireRec> owr;
+  std::vector<OWireParam> ow_par;
+  std::vector<long long> ow_idx;
+  std::vector<double> ow_ws, ow_wj, ow_amp;
+  int ow_seg = 0;
+  size_t off_ow_par = 0, off_ow_idx = 0, off_ow_ws = 0, off_ow_wj = 0, off_ow_amp = 0, off_ow_cur = 0,
+         off_ow_q = 0, off_ow_rec = 0;
+  OWireView ow_view{};
   std::vector<LumpedRec> lumped;
   std::vector<ProbeRec> probes;
 
@@ -506,6 +517,57 @@ void build_sources_probes(fdtd_ctx* c) {
   }
 }
 
+int owire_segments(const OWireRec& r) {
+  double l2 = 0.0;
+  for (int u = 0; u < 3; ++u) l2 += (r.b[u] - r.a[u]) * (r.b[u] - r.a[u]);
+  return (int)std::floor(std::sqrt(l2));
+}
+
+// Per segment and E component the 8 trilinear samples of the segment midpoint
+// on that component's lattice (samples at integer node positions moved half
+// a cell along the component), the wire's telegraph factors and the driving
+// current table.
+void build_owires(fdtd_ctx* c) {
+  const int ms = c->P.max_steps;
+  const double dx = c->P.dx, r0 = c->P.wire_r0_factor * dx;
+  c->ow_par.clear(); c->ow_idx.clear(); c->ow_ws.clear(); c->ow_wj.clear();
+  c->ow_amp.assign(c->owr.size() * (size_t)ms, 0.0);
+  int seg0 = 0;
+  for (size_t w = 0; w < c->owr.size(); ++w) {
+    const OWireRec& r = c->owr[w];
+    double d[3], len = 0.0;
+    for (int u = 0; u < 3; ++u) { d[u] = r.b[u] - r.a[u]; len += d[u] * d[u]; }
+    len = std::sqrt(len);
+    const int n = owire_segments(r);
+    const double dl = len / n, dlm = dl * dx, lg = std::log(r0 / r.radius);
+    const double Lp = kMu0 * lg / (2.0 * kPi), Cp = 2.0 * kPi * kEps0 / lg;
+    c->ow_par.push_back({seg0, n, r.src, r.rec, c->dt / Lp, 1.0 / (Cp * dlm), c->dt / dlm, 0.0});
+    for (int k = 0; k < n; ++k) {
+      double m[3];
+      for (int u = 0; u < 3; ++u) m[u] = r.a[u] + (k + 0.5) * dl * d[u] / len;
+      for (int a = 0; a < 3; ++a) {
+        int lo[3];
+        double f[3];
+        for (int u = 0; u < 3; ++u) {
+          const double x = u == a ? m[u] - 0.5 : m[u];
+          lo[u] = (int)std::floor(x);
+          f[u] = x - lo[u];
+        }
+        for (int q = 0; q < 8; ++q) {
+          const int bx = q & 1, by = (q >> 1) & 1, bz = (q >> 2) & 1;
+          const double wt = (bx ? f[0] : 1.0 - f[0]) * (by ? f[1] : 1.0 - f[1]) * (bz ? f[2] : 1.0 - f[2]);
+          c->ow_idx.push_back(node_index(c, lo[0] + bx, lo[1] + by, lo[2] + bz));
+          c->ow_ws.push_back(d[a] / len * wt);
+          c->ow_wj.push_back(d[a] / len * wt * dlm / (dx * dx));
+        }
+      }
+    }
+    for (int t = 0; t < ms && t < (int)r.amps.size(); ++t) c->ow_amp[w * ms + t] = r.amps[t];
+    seg0 += n;
+  }
+  c->ow_seg = seg0;
+}
+
 void layout(fdtd_ctx* c) {
   const size_t ts = tsize(c);
   const size_t N = (size_t)c->ncell;
@@ -540,6 +602,14 @@ void layout(fdtd_ctx* c) {
   c->off_term_idx = take(c->term_idx.size() * sizeof(long long));
   c->off_term_w = take(c->term_w.size() * sizeof(double));
   c->off_out = take(c->probes.size() * (size_t)c->P.max_steps * sizeof(double));
+  c->off_ow_par = take(c->ow_par.size() * sizeof(OWireParam));
+  c->off_ow_idx = take(c->ow_idx.size() * sizeof(long long));
+  c->off_ow_ws = take(c->ow_ws.size() * sizeof(double));
+  c->off_ow_wj = take(c->ow_wj.size() * sizeof(double));
+  c->off_ow_amp = take(c->ow_amp.size() * sizeof(double));
+  c->off_ow_cur = take((size_t)c->ow_seg * sizeof(double));
+  c->off_ow_q = take((size_t)(c->ow_seg + c->owr.size()) * sizeof(double));
+  c->off_ow_rec = take(c->owr.size() * (size_t)c->P.max_steps * sizeof(double));
   c->max_tiles = 0;
   if (np > 0) {  // bound for 32-wide, 4-high tiles and chunks of >= 8 planes
     c->max_tiles = (size_t)(c->N[0] / 32 + 6) * (c->N[1] / 4 + 6) * (c->N[2] / 8 + 6);
@@ -666,6 +736,33 @@ int upload(fdtd_ctx* c) {
     if (e != hipSuccess) return hip_fail(c, e, "upload Debye tables");
   }
   e = hipMemsetAsync(g.pr_out, 0, c->probes.size() * (size_t)c->P.max_steps * sizeof(double), st);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
+  if (!c->owr.empty()) {
+    OWireView& w = c->ow_view;
+    w.n_wire = (int)c->owr.size();
+    w.max_steps = c->P.max_steps;
+    w.par = (const OWireParam*)(c->ws + c->off_ow_par);
+    w.idx = (const long long*)(c->ws + c->off_ow_idx);
+    w.ws = (const double*)(c->ws + c->off_ow_ws);
+    w.wj = (const double*)(c->ws + c->off_ow_wj);
+    w.amp = (const double*)(c->ws + c->off_ow_amp);
+    w.cur = (double*)(c->ws + c->off_ow_cur);
+    w.q = (double*)(c->ws + c->off_ow_q);
+    w.rec = (double*)(c->ws + c->off_ow_rec);
+    const Up wups[] = {
+        {(void*)w.par, c->ow_par.data(), c->ow_par.size() * sizeof(OWireParam)},
+        {(void*)w.idx, c->ow_idx.data(), c->ow_idx.size() * sizeof(long long)},
+        {(void*)w.ws, c->ow_ws.data(), c->ow_ws.size() * sizeof(double)},
+        {(void*)w.wj, c->ow_wj.data(), c->ow_wj.size() * sizeof(double)},
+        {(void*)w.amp, c->ow_amp.data(), c->ow_amp.size() * sizeof(double)},
+    };
+    for (const Up& u : wups) {
+      e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return hip_fail(c, e, "upload oblique-wire tables");
+    }
+    // currents, charges and the record are contiguous from off_ow_cur
+    e = hipMemsetAsync(w.cur, 0, c->off_ow_rec + c->owr.size() * (size_t)c->P.max_steps * sizeof(double) - c->off_ow_cur, st);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);  // staging buffers are freed on return
   if (e != hipSuccess) return hip_fail(c, e, "upload");
   return FDTD_OK;
@@ -679,6 +776,7 @@ int freeze(fdtd_ctx* c) {
   if (rc) return rc;
   build_cpml(c);
   build_sources_probes(c);
+  build_owires(c);
   layout(c);
   if (c->ws_bytes == 0) return fail(c, FDTD_EINVAL, "a CPML state array or the source table exceeds 4 GiB");
   c->frozen = true;
@@ -760,6 +858,7 @@ int fdtd_set_debye(fdtd_ctx* c, int n_poles, const double* tau, const double* d_
   if (!c || !tau || !d_eps || n_poles < 1 || n_poles > D_MAXPOLE) return fail(c, FDTD_EINVAL, "bad Debye arguments");
   if (c->frozen) return fail(c, FDTD_ESTATE, "set-up after the workspace size was taken");
   if (c->mats.empty()) return fail(c, FDTD_ESTATE, "Debye poles before the materials");
+  if (!c->owr.empty()) return fail(c, FDTD_EINVAL, "Debye media in a grid with oblique wires");
   if (c->P.loss_mode != FDTD_LOSS_SEMI) return fail(c, FDTD_EINVAL, "Debye media need the semi-implicit loss form");
   const size_t nm = c->mats.size();
   for (int p = 0; p < n_poles; ++p)
@@ -797,6 +896,57 @@ int fdtd_add_source(fdtd_ctx* c, int kind, int axis, int i, int j, int k, const 
   if (!edge_updated(c, axis, p)) return fail(c, FDTD_ERANGE, "source edge outside the updated edges");
   if (!finite_all(amps, (size_t)n)) return fail(c, FDTD_ENONFINITE, "non-finite source sample");
   c->srcs.push_back({axis, {i, j, k}, std::vector<double>(amps, amps + n)});
+  return FDTD_OK;
+}
+
+int fdtd_add_oblique_wire(fdtd_ctx* c, const double* a, const double* b, double radius, int src_seg,
+                          const double* amps, int n_amps, int rec_seg, int* id) {
+  if (!c || !a || !b || n_amps < 0 || (n_amps > 0 && !amps)) return fail(c, FDTD_EINVAL, "bad oblique-wire arguments");
+  if (c->frozen) return fail(c, FDTD_ESTATE, "set-up after the workspace size was taken");
+  if (c->npole) return fail(c, FDTD_EINVAL, "oblique wires in a grid with Debye media");
+  OWireRec r;
+  double l2 = 0.0;
+  for (int u = 0; u < 3; ++u) {
+    if (!std::isfinite(a[u]) || !std::isfinite(b[u])) return fail(c, FDTD_ENONFINITE, "non-finite wire end point");
+    const double lo = c->P.npml + 1.0, hi = c->N[u] - c->P.npml - 2.0;
+    if (a[u] < lo || a[u] > hi || b[u] < lo || b[u] > hi)
+      return fail(c, FDTD_ERANGE, "oblique wire reaches the CPML or the wall");
+    r.a[u] = a[u];
+    r.b[u] = b[u];
+    l2 += (b[u] - a[u]) * (b[u] - a[u]);
+  }
+  if (!(std::sqrt(l2) >= 1.0)) return fail(c, FDTD_EINVAL, "oblique wire shorter than one cell");
+  if (!(radius > 0) || !(radius < c->P.wire_r0_factor * c->P.dx))
+    return fail(c, FDTD_EINVAL, "oblique-wire radius out of (0, wire_r0_factor dx)");
+  if (n_amps && !finite_all(amps, (size_t)n_amps)) return fail(c, FDTD_ENONFINITE, "non-finite source sample");
+  r.radius = radius;
+  const int n = owire_segments(r);
+  if (src_seg < -1 || src_seg >= n || rec_seg < -1 || rec_seg >= n) return fail(c, FDTD_ERANGE, "segment index");
+  r.src = src_seg;
+  r.rec = rec_seg;
+  if (n_amps) r.amps.assign(amps, amps + n_amps);
+  c->owr.push_back(r);
+  if (id) *id = (int)c->owr.size() - 1;
+  return FDTD_OK;
+}
+
+int fdtd_oblique_wire_read(fdtd_ctx* c, int id, double* cur, double* q, double* rec, int n_rec_max, int* n_seg,
+                           int* n_written) {
+  if (!c || id < 0 || id >= (int)c->owr.size() || n_rec_max < 0) return fail(c, FDTD_EINVAL, "bad oblique-wire id");
+  const OWireRec& r = c->owr[id];
+  const int n = owire_segments(r);
+  if (n_seg) *n_seg = n;
+  const int nr = r.rec >= 0 ? (int)std::min<long long>((long long)c->steps_done, n_rec_max) : 0;
+  if (n_written) *n_written = rec ? nr : 0;
+  if (!cur && !q && !(rec && nr)) return FDTD_OK;
+  if (!c->ws) return fail(c, FDTD_ESTATE, "no workspace bound");
+  hipError_t e = hipStreamSynchronize(c->stream);
+  const OWireParam& p = c->ow_par[id];
+  if (e == hipSuccess && cur) e = hipMemcpy(cur, c->ow_view.cur + p.seg0, sizeof(double) * n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && q) e = hipMemcpy(q, c->ow_view.q + p.seg0 + id, sizeof(double) * (n + 1), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && rec && nr)
+    e = hipMemcpy(rec, c->ow_view.rec + (size_t)id * c->P.max_steps, sizeof(double) * nr, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "oblique-wire read");
   return FDTD_OK;
 }
 
@@ -987,7 +1137,8 @@ int fdtd_step(fdtd_ctx* c, int n) {
   const bool tb2_ok = tb2_cpml_fits(c->P.npml, c->P.precision);
   int chosen = c->variant != FDTD_KERNEL_AUTO ? c->variant : listable ? FDTD_KERNEL_TB2 : FDTD_KERNEL_FUSED;
   if (chosen == FDTD_KERNEL_TB2 && !tb2_ok) chosen = FDTD_KERNEL_FUSED;
-  if (c->npole) chosen = FDTD_KERNEL_SPLIT;  // Debye media: the split pass only
+  if (c->npole && !c->owr.empty()) return fail(c, FDTD_EINVAL, "oblique wires in a grid with Debye media");
+  if (c->npole || !c->owr.empty()) chosen = FDTD_KERNEL_SPLIT;  // Debye media, oblique wires: the split pass only
   for (int t = 0; t < n;) {
     // the two-step pass needs two steps; an odd remainder takes one fused step
     const int variant = (chosen == FDTD_KERNEL_TB2 && n - t < 2) ? FDTD_KERNEL_FUSED : chosen;
@@ -1036,6 +1187,9 @@ int fdtd_step(fdtd_ctx* c, int n) {
         if (he == hipSuccess) he = hipStreamWaitEvent(c->stream, c->ev_join, 0);
         if (he != hipSuccess) return hip_fail(c, he, "stream join");
       }
+    } else if (!c->owr.empty()) {
+      e = launch_step_owire(c->P.precision, view, c->cls16, &c->ow_view, c->ow_seg, (int)c->steps_done,
+                            (void*)c->stream);
     } else if (c->npole) {
       const void* dview = c->P.precision == 64 ? (const void*)&c->d64 : (const void*)&c->d32;
       e = launch_step_debye(c->P.precision, view, dview, c->cls16, (int)c->steps_done, (void*)c->stream);
@@ -1387,7 +1541,7 @@ int fdtd_batch_pack(fdtd_ctx* const* grids, int n, void* hip_stream, fdtd_batch*
     int rc = freeze(c);
     if (rc) { delete b; return rc; }
     if (c->ws) { delete b; return FDTD_ESTATE; }  // already bound on its own
-    if (c->npole) { delete b; return FDTD_EINVAL; }  // Debye media run on their own (split pass)
+    if (c->npole || !c->owr.empty()) { delete b; return FDTD_EINVAL; }  // Debye media, oblique wires: split pass on their own
     if (g == 0) {
       b->prec = c->P.precision;
       b->cls16 = c->cls16;

@@ -42,6 +42,10 @@ SIGNATURES = [
     ("fdtd_set_materials", C.c_int, [_vp, _vp, C.POINTER(Material), C.c_int]),
     ("fdtd_set_debye", C.c_int, [_vp, C.c_int, _vp, _vp]),
     ("fdtd_add_lumped", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]),
+    ("fdtd_add_oblique_wire", C.c_int, [_vp, _vp, _vp, C.c_double, C.c_int, _vp, C.c_int, C.c_int,
+                                        C.POINTER(C.c_int)]),
+    ("fdtd_oblique_wire_read", C.c_int, [_vp, C.c_int, _vp, _vp, _vp, C.c_int, C.POINTER(C.c_int),
+                                         C.POINTER(C.c_int)]),
     ("fdtd_add_source_r", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int, C.c_double]),
     ("fdtd_add_wire", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]),
     ("fdtd_add_source", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int]),
@@ -166,6 +170,32 @@ class Grid:
     def add_lumped(self, kind, axis, i, j, k, value):
         """Lumped resistor (kind 0, ohm) or capacitor (kind 1, F) on an E edge."""
         self._chk(lib().fdtd_add_lumped(self._h, kind, axis, i, j, k, float(value)))
+
+    def add_oblique_wire(self, a, b, radius, src_seg=-1, amps=None, rec_seg=-1) -> int:
+        """Oblique thin wire from a to b (cells); src_seg drives that segment's
+        current with amps (A), rec_seg records that segment's current."""
+        pa = np.ascontiguousarray(a, dtype=np.float64)
+        pb = np.ascontiguousarray(b, dtype=np.float64)
+        am = np.ascontiguousarray([] if amps is None else amps, dtype=np.float64)
+        wid = C.c_int(-1)
+        self._chk(lib().fdtd_add_oblique_wire(self._h, pa.ctypes.data, pb.ctypes.data, float(radius), int(src_seg),
+                                              am.ctypes.data, am.size, int(rec_seg), C.byref(wid)))
+        return wid.value
+
+    def oblique_wire_segments(self, wid) -> int:
+        ns = C.c_int(0)
+        self._chk(lib().fdtd_oblique_wire_read(self._h, wid, None, None, None, 0, C.byref(ns), None))
+        return ns.value
+
+    def oblique_wire(self, wid, max_rec=None):
+        """(segment currents, end-point charges per unit length, record)."""
+        ns, nw = C.c_int(self.oblique_wire_segments(wid)), C.c_int(0)
+        cur = np.zeros(ns.value, np.float64)
+        q = np.zeros(ns.value + 1, np.float64)
+        rec = np.zeros(int(max_rec if max_rec is not None else self.max_steps), np.float64)
+        self._chk(lib().fdtd_oblique_wire_read(self._h, wid, cur.ctypes.data, q.ctypes.data, rec.ctypes.data,
+                                               rec.size, C.byref(ns), C.byref(nw)))
+        return cur, q, rec[:nw.value].copy()
 
     def add_source_r(self, kind, axis, i, j, k, amps, r):
         """Non-ideal source: current (kind 0) with shunt r, or voltage (kind 1)

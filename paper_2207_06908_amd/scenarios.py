@@ -164,6 +164,8 @@ class Scenario:
     # non-ideal sources (kind 0 current / 1 voltage, axis, i, j, k, amps, r)
     lumped: List[Tuple[int, int, int, int, int, float]] = field(default_factory=list)
     sources_r: List[Tuple[int, int, int, int, int, np.ndarray, float]] = field(default_factory=list)
+    # oblique thin wires: (end a, end b in cells, radius, driven segment, amps, recorded segment)
+    owires: List[tuple] = field(default_factory=list)
     meta: dict = field(default_factory=dict)
 
     @property
@@ -192,6 +194,8 @@ def apply(sc: Scenario, sim) -> List[int]:
         sim.add_source_r(kind, ax, i, j, k, amps, r)
     for (kind, ax, i, j, k, v) in sc.lumped:
         sim.add_lumped(kind, ax, i, j, k, v)
+    for (a, b, r, src, amps, rec) in sc.owires:
+        sim.add_oblique_wire(a, b, r, src, amps, rec)
     ids = []
     for (_name, kind, ax, i, j, k, n) in sc.probes:
         ids.append(sim.add_probe(kind, ax, i, j, k, n))
@@ -448,3 +452,19 @@ def config3(n_grids: int = 256, seed: int = 3, n_steps: int = 2000) -> List[Scen
         dims = grid_dims_for(c, rng)
         out.append(electrode_grid(c, dims, n_steps=n_steps, name=f"config3_g{g}"))
     return out
+
+
+def config2_oblique(**kw) -> Scenario:
+    """The config-2 scene (any of config2's size arguments) plus a slanted
+    5 cm conductor in the air beside the vertical wire, like a tower leg:
+    it rises 30 cells over a 20 x 12-cell run, is driven at its lowest
+    segment by a tenth of the scene's source current, and its top segment's
+    current is recorded."""
+    sc = config2(**kw)
+    sc.name = sc.name.replace("config2", "config2_oblique")
+    _ax, ic, jc, ks, _n, _a = sc.wires[0]
+    a = (ic + 12.25, jc - 6.5, ks + 4.4)
+    b = (ic + 32.25, jc + 5.5, ks + 34.4)
+    n_seg = int(np.floor(np.sqrt(20.0 ** 2 + 12.0 ** 2 + 30.0 ** 2)))
+    sc.owires = [(a, b, 0.05, 0, sc.sources[0][4] * 0.1, n_seg - 1)]
+    return sc

@@ -228,3 +228,33 @@ def test_lumped_and_nonideal_source_validation():
     w.add_wire(2, 5, 5, 2, 4, 0.01)
     w.add_lumped(0, 2, 5, 5, 3, 50.0)            # on the wire's axial edge
     assert _code(lambda: w.workspace_bytes() or w.finalize()) == -2
+
+
+def test_oblique_wire_validation():
+    """fdtd_add_oblique_wire: ends one cell clear of the walls (and CPML), at
+    least one cell long, 0 < radius < r0, segment indices in [-1, n_seg),
+    finite inputs, not with Debye media either way round; the segment count
+    is floor(length) before a workspace exists."""
+    g = _grid(npml=0)
+    amps = np.ones(4)
+    assert _code(lambda: g.add_oblique_wire((0.5, 2, 2), (5, 5, 5), 0.01)) == -2     # off the x = 0 wall by < 1
+    assert _code(lambda: g.add_oblique_wire((2, 2, 2), (2, 2, 7.5), 0.01)) == -2     # z > nz - 2
+    assert _code(lambda: g.add_oblique_wire((2, 2, 2), (2.5, 2.5, 2.5), 0.01)) == -1 # shorter than a cell
+    assert _code(lambda: g.add_oblique_wire((2, 2, 2), (6, 5, 5), 0.2)) == -1        # radius >= r0 = 0.104 m
+    assert _code(lambda: g.add_oblique_wire((2, 2, 2), (float("nan"), 5, 5), 0.01)) == -7
+    assert _code(lambda: g.add_oblique_wire((2, 2, 2), (6, 5, 5), 0.01, src_seg=5, amps=amps)) == -2
+    assert _code(lambda: g.add_oblique_wire((2, 2, 2), (6, 5, 5), 0.01, rec_seg=-2)) == -2
+    assert _code(lambda: g.add_oblique_wire((2, 2, 2), (6, 5, 5), 0.01, src_seg=0, amps=[1.0, float("inf")])) == -7
+    w = g.add_oblique_wire((2, 2, 2), (6, 5, 5), 0.01, src_seg=0, amps=amps, rec_seg=4)  # length 5.83
+    assert w == 0
+    assert g.oblique_wire_segments(w) == 5
+    assert _code(lambda: g.oblique_wire(w)) == -3                                    # no workspace yet
+    cm = np.zeros((9, 10, 12), np.uint8)
+    g.set_materials(cm, [(1.0, 0.0, 1.0)])
+    assert _code(lambda: g.set_debye([1e-6], [[5.0]])) == -1
+    d = _grid(npml=0)
+    d.set_materials(cm, [(1.0, 0.0, 1.0)])
+    d.set_debye([1e-6], [[5.0]])
+    assert _code(lambda: d.add_oblique_wire((2, 2, 2), (6, 5, 5), 0.01)) == -1
+    g.workspace_bytes()
+    assert _code(lambda: g.add_oblique_wire((2, 2, 2), (6, 5, 5), 0.01)) == -3

@@ -1,0 +1,97 @@
+"""GPU parity for the oblique thin wire (the arbitrarily located wire model
+of Section 2.3): fields, segment currents, charges and the recorded current
+against the FP64 oracle on the same seeded inputs, element by element; the
+lumped-source identity of a wire on a grid edge; and charge conservation at
+the full 512 x 512 x 384 size in the launch configuration the bench times."""
+import numpy as np
+import pytest
+
+from paper_2207_06908_amd import scenarios as S
+from tests.test_gpu_parity import _random_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2207_06908_amd import fdtd
+    fdtd.lib()
+    return fdtd
+
+
+def _owire_case(nx, ny, nz, npml, seed, nsteps=60):
+    """The random case (random media, axis wires, sources, probes) plus a
+    driven skew wire, a second undriven skew wire that is recorded, and a
+    wire along z on Ez samples."""
+    sc = _random_case(nx, ny, nz, npml, seed=seed, nsteps=nsteps)
+    amps = S.gaussian(nsteps, sc.dt, 12 * sc.dt, 4 * sc.dt, 3.0)
+    lo = npml + 1.0
+    hx, hy, hz = nx - npml - 2.0, ny - npml - 2.0, nz - npml - 2.0
+    sc.owires = [((lo + 0.3, lo + 1.7, lo + 0.6), (hx - 0.4, hy - 0.9, hz - 0.2), 0.004, 1, amps, 3),
+                 ((hx - 0.1, lo + 0.2, hz - 1.3), (lo + 2.5, hy - 0.05, lo + 0.75), 0.01, -1, None, 2),
+                 ((lo + 2.0, lo + 2.0, lo), (lo + 2.0, lo + 2.0, hz), 0.002, -1, None, 0)]
+    return sc
+
+
+@pytest.mark.parametrize("variant", [0, 3])
+@pytest.mark.parametrize("dims,npml", [((40, 24, 22), 4), ((21, 19, 17), 0)])
+def test_owire_fields_and_wire_state_elementwise(fd, oracle_mod, variant, dims, npml):
+    sc = _owire_case(*dims, npml, seed=dims[0] + 11)
+    print(f"owire {dims} npml={npml} variant={variant}", flush=True)
+    o = oracle_mod.Oracle.from_params(sc.params())
+    S.apply(sc, o)
+    o.step(sc.n_steps)
+    for prec, tol in ((64, 1e-11), (32, 2e-5)):
+        g = fd.Grid.from_params(sc.params(), precision=prec)
+        S.apply(sc, g)
+        g.set_kernel(variant)
+        g.step(sc.n_steps)
+        for c in range(6):
+            ref, got = o.get_field(c), g.get_field(c)
+            scale = max(float(np.abs(ref).max()), 1e-300)
+            err = float(np.abs(got - ref).max()) / scale
+            assert err <= tol, (prec, c, err)
+        for w in range(len(sc.owires)):
+            for ref, got in zip(o.oblique_wire(w), g.oblique_wire(w)):
+                assert ref.shape == got.shape
+                scale = max(float(np.abs(ref).max()), 1e-300)
+                assert float(np.abs(got - ref).max()) / scale <= tol, (prec, w)
+        assert np.abs(o.oblique_wire(1)[2]).max() > 0     # the undriven wire picked up current
+
+
+def test_owire_on_an_edge_first_step_is_a_lumped_source_on_the_gpu(fd):
+    """FP64: a z-wire with midpoints on Ez samples, driven at segment 3, leaves
+    after one step the fields of a lumped current source on that edge."""
+    n, I0 = 20, 2.0
+    res = []
+    for use_wire in (True, False):
+        g = fd.Grid(n, n, n, 0.1, npml=4, max_steps=2, precision=64)
+        g.set_materials(np.zeros((n, n, n), np.uint8), [(1.0, 0.0, 1.0)])
+        if use_wire:
+            g.add_oblique_wire((10, 10, 6), (10, 10, 13), 0.002, src_seg=3, amps=[I0, I0])
+        else:
+            g.add_source(2, 10, 10, 9, [I0, I0])
+        g.step(1)
+        res.append([g.get_field(c) for c in range(6)])
+    for c in range(6):
+        np.testing.assert_allclose(res[0][c], res[1][c], rtol=1e-13, atol=1e-300)
+    assert np.abs(res[0][2]).max() > 0
+
+
+def test_owire_full_size_conserves_charge(fd):
+    """The 512 x 512 x 384 scene with the slanted conductor, FP32 fields, the
+    bench's launch configuration: after 200 steps the wire's charge sums to
+    zero (the charges are kept in FP64), the record is finite and nonzero."""
+    sc = S.config2_oblique(n_steps=200)
+    print(f"owire full size {sc.name}", flush=True)
+    g = fd.Grid.from_params(sc.params(), precision=32)
+    S.apply(sc, g)
+    g.step(sc.n_steps)
+    cur, q, rec = g.oblique_wire(0)
+    wt = np.ones(q.size)
+    wt[0] = wt[-1] = 0.5
+    assert rec.size == 200 and np.all(np.isfinite(rec)) and np.abs(rec).max() > 0
+    assert np.all(np.isfinite(cur)) and np.abs(q).max() > 0
+    assert abs(float(q @ wt)) <= 1e-12 * float(np.abs(q) @ wt)
