@@ -149,8 +149,9 @@ int fdtd_add_source(fdtd_ctx* c, int kind, int axis, int i, int j, int k,
  * src_seg >= 0 drives that segment's current with amps[n] (A, at
  * (n + 1/2) dt; 0 after the last sample; n_amps may be 0); rec_seg >= 0
  * records that segment's current every step.  Grids with oblique wires run
- * the split pass, cannot take Debye media (FDTD_EINVAL either way round)
- * and cannot join a batch.  id (may be NULL) receives the wire's index.
+ * one-step passes (the two-step pass, asked for or chosen by default, gives
+ * way to the fused pass; the split pass stays available), cannot take
+ * Debye media (FDTD_EINVAL either way round) and cannot join a batch.  id (may be NULL) receives the wire's index.
  * FDTD_ERANGE for an end point out of range or a segment index outside
  * [-1, n_seg), FDTD_ENONFINITE for a non-finite end point or sample,
  * FDTD_ESTATE after the workspace size was taken. */

@@ -118,9 +118,11 @@ int launch_step(int prec, const void* view, int cls16, int variant, int step, in
                 void* stream);
 // Split step (H then E, in place) of a grid with Debye poles: `dview` is a
 // DebyeView<float> or DebyeView<double>.
-// One split step with oblique wires: H, the wire currents and charges, E,
-// then the wires' currents onto E (n_seg segments over all wires).
-int launch_step_owire(int prec, const void* view, int cls16, const OWireView* ow, int n_seg, int step, void* stream);
+// Oblique wires around one one-step field pass (split or fused): the wire
+// currents and charges from the input E before it, the wires' currents onto
+// the output E after it (n_seg segments over all wires).
+int launch_owire_iq(int prec, const void* view, const OWireView* ow, int step, void* stream);
+int launch_owire_inject(int prec, const void* view, int cls16, const OWireView* ow, int n_seg, void* stream);
 int launch_step_debye(int prec, const void* view, const void* dview, int cls16, int step, void* stream);
 
 // Fused (variant 2) or two-step (variant 3) pass of one grid over a tile

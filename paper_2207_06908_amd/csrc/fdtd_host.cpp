@@ -1138,7 +1138,9 @@ int fdtd_step(fdtd_ctx* c, int n) {
   int chosen = c->variant != FDTD_KERNEL_AUTO ? c->variant : listable ? FDTD_KERNEL_TB2 : FDTD_KERNEL_FUSED;
   if (chosen == FDTD_KERNEL_TB2 && !tb2_ok) chosen = FDTD_KERNEL_FUSED;
   if (c->npole && !c->owr.empty()) return fail(c, FDTD_EINVAL, "oblique wires in a grid with Debye media");
-  if (c->npole || !c->owr.empty()) chosen = FDTD_KERNEL_SPLIT;  // Debye media, oblique wires: the split pass only
+  if (c->npole) chosen = FDTD_KERNEL_SPLIT;  // Debye media: the split pass only
+  // oblique wires sample E^n and feed E^{n+1}: one-step passes only
+  if (!c->owr.empty() && chosen == FDTD_KERNEL_TB2) chosen = FDTD_KERNEL_FUSED;
   for (int t = 0; t < n;) {
     // the two-step pass needs two steps; an odd remainder takes one fused step
     const int variant = (chosen == FDTD_KERNEL_TB2 && n - t < 2) ? FDTD_KERNEL_FUSED : chosen;
@@ -1176,6 +1178,10 @@ int fdtd_step(fdtd_ctx* c, int n) {
       if (er != hipSuccess) return hip_fail(c, er, "hipEventRecord");
     }
     int e;
+    if (!c->owr.empty()) {
+      e = launch_owire_iq(c->P.precision, view, &c->ow_view, (int)c->steps_done, (void*)c->stream);
+      if (e) return fail(c, FDTD_EDEVICE, std::string("oblique-wire launch: ") + hipGetErrorString((hipError_t)e));
+    }
     if (lists) {
       hipError_t he = hipEventRecord(c->ev_fork, c->stream);
       if (he == hipSuccess) he = hipStreamWaitEvent(c->aux, c->ev_fork, 0);
@@ -1187,9 +1193,6 @@ int fdtd_step(fdtd_ctx* c, int n) {
         if (he == hipSuccess) he = hipStreamWaitEvent(c->stream, c->ev_join, 0);
         if (he != hipSuccess) return hip_fail(c, he, "stream join");
       }
-    } else if (!c->owr.empty()) {
-      e = launch_step_owire(c->P.precision, view, c->cls16, &c->ow_view, c->ow_seg, (int)c->steps_done,
-                            (void*)c->stream);
     } else if (c->npole) {
       const void* dview = c->P.precision == 64 ? (const void*)&c->d64 : (const void*)&c->d32;
       e = launch_step_debye(c->P.precision, view, dview, c->cls16, (int)c->steps_done, (void*)c->stream);
@@ -1198,6 +1201,10 @@ int fdtd_step(fdtd_ctx* c, int n) {
                       (void*)c->stream);
     }
     if (e) return fail(c, FDTD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString((hipError_t)e));
+    if (!c->owr.empty()) {
+      e = launch_owire_inject(c->P.precision, view, c->cls16, &c->ow_view, c->ow_seg, (void*)c->stream);
+      if (e) return fail(c, FDTD_EDEVICE, std::string("oblique-wire launch: ") + hipGetErrorString((hipError_t)e));
+    }
     if (variant != FDTD_KERNEL_SPLIT) c->cur ^= 1;
     if (slot >= 0) {
       hipError_t er = hipEventRecord(c->ev1[slot], c->stream);

@@ -1046,9 +1046,10 @@ hipError_t step_split(const GridView<T>& g, int step, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Oblique thin wires: one block per wire.  New segment currents from E^n and
-// the charges q^n (the driven segment takes its sample), then the charges
-// from the new currents; both before the E update of the step.
+// Oblique thin wires: one block per wire.  New segment currents from E^n (the
+// input field set) and the charges q^n (the driven segment takes its sample),
+// then the charges from the new currents; both before the step's field pass,
+// which they do not depend on.
 template <typename T>
 __global__ void __launch_bounds__(256) k_owire_iq(GridView<T> g, OWireView w, int step) {
   const OWireParam p = w.par[blockIdx.x];
@@ -1061,7 +1062,7 @@ __global__ void __launch_bounds__(256) k_owire_iq(GridView<T> g, OWireView w, in
     } else {
       const size_t b = (size_t)(p.seg0 + s) * 24;
       double et = 0.0;
-      for (int e = 0; e < 24; ++e) et += w.ws[b + e] * (double)g.fo[e >> 3][w.idx[b + e]];
+      for (int e = 0; e < 24; ++e) et += w.ws[b + e] * (double)g.fi[e >> 3][w.idx[b + e]];
       v = cur[s] + p.dtL * (et - (q[s + 1] - q[s]) * p.invCdl);
     }
     cur[s] = v;
@@ -1074,7 +1075,8 @@ __global__ void __launch_bounds__(256) k_owire_iq(GridView<T> g, OWireView w, in
   if (threadIdx.x == 0 && p.rec >= 0) w.rec[(size_t)blockIdx.x * w.max_steps + step] = cur[p.rec];
 }
 
-// The wires' current moments onto E after the E update: one thread per
+// The wires' current moments onto the output E after the step's field pass
+// (its lumped sources included): one thread per
 // (segment, component, corner) entry; neighbouring segments share samples.
 template <typename T, typename CI>
 __global__ void __launch_bounds__(256) k_owire_inject(GridView<T> g, OWireView w, int n_seg) {
@@ -1085,23 +1087,6 @@ __global__ void __launch_bounds__(256) k_owire_inject(GridView<T> g, OWireView w
   const int cls = ((const CI*)g.cls)[n];
   const double cbdx = (double)g.ctab[cls * K_STRIDE + K_CBX + 2 * a];
   atomicAdd(&g.fo[a][n], (T)(-cbdx * w.cur[e / 24] * w.wj[e]));
-}
-
-template <typename T, typename CI>
-hipError_t step_split_owire(const GridView<T>& g, const OWireView& w, int n_seg, int step, hipStream_t st) {
-  const dim3 blk(64, 4, 1), grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
-  if (g.npml > 0)
-    hipLaunchKernelGGL((k_h_split<T, CI, true>), grd, blk, 0, st, g);
-  else
-    hipLaunchKernelGGL((k_h_split<T, CI, false>), grd, blk, 0, st, g);
-  hipLaunchKernelGGL((k_owire_iq<T>), dim3(w.n_wire), dim3(256), 0, st, g, w, step);
-  if (g.npml > 0)
-    hipLaunchKernelGGL((k_e_split<T, CI, true>), grd, blk, 0, st, g, step);
-  else
-    hipLaunchKernelGGL((k_e_split<T, CI, false>), grd, blk, 0, st, g, step);
-  const long long ne = (long long)n_seg * 24;
-  hipLaunchKernelGGL((k_owire_inject<T, CI>), dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, g, w, n_seg);
-  return hipGetLastError();
 }
 
 template <typename T, typename CI>
@@ -1117,19 +1102,28 @@ hipError_t step_split_debye(const GridView<T>& g, const DebyeView<T>& d, int ste
   return hipGetLastError();
 }
 
-int launch_step_owire(int prec, const void* view, int cls16, const OWireView* ow, int n_seg, int step, void* stream) {
+int launch_owire_iq(int prec, const void* view, const OWireView* ow, int step, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e;
+  if (prec == 64)
+    hipLaunchKernelGGL((k_owire_iq<double>), dim3(ow->n_wire), dim3(256), 0, st, *(const GridView<double>*)view, *ow, step);
+  else
+    hipLaunchKernelGGL((k_owire_iq<float>), dim3(ow->n_wire), dim3(256), 0, st, *(const GridView<float>*)view, *ow, step);
+  return (int)hipGetLastError();
+}
+
+int launch_owire_inject(int prec, const void* view, int cls16, const OWireView* ow, int n_seg, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const dim3 grd((unsigned)(((long long)n_seg * 24 + 255) / 256)), blk(256);
   if (prec == 64) {
     const GridView<double>& g = *(const GridView<double>*)view;
-    e = cls16 ? step_split_owire<double, uint16_t>(g, *ow, n_seg, step, st)
-              : step_split_owire<double, uint8_t>(g, *ow, n_seg, step, st);
+    if (cls16) hipLaunchKernelGGL((k_owire_inject<double, uint16_t>), grd, blk, 0, st, g, *ow, n_seg);
+    else hipLaunchKernelGGL((k_owire_inject<double, uint8_t>), grd, blk, 0, st, g, *ow, n_seg);
   } else {
     const GridView<float>& g = *(const GridView<float>*)view;
-    e = cls16 ? step_split_owire<float, uint16_t>(g, *ow, n_seg, step, st)
-              : step_split_owire<float, uint8_t>(g, *ow, n_seg, step, st);
+    if (cls16) hipLaunchKernelGGL((k_owire_inject<float, uint16_t>), grd, blk, 0, st, g, *ow, n_seg);
+    else hipLaunchKernelGGL((k_owire_inject<float, uint8_t>), grd, blk, 0, st, g, *ow, n_seg);
   }
-  return (int)e;
+  return (int)hipGetLastError();
 }
 
 int launch_step_debye(int prec, const void* view, const void* dview, int cls16, int step, void* stream) {

@@ -35,7 +35,7 @@ def _owire_case(nx, ny, nz, npml, seed, nsteps=60):
     return sc
 
 
-@pytest.mark.parametrize("variant", [0, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])   # auto, split, fused; the two-step pass gives way to fused
 @pytest.mark.parametrize("dims,npml", [((40, 24, 22), 4), ((21, 19, 17), 0)])
 def test_owire_fields_and_wire_state_elementwise(fd, oracle_mod, variant, dims, npml):
     sc = _owire_case(*dims, npml, seed=dims[0] + 11)
