@@ -95,3 +95,38 @@ def test_owire_full_size_conserves_charge(fd):
     assert rec.size == 200 and np.all(np.isfinite(rec)) and np.abs(rec).max() > 0
     assert np.all(np.isfinite(cur)) and np.abs(q).max() > 0
     assert abs(float(q @ wt)) <= 1e-12 * float(np.abs(q) @ wt)
+
+
+@pytest.mark.parametrize("dims,npml", [((26, 22, 19), 3), ((17, 15, 13), 0)])
+def test_owire_edge_cases_elementwise(fd, oracle_mod, dims, npml):
+    """A one-segment wire at the lower range limit, driven and recorded on the
+    same segment; the longest diagonal the range allows (ends exactly at both
+    limits); a driven segment whose waveform is empty (held at zero)."""
+    sc = _random_case(*dims, npml, seed=dims[1] + 7, nsteps=50)
+    amps = S.gaussian(50, sc.dt, 10 * sc.dt, 3 * sc.dt, 2.0)
+    lo = npml + 1.0
+    hi = [d - npml - 2.0 for d in dims]
+    sc.owires = [((lo, lo, lo), (lo + 1.0, lo, lo), 0.003, 0, amps, 0),
+                 ((lo, lo, lo), (hi[0], hi[1], hi[2]), 0.005, -1, None, -1),
+                 ((hi[0], lo + 0.5, lo + 1.0), (hi[0] - 4.5, hi[1], hi[2] - 0.5), 0.002, 2, None, 3)]
+    print(f"owire edges {dims} npml={npml}", flush=True)
+    o = oracle_mod.Oracle.from_params(sc.params())
+    S.apply(sc, o)
+    o.step(sc.n_steps)
+    assert o.oblique_wire(0)[0].size == 1
+    for prec, tol in ((64, 1e-11), (32, 2e-5)):
+        g = fd.Grid.from_params(sc.params(), precision=prec)
+        S.apply(sc, g)
+        g.step(sc.n_steps)
+        for c in range(6):
+            ref, got = o.get_field(c), g.get_field(c)
+            scale = max(float(np.abs(ref).max()), 1e-300)
+            assert float(np.abs(got - ref).max()) / scale <= tol, (prec, c)
+        for w in range(3):
+            for ref, got in zip(o.oblique_wire(w), g.oblique_wire(w)):
+                assert ref.shape == got.shape
+                if ref.size == 0:       # no recorded segment
+                    continue
+                scale = max(float(np.abs(ref).max()), 1e-300)
+                assert float(np.abs(got - ref).max()) / scale <= tol, (prec, w)
+        assert g.oblique_wire(2)[0][2] == 0.0       # driven by an empty waveform
