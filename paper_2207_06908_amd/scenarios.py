@@ -202,6 +202,28 @@ def apply(sc: Scenario, sim) -> List[int]:
     return ids
 
 
+def random_case(nx, ny, nz, npml, seed, nsteps=60, n_mats=6):
+    """Test input: a ragged grid with random materials (lossy, mu != 1),
+    thin wires along all three axes, two current sources and one probe of
+    each kind, for element-wise field comparison between backends."""
+    rng = np.random.default_rng(seed)
+    dx = 0.25
+    dt = courant_dt(dx)
+    mats = [(float(rng.uniform(1, 20)), float(rng.uniform(0, 0.05)), float(rng.uniform(1, 3)))
+            for _ in range(n_mats)]
+    cm = rng.integers(0, n_mats, size=(nz, ny, nx)).astype(np.uint8)
+    amps = gaussian(nsteps, dt, 15 * dt, 5 * dt, 3.0)
+    sc = Scenario(f"rand{seed}", nx, ny, nz, dx, dt, nsteps, cm, mats, npml=npml,
+                    pml=(3.0, 1.0, 2.0, 0.02, 1.0))
+    sc.wires = [(0, 1, ny // 2, nz // 2, nx - 2, 0.004), (2, nx // 3, ny // 3, 1, nz - 3, 0.01),
+                (1, nx // 2, 1, nz // 3, ny - 2, 0.002)]
+    sc.sources = [(2, nx // 2, ny // 2 + 1, nz // 2, amps), (0, nx // 4, ny // 3, nz // 3 + 1, -amps)]
+    sc.probes = [("e", 0, 1, nx // 3, ny // 2, nz // 2 + 2, 1),
+                 ("v", 1, 0, 1, ny // 2 + 2, nz // 2, nx - 3),
+                 ("i", 2, 2, nx // 2, ny // 2 + 1, nz // 2, 1)]
+    return sc
+
+
 # ---------------------------------------------------------------------------
 # Workloads
 # ---------------------------------------------------------------------------

@@ -6,7 +6,6 @@ import numpy as np
 import pytest
 
 from paper_2207_06908_amd import scenarios as S
-from tests.test_gpu_parity import _random_case
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +28,7 @@ def _say(msg):
 def _debye_case(nx, ny, nz, npml, seed, nsteps=60):
     """The random case (CPML, wires along all axes, sources, every probe
     kind) with pole increments on half of its materials."""
-    sc = _random_case(nx, ny, nz, npml, seed=seed, nsteps=nsteps)
+    sc = S.random_case(nx, ny, nz, npml, seed=seed, nsteps=nsteps)
     rng = np.random.default_rng(seed + 100)
     de = rng.uniform(0.5, 30.0, size=(len(sc.materials), len(TAU)))
     de[::2] = 0.0
@@ -82,7 +81,7 @@ def test_debye_zero_increments_bitwise_split(fd):
     pass (classes, coefficients and the update reduce exactly)."""
     outs = []
     for debye in (True, False):
-        sc = _random_case(45, 21, 13, 3, seed=9, nsteps=40)
+        sc = S.random_case(45, 21, 13, 3, seed=9, nsteps=40)
         if debye:
             sc.debye = (TAU, np.zeros((len(sc.materials), len(TAU))))
         g = fd.Grid.from_params(sc.params(), precision=32)

@@ -6,7 +6,6 @@ import numpy as np
 import pytest
 
 from paper_2207_06908_amd import scenarios as S
-from tests.test_gpu_parity import _random_case
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +23,7 @@ def _lumped_case(nx, ny, nz, npml, seed, nsteps=60):
     """The random case plus resistors and capacitors on edges in the middle,
     on tile seams (x 59-61, y 7-8) and in the CPML, a resistive voltage
     source and a current source with a shunt."""
-    sc = _random_case(nx, ny, nz, npml, seed=seed, nsteps=nsteps)
+    sc = S.random_case(nx, ny, nz, npml, seed=seed, nsteps=nsteps)
     amps = S.gaussian(nsteps, sc.dt, 12 * sc.dt, 4 * sc.dt, 5.0)
     k = nz // 2
     sc.lumped = [(0, 2, nx // 2 - 3, ny // 2, k, 50.0), (1, 2, nx // 2 - 3, ny // 2, k, 2e-11),

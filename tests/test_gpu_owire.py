@@ -1,13 +1,13 @@
 """GPU parity for the oblique thin wire (the arbitrarily located wire model
 of Section 2.3): fields, segment currents, charges and the recorded current
 against the FP64 oracle on the same seeded inputs, element by element; the
-lumped-source identity of a wire on a grid edge; and charge conservation at
-the full 512 x 512 x 384 size in the launch configuration the bench times."""
+lumped-source identity of a wire on a grid edge; bitwise reproducibility;
+and charge conservation at the full 512 x 512 x 384 size in the launch
+configuration the bench times."""
 import numpy as np
 import pytest
 
 from paper_2207_06908_amd import scenarios as S
-from tests.test_gpu_parity import _random_case
 
 pytestmark = pytest.mark.gpu
 
@@ -25,7 +25,7 @@ def _owire_case(nx, ny, nz, npml, seed, nsteps=60):
     """The random case (random media, axis wires, sources, probes) plus a
     driven skew wire, a second undriven skew wire that is recorded, and a
     wire along z on Ez samples."""
-    sc = _random_case(nx, ny, nz, npml, seed=seed, nsteps=nsteps)
+    sc = S.random_case(nx, ny, nz, npml, seed=seed, nsteps=nsteps)
     amps = S.gaussian(nsteps, sc.dt, 12 * sc.dt, 4 * sc.dt, 3.0)
     lo = npml + 1.0
     hx, hy, hz = nx - npml - 2.0, ny - npml - 2.0, nz - npml - 2.0
@@ -102,7 +102,7 @@ def test_owire_edge_cases_elementwise(fd, oracle_mod, dims, npml):
     """A one-segment wire at the lower range limit, driven and recorded on the
     same segment; the longest diagonal the range allows (ends exactly at both
     limits); a driven segment whose waveform is empty (held at zero)."""
-    sc = _random_case(*dims, npml, seed=dims[1] + 7, nsteps=50)
+    sc = S.random_case(*dims, npml, seed=dims[1] + 7, nsteps=50)
     amps = S.gaussian(50, sc.dt, 10 * sc.dt, 3 * sc.dt, 2.0)
     lo = npml + 1.0
     hi = [d - npml - 2.0 for d in dims]
@@ -130,3 +130,20 @@ def test_owire_edge_cases_elementwise(fd, oracle_mod, dims, npml):
                 scale = max(float(np.abs(ref).max()), 1e-300)
                 assert float(np.abs(got - ref).max()) / scale <= tol, (prec, w)
         assert g.oblique_wire(2)[0][2] == 0.0       # driven by an empty waveform
+
+
+def test_owire_runs_are_bitwise_reproducible(fd):
+    """FP32: two runs of the skew-wire case give the same bits in every
+    field and in the wire state (each touched edge sums its wire terms in a
+    fixed order; no atomics)."""
+    sc = _owire_case(40, 24, 22, 4, seed=51, nsteps=80)
+    print("owire reproducibility", flush=True)
+    runs = []
+    for _ in range(2):
+        g = fd.Grid.from_params(sc.params(), precision=32)
+        S.apply(sc, g)
+        g.step(sc.n_steps)
+        runs.append([g.get_field(c) for c in range(6)] + [x for w in range(3) for x in g.oblique_wire(w)])
+    assert np.abs(runs[0][0]).max() > 0
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)

@@ -57,27 +57,6 @@ def test_config1_fp64_and_fp32(fd, oracle_mod, variant):
     assert max(e32.values()) <= 2e-5
 
 
-def _random_case(nx, ny, nz, npml, seed, nsteps=60, n_mats=6):
-    """Ragged grid, random materials (lossy, mu != 1), wires along all axes,
-    two sources, every probe kind; used for element-wise field comparison."""
-    rng = np.random.default_rng(seed)
-    dx = 0.25
-    dt = S.courant_dt(dx)
-    mats = [(float(rng.uniform(1, 20)), float(rng.uniform(0, 0.05)), float(rng.uniform(1, 3)))
-            for _ in range(n_mats)]
-    cm = rng.integers(0, n_mats, size=(nz, ny, nx)).astype(np.uint8)
-    amps = S.gaussian(nsteps, dt, 15 * dt, 5 * dt, 3.0)
-    sc = S.Scenario(f"rand{seed}", nx, ny, nz, dx, dt, nsteps, cm, mats, npml=npml,
-                    pml=(3.0, 1.0, 2.0, 0.02, 1.0))
-    sc.wires = [(0, 1, ny // 2, nz // 2, nx - 2, 0.004), (2, nx // 3, ny // 3, 1, nz - 3, 0.01),
-                (1, nx // 2, 1, nz // 3, ny - 2, 0.002)]
-    sc.sources = [(2, nx // 2, ny // 2 + 1, nz // 2, amps), (0, nx // 4, ny // 3, nz // 3 + 1, -amps)]
-    sc.probes = [("e", 0, 1, nx // 3, ny // 2, nz // 2 + 2, 1),
-                 ("v", 1, 0, 1, ny // 2 + 2, nz // 2, nx - 3),
-                 ("i", 2, 2, nx // 2, ny // 2 + 1, nz // 2, 1)]
-    return sc
-
-
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("dims,npml", [((70, 13, 11), 3), ((130, 9, 17), 4), ((5, 66, 7), 2), ((64, 8, 8), 0)])
 def test_fields_elementwise(fd, oracle_mod, variant, dims, npml):
@@ -85,7 +64,7 @@ def test_fields_elementwise(fd, oracle_mod, variant, dims, npml):
     span several tiles with ragged tails (x not a multiple of 64, y not a
     multiple of 4), with CPML, wires along all three axes and sources."""
     nx, ny, nz = dims
-    sc = _random_case(nx, ny, nz, npml, seed=nx + ny)
+    sc = S.random_case(nx, ny, nz, npml, seed=nx + ny)
     _say(f"fields {dims} npml={npml} variant={variant}")
     o = oracle_mod.Oracle.from_params(sc.params())
     S.apply(sc, o)
@@ -142,7 +121,7 @@ def test_variants_bitwise_equal(fd, dims, npml):
     steps come in odd chunks (the two-step pass then ends with one fused
     step).  The larger grids have tiles in every CPML group of the tile
     lists (clear of the x and y slabs, x only, y only, corners)."""
-    sc = _random_case(*dims, npml, seed=3, nsteps=41, n_mats=3)
+    sc = S.random_case(*dims, npml, seed=3, nsteps=41, n_mats=3)
     runs = [(1, 0, 0, [41]), (2, 8, 32, [41]), (2, 4, 7, [41]), (3, 8, 64, [41]), (3, 4, 5, [3, 10, 1, 27]),
             (3, 8, 16, [2, 39]), (3, 12, 64, [41]), (3, 12, 8, [5, 36])]
     outs = []
@@ -167,7 +146,7 @@ def test_sources_on_tile_seams(fd, oracle_mod):
     each variant and tile shape against the oracle element by element, and
     all of them bit for bit against the split variant."""
     nx, ny, nz, npml, nsteps = 150, 40, 35, 6, 30
-    sc = _random_case(nx, ny, nz, npml, seed=11, nsteps=nsteps, n_mats=3)
+    sc = S.random_case(nx, ny, nz, npml, seed=11, nsteps=nsteps, n_mats=3)
     amps = S.gaussian(nsteps, sc.dt, 10 * sc.dt, 4 * sc.dt, 2.0)
     spots = [(2, 7, 8, 9), (0, 8, 15, 16), (1, 67, 16, 17), (2, 68, 23, 8), (2, 69, 24, 24), (0, 127, 7, 12),
              (1, 128, 31, 20), (2, 63, 12, 16), (2, 64, 13, 31), (0, 65, 32, 7),
@@ -201,7 +180,7 @@ def test_sources_on_tile_seams(fd, oracle_mod):
 def test_thick_cpml_two_step_request_takes_the_fused_pass(fd):
     """With 2 npml above what the two-step tiles hold in LDS, a two-step (or
     default) request runs the fused pass: same bits as the split pass."""
-    sc = _random_case(150, 150, 146, 70, seed=5, nsteps=9, n_mats=2)
+    sc = S.random_case(150, 150, 146, 70, seed=5, nsteps=9, n_mats=2)
     outs = []
     for variant in (1, 3, 0):
         g = fd.Grid.from_params(sc.params(), precision=32)

@@ -679,8 +679,7 @@ def test_debye_relaxation_converges_to_the_ode_at_second_order():
 def test_debye_with_zero_increments_is_plain_media():
     """Declaring poles whose increments are all zero changes no bit of the
     fields (CPML, wires, sources, every material kind)."""
-    import tests.test_gpu_parity as tp
-    sc = tp._random_case(23, 17, 15, 3, seed=4, nsteps=40)
+    sc = S.random_case(23, 17, 15, 3, seed=4, nsteps=40)
     runs = []
     for debye in (False, True):
         o = _orc().from_params(sc.params())
@@ -838,3 +837,339 @@ def test_oblique_wire_swapping_x_and_y_swaps_the_fields():
     np.testing.assert_allclose(r1, r2, rtol=1e-9, atol=1e-12 * np.abs(r1).max())
     np.testing.assert_allclose(z1, z2.swapaxes(1, 2), rtol=1e-9, atol=1e-12 * np.abs(z1).max())
     np.testing.assert_allclose(x1, y2.swapaxes(1, 2), rtol=1e-9, atol=1e-12 * np.abs(x1).max())
+
+
+# ---------------------------------------------------------------------------
+# Heterogeneous media: the edge and face averaging of eps, sigma, mu and the
+# pole increments (Section 2.1, eqs. 2-5 with per-cell parameters)
+# ---------------------------------------------------------------------------
+
+def _hetero_case(nx, ny, nz, seed, npml=0, nsteps=120):
+    """Random lossy, mu != 1, two-pole Debye medium (5 materials over random
+    cells), random initial fields and two current sources."""
+    rng = np.random.default_rng(seed)
+    mats = [(float(rng.uniform(1, 12)), float(rng.uniform(0.0, 0.05)), float(rng.uniform(1, 4)))
+            for _ in range(5)]
+    cm = rng.integers(0, 5, size=(nz, ny, nx)).astype(np.uint8)
+    deps = rng.uniform(0.0, 8.0, size=(5, 2))
+    fields = [rng.standard_normal((nz, ny, nx)) * (1.0 if c < 3 else 1 / ETA0) for c in range(6)]
+    for c in range(6):  # wall values: tangential E and normal H on the index-0 planes
+        for ax in range(3):
+            if (c < 3 and ax != c) or (c >= 3 and ax == c - 3):
+                sl = [slice(None)] * 3
+                sl[2 - ax] = 0
+                fields[c][tuple(sl)] = 0.0
+    dt = S.courant_dt(0.3)
+    amps = S.gaussian(nsteps, dt, 20 * dt, 6 * dt, 2.0)
+    srcs = [(0, 2, 3, 2, amps), (2, nx - 3, ny - 4, 1, -0.5 * amps)]
+    return dict(N=(nx, ny, nz), npml=npml, mats=mats, cm=cm, deps=deps, fields=fields, srcs=srcs,
+                nsteps=nsteps, dt=dt)
+
+
+def _run_hetero(case):
+    nx, ny, nz = case["N"]
+    o = _orc()(nx, ny, nz, 0.3, dt=case["dt"], npml=case["npml"], pml_kappa_max=2.0, pml_alpha_max=0.02,
+               max_steps=case["nsteps"])
+    o.set_materials(case["cm"], case["mats"])
+    o.set_debye([2e-9, 4e-8], case["deps"])
+    for (u, i, j, k, amps) in case["srcs"]:
+        o.add_source(u, i, j, k, amps)
+    for c in range(6):
+        o.set_field(c, case["fields"][c])
+    o.step(case["nsteps"])
+    return [o.get_field(c) for c in range(6)]
+
+
+def _mirror_field(F, comp, axis):
+    """Image of a stored component under the reflection x_axis -> N - x_axis.
+    Components at half-integer positions along the axis (E_axis, and H
+    across it) map index i -> N-1-i; the others map i -> N-i, index 0 being
+    a wall value (0) on both sides.  E_axis and the H components across the
+    axis change sign (E is a polar vector, H an axial one)."""
+    d = 2 - axis
+    half = (comp == axis) if comp < 3 else (comp - 3 != axis)
+    sign = -1.0 if (comp < 3) == (comp % 3 == axis) else 1.0
+    if half:
+        G = np.flip(F, d)
+    else:
+        sl = [slice(None)] * 3
+        sl[d] = slice(1, None)
+        G = np.zeros_like(F)
+        G[tuple(sl)] = np.flip(F[tuple(sl)], d)
+        sl[d] = 0
+        assert not np.any(F[tuple(sl)])
+    return sign * G
+
+
+@pytest.mark.parametrize("npml", [0, 2])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_mirror_image_of_a_heterogeneous_medium(axis, npml):
+    """Reflecting the cells, the initial fields and the sources of a random
+    lossy, mu != 1, Debye medium reflects every field (1e-12).  An edge or
+    face mean that reaches one cell too far on either side, along any axis,
+    breaks the symmetry."""
+    nx, ny, nz = 9, 8, 7
+    base = _hetero_case(nx, ny, nz, seed=31 + axis, npml=npml)
+    N = base["N"][axis]
+    img = dict(base)
+    img["cm"] = np.flip(base["cm"], 2 - axis).copy()
+    img["fields"] = [_mirror_field(base["fields"][c], c, axis) for c in range(6)]
+    srcs = []
+    for (u, i, j, k, amps) in base["srcs"]:
+        p = [i, j, k]
+        if u == axis:
+            p[axis] = N - 1 - p[axis]
+            amps = -amps
+        else:
+            p[axis] = N - p[axis]
+        srcs.append((u, *p, amps))
+    img["srcs"] = srcs
+    f0, f1 = _run_hetero(base), _run_hetero(img)
+    for c in range(6):
+        want = _mirror_field(f0[c], c, axis)
+        scale = np.abs(f0[c]).max()
+        assert scale > 0
+        assert np.abs(f1[c] - want).max() <= 1e-12 * scale, c
+
+
+@pytest.mark.parametrize("npml", [0, 2])
+def test_axis_rotation_of_a_heterogeneous_medium(npml):
+    """The cyclic relabelling x -> y -> z -> x of a random heterogeneous
+    medium (a proper rotation of the cubic grid) permutes the components of
+    every field the same way (1e-12): each component averages over the cells
+    and faces of its own orientation."""
+    nx, ny, nz = 9, 8, 7
+    base = _hetero_case(nx, ny, nz, seed=41, npml=npml)
+    rot = lambda a: np.transpose(a, (1, 2, 0)).copy()  # (z, y, x) -> (z', y', x') = (y, x, z)
+    img = dict(base)
+    img["N"] = (nz, nx, ny)
+    img["cm"] = rot(base["cm"])
+    img["fields"] = [None] * 6
+    for c in range(6):
+        b, u = divmod(c, 3)
+        img["fields"][3 * b + (u + 1) % 3] = rot(base["fields"][c])
+    img["srcs"] = [((u + 1) % 3, k, i, j, amps) for (u, i, j, k, amps) in base["srcs"]]
+    f0, f1 = _run_hetero(base), _run_hetero(img)
+    for c in range(6):
+        b, u = divmod(c, 3)
+        got = f1[3 * b + (u + 1) % 3]
+        want = rot(f0[c])
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(f0[c]).max(), c
+
+
+def _edge_network(N, dx, cell_val, src):
+    """Kirchhoff network of the grid's edges: branch admittance dx * (mean of
+    the four cells that share the edge) -- each cell fills a quarter of the
+    edge's dx^2 cross-section and the quarters act in parallel -- the
+    perfect-conductor walls merged into one ground node, and a current
+    source I along +u in the edge `src`.  Solves for the node potentials and
+    returns E on every edge as arrays of the stored shape (z, y, x)."""
+    nx, ny, nz = N
+    idx = -np.ones((nz + 1, ny + 1, nx + 1), int)
+    inner = [(i, j, k) for k in range(1, nz) for j in range(1, ny) for i in range(1, nx)]
+    for n, (i, j, k) in enumerate(inner):
+        idx[k, j, i] = n
+    L = np.zeros((len(inner), len(inner)))
+    b = np.zeros(len(inner))
+    branches = []
+    for u in range(3):
+        v, w = (u + 1) % 3, (u + 2) % 3
+        for k in range(nz + 1):
+            for j in range(ny + 1):
+                for i in range(nx + 1):
+                    p = [i, j, k]
+                    if p[u] >= N[u] or not (1 <= p[v] <= N[v] - 1 and 1 <= p[w] <= N[w] - 1):
+                        continue
+                    vals = []
+                    for dv in (-1, 0):
+                        for dw in (-1, 0):
+                            q = list(p)
+                            q[v] += dv
+                            q[w] += dw
+                            vals.append(cell_val[q[2], q[1], q[0]])
+                    G = dx * float(np.mean(vals))
+                    e = list(p)
+                    e[u] += 1
+                    a, c = idx[p[2], p[1], p[0]], idx[e[2], e[1], e[0]]
+                    for x, y in ((a, c), (c, a)):
+                        if x >= 0:
+                            L[x, x] += G
+                            if y >= 0:
+                                L[x, y] -= G
+                    branches.append((u, p, a, c))
+    su, sp, I = src
+    e = list(sp)
+    e[su] += 1
+    a, c = idx[sp[2], sp[1], sp[0]], idx[e[2], e[1], e[0]]
+    if a >= 0:
+        b[a] -= I
+    if c >= 0:
+        b[c] += I
+    phi = np.linalg.solve(L, b)
+    E = [np.zeros((nz, ny, nx)) for _ in range(3)]
+    for (u, p, a, c) in branches:
+        pa = phi[a] if a >= 0 else 0.0
+        pc = phi[c] if c >= 0 else 0.0
+        E[u][p[2], p[1], p[0]] = (pa - pc) / dx
+    return E
+
+
+def test_dc_field_in_a_random_conductor_is_its_resistor_network():
+    """A steady current source in a random conducting medium: the late-time
+    field solves Kirchhoff's laws on the edge network whose conductances are
+    the cells' conductivities in parallel (arithmetic edge mean of sigma), to
+    1e-9.  A geometric or harmonic mean, or a mean over the wrong cells,
+    changes the branch conductances and misses by far more."""
+    nx, ny, nz, dx = 7, 6, 6, 0.5
+    rng = np.random.default_rng(8)
+    mats = [(float(rng.uniform(1, 8)), float(rng.uniform(0.02, 0.3)), float(rng.uniform(1, 3))) for _ in range(5)]
+    cm = rng.integers(0, 5, size=(nz, ny, nx)).astype(np.uint8)
+    n, I0 = 16000, 0.7
+    o = _orc()(nx, ny, nz, dx, max_steps=n)
+    o.set_materials(cm, mats)
+    src = (1, (3, 2, 3), I0)
+    amps = I0 * _ramp(n, o.dt)
+    o.add_source(src[0], *src[1], amps)
+    o.step(n - 1)
+    prev = o.get_field(EY)
+    o.step(1)
+    got = [o.get_field(c) for c in range(3)]
+    sig = np.array([m[1] for m in mats])[cm]
+    want = _edge_network((nx, ny, nz), dx, sig, src)
+    scale = max(np.abs(w).max() for w in want)
+    assert np.abs(got[1] - prev).max() <= 1e-12 * scale  # settled
+    for c in range(3):
+        assert np.abs(got[c] - want[c]).max() <= 1e-9 * scale, c
+
+
+def test_debye_field_ramp_is_the_capacitor_network_of_static_permittivities():
+    """A steady current source in a random loss-free Debye medium: once the
+    poles have damped the transients, E grows linearly and its rate solves
+    the edge network whose admittances are the cells' static permittivities
+    eps0 (eps_inf + sum of increments) in parallel -- the arithmetic edge mean
+    of eps_inf and of each pole increment (1e-8)."""
+    nx, ny, nz, dx = 7, 6, 6, 0.5
+    rng = np.random.default_rng(12)
+    mats = [(float(rng.uniform(1, 5)), 0.0, float(rng.uniform(1, 3))) for _ in range(5)]
+    deps = rng.uniform(2.0, 10.0, size=(5, 2))
+    cm = rng.integers(0, 5, size=(nz, ny, nx)).astype(np.uint8)
+    n, I0 = 12000, 0.3
+    o = _orc()(nx, ny, nz, dx, max_steps=n)
+    o.set_materials(cm, mats)
+    dt = o.dt
+    o.set_debye([6 * dt, 15 * dt], deps)
+    src = (0, (2, 3, 2), I0)
+    o.add_source(src[0], *src[1], I0 * _ramp(n, dt, tau_steps=40.0))
+    o.step(n - 2)
+    f = []
+    for _ in range(3):
+        f.append([o.get_field(c) for c in range(3)])
+        if len(f) < 3:
+            o.step(1)
+    rate = [(f[2][c] - f[1][c]) / dt for c in range(3)]
+    rate_prev = [(f[1][c] - f[0][c]) / dt for c in range(3)]
+    eps_s = EPS0 * (np.array([m[0] for m in mats]) + deps.sum(axis=1))[cm]
+    want = _edge_network((nx, ny, nz), dx, eps_s, src)
+    scale = max(np.abs(w).max() for w in want)
+    for c in range(3):
+        assert np.abs(rate[c] - rate_prev[c]).max() <= 1e-9 * scale  # transients gone
+        assert np.abs(rate[c] - want[c]).max() <= 1e-8 * scale, c
+
+
+def test_layered_cavity_mode_closed_form():
+    """A PEC box layered along z (eps_r 1 / 9 / 4, mu_r 1 / 3 / 1.5).  The
+    field Ex = sin(pi j / Ny) f_k, uniform in x, couples only to Hy and Hz
+    and reduces the scheme to a 1D chain along z: Ex edges on a layer
+    interface carry the mean of the two layers' eps (four cells, two on
+    each side), Hz faces on it the harmonic mean of their mu (two cells in
+    series), Hy faces the mu of their own layer.  An eigenvector v of that
+    chain (eigenvalue -Omega^2) evolves as v cos((n + 1/2) theta) /
+    cos(theta / 2), sin(theta / 2) = Omega dt / 2 (1e-10 over 600 steps)."""
+    nx, ny, nz, dx = 3, 7, 12, 0.4
+    layers = [(1.0, 1.0)] * 4 + [(9.0, 3.0)] * 4 + [(4.0, 1.5)] * 4
+    er = np.array([l[0] for l in layers])
+    mr = np.array([l[1] for l in layers])
+    cm = np.repeat(np.arange(nz), nx * ny).reshape(nz, ny, nx).astype(np.uint8)
+    o = _orc()(nx, ny, nz, dx, max_steps=600)
+    o.set_materials(cm, [(float(er[k]), 0.0, float(mr[k])) for k in range(nz)])
+    dt = o.dt
+    kap = 4 * math.sin(math.pi / (2 * ny)) ** 2
+    eps_x = EPS0 * 0.5 * (er[:-1] + er[1:])                  # Ex at node planes k = 1..nz-1
+    mu_y = MU0 * mr                                           # Hy in layer k = 0..nz-1
+    mu_z = MU0 * 2.0 / (1.0 / mr[:-1] + 1.0 / mr[1:])        # Hz at node planes k = 1..nz-1
+    nf = nz - 1
+    # f: Ex (k = 1..nz-1); g: Hy (k = 0..nz-1); h: Hz (k = 1..nz-1), Hz = (s_{j+1} - s_j) h
+    B = np.zeros((nz + nf, nf))   # dH/dt = B f
+    for k in range(nz):           # dHy_k/dt = -(f_{k+1} - f_k) / (mu dx)
+        if k + 1 <= nf:
+            B[k, k] -= 1.0 / (mu_y[k] * dx)
+        if k >= 1:
+            B[k, k - 1] += 1.0 / (mu_y[k] * dx)
+    for k in range(nf):           # dh_k/dt = f_k / (mu dx)
+        B[nz + k, k] = 1.0 / (mu_z[k] * dx)
+    A = np.zeros((nf, nz + nf))   # df/dt = A (g, h)
+    for k in range(nf):           # eps df_k/dt = (-kap h_k - (g_k - g_{k-1})) / dx, node plane k+1
+        A[k, nz + k] = -kap / (eps_x[k] * dx)
+        A[k, k + 1] -= 1.0 / (eps_x[k] * dx)
+        A[k, k] += 1.0 / (eps_x[k] * dx)
+    lam, V = np.linalg.eig(A @ B)
+    order = np.argsort(-lam.real)
+    s = np.sin(np.pi * np.arange(ny) / ny)
+    for pick in (order[0], order[3], order[-1]):
+        Om2 = -lam[pick].real
+        assert Om2 > 0 and abs(lam[pick].imag) < 1e-9 * Om2
+        v = V[:, pick].real
+        v /= np.abs(v).max()
+        theta = 2 * math.asin(math.sqrt(Om2) * dt / 2)
+        ex0 = np.zeros((nz, ny, nx))
+        ex0[1:, :, :] = v[:, None, None] * s[None, :, None]
+        o2 = _orc()(nx, ny, nz, dx, max_steps=600)
+        o2.set_materials(cm, [(float(er[k]), 0.0, float(mr[k])) for k in range(nz)])
+        o2.set_field(EX, ex0)
+        done = 0
+        for n in (1, 37, 250, 599):
+            o2.step(n - done)
+            done = n
+            want = ex0 * math.cos((n + 0.5) * theta) / math.cos(theta / 2)
+            assert np.abs(o2.get_field(EX) - want).max() <= 1e-10, (pick, n)
+
+
+# ---------------------------------------------------------------------------
+# Thin wires in Debye media, and the oblique wire's line constants
+# (method accuracy, as for the axis wires above)
+# ---------------------------------------------------------------------------
+
+def test_thin_wire_line_impedance_in_debye_soil():
+    """The matched two-wire line of the axis-wire test, now in a uniform
+    one-pole Debye medium (eps_inf 3, increment 5, tau 10 dt, no
+    conduction): once the ramp (60 dt) is slow against tau, the line sees
+    the static permittivity eps_s = 8, and the late-time V / I approaches
+    (eta0 / (pi sqrt(eps_s))) acosh(h / a) within 3 %.  The radial edges of
+    the wire scale the whole permittivity function (eps_inf and the
+    increment) by the wire factor; scaling eps_inf alone would leave the
+    line at a different impedance."""
+    a, nsteps = 0.005, 900
+    nx, ny, nz, dx, npml = 90, 40, 44, 0.5, 8
+    dt = S.courant_dt(dx)
+    t = (np.arange(nsteps) + 0.5) * dt
+    ramp = 60 * dt
+    amps = np.where(t < ramp, 0.5 * (1 - np.cos(np.pi * t / ramp)), 1.0)
+    o = _orc()(nx, ny, nz, dx, dt=dt, npml=npml, max_steps=nsteps)
+    o.set_materials(np.zeros((nz, ny, nx), np.uint8), [(3.0, 0.0, 1.0)])
+    o.set_debye([10 * dt], [[5.0]])
+    j0, k1, k2, i0 = 20, 18, 26, 14
+    o.add_wire(0, i0, j0, k1, nx - i0, a)
+    o.add_wire(0, i0, j0, k2, nx - i0, a)
+    kg = (k1 + k2) // 2
+    o.add_wire(2, i0, j0, k1, kg - k1, a)
+    o.add_wire(2, i0, j0, kg + 1, k2 - kg - 1, a)
+    o.add_source(2, i0, j0, kg, amps)
+    pv = o.add_probe(1, 2, i0, j0, kg, 1)
+    pi = o.add_probe(2, 2, i0, j0, kg, 1)
+    o.step(nsteps)
+    V, I = -o.probe(pv), o.probe(pi)
+    h = (k2 - k1) * dx / 2
+    z = (V[-100:] / I[-100:]).mean()
+    z0 = ETA0 / (math.pi * math.sqrt(8.0)) * math.acosh(h / a)
+    print('debye line', z, z0, (z - z0) / z0)
+    assert abs(z - z0) / z0 <= 0.03, (z, z0)
