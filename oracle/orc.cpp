@@ -16,7 +16,9 @@
 // scaling of pole increments in Debye media.  The oblique wire's equivalent
 // radius (the same r0 as the axis wires) and its vacuum L' and C' are a
 // reading (the paper names the model, not its equations); its transfer
-// weights, telegraph step and charge bookkeeping are pinned.
+// weights, telegraph step and charge bookkeeping are pinned, and so is the
+// line it forms (speed c0; impedance within the accuracy stated at its
+// test).
 #include "orc.h"
 
 #include <cmath>
@@ -561,60 +563,97 @@ void inject_sources(orc_sim* s) {
   }
 }
 
-// ---- Oblique thin wire (Section 2.4: the arbitrarily oriented wire model
+// ---- Oblique thin wire (Section 2.3: the arbitrarily located wire model
 // the paper takes from the literature; the formulation here is this
 // oracle's reading of that model, see the header) ----
 //
-// Each wire owns a 1D grid along its axis.  Segment k (midpoint
-// m_k = A + (k + 1/2) dl t) carries the current I_k at times n + 1/2; the end
-// points of the segments carry the charge per unit length q_k at integer
-// times.  Telegraph equations with the in-cell inductance and capacitance
-//   L' dI_k/dt = E_t(m_k) - (q_{k+1} - q_k) / (C' dl)
+// Each wire owns a 1D grid along its axis: nodes r_k = A + k dl t
+// (k = 0..n) and segments r_k -> r_{k+1}.  Segment k carries the current
+// I_k at times n + 1/2; node k carries the charge per unit length q_k at
+// integer times.  Telegraph equations with the in-cell inductance and
+// capacitance
+//   L' dI_k/dt = E_t,k - (q_{k+1} - q_k) / (C' dl)
 //   dq_k/dt    = -(I_k - I_{k-1}) / len_k    (I_{-1} = I_n = 0, len_k = dl / 2 at the two ends)
 // with L' = mu0 ln(r0/a) / (2 pi), C' = 2 pi eps0 / ln(r0/a), r0 = wire_r0_factor dx.
-// E_t is the field along t, each E component interpolated trilinearly from
-// its own Yee lattice; the segment's current moment I_k dl t goes back to the
-// same samples with the same weights as a current density over dx^3.
+//
+// Coupling to the grid conserves charge.  The grid holds the wire's charge
+// Q_k = q_k len_k at the grid nodes with the trilinear (cloud-in-cell)
+// weights S_p(r_k) of r_k.  A current I_k on segment k moves charge from
+// r_k to r_{k+1}, so it must enter the grid as edge currents I_k D_k(e)
+// whose discrete divergence is -(S(r_{k+1}) - S(r_k)): then Gauss's law on
+// the grid tracks the wire's charge exactly, and a steady current leaves
+// no charge behind on the grid.  D_k is the density decomposition of
+// Esirkepov (Comput. Phys. Commun. 135, 2001) for that displacement, which
+// splits the change of a product of 1D shapes into one flux per axis:
+//   W_x(i, j, k) = dS_x(i) [S0_y S0_z + dS_y S0_z / 2 + S0_y dS_z / 2 + dS_y dS_z / 3](j, k),
+//   D_x(edge i+1/2, j, k) = -sum_{i' <= i} W_x(i', j, k),
+// with S0, S1 the 1D tent weights of r_k and r_{k+1} along each axis and
+// dS = S1 - S0 (likewise for y and z).  D is dimensionless (edge lengths per
+// unit length of displacement in cells): the current density on edge e is
+// I_k D_k(e) / dx^2, and the field the segment sees is the adjoint sum
+//   E_t,k = sum_e D_k(e) E_e / dl_cells,
+// so the wire and the grid exchange energy without loss or gain.  In a
+// uniform field E_t,k = t . E exactly (the first moment of D is the
+// displacement dl t).  Perfectly conducting edges take no current.
+struct OwEntry { int a, p[3]; double d; };
 
-// Trilinear weights of the point p (cells) on the lattice of E component a,
-// whose samples sit at integer positions moved half a cell along a.
-static void owire_weights(const double p[3], int a, int base[3], double w[8]) {
-  double f[3];
+static void owire_pattern(const OWire& w, int k, std::vector<OwEntry>& out) {
+  out.clear();
+  double r0[3], r1[3];
   for (int u = 0; u < 3; ++u) {
-    const double x = p[u] - (u == a ? 0.5 : 0.0);
-    base[u] = (int)std::floor(x);
-    f[u] = x - base[u];
+    r0[u] = w.A[u] + k * w.dl * w.t[u];
+    r1[u] = w.A[u] + (k + 1) * w.dl * w.t[u];
   }
-  for (int c = 0; c < 8; ++c)
-    w[c] = ((c & 1) ? f[0] : 1.0 - f[0]) * ((c & 2) ? f[1] : 1.0 - f[1]) * ((c & 4) ? f[2] : 1.0 - f[2]);
-}
-
-static void owire_mid(const OWire& w, int k, double m[3]) {
-  for (int u = 0; u < 3; ++u) m[u] = w.A[u] + (k + 0.5) * w.dl * w.t[u];
+  // 1D tent weights on the nodes lo[u] .. lo[u] + n[u] - 1 (at most 4, since dl < 2)
+  int lo[3], n[3];
+  double s0[3][4], ds[3][4];
+  for (int u = 0; u < 3; ++u) {
+    lo[u] = (int)std::floor(std::min(r0[u], r1[u]));
+    n[u] = (int)std::floor(std::max(r0[u], r1[u])) + 2 - lo[u];
+    for (int m = 0; m < n[u]; ++m) {
+      const double x = lo[u] + m;
+      const double a0 = std::max(0.0, 1.0 - std::fabs(r0[u] - x));
+      const double a1 = std::max(0.0, 1.0 - std::fabs(r1[u] - x));
+      s0[u][m] = a0;
+      ds[u][m] = a1 - a0;
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    for (int mc = 0; mc < n[c]; ++mc)
+      for (int mb = 0; mb < n[b]; ++mb) {
+        const double T = s0[b][mb] * s0[c][mc] + 0.5 * ds[b][mb] * s0[c][mc] + 0.5 * s0[b][mb] * ds[c][mc] +
+                         ds[b][mb] * ds[c][mc] / 3.0;
+        double D = 0.0;
+        for (int ma = 0; ma + 1 < n[a]; ++ma) {
+          D -= ds[a][ma] * T;
+          if (D == 0.0) continue;
+          OwEntry e;
+          e.a = a;
+          e.p[a] = lo[a] + ma;
+          e.p[b] = lo[b] + mb;
+          e.p[c] = lo[c] + mc;
+          e.d = D;
+          out.push_back(e);
+        }
+      }
+  }
 }
 
 // I^{n+1/2} from E^n and q^n, then q^{n+1} from I^{n+1/2} (before the E update).
 void owire_currents(orc_sim* s) {
-  const double dlm_of = s->dx;
+  std::vector<OwEntry> pat;
   for (OWire& w : s->owires) {
-    const double dlm = w.dl * dlm_of;
+    const double dlm = w.dl * s->dx;
     for (int k = 0; k < w.n; ++k) {
       if (k == w.src) {
         w.I[k] = s->step < (long)w.amps.size() ? w.amps[s->step] : 0.0;
         continue;
       }
-      double m[3];
-      owire_mid(w, k, m);
+      owire_pattern(w, k, pat);
       double et = 0.0;
-      for (int a = 0; a < 3; ++a) {
-        if (w.t[a] == 0.0) continue;
-        int b[3];
-        double wt[8];
-        owire_weights(m, a, b, wt);
-        double v = 0.0;
-        for (int c = 0; c < 8; ++c) v += wt[c] * s->E[a](b[0] + (c & 1), b[1] + ((c >> 1) & 1), b[2] + ((c >> 2) & 1));
-        et += w.t[a] * v;
-      }
+      for (const OwEntry& e : pat) et += e.d * s->E[e.a](e.p[0], e.p[1], e.p[2]);
+      et /= w.dl;
       w.I[k] += s->dt / w.Lp * (et - (w.q[k + 1] - w.q[k]) / (w.Cp * dlm));
     }
     for (int j = 0; j <= w.n; ++j) {
@@ -626,29 +665,20 @@ void owire_currents(orc_sim* s) {
   }
 }
 
-// After the E update and the lumped sources: E -= Cb J, J = I dl t w / dx^3;
-// perfectly conducting edges keep E = 0.
+// After the E update and the lumped sources: E -= Cb J with J = I_k D_k / dx^2.
 void owire_inject(orc_sim* s) {
-  const double vol = s->dx * s->dx * s->dx;
-  for (const OWire& w : s->owires) {
-    const double dlm = w.dl * s->dx;
+  const double area = s->dx * s->dx;
+  std::vector<OwEntry> pat;
+  for (const OWire& w : s->owires)
     for (int k = 0; k < w.n; ++k) {
-      double m[3];
-      owire_mid(w, k, m);
-      for (int a = 0; a < 3; ++a) {
-        if (w.t[a] == 0.0) continue;
-        int b[3];
-        double wt[8];
-        owire_weights(m, a, b, wt);
-        for (int c = 0; c < 8; ++c) {
-          const int i = b[0] + (c & 1), j = b[1] + ((c >> 1) & 1), kk = b[2] + ((c >> 2) & 1);
-          const size_t li = ((size_t)kk * s->E[a].n1 + j) * s->E[a].n0 + i;
-          if (s->pec[a][li]) continue;
-          s->E[a](i, j, kk) -= s->Cb[a](i, j, kk) * w.I[k] * w.t[a] * wt[c] * dlm / vol;
-        }
+      owire_pattern(w, k, pat);
+      for (const OwEntry& e : pat) {
+        A3& E = s->E[e.a];
+        const size_t li = ((size_t)e.p[2] * E.n1 + e.p[1]) * E.n0 + e.p[0];
+        if (s->pec[e.a][li]) continue;
+        E.v[li] -= s->Cb[e.a].v[li] * w.I[k] * e.d / area;
       }
     }
-  }
 }
 
 // Debye polarisation currents, after the E update and the sources of the

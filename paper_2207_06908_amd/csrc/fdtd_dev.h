@@ -2,6 +2,7 @@
 // the HIP kernels of this library.
 #pragma once
 #include <stdint.h>
+#include <string>
 
 namespace mi355fdtd {
 
@@ -97,11 +98,15 @@ struct OWireParam {
   double pad;
 };
 struct OWireView {
-  int n_wire, max_steps;
+  int n_wire, max_steps, n_edge, pad;
   const OWireParam* par;
-  const long long* idx;
-  const double* ws;
-  const double* wj;
+  const int* seg_off;         // [total segments + 1]: gather terms of each segment
+  const long long* g_key;     // E component << 40 | node index of a gather term
+  const double* g_w;          // its weight: E_t = sum g_w E
+  const long long* e_key;     // [n_edge] E edges the wires inject into (component << 40 | node)
+  const int* e_off;           // [n_edge + 1]: injection terms of each edge
+  const int* j_seg;           // segment of an injection term (increasing within an edge)
+  const double* j_w;          // its weight: E -= (Cb / dx) sum j_w I_seg
   const double* amp;          // [n_wire][max_steps] driven-segment current (A)
   double* cur;                // segment currents (A)
   double* q;                  // end-point charges per unit length (C/m)
@@ -122,7 +127,7 @@ int launch_step(int prec, const void* view, int cls16, int variant, int step, in
 // currents and charges from the input E before it, the wires' currents onto
 // the output E after it (n_seg segments over all wires).
 int launch_owire_iq(int prec, const void* view, const OWireView* ow, int step, void* stream);
-int launch_owire_inject(int prec, const void* view, int cls16, const OWireView* ow, int n_seg, void* stream);
+int launch_owire_inject(int prec, const void* view, int cls16, const OWireView* ow, void* stream);
 int launch_step_debye(int prec, const void* view, const void* dview, int cls16, int step, void* stream);
 
 // Fused (variant 2) or two-step (variant 3) pass of one grid over a tile

@@ -74,11 +74,12 @@ struct fdtd_ctx {
   std::vector<SrcRec> srcs;
   std::vector<OWireRec> owr;
   std::vector<OWireParam> ow_par;
-  std::vector<long long> ow_idx;
-  std::vector<double> ow_ws, ow_wj, ow_amp;
+  std::vector<int> ow_seg_off, ow_eoff, ow_jseg;
+  std::vector<long long> ow_gkey, ow_ekey;
+  std::vector<double> ow_gw, ow_jw, ow_amp;
   int ow_seg = 0;
-  size_t off_ow_par = 0, off_ow_idx = 0, off_ow_ws = 0, off_ow_wj = 0, off_ow_amp = 0, off_ow_cur = 0,
-         off_ow_q = 0, off_ow_rec = 0;
+  size_t off_ow_par = 0, off_ow_segoff = 0, off_ow_gkey = 0, off_ow_gw = 0, off_ow_ekey = 0, off_ow_eoff = 0,
+         off_ow_jseg = 0, off_ow_jw = 0, off_ow_amp = 0, off_ow_cur = 0, off_ow_q = 0, off_ow_rec = 0;
   OWireView ow_view{};
   std::vector<LumpedRec> lumped;
   std::vector<ProbeRec> probes;
@@ -523,15 +524,71 @@ int owire_segments(const OWireRec& r) {
   return (int)std::floor(std::sqrt(l2));
 }
 
-// Per segment and E component the 8 trilinear samples of the segment midpoint
-// on that component's lattice (samples at integer node positions moved half
-// a cell along the component), the wire's telegraph factors and the driving
-// current table.
+// Charge-conserving coupling of an oblique wire to the grid (Section 2.3,
+// the arbitrarily located wire model; formulation of this library).  The
+// grid carries the wire's node charges with the tent (cloud-in-cell)
+// weights of the node positions, so a segment current I moving charge from
+// node p0 to node p1 must enter the grid as edge currents I D(e) whose
+// divergence is minus the change of those weights.  D is taken from
+// Esirkepov's density decomposition (2001): with per-axis tent weights
+// w0_u, w1_u at the two nodes and dw_u = w1_u - w0_u, the change
+// prod w1 - prod w0 splits into one term per axis,
+//   X_a = dw_a * (w0_b w0_c + (dw_b w0_c + w0_b dw_c) / 2 + dw_b dw_c / 3),
+// and the flux along a through the edge after node i is minus the running
+// sum of X_a up to i.  The wire samples the field with the same D (the
+// adjoint), so the exchange of energy is exact and a uniform field gives
+// E_t = t . E.  Each segment spans less than two cells, so each axis has at
+// most four tent nodes.
+struct OwTerm { int comp, i, j, k; double d; };
+
+static void owire_flux(const double p0[3], const double p1[3], std::vector<OwTerm>& terms) {
+  terms.clear();
+  int base[3], cnt[3];
+  double w0[3][4] = {}, dw[3][4] = {};
+  for (int u = 0; u < 3; ++u) {
+    const double lo = std::min(p0[u], p1[u]), hi = std::max(p0[u], p1[u]);
+    base[u] = (int)std::floor(lo);
+    cnt[u] = (int)std::floor(hi) - base[u] + 2;
+    for (int m = 0; m < cnt[u]; ++m) {
+      const double node = base[u] + m;
+      const double t0 = 1.0 - std::fabs(p0[u] - node), t1 = 1.0 - std::fabs(p1[u] - node);
+      w0[u][m] = t0 > 0.0 ? t0 : 0.0;
+      dw[u][m] = (t1 > 0.0 ? t1 : 0.0) - w0[u][m];
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, cax = (a + 2) % 3;
+    for (int mc = 0; mc < cnt[cax]; ++mc)
+      for (int mb = 0; mb < cnt[b]; ++mb) {
+        const double tr = w0[b][mb] * w0[cax][mc] + 0.5 * (dw[b][mb] * w0[cax][mc] + w0[b][mb] * dw[cax][mc]) +
+                          dw[b][mb] * dw[cax][mc] / 3.0;
+        double flux = 0.0;
+        for (int ma = 0; ma + 1 < cnt[a]; ++ma) {
+          flux -= dw[a][ma] * tr;
+          if (flux == 0.0) continue;
+          int q[3];
+          q[a] = base[a] + ma;
+          q[b] = base[b] + mb;
+          q[cax] = base[cax] + mc;
+          terms.push_back({a, q[0], q[1], q[2], flux});
+        }
+      }
+  }
+}
+
+// Tables of every oblique wire: the telegraph factors, per segment its
+// gather terms (E key, D / dl), per touched E edge its injection terms
+// (segment, D / dx, for E -= (Cb / dx) sum D I / dx) in increasing segment
+// order, and the driving current.
 void build_owires(fdtd_ctx* c) {
   const int ms = c->P.max_steps;
   const double dx = c->P.dx, r0 = c->P.wire_r0_factor * dx;
-  c->ow_par.clear(); c->ow_idx.clear(); c->ow_ws.clear(); c->ow_wj.clear();
+  c->ow_par.clear(); c->ow_seg_off.clear(); c->ow_gkey.clear(); c->ow_gw.clear();
+  c->ow_ekey.clear(); c->ow_eoff.clear(); c->ow_jseg.clear(); c->ow_jw.clear();
   c->ow_amp.assign(c->owr.size() * (size_t)ms, 0.0);
+  struct Inj { long long key; int seg; double w; };
+  std::vector<Inj> inj;
+  std::vector<OwTerm> terms;
   int seg0 = 0;
   for (size_t w = 0; w < c->owr.size(); ++w) {
     const OWireRec& r = c->owr[w];
@@ -543,29 +600,37 @@ void build_owires(fdtd_ctx* c) {
     const double Lp = kMu0 * lg / (2.0 * kPi), Cp = 2.0 * kPi * kEps0 / lg;
     c->ow_par.push_back({seg0, n, r.src, r.rec, c->dt / Lp, 1.0 / (Cp * dlm), c->dt / dlm, 0.0});
     for (int k = 0; k < n; ++k) {
-      double m[3];
-      for (int u = 0; u < 3; ++u) m[u] = r.a[u] + (k + 0.5) * dl * d[u] / len;
-      for (int a = 0; a < 3; ++a) {
-        int lo[3];
-        double f[3];
-        for (int u = 0; u < 3; ++u) {
-          const double x = u == a ? m[u] - 0.5 : m[u];
-          lo[u] = (int)std::floor(x);
-          f[u] = x - lo[u];
-        }
-        for (int q = 0; q < 8; ++q) {
-          const int bx = q & 1, by = (q >> 1) & 1, bz = (q >> 2) & 1;
-          const double wt = (bx ? f[0] : 1.0 - f[0]) * (by ? f[1] : 1.0 - f[1]) * (bz ? f[2] : 1.0 - f[2]);
-          c->ow_idx.push_back(node_index(c, lo[0] + bx, lo[1] + by, lo[2] + bz));
-          c->ow_ws.push_back(d[a] / len * wt);
-          c->ow_wj.push_back(d[a] / len * wt * dlm / (dx * dx));
-        }
+      double p0[3], p1[3];
+      for (int u = 0; u < 3; ++u) {
+        p0[u] = r.a[u] + k * dl * d[u] / len;
+        p1[u] = r.a[u] + (k + 1) * dl * d[u] / len;
+      }
+      owire_flux(p0, p1, terms);
+      c->ow_seg_off.push_back((int)c->ow_gkey.size());
+      for (const OwTerm& t : terms) {
+        const long long key = ((long long)t.comp << 40) | node_index(c, t.i, t.j, t.k);
+        c->ow_gkey.push_back(key);
+        c->ow_gw.push_back(t.d / dl);
+        inj.push_back({key, seg0 + k, t.d / dx});  // the class table holds Cb / dx
       }
     }
     for (int t = 0; t < ms && t < (int)r.amps.size(); ++t) c->ow_amp[w * ms + t] = r.amps[t];
     seg0 += n;
   }
+  c->ow_seg_off.push_back((int)c->ow_gkey.size());
   c->ow_seg = seg0;
+  std::stable_sort(inj.begin(), inj.end(), [](const Inj& x, const Inj& y) {
+    return x.key != y.key ? x.key < y.key : x.seg < y.seg;
+  });
+  for (size_t e = 0; e < inj.size(); ++e) {
+    if (e == 0 || inj[e].key != inj[e - 1].key) {
+      c->ow_ekey.push_back(inj[e].key);
+      c->ow_eoff.push_back((int)e);
+    }
+    c->ow_jseg.push_back(inj[e].seg);
+    c->ow_jw.push_back(inj[e].w);
+  }
+  c->ow_eoff.push_back((int)inj.size());
 }
 
 void layout(fdtd_ctx* c) {
@@ -603,9 +668,13 @@ void layout(fdtd_ctx* c) {
   c->off_term_w = take(c->term_w.size() * sizeof(double));
   c->off_out = take(c->probes.size() * (size_t)c->P.max_steps * sizeof(double));
   c->off_ow_par = take(c->ow_par.size() * sizeof(OWireParam));
-  c->off_ow_idx = take(c->ow_idx.size() * sizeof(long long));
-  c->off_ow_ws = take(c->ow_ws.size() * sizeof(double));
-  c->off_ow_wj = take(c->ow_wj.size() * sizeof(double));
+  c->off_ow_segoff = take(c->ow_seg_off.size() * sizeof(int));
+  c->off_ow_gkey = take(c->ow_gkey.size() * sizeof(long long));
+  c->off_ow_gw = take(c->ow_gw.size() * sizeof(double));
+  c->off_ow_ekey = take(c->ow_ekey.size() * sizeof(long long));
+  c->off_ow_eoff = take(c->ow_eoff.size() * sizeof(int));
+  c->off_ow_jseg = take(c->ow_jseg.size() * sizeof(int));
+  c->off_ow_jw = take(c->ow_jw.size() * sizeof(double));
   c->off_ow_amp = take(c->ow_amp.size() * sizeof(double));
   c->off_ow_cur = take((size_t)c->ow_seg * sizeof(double));
   c->off_ow_q = take((size_t)(c->ow_seg + c->owr.size()) * sizeof(double));
@@ -741,19 +810,28 @@ int upload(fdtd_ctx* c) {
     OWireView& w = c->ow_view;
     w.n_wire = (int)c->owr.size();
     w.max_steps = c->P.max_steps;
+    w.n_edge = (int)c->ow_ekey.size();
     w.par = (const OWireParam*)(c->ws + c->off_ow_par);
-    w.idx = (const long long*)(c->ws + c->off_ow_idx);
-    w.ws = (const double*)(c->ws + c->off_ow_ws);
-    w.wj = (const double*)(c->ws + c->off_ow_wj);
+    w.seg_off = (const int*)(c->ws + c->off_ow_segoff);
+    w.g_key = (const long long*)(c->ws + c->off_ow_gkey);
+    w.g_w = (const double*)(c->ws + c->off_ow_gw);
+    w.e_key = (const long long*)(c->ws + c->off_ow_ekey);
+    w.e_off = (const int*)(c->ws + c->off_ow_eoff);
+    w.j_seg = (const int*)(c->ws + c->off_ow_jseg);
+    w.j_w = (const double*)(c->ws + c->off_ow_jw);
     w.amp = (const double*)(c->ws + c->off_ow_amp);
     w.cur = (double*)(c->ws + c->off_ow_cur);
     w.q = (double*)(c->ws + c->off_ow_q);
     w.rec = (double*)(c->ws + c->off_ow_rec);
     const Up wups[] = {
         {(void*)w.par, c->ow_par.data(), c->ow_par.size() * sizeof(OWireParam)},
-        {(void*)w.idx, c->ow_idx.data(), c->ow_idx.size() * sizeof(long long)},
-        {(void*)w.ws, c->ow_ws.data(), c->ow_ws.size() * sizeof(double)},
-        {(void*)w.wj, c->ow_wj.data(), c->ow_wj.size() * sizeof(double)},
+        {(void*)w.seg_off, c->ow_seg_off.data(), c->ow_seg_off.size() * sizeof(int)},
+        {(void*)w.g_key, c->ow_gkey.data(), c->ow_gkey.size() * sizeof(long long)},
+        {(void*)w.g_w, c->ow_gw.data(), c->ow_gw.size() * sizeof(double)},
+        {(void*)w.e_key, c->ow_ekey.data(), c->ow_ekey.size() * sizeof(long long)},
+        {(void*)w.e_off, c->ow_eoff.data(), c->ow_eoff.size() * sizeof(int)},
+        {(void*)w.j_seg, c->ow_jseg.data(), c->ow_jseg.size() * sizeof(int)},
+        {(void*)w.j_w, c->ow_jw.data(), c->ow_jw.size() * sizeof(double)},
         {(void*)w.amp, c->ow_amp.data(), c->ow_amp.size() * sizeof(double)},
     };
     for (const Up& u : wups) {
@@ -1202,7 +1280,7 @@ int fdtd_step(fdtd_ctx* c, int n) {
     }
     if (e) return fail(c, FDTD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString((hipError_t)e));
     if (!c->owr.empty()) {
-      e = launch_owire_inject(c->P.precision, view, c->cls16, &c->ow_view, c->ow_seg, (void*)c->stream);
+      e = launch_owire_inject(c->P.precision, view, c->cls16, &c->ow_view, (void*)c->stream);
       if (e) return fail(c, FDTD_EDEVICE, std::string("oblique-wire launch: ") + hipGetErrorString((hipError_t)e));
     }
     if (variant != FDTD_KERNEL_SPLIT) c->cur ^= 1;

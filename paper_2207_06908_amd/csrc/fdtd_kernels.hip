@@ -1049,7 +1049,8 @@ hipError_t step_split(const GridView<T>& g, int step, hipStream_t st) {
 // Oblique thin wires: one block per wire.  New segment currents from E^n (the
 // input field set) and the charges q^n (the driven segment takes its sample),
 // then the charges from the new currents; both before the step's field pass,
-// which they do not depend on.
+// which they do not depend on.  Each segment sums its gather terms in table
+// order.
 template <typename T>
 __global__ void __launch_bounds__(256) k_owire_iq(GridView<T> g, OWireView w, int step) {
   const OWireParam p = w.par[blockIdx.x];
@@ -1060,9 +1061,11 @@ __global__ void __launch_bounds__(256) k_owire_iq(GridView<T> g, OWireView w, in
     if (s == p.src) {
       v = w.amp[(size_t)blockIdx.x * w.max_steps + step];
     } else {
-      const size_t b = (size_t)(p.seg0 + s) * 24;
       double et = 0.0;
-      for (int e = 0; e < 24; ++e) et += w.ws[b + e] * (double)g.fi[e >> 3][w.idx[b + e]];
+      for (int e = w.seg_off[p.seg0 + s], e1 = w.seg_off[p.seg0 + s + 1]; e < e1; ++e) {
+        const long long key = w.g_key[e];
+        et += w.g_w[e] * (double)g.fi[(int)(key >> 40)][key & ((1ll << 40) - 1)];
+      }
       v = cur[s] + p.dtL * (et - (q[s + 1] - q[s]) * p.invCdl);
     }
     cur[s] = v;
@@ -1075,18 +1078,22 @@ __global__ void __launch_bounds__(256) k_owire_iq(GridView<T> g, OWireView w, in
   if (threadIdx.x == 0 && p.rec >= 0) w.rec[(size_t)blockIdx.x * w.max_steps + step] = cur[p.rec];
 }
 
-// The wires' current moments onto the output E after the step's field pass
-// (its lumped sources included): one thread per
-// (segment, component, corner) entry; neighbouring segments share samples.
+// The wires' currents onto the output E after the step's field pass (its
+// lumped sources included): one thread per touched E edge sums its terms in
+// increasing segment order and updates the edge once, so the result does
+// not depend on scheduling.
 template <typename T, typename CI>
-__global__ void __launch_bounds__(256) k_owire_inject(GridView<T> g, OWireView w, int n_seg) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)n_seg * 24) return;
-  const int a = (int)(e % 24) >> 3;
-  const long long n = w.idx[e];
+__global__ void __launch_bounds__(256) k_owire_inject(GridView<T> g, OWireView w) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= w.n_edge) return;
+  const long long key = w.e_key[e];
+  const int a = (int)(key >> 40);
+  const long long n = key & ((1ll << 40) - 1);
+  double sum = 0.0;
+  for (int t = w.e_off[e], t1 = w.e_off[e + 1]; t < t1; ++t) sum += w.j_w[t] * w.cur[w.j_seg[t]];
   const int cls = ((const CI*)g.cls)[n];
   const double cbdx = (double)g.ctab[cls * K_STRIDE + K_CBX + 2 * a];
-  atomicAdd(&g.fo[a][n], (T)(-cbdx * w.cur[e / 24] * w.wj[e]));
+  g.fo[a][n] = (T)((double)g.fo[a][n] - cbdx * sum);
 }
 
 template <typename T, typename CI>
@@ -1111,17 +1118,17 @@ int launch_owire_iq(int prec, const void* view, const OWireView* ow, int step, v
   return (int)hipGetLastError();
 }
 
-int launch_owire_inject(int prec, const void* view, int cls16, const OWireView* ow, int n_seg, void* stream) {
+int launch_owire_inject(int prec, const void* view, int cls16, const OWireView* ow, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  const dim3 grd((unsigned)(((long long)n_seg * 24 + 255) / 256)), blk(256);
+  const dim3 grd((unsigned)((ow->n_edge + 255) / 256)), blk(256);
   if (prec == 64) {
     const GridView<double>& g = *(const GridView<double>*)view;
-    if (cls16) hipLaunchKernelGGL((k_owire_inject<double, uint16_t>), grd, blk, 0, st, g, *ow, n_seg);
-    else hipLaunchKernelGGL((k_owire_inject<double, uint8_t>), grd, blk, 0, st, g, *ow, n_seg);
+    if (cls16) hipLaunchKernelGGL((k_owire_inject<double, uint16_t>), grd, blk, 0, st, g, *ow);
+    else hipLaunchKernelGGL((k_owire_inject<double, uint8_t>), grd, blk, 0, st, g, *ow);
   } else {
     const GridView<float>& g = *(const GridView<float>*)view;
-    if (cls16) hipLaunchKernelGGL((k_owire_inject<float, uint16_t>), grd, blk, 0, st, g, *ow, n_seg);
-    else hipLaunchKernelGGL((k_owire_inject<float, uint8_t>), grd, blk, 0, st, g, *ow, n_seg);
+    if (cls16) hipLaunchKernelGGL((k_owire_inject<float, uint16_t>), grd, blk, 0, st, g, *ow);
+    else hipLaunchKernelGGL((k_owire_inject<float, uint8_t>), grd, blk, 0, st, g, *ow);
   }
   return (int)hipGetLastError();
 }
