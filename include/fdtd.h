@@ -210,6 +210,24 @@ size_t fdtd_workspace_bytes(fdtd_ctx* c);
  * Errors: ENOMEM, ESTATE, EDEVICE. */
 int fdtd_bind_workspace(fdtd_ctx* c, void* dev_ptr, size_t bytes);
 
+/* Allocation-free binding, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): instead of a caller-owned workspace, the context uses a static
+ * device array of FDTD_STATIC_BYTES (64 MiB) that the library holds on each
+ * GPU it runs on until the process ends -- enough for a 48^3 grid with all
+ * its tables, or about a million cells in FP32.  It binds the array of the
+ * current device (the context's stream must belong to it), then behaves as
+ * fdtd_bind_workspace: tables uploaded, every field, CPML, wire state and
+ * probe record zeroed, so nothing an earlier context left in the array
+ * survives.  Only one live context per device may hold the array: binding a
+ * second one returns FDTD_ESTATE until the first is destroyed (work of two
+ * contexts on one array would race).  Calls no hipMalloc or hipFree.
+ * Errors: ENOMEM (workspace larger than FDTD_STATIC_BYTES, checked before
+ * any HIP call), ESTATE (already bound, or the array is held), EDEVICE, and
+ * fdtd_finalize's errors. */
+#define FDTD_STATIC_BYTES ((size_t)64 << 20)
+int fdtd_bind_static(fdtd_ctx* c);
+
 /* Select a kernel variant (FDTD_KERNEL_*) and tile parameters (0 = default:
  * 8 rows; 20 planes for the two-step pass, 32 otherwise): tile_y (rows per
  * tile) in {4, 8}, or 12 for FDTD_KERNEL_TB2; tile_z (planes per z chunk)

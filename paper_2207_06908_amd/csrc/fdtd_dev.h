@@ -174,3 +174,10 @@ int launch_batch_pass_tb2(int prec, int cls16, const void* views, const void* ti
 // *d += v on the stream (advances the device step counter).
 int launch_add(int* d, int v, void* stream);
 }  // namespace mi355fdtd
+
+// Host-side hooks between fdtd_host.cpp and fdtd_static.hip: record an
+// error message on a context and return its code; drop a context's claim on
+// the static workspace of any device (called by fdtd_destroy).
+struct fdtd_ctx;
+int fdtd_fail_code(fdtd_ctx* c, int code, const std::string& msg);
+void fdtd_static_release(const fdtd_ctx* c);

@@ -130,12 +130,14 @@ struct fdtd_ctx {
   GridView<double> v64[2][2] = {};
 };
 
-namespace {
-
-int fail(fdtd_ctx* c, int code, const std::string& msg) {
+int fdtd_fail_code(fdtd_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
   return code;
 }
+
+namespace {
+
+int fail(fdtd_ctx* c, int code, const std::string& msg) { return fdtd_fail_code(c, code, msg); }
 
 int tsize(const fdtd_ctx* c) { return c->P.precision == 64 ? 8 : 4; }
 
@@ -1843,6 +1845,8 @@ void fdtd_batch_destroy(fdtd_batch* b) {
 
 void fdtd_destroy(fdtd_ctx* c) {
   if (!c) return;
+  if (c->ws) (void)hipStreamSynchronize(c->stream);  // nothing may still use the workspace
+  fdtd_static_release(c);
   if (c->aux) (void)hipStreamSynchronize(c->aux);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);

@@ -54,6 +54,7 @@ SIGNATURES = [
     ("fdtd_finalize", C.c_int, [_vp]),
     ("fdtd_workspace_bytes", C.c_size_t, [_vp]),
     ("fdtd_bind_workspace", C.c_int, [_vp, _vp, C.c_size_t]),
+    ("fdtd_bind_static", C.c_int, [_vp]),
     ("fdtd_set_kernel", C.c_int, [_vp, C.c_int, C.c_int, C.c_int]),
     ("fdtd_step", C.c_int, [_vp, C.c_int]),
     ("fdtd_probe", C.c_int, [_vp, C.c_int, _vp, C.c_int, C.POINTER(C.c_int)]),
@@ -236,6 +237,21 @@ class Grid:
         nbytes = self.workspace_bytes()
         self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._chk(lib().fdtd_bind_workspace(self._h, C.c_void_p(self._ws.data_ptr()), nbytes))
+
+    def bind_static(self):
+        """Bind the library's static device array instead of a workspace
+        (fdtd_bind_static; no device allocation)."""
+        if self._ws is not None:
+            raise FdtdError(-3, "workspace already bound")
+        self._chk(lib().fdtd_bind_static(self._h))
+        self._ws = "static"
+
+    def close(self):
+        """Destroy the context now (releases the static array if it holds it)."""
+        h = getattr(self, "_h", None)
+        if h:
+            lib().fdtd_destroy(h)
+            self._h = None
 
     def step(self, n):
         self.bind()
