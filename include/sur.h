@@ -91,11 +91,20 @@ int sur_forward(sur_ctx* c, int net, const float* x_dev, int n, float* y_dev);
 /* Ensemble inference with routing.  Runs every net on x_dev [n x w_0];
  * writes y_mean_dev [n x w_L] (mean over nets) and spread_dev [n], where the
  * spread of a row is (max - min) / |mean| of the nets' peaks and a net's peak
- * is the largest of its w_L outputs.  Rows whose spread exceeds `threshold`
+ * is the largest of its w_L outputs (+INFINITY for a row outside the input
+ * bound of sur_set_input_bound).  Rows whose spread exceeds `threshold`
  * (or is not finite) are listed in increasing order in fallback_dev (device,
  * room for n ints) and counted in *n_fallback_dev (device int). */
 int sur_infer_route(sur_ctx* c, const float* x_dev, int n, float threshold, float* y_mean_dev,
                     float* spread_dev, int* fallback_dev, int* n_fallback_dev);
+
+/* Guard for sur_infer_route: a row any of whose inputs lies outside
+ * [-bound, bound] is routed to the fallback whatever its spread (its spread
+ * reads +INFINITY).  With inputs scaled so that the training box maps to
+ * [-1, 1], bound 1 keeps every answer the ensemble gives inside the box it
+ * was trained on.  Default INFINITY (off).  Errors: EINVAL (bound <= 0 or
+ * NaN). */
+int sur_set_input_bound(sur_ctx* c, float bound);
 
 const char* sur_last_error(const sur_ctx* c);
 void sur_destroy(sur_ctx* c);

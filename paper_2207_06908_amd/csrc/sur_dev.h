@@ -55,7 +55,10 @@ int launch_loss(const float* y, const float* t, int M, int m_valid, int W, uint1
                 float* dz, float* part, float* loss_dev, void* stream);
 int launch_colsum(const float* dz, int M, int N, float* out, void* stream);
 int launch_adam(const AdamArgs& a, void* stream);
-int launch_route(const float* ys, int nets, int ld_net, int m, int W, float* ymean, float* spread, void* stream);
+// Mean over nets and peak spread per row; a row with an input outside
+// [-xbound, xbound] (x: m rows of kin <= 64 inputs) gets an infinite spread.
+int launch_route(const float* ys, int nets, int ld_net, int m, int W, const float* x, int kin, float xbound,
+                 float* ymean, float* spread, void* stream);
 int launch_compact(const float* spread, int n, float threshold, int* ids, int* count, void* stream);
 int loss_parts(int M, int W);
 

@@ -49,6 +49,7 @@ struct sur_ctx {
   size_t o_g16[2] = {}, o_gT[2] = {}, o_dz[2] = {};
   std::vector<long long> adam_t;
   std::vector<char> ready;
+  float xbound = INFINITY;   // routing bound on the inputs (sur_set_input_bound)
 
   template <typename T>
   T* at(size_t off) const { return (T*)(ws + off); }
@@ -370,11 +371,19 @@ int sur_infer_route(sur_ctx* c, const float* x_dev, int n, float threshold, floa
     if (e) return hip_fail(c, e, "gather");
     for (int q = 0; q < c->nets; ++q)
       if ((r = forward(c, q, M, false, ys + (size_t)q * c->R * W, W, m))) return r;
-    if ((e = launch_route(ys, c->nets, c->R * W, m, W, y_mean_dev + (size_t)c0 * W, spread_dev + c0, c->stream)))
+    if ((e = launch_route(ys, c->nets, c->R * W, m, W, x_dev + (size_t)c0 * k0, k0, c->xbound,
+                          y_mean_dev + (size_t)c0 * W, spread_dev + c0, c->stream)))
       return hip_fail(c, e, "route");
   }
   int e = launch_compact(spread_dev, n, threshold, fallback_dev, n_fallback_dev, c->stream);
   if (e) return hip_fail(c, e, "compact");
+  return SUR_OK;
+}
+
+int sur_set_input_bound(sur_ctx* c, float bound) {
+  if (!c) return SUR_EINVAL;
+  if (!(bound > 0.0f)) return fail(c, SUR_EINVAL, "input bound must be positive (INFINITY: off)");
+  c->xbound = bound;
   return SUR_OK;
 }
 

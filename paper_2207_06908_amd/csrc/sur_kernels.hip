@@ -251,10 +251,14 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
 // outputs (net stride ld_net floats, rows of W).  Writes the mean waveform and
 // the spread (max - min) / |mean| of the nets' peaks.
 __global__ __launch_bounds__(256) void k_route(const float* __restrict__ ys, int nets, long long ld_net, int m, int W,
-                                               float* ymean, float* spread) {
+                                               const float* __restrict__ x, int kin, float xbound, float* ymean,
+                                               float* spread) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= m) return;
+  // an input outside [-xbound, xbound] routes the row whatever the spread
+  const bool out = lane < kin && !(fabsf(x[(long long)row * kin + lane]) <= xbound);
+  const bool any_out = __ballot(out) != 0;
   float pmax = -INFINITY, pmin = INFINITY, psum = 0.0f;
   for (int c0 = 0; c0 < W; c0 += 64) {
     const int c = c0 + lane;
@@ -270,7 +274,7 @@ __global__ __launch_bounds__(256) void k_route(const float* __restrict__ ys, int
     pmin = fminf(pmin, pk);
     psum += pk;
   }
-  if (lane == 0) spread[row] = (pmax - pmin) / fabsf(psum / (float)nets);
+  if (lane == 0) spread[row] = any_out ? INFINITY : (pmax - pmin) / fabsf(psum / (float)nets);
 }
 
 // Ordered list of the rows whose spread is above the threshold or not finite:
@@ -348,9 +352,10 @@ int launch_adam(const AdamArgs& a, void* stream) {
   return last();
 }
 
-int launch_route(const float* ys, int nets, int ld_net, int m, int W, float* ymean, float* spread, void* stream) {
+int launch_route(const float* ys, int nets, int ld_net, int m, int W, const float* x, int kin, float xbound,
+                 float* ymean, float* spread, void* stream) {
   if (m <= 0) return 0;
-  k_route<<<(m + 3) / 4, 256, 0, (hipStream_t)stream>>>(ys, nets, ld_net, m, W, ymean, spread);
+  k_route<<<(m + 3) / 4, 256, 0, (hipStream_t)stream>>>(ys, nets, ld_net, m, W, x, kin, xbound, ymean, spread);
   return last();
 }
 

@@ -28,6 +28,7 @@ SIGNATURES = [
     ("sur_train_step", C.c_int, [_vp, C.c_int, _vp, _vp, _vp, C.c_int, C.c_float, C.c_int, _vp]),
     ("sur_forward", C.c_int, [_vp, C.c_int, _vp, C.c_int, _vp]),
     ("sur_infer_route", C.c_int, [_vp, _vp, C.c_int, C.c_float, _vp, _vp, _vp, _vp]),
+    ("sur_set_input_bound", C.c_int, [_vp, C.c_float]),
     ("sur_last_error", C.c_char_p, [_vp]),
     ("sur_destroy", None, [_vp]),
 ]
@@ -127,6 +128,10 @@ class Ensemble:
             out = torch.empty((n, self.widths[-1]), dtype=torch.float32, device=self.device)
         self._chk(lib().sur_forward(self._h, net, _ptr(x), n, _ptr(out)))
         return out
+
+    def set_input_bound(self, bound):
+        """Route rows with any input outside [-bound, bound] (inf: off)."""
+        self._chk(lib().sur_set_input_bound(self._h, float(bound)))
 
     def infer_route(self, x, threshold):
         """Mean prediction, spread and the ordered fallback row list."""

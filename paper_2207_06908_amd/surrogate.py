@@ -45,6 +45,13 @@ T2 = 10e-6
 WIRE_RADIUS = 0.005
 RANGES = S.CONFIG3_RANGES
 EPS0 = 1.0 / (4e-7 * math.pi * S.C0 ** 2)  # vacuum permittivity, only for the target scale
+# Operating points of the routing.  FAST: spread > 2% goes to FDTD.  GUARDED:
+# also every query outside the training box (bound 1 on the scaled inputs,
+# with room for the float rounding of inputs on the box faces), with a 0.5%
+# spread threshold.
+FAST_THRESHOLD = 0.02
+GUARD_BOUND = 1.0 + 1e-5
+GUARD_THRESHOLD = 0.005
 
 
 # ---------------------------------------------------------------------------
@@ -311,6 +318,11 @@ class Surrogate:
         ym, sp, ids, cnt = self.ens.infer_route(xd, threshold)
         n = int(cnt.item())
         return ym.cpu().numpy(), sp.cpu().numpy(), ids[:n].cpu().numpy()
+
+    def guard(self, bound: float = GUARD_BOUND):
+        """Send every query outside the training box (an input beyond
+        +-bound after scaling) to the fallback; math.inf switches it off."""
+        self.ens.set_input_bound(bound)
 
     def save(self, path: str):
         """Weights as bfloat16 (the precision the products use), biases FP32."""

@@ -2,7 +2,9 @@
 
 Queries are drawn from ranges 20% wider than the training ranges.  The
 ensemble answers all of them in one batched inference; queries whose nets
-disagree on the GPR peak by more than 2% go to the batched FDTD engine.  The
+disagree on the GPR peak by more than 2% go to the batched FDTD engine (the
+fast rule), or, under the guarded rule, also every query outside the
+training box and every query whose nets disagree by more than 0.5%.  The
 same queries also run through FDTD alone, which is both the reference for the
 errors and the throughput the surrogate is compared with.  The nets are the
 committed ones (paper_2207_06908_amd/data/surrogate_weights.npz, written by
@@ -21,16 +23,19 @@ pytestmark = pytest.mark.gpu
 WEIGHTS = os.path.join(os.path.dirname(U.__file__), "data", "surrogate_weights.npz")
 
 
-def _loop_vs_fdtd(n, seed, widen):
+def _loop_vs_fdtd(n, seed, widen, guarded=False):
     cases = S.draw_cases(n, seed=seed, widen=widen)
     X = torch.from_numpy(U.features(cases)).cuda()
     sur = U.Surrogate(n_nets=4, max_rows=8192)
     sur.load(WEIGHTS)
-    sur.route(X[:64], 0.02)  # warm-up
+    thr = U.GUARD_THRESHOLD if guarded else U.FAST_THRESHOLD
+    if guarded:
+        sur.guard()
+    sur.route(X[:64], thr)  # warm-up
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    ym, sp, ids, cnt = sur.ens.infer_route(X, 0.02)
+    ym, sp, ids, cnt = sur.ens.infer_route(X, thr)
     e1.record()
     torch.cuda.synchronize()
     infer_s = e0.elapsed_time(e1) / 1e3
@@ -45,7 +50,7 @@ def _loop_vs_fdtd(n, seed, widen):
     pe = U.peak_error(answer, ref)
     loop_s = infer_s + fdtd_s * fb.size / n      # fallback cases at the engine's per-case cost
     gain = (n / loop_s) / (n / fdtd_s)
-    print(f"widen {widen}: fallback {fb.size}/{n}; peak error median {np.median(pe):.4f} "
+    print(f"widen {widen} guarded {guarded}: fallback {fb.size}/{n}; peak error median {np.median(pe):.4f} "
           f"p95 {np.percentile(pe, 95):.4f} max {pe.max():.4f}; FDTD {n / fdtd_s:.1f} cases/s, "
           f"surrogate in the loop {n / loop_s:.1f} cases/s, gain {gain:.1f}x")
     return pe, fb, gain
@@ -63,9 +68,23 @@ def test_surrogate_gain_inside_the_training_ranges():
 
 def test_surrogate_gain_on_the_widened_sweep():
     """Queries from ranges 20% wider than training (the surrogate-in-the-loop
-    sweep): routing sends the queries the nets disagree on to FDTD; most of
-    the rest stay within 2%."""
+    sweep), fast rule: routing sends the queries the nets disagree on (about
+    1%) to FDTD; about 97% of the answers stay within 2%, the rest are
+    extrapolations the spread does not flag (measured on 4096 queries: 2.5%
+    of all answers exceed 2%, nearly all outside the training box)."""
     pe, fb, gain = _loop_vs_fdtd(256, 2025, 0.1)
-    assert np.mean(pe <= 0.02) >= 0.90
-    assert fb.size <= 0.06 * 256
-    assert gain >= 15.0
+    assert np.mean(pe <= 0.02) >= 0.94
+    assert fb.size <= 0.03 * 256
+    assert gain >= 30.0
+
+
+def test_guarded_routing_delivers_every_answer_within_2pct():
+    """Same widened sweep, guarded rule: every query outside the training
+    box and every query whose nets disagree by more than 0.5% goes to FDTD.
+    Every delivered answer is then within 2% of FDTD (a routed query is
+    answered by FDTD itself); the price is the fallback fraction, about 45%
+    on this sweep."""
+    pe, fb, gain = _loop_vs_fdtd(256, 2026, 0.1, guarded=True)
+    assert pe.max() <= 0.02, pe.max()
+    assert 0.2 * 256 <= fb.size <= 0.7 * 256
+    assert gain >= 1.3
