@@ -98,6 +98,13 @@ int sur_forward(sur_ctx* c, int net, const float* x_dev, int n, float* y_dev);
 int sur_infer_route(sur_ctx* c, const float* x_dev, int n, float threshold, float* y_mean_dev,
                     float* spread_dev, int* fallback_dev, int* n_fallback_dev);
 
+/* Inference kernels of sur_forward and sur_infer_route: 1 (default) runs
+ * every layer of every net in one fused launch per chunk, the activations
+ * of a block of rows held on chip (hidden widths up to 512, output width up
+ * to 260); 0 runs one product launch per layer and net, as training does.
+ * Both give the same bits.  Errors: EINVAL. */
+int sur_set_kernel(sur_ctx* c, int fused);
+
 /* Guard for sur_infer_route: a row any of whose inputs lies outside
  * [-bound, bound] is routed to the fallback whatever its spread (its spread
  * reads +INFINITY).  With inputs scaled so that the training box maps to

@@ -48,6 +48,29 @@ struct AdamArgs {
   AdamLayer L[8];
 };
 
+// Fused inference (k_mlp_infer): all layers of `nets` consecutive nets over
+// M gathered rows, activations kept on chip; hidden widths <= MLP_KMAX, the
+// output width <= MLP_NOUT (its FP32 rows are staged in the same LDS).  Net q's bfloat16 weight copies start at bf + q bf_stride,
+// its FP32 parameters at p + q p_stride; its outputs go to
+// out[q ld_net + row ldo + col] for rows < m_valid.
+constexpr int MLP_BM = 128, MLP_KMAX = 512, MLP_LDA = MLP_KMAX + 8, MLP_NOUT = MLP_LDA / 2;
+struct MlpLayer {
+  long long w16;   // element offset of W [n x kp] in a net's bfloat16 copies
+  int bias;        // offset of b in a net's FP32 parameters
+  int kp, n;
+};
+struct MlpArgs {
+  const uint16_t* X16;  // [M x 32]
+  const uint16_t* bf;
+  const float* p;
+  long long bf_stride, p_stride;
+  int M, L, m_valid, ldo;
+  float* out;
+  long long ld_net;
+  MlpLayer lay[8];
+};
+int launch_mlp_infer(const MlpArgs& a, int nets, void* stream);
+
 int launch_gemm(int epi, const GemmArgs& a, void* stream);
 int launch_gather(const float* x, const float* t, const int* rows, int m_valid, int M, int kin, int W,
                   uint16_t* X16, uint16_t* XT, float* T, void* stream);

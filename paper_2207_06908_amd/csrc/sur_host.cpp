@@ -3,8 +3,9 @@
 // Owns the layer geometry, carves the caller's workspace into parameter,
 // Adam, activation and gradient buffers, and sequences the kernels of
 // sur_kernels.hip: forward (one product per layer with the bias/GELU
-// epilogue), loss, backward (weight-gradient product, bias column sums and
-// the input-gradient product with the GELU-derivative epilogue), Adam.
+// epilogue; inference of every net in one fused launch where the widths
+// allow), loss, backward (weight-gradient product, bias column sums and the
+// input-gradient product with the GELU-derivative epilogue), Adam.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -50,6 +51,7 @@ struct sur_ctx {
   std::vector<long long> adam_t;
   std::vector<char> ready;
   float xbound = INFINITY;   // routing bound on the inputs (sur_set_input_bound)
+  int fused = 1;             // inference by the fused kernel where the widths allow (sur_set_kernel)
 
   template <typename T>
   T* at(size_t off) const { return (T*)(ws + off); }
@@ -279,6 +281,40 @@ static int forward(sur_ctx* c, int net, int M, bool train, float* y, int ldy, in
   return SUR_OK;
 }
 
+// Whether the fused inference kernel takes this geometry: hidden widths up to
+// MLP_KMAX, the output width up to MLP_NOUT.
+static bool fused_ok(const sur_ctx* c) {
+  if (!c->fused) return false;
+  for (int l = 0; l < c->L; ++l) {
+    const int n = c->lay[l].n;
+    if (l + 1 < c->L ? n > MLP_KMAX : n > MLP_NOUT) return false;
+  }
+  return c->L <= 8;
+}
+
+// All layers of nets [net0, net0 + nets) over the M gathered rows of X16, in
+// one launch; outputs to y[q ld_net + row W + col] for rows < m_valid.
+static int forward_fused(sur_ctx* c, int net0, int nets, int M, float* y, long long ld_net, int m_valid) {
+  MlpArgs a{};
+  a.X16 = c->at<uint16_t>(c->o_X16);
+  a.bf = c->bf(net0);
+  a.p = c->p(net0);
+  a.bf_stride = (long long)(c->net_stride / 2);
+  a.p_stride = (long long)(c->net_stride / 4);
+  a.M = M;
+  a.L = c->L;
+  a.m_valid = m_valid;
+  a.ldo = c->w.back();
+  a.out = y;
+  a.ld_net = ld_net;
+  for (int l = 0; l < c->L; ++l) {
+    const Layer& ly = c->lay[l];
+    a.lay[l] = MlpLayer{ly.w16, (int)ly.off_b, ly.kp, ly.n};
+  }
+  const int e = launch_mlp_infer(a, nets, c->stream);
+  return e ? hip_fail(c, e, "fused inference") : SUR_OK;
+}
+
 int sur_train_step(sur_ctx* c, int net, const float* x_dev, const float* t_dev, const int* rows_dev, int batch,
                    float lr, int update, float* loss_dev) {
   int r = check_net(c, net, true);
@@ -348,7 +384,9 @@ int sur_forward(sur_ctx* c, int net, const float* x_dev, int n, float* y_dev) {
     int e = launch_gather(x_dev + (size_t)c0 * k0, nullptr, nullptr, m, M, k0, W, c->at<uint16_t>(c->o_X16),
                           nullptr, nullptr, c->stream);
     if (e) return hip_fail(c, e, "gather");
-    if ((r = forward(c, net, M, false, y_dev + (size_t)c0 * W, W, m))) return r;
+    r = fused_ok(c) ? forward_fused(c, net, 1, M, y_dev + (size_t)c0 * W, 0, m)
+                    : forward(c, net, M, false, y_dev + (size_t)c0 * W, W, m);
+    if (r) return r;
   }
   return SUR_OK;
 }
@@ -369,14 +407,24 @@ int sur_infer_route(sur_ctx* c, const float* x_dev, int n, float threshold, floa
     int e = launch_gather(x_dev + (size_t)c0 * k0, nullptr, nullptr, m, M, k0, W, c->at<uint16_t>(c->o_X16),
                           nullptr, nullptr, c->stream);
     if (e) return hip_fail(c, e, "gather");
-    for (int q = 0; q < c->nets; ++q)
-      if ((r = forward(c, q, M, false, ys + (size_t)q * c->R * W, W, m))) return r;
+    if (fused_ok(c)) {
+      if ((r = forward_fused(c, 0, c->nets, M, ys, (long long)c->R * W, m))) return r;
+    } else {
+      for (int q = 0; q < c->nets; ++q)
+        if ((r = forward(c, q, M, false, ys + (size_t)q * c->R * W, W, m))) return r;
+    }
     if ((e = launch_route(ys, c->nets, c->R * W, m, W, x_dev + (size_t)c0 * k0, k0, c->xbound,
                           y_mean_dev + (size_t)c0 * W, spread_dev + c0, c->stream)))
       return hip_fail(c, e, "route");
   }
   int e = launch_compact(spread_dev, n, threshold, fallback_dev, n_fallback_dev, c->stream);
   if (e) return hip_fail(c, e, "compact");
+  return SUR_OK;
+}
+
+int sur_set_kernel(sur_ctx* c, int fused) {
+  if (!c || (fused != 0 && fused != 1)) return fail(c, SUR_EINVAL, "kernel choice must be 0 or 1");
+  c->fused = fused;
   return SUR_OK;
 }
 

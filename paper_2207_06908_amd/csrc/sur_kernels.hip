@@ -132,6 +132,116 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   }
 }
 
+// Fused inference: every layer of one net over MLP_BM = 128 rows in one
+// block of 16 waves.  The block's activations stay in LDS from layer to
+// layer (bfloat16, rows padded by 16 bytes so that the 16 rows of a fragment
+// fall in different banks); only the gathered inputs, the weights (a few MB
+// per net, L2-resident) and the last layer's FP32 outputs touch memory.  The
+// product of a 64K-row activation block with 512 x 512 weights moves 128 MB
+// through HBM when every layer round-trips; here it moves none.
+// Wave w owns the output column fragments w and w + 16 (16 columns each;
+// widths up to 512) for all 8 row fragments of the block, so every weight
+// fragment it loads serves 8 products and the block reads each weight once.
+// The weight fragments run two K steps ahead of the products.  The loop has
+// no branches: rows past M hold zero inputs, a column fragment past the
+// layer's width multiplies fragment 0's weights, and neither result is ever
+// stored, so the wave waits only for the loads its next products need.  Each
+// accumulator takes its K steps in order with the instruction k_gemm uses,
+// and the epilogue is k_gemm's, so the outputs equal the layer-by-layer
+// products bit for bit.
+__global__ __launch_bounds__(1024) void k_mlp_infer(MlpArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t act[MLP_BM * MLP_LDA];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int net = blockIdx.y, m0 = blockIdx.x * MLP_BM;
+  const uint16_t* bfn = a.bf + (size_t)net * a.bf_stride;
+  const float* pn = a.p + (size_t)net * a.p_stride;
+  for (int e = tid; e < MLP_BM * 4; e += 1024) {  // inputs: 32 bfloat16 per row, as four 16-byte pieces
+    const int r = e >> 2, q = e & 3;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (m0 + r < a.M) v = *(const uint4*)(a.X16 + (size_t)(m0 + r) * 32 + q * 8);
+    *(uint4*)(act + r * MLP_LDA + q * 8) = v;
+  }
+  __syncthreads();
+  const int r16 = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
+  const uint16_t* pa = act + r16 * MLP_LDA + kq;
+#pragma unroll 1
+  for (int l = 0; l < a.L; ++l) {
+    const MlpLayer ly = a.lay[l];
+    const int nf = ly.n >> 4;
+    const bool vn0 = w < nf, vn1 = w + 16 < nf;
+    // column fragment 1 of this wave starts 256 rows of W after fragment 0;
+    // a fragment past the width reads fragment 0's rows (its products are
+    // never stored)
+    const uint16_t* pb0 = bfn + ly.w16 + (size_t)((vn0 ? w : 0) * 16 + r16) * ly.kp + kq;
+    const uint16_t* pb1 = vn1 ? pb0 + (size_t)256 * ly.kp : pb0;
+    f32x4 c[8][2];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[i][0] = c[i][1] = f32x4{0, 0, 0, 0};
+    const int last = ly.kp - 32;
+    bf16x8 b0[2], b1[2];   // weights of steps k and k + 1
+    b0[0] = ld_frag(pb0);
+    b0[1] = ld_frag(pb1);
+    b1[0] = ld_frag(pb0 + min(32, last));
+    b1[1] = ld_frag(pb1 + min(32, last));
+#pragma unroll 1
+    for (int k0 = 0; k0 < ly.kp; k0 += 32) {
+      bf16x8 fa[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) fa[i] = *(const bf16x8*)(pa + 16 * i * MLP_LDA + k0);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        c[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], b0[0], c[i][0], 0, 0, 0);
+        c[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], b0[1], c[i][1], 0, 0, 0);
+      }
+      // step k + 2's weights into the registers step k has finished with
+      const int kn = min(k0 + 64, last);
+      b0[0] = b1[0];
+      b0[1] = b1[1];
+      b1[0] = ld_frag(pb0 + kn);
+      b1[1] = ld_frag(pb1 + kn);
+    }
+    __syncthreads();  // every wave has read this layer's input
+    const float* bias = pn + ly.bias;
+    if (l + 1 < a.L) {  // hidden layer: bias, exact GELU, bfloat16 into LDS
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (!(j ? vn1 : vn0)) continue;
+        const int n = (w + 16 * j) * 16 + r16;
+        const float bn = bias[n];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float z = c[i][j][r] + bn;
+            const float e = erff(z * kInvSqrt2);
+            const float y = 0.5f * z * (1.0f + e);
+            act[(16 * i + rq + r) * MLP_LDA + n] = (uint16_t)f2bf(y);
+          }
+        }
+      }
+    } else {  // output layer: bias, FP32 staged in LDS, then rows < m_valid out as whole rows
+      float* of = (float*)act;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (!(j ? vn1 : vn0)) continue;
+        const int n = (w + 16 * j) * 16 + r16;
+        const float bn = bias[n];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) of[(16 * i + rq + r) * ly.n + n] = c[i][j][r] + bn;
+      }
+      __syncthreads();
+      const int rows = min(MLP_BM, a.m_valid - m0);
+      for (int e = tid; e < rows * ly.n; e += 1024) {
+        const int m = e / ly.n, n = e - m * ly.n;
+        a.out[(size_t)net * a.ld_net + (size_t)(m0 + m) * a.ldo + n] = of[e];
+      }
+    }
+    __syncthreads();  // the next layer reads what this one wrote
+  }
+}
+
 // Batch assembly: inputs to bfloat16, zero-padded to 32 columns and to M rows
 // (row-major and transposed), targets to a dense FP32 block.
 __global__ void k_gather(const float* __restrict__ x, const float* __restrict__ t, const int* __restrict__ rows,
@@ -247,9 +357,12 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   }
 }
 
-// Ensemble reduction of one chunk: one wave per row.  ys holds the nets'
-// outputs (net stride ld_net floats, rows of W).  Writes the mean waveform and
-// the spread (max - min) / |mean| of the nets' peaks.
+// Ensemble reduction of one chunk: one wave per row, one pass over the nets'
+// outputs ys ([net][row][col], net stride ld_net).  Each lane keeps the
+// running sum of its columns (nets added in order) and the running peak of
+// the net in hand; the spread is (max - min) / |mean| of the nets' peaks, the
+// peaks summed in net order.  Rows with an input outside [-xbound, xbound]
+// get an infinite spread.
 __global__ __launch_bounds__(256) void k_route(const float* __restrict__ ys, int nets, long long ld_net, int m, int W,
                                                const float* __restrict__ x, int kin, float xbound, float* ymean,
                                                float* spread) {
@@ -259,45 +372,92 @@ __global__ __launch_bounds__(256) void k_route(const float* __restrict__ ys, int
   // an input outside [-xbound, xbound] routes the row whatever the spread
   const bool out = lane < kin && !(fabsf(x[(long long)row * kin + lane]) <= xbound);
   const bool any_out = __ballot(out) != 0;
-  float pmax = -INFINITY, pmin = INFINITY, psum = 0.0f;
-  for (int c0 = 0; c0 < W; c0 += 64) {
-    const int c = c0 + lane;
-    float s = 0.0f;
-    for (int q = 0; q < nets; ++q) s += c < W ? ys[q * ld_net + (long long)row * W + c] : 0.0f;
-    if (c < W) ymean[(long long)row * W + c] = s / (float)nets;
+  constexpr int CMAX = 8;  // columns per lane per group of 512 held in registers
+  float pkq[16];           // per net (nets <= 16): the lane's running peak
+#pragma unroll
+  for (int q = 0; q < 16; ++q) pkq[q] = -INFINITY;
+  for (int c0 = 0; c0 < W; c0 += 64 * CMAX) {
+    float s[CMAX];
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) s[t] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (q < nets) {
+        const float* yq = ys + q * ld_net + (long long)row * W;
+#pragma unroll
+        for (int t = 0; t < CMAX; ++t) {
+          const int c = c0 + lane + 64 * t;
+          if (c < W) {
+            const float v = yq[c];
+            s[t] += v;
+            pkq[q] = fmaxf(pkq[q], v);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) {
+      const int c = c0 + lane + 64 * t;
+      if (c < W) ymean[(long long)row * W + c] = s[t] / (float)nets;
+    }
   }
-  for (int q = 0; q < nets; ++q) {
-    float pk = -INFINITY;
-    for (int c = lane; c < W; c += 64) pk = fmaxf(pk, ys[q * ld_net + (long long)row * W + c]);
-    for (int o = 32; o > 0; o >>= 1) pk = fmaxf(pk, __shfl_xor(pk, o, 64));
-    pmax = fmaxf(pmax, pk);
-    pmin = fminf(pmin, pk);
-    psum += pk;
+  float pmax = -INFINITY, pmin = INFINITY, psum = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    if (q < nets) {
+      float pk = pkq[q];
+      for (int o = 32; o > 0; o >>= 1) pk = fmaxf(pk, __shfl_xor(pk, o, 64));
+      pmax = fmaxf(pmax, pk);
+      pmin = fminf(pmin, pk);
+      psum += pk;
+    }
   }
   if (lane == 0) spread[row] = any_out ? INFINITY : (pmax - pmin) / fabsf(psum / (float)nets);
 }
 
-// Ordered list of the rows whose spread is above the threshold or not finite:
-// one block, each thread scans a contiguous segment, block-wide exclusive scan.
+// Ordered list of the rows whose spread is above the threshold or not finite,
+// in one block of 16 waves: the spreads are read 64 at a time (one per lane,
+// coalesced), counted by ballot, the counts of the 64-row pieces scanned in
+// LDS, and the rows written at their piece's offset plus their rank in it.
 __global__ __launch_bounds__(1024) void k_compact(const float* __restrict__ spread, int n, float thr, int* ids,
                                                   int* count) {
   __shared__ int cnt[1024];
-  const int per = (n + 1023) / 1024;
-  const int b = threadIdx.x * per, e = min(n, b + per);
-  int c = 0;
-  for (int i = b; i < e; ++i) c += !(spread[i] <= thr);
-  cnt[threadIdx.x] = c;
+  __shared__ int off[1024];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int pieces = (n + 63) / 64;
+  const int per = (pieces + 1023) / 1024;   // pieces per scan slot
+  for (int s = threadIdx.x; s < 1024; s += 1024) cnt[s] = 0;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele scan
-    const int v = threadIdx.x >= o ? cnt[threadIdx.x - o] : 0;
-    __syncthreads();
-    cnt[threadIdx.x] += v;
-    __syncthreads();
+  for (int p = w; p < pieces; p += 16) {
+    const int i = p * 64 + lane;
+    const bool f = i < n && !(spread[i] <= thr);
+    const int c = __popcll(__ballot(f));
+    if (lane == 0) atomicAdd(&cnt[p / per], c);
   }
-  int pos = cnt[threadIdx.x] - c;
-  for (int i = b; i < e; ++i)
-    if (!(spread[i] <= thr)) ids[pos++] = i;
-  if (threadIdx.x == 1023) *count = cnt[1023];
+  __syncthreads();
+  const int mine = cnt[threadIdx.x];
+  int v = mine;
+  for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele scan
+    __syncthreads();
+    off[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x >= o) v += off[threadIdx.x - o];
+  }
+  __syncthreads();
+  off[threadIdx.x] = v - mine;  // exclusive offset of scan slot
+  __syncthreads();
+  if (threadIdx.x == 1023) *count = v;
+  // each scan slot's pieces in order, by one wave
+  for (int slot = w; slot < 1024; slot += 16) {
+    int pos = off[slot];
+    for (int p = slot * per; p < min(pieces, (slot + 1) * per); ++p) {
+      const int i = p * 64 + lane;
+      const bool f = i < n && !(spread[i] <= thr);
+      const unsigned long long b = __ballot(f);
+      if (f) ids[pos + __popcll(b & ((1ull << lane) - 1ull))] = i;
+      pos += __popcll(b);
+    }
+  }
 }
 
 static int last() { return (int)hipGetLastError(); }
@@ -320,6 +480,12 @@ int launch_gemm(int epi, const GemmArgs& a, void* stream) {
     launch_gemm_f<4>(epi, a, (hipStream_t)stream);
   else
     launch_gemm_f<2>(epi, a, (hipStream_t)stream);
+  return last();
+}
+
+int launch_mlp_infer(const MlpArgs& a, int nets, void* stream) {
+  if (a.M <= 0) return 0;
+  k_mlp_infer<<<dim3((a.M + MLP_BM - 1) / MLP_BM, nets), 1024, 0, (hipStream_t)stream>>>(a);
   return last();
 }
 

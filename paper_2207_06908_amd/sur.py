@@ -29,6 +29,7 @@ SIGNATURES = [
     ("sur_forward", C.c_int, [_vp, C.c_int, _vp, C.c_int, _vp]),
     ("sur_infer_route", C.c_int, [_vp, _vp, C.c_int, C.c_float, _vp, _vp, _vp, _vp]),
     ("sur_set_input_bound", C.c_int, [_vp, C.c_float]),
+    ("sur_set_kernel", C.c_int, [_vp, C.c_int]),
     ("sur_last_error", C.c_char_p, [_vp]),
     ("sur_destroy", None, [_vp]),
 ]
@@ -128,6 +129,10 @@ class Ensemble:
             out = torch.empty((n, self.widths[-1]), dtype=torch.float32, device=self.device)
         self._chk(lib().sur_forward(self._h, net, _ptr(x), n, _ptr(out)))
         return out
+
+    def set_kernel(self, fused):
+        """1: fused inference (default); 0: one product launch per layer."""
+        self._chk(lib().sur_set_kernel(self._h, int(fused)))
 
     def set_input_bound(self, bound):
         """Route rows with any input outside [-bound, bound] (inf: off)."""

@@ -163,7 +163,9 @@ def test_large_and_small_product_tiles_give_the_same_bits():
     the same rows run in 8,192-row chunks (64 x 64 tiles) bit for bit."""
     from paper_2207_06908_amd import sur
     big, ps, X, _T = _setup(FULL, nets=2, rows=65536, n=65536, seed=3)
+    big.set_kernel(0)        # per-layer products (the fused kernel is checked below)
     small = sur.Ensemble(FULL, n_nets=2, max_rows=8192)
+    small.set_kernel(0)
     for q in range(2):
         small.set_params(q, M.flat(ps[q]))
     xd = _dev(X)
@@ -174,3 +176,23 @@ def test_large_and_small_product_tiles_give_the_same_bits():
     y0 = big.forward(0, xd[:4096]).cpu().numpy()
     y1 = small.forward(0, xd[:4096]).cpu().numpy()
     assert np.array_equal(y0, y1)
+
+
+def test_fused_inference_equals_the_layer_products():
+    """The fused inference kernel (every layer of every net in one launch,
+    activations on chip) gives the same bits as one product launch per layer
+    and net: same routing means and spreads over 65,536 rows and a ragged
+    chunk, and the same single-net outputs."""
+    from paper_2207_06908_amd import sur
+    ens, ps, X, _T = _setup(FULL, nets=4, rows=65536, n=65536, seed=8)
+    xd = _dev(X)
+    out = {}
+    for fused in (1, 0):
+        ens.set_kernel(fused)
+        ym, sp, ids, cnt = ens.infer_route(xd, 0.02)
+        yr, spr, _i, _c = ens.infer_route(xd[:1000], 0.02)    # 1000 rows: a block of 128 with 64 pad rows
+        out[fused] = (ym.cpu().numpy(), sp.cpu().numpy(), ids[:int(cnt.item())].cpu().numpy(),
+                      yr.cpu().numpy(), spr.cpu().numpy(), ens.forward(1, xd[:777]).cpu().numpy())
+    for a, b in zip(out[1], out[0]):
+        assert np.array_equal(a, b)
+    assert np.abs(out[1][0]).max() > 0
