@@ -88,8 +88,9 @@ typedef struct {
 /* Fill *p with the defaults above (grid size and dx left at zero). */
 void fdtd_default_params(fdtd_params* p);
 
-/* Validate p and create a host-side context.  hip_stream is a hipStream_t or
- * NULL.  Errors: EINVAL (bad sizes, npml leaves no interior, bad precision or
+/* Validate p and create a host-side context for one grid (the uniform
+ * staggered Yee grid of Section 2.1, eqs. 4-5, with the CPML of Section 2.2
+ * when npml > 0).  hip_stream is a hipStream_t or NULL.  Errors: EINVAL (bad sizes, npml leaves no interior, bad precision or
  * loss mode), EUNSTABLE (dt above the Courant limit). */
 int fdtd_create(const fdtd_params* p, void* hip_stream, fdtd_ctx** out);
 
@@ -142,10 +143,12 @@ int fdtd_add_source(fdtd_ctx* c, int kind, int axis, int i, int j, int k,
  * length q_k at their ends (open ends), stepped by the telegraph equations
  *   L' dI_k/dt = E_t(mid_k) - (q_{k+1} - q_k) / (C' dl),  dq_k/dt = -dI/dl,
  * L' = mu0 ln(r0/radius) / (2 pi), C' = 2 pi eps0 / ln(r0/radius),
- * r0 = wire_r0_factor dx.  E_t is each E component interpolated trilinearly
- * at the midpoint and projected on the wire; the current moment I_k dl goes
- * back to the same samples with the same weights as a current density
- * over dx^3 (E -= Cb J after the E update).
+ * r0 = wire_r0_factor dx.  The coupling conserves charge: the grid holds
+ * the wire's node charges with cloud-in-cell weights, segment k's current
+ * enters the E edges around it as the fluxes of Esirkepov's density
+ * decomposition for the move from node k to node k+1 (E -= Cb J after the E
+ * update, each touched edge summing its terms in a fixed order), and E_t,k
+ * is the same-weighted sum of those edges' E over the segment length.
  * src_seg >= 0 drives that segment's current with amps[n] (A, at
  * (n + 1/2) dt; 0 after the last sample; n_amps may be 0); rec_seg >= 0
  * records that segment's current every step.  Grids with oblique wires run
@@ -186,7 +189,10 @@ int fdtd_add_lumped(fdtd_ctx* c, int kind, int axis, int i, int j, int k, double
 int fdtd_add_source_r(fdtd_ctx* c, int kind, int axis, int i, int j, int k, const double* amps, int n_samples,
                       double r_internal);
 
-/* Probe (recorded every step, FP64):
+/* Probe (recorded every step, FP64), the quantities the paper's model files
+ * ask for with their output and calculate commands (Section 4.1): a field
+ * component, a voltage as a line integral of E, a current as a loop
+ * integral of H:
  *   FDTD_PR_E      value of the edge (axis, i, j, k) (n_cells = 1);
  *   FDTD_PR_VLINE  sum of E_axis dx over n_cells edges from node (i, j, k)
  *                  along +axis, i.e. phi(start) - phi(end);
@@ -238,7 +244,9 @@ int fdtd_bind_static(fdtd_ctx* c);
  * Results do not depend on the choice (bitwise).  Errors: EINVAL. */
 int fdtd_set_kernel(fdtd_ctx* c, int variant, int tile_y, int tile_z);
 
-/* Advance n_steps steps, asynchronously on the stream.  Errors: ESTATE (not
+/* Advance n_steps steps of the leapfrog scheme (Section 2.1: the H update
+ * of eq. 5, then the E update of eq. 4 with the sources, then the probes),
+ * asynchronously on the stream.  Errors: ESTATE (not
  * bound), ERANGE (beyond max_steps), EDEVICE. */
 int fdtd_step(fdtd_ctx* c, int n_steps);
 

@@ -779,7 +779,12 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
     }
     const int s1 = (k + 2) & 1, s1m = s1 ^ 1;
     for (int c = 0; c < 3; ++c) sm.se1[s1][c][v][u] = e1c[c];
-    __syncthreads();
+    // No barrier here: C reads the neighbours' E^{n+1} of plane k-1 (slot
+    // s1m, written in the previous iteration, before its two barriers) and
+    // this thread's own E^{n+1} of plane k (a register).  Slot s1, written
+    // just now, is read by the next iteration's C, after that iteration's
+    // first two barriers; it last held plane k-2, whose readers finished
+    // before this iteration's barriers.
     // C: H^{n+3/2}, plane k-1
     const int km = k - 1;
     T h2c[3] = {T(0), T(0), T(0)};

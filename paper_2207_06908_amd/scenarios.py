@@ -295,7 +295,7 @@ def config2(nx: int = 512, ny: int = 512, nz: int = 384, dx: float = 0.5, npml: 
                     meta=dict(ks=ks, kg=kg))
 
 
-# Measured soil of the paper's buried-wire example (Section 3, four-term
+# Measured soil of the paper's buried-wire example (Section 4.1, four-term
 # Debye expansion): eps_inf, static conductivity [S/m], and per pole
 # (delta eps, tau [s]).
 DEBYE_SOIL_EPS_INF = 16.381
@@ -329,7 +329,7 @@ def config2_lumped(**kw) -> Scenario:
     return sc
 
 
-# The apparent-resistivity array of the paper's second example (Section 3):
+# The apparent-resistivity array of the paper's third example (Section 4.3):
 # three soil layers, each a four-pole Debye expansion of its Messier-model
 # properties (eps_inf, sigma0 [S/m], (delta eps, tau [s]) per pole).
 ARRAY_LAYERS = (

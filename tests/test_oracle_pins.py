@@ -747,7 +747,7 @@ def test_resistive_voltage_source_divides_with_a_load():
     assert V[-1] == pytest.approx(V0 * RL / (Rs + RL), rel=1e-3)
 
 
-# ---- Oblique thin wire (Section 2.4) ----
+# ---- Oblique thin wire (Section 2.3) ----
 
 def _owire_box(n=20, npml=4, steps=4):
     o = _orc()(n, n, n, 0.1, npml=npml, max_steps=steps)
