@@ -244,6 +244,15 @@ int fdtd_bind_static(fdtd_ctx* c);
  * Results do not depend on the choice (bitwise).  Errors: EINVAL. */
 int fdtd_set_kernel(fdtd_ctx* c, int variant, int tile_y, int tile_z);
 
+/* Graph replay: graph_steps (a multiple of 4; 0 = off, the default) steps
+ * of launches are captured once into a HIP graph (per parity of the field
+ * set they start from) and replayed for each run of that many steps, the
+ * kernels taking the step from a counter in the workspace.  For small grids,
+ * whose steps are short next to the launch overhead.  Results do not depend
+ * on it (bitwise).  While timing is enabled, a replay is timed whole, its
+ * probe kernels included.  Errors: EINVAL. */
+int fdtd_set_graph(fdtd_ctx* c, int graph_steps);
+
 /* Advance n_steps steps of the leapfrog scheme (Section 2.1: the H update
  * of eq. 5, then the E update of eq. 4 with the sources, then the probes),
  * asynchronously on the stream.  Errors: ESTATE (not

@@ -61,6 +61,10 @@ struct GridView {
   const long long* term_idx;
   const double* term_w;
   double* pr_out;                // [n_probe][max_steps]
+  // step counter in device memory for launches replayed from a captured
+  // graph: a kernel's step is *dstep plus its step argument (nullptr: the
+  // argument alone)
+  const int* dstep;
 };
 
 // Debye media (auxiliary differential equation), for the split E update:
@@ -173,6 +177,8 @@ int launch_batch_pass_tb2(int prec, int cls16, const void* views, const void* ti
                           void* stream2, void* ev_fork, void* ev_join);
 // *d += v on the stream (advances the device step counter).
 int launch_add(int* d, int v, void* stream);
+// *d = v on the stream.
+int launch_set(int* d, int v, void* stream);
 }  // namespace mi355fdtd
 
 // Host-side hooks between fdtd_host.cpp and fdtd_static.hip: record an

@@ -118,6 +118,15 @@ struct fdtd_ctx {
   int cur = 0;
   long long steps_done = 0;
   int variant = FDTD_KERNEL_AUTO, tile_y = 0, tile_z = 0;
+  // graph replay (fdtd_set_graph): G steps captured once per parity of the
+  // field set they start from, replayed with the step taken from a device
+  // counter at off_dstep
+  int graph_steps = 0;
+  long long graph_key = -1;          // launch shape the graphs were captured for
+  size_t off_dstep = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
   // kernel timing: a ring of event pairs, drained when a slot is reused
   bool timing = false;
   static constexpr int kRing = 64;
@@ -681,6 +690,7 @@ void layout(fdtd_ctx* c) {
   c->off_ow_cur = take((size_t)c->ow_seg * sizeof(double));
   c->off_ow_q = take((size_t)(c->ow_seg + c->owr.size()) * sizeof(double));
   c->off_ow_rec = take(c->owr.size() * (size_t)c->P.max_steps * sizeof(double));
+  c->off_dstep = take(sizeof(int));
   c->max_tiles = 0;
   if (np > 0) {  // bound for 32-wide, 4-high tiles and chunks of >= 8 planes
     c->max_tiles = (size_t)(c->N[0] / 32 + 6) * (c->N[1] / 4 + 6) * (c->N[2] / 8 + 6);
@@ -1202,6 +1212,103 @@ int ensure_tiles(fdtd_ctx* c, int variant, int ty, int kz) {
   return FDTD_OK;
 }
 
+// The launches of one step (or one two-step pass) on stream st.  step is the
+// absolute step for an eager launch, or the offset from the device counter
+// dstep for a launch captured into a graph.  With slot >= 0 the end event of
+// the update kernels is recorded before the probes.
+int launch_pass(fdtd_ctx* c, hipStream_t st, int variant, bool lists, int lty, int step, const int* dstep, int slot) {
+  const int in = c->cur, out = variant == FDTD_KERNEL_SPLIT ? c->cur : 1 - c->cur;
+  GridView<float> v32 = c->v32[in][out], p32 = c->v32[out][out];
+  GridView<double> v64 = c->v64[in][out], p64 = c->v64[out][out];
+  v32.dstep = p32.dstep = dstep;
+  v64.dstep = p64.dstep = dstep;
+  const bool d64 = c->P.precision == 64;
+  const void* view = d64 ? (const void*)&v64 : (const void*)&v32;
+  const void* pview = d64 ? (const void*)&p64 : (const void*)&p32;
+  int e;
+  if (!c->owr.empty()) {
+    e = launch_owire_iq(c->P.precision, view, &c->ow_view, step, (void*)st);
+    if (e) return fail(c, FDTD_EDEVICE, std::string("oblique-wire launch: ") + hipGetErrorString((hipError_t)e));
+  }
+  if (lists) {
+    hipError_t he = hipEventRecord(c->ev_fork, st);
+    if (he == hipSuccess) he = hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+    if (he != hipSuccess) return hip_fail(c, he, "stream fork");
+    e = launch_lists_step(c->P.precision, view, c->cls16, variant, step, lty, c->ws + c->off_tiles, c->tl_cnt,
+                          (void*)st, (void*)c->aux);
+    if (!e) {
+      he = hipEventRecord(c->ev_join, c->aux);
+      if (he == hipSuccess) he = hipStreamWaitEvent(st, c->ev_join, 0);
+      if (he != hipSuccess) return hip_fail(c, he, "stream join");
+    }
+  } else if (c->npole) {
+    DebyeView<float> d32 = c->d32;
+    DebyeView<double> d64v = c->d64;
+    const void* dview = d64 ? (const void*)&d64v : (const void*)&d32;
+    e = launch_step_debye(c->P.precision, view, dview, c->cls16, step, (void*)st);
+  } else {
+    e = launch_step(c->P.precision, view, c->cls16, variant, step, c->tile_y, c->tile_z, (void*)st);
+  }
+  if (e) return fail(c, FDTD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString((hipError_t)e));
+  if (!c->owr.empty()) {
+    e = launch_owire_inject(c->P.precision, view, c->cls16, &c->ow_view, (void*)st);
+    if (e) return fail(c, FDTD_EDEVICE, std::string("oblique-wire launch: ") + hipGetErrorString((hipError_t)e));
+  }
+  if (slot >= 0) {  // the timed span ends with the update kernels
+    hipError_t he = hipEventRecord(c->ev1[slot], st);
+    if (he != hipSuccess) return hip_fail(c, he, "hipEventRecord");
+  }
+  if (variant == FDTD_KERNEL_TB2)
+    e = launch_probes2(c->P.precision, view, c->cls16, step, lists ? 0 : 1, (void*)st);
+  else
+    e = launch_probes(c->P.precision, pview, step, (void*)st);
+  if (e) return fail(c, FDTD_EDEVICE, std::string("probe launch: ") + hipGetErrorString((hipError_t)e));
+  return FDTD_OK;
+}
+
+void drop_graphs(fdtd_ctx* c) {
+  for (int q = 0; q < 2; ++q) {
+    if (c->gexec[q]) (void)hipGraphExecDestroy(c->gexec[q]);
+    if (c->graph[q]) (void)hipGraphDestroy(c->graph[q]);
+    c->gexec[q] = nullptr;
+    c->graph[q] = nullptr;
+  }
+}
+
+// Capture graph_steps steps from the current field-set parity: step offsets
+// 0 .. G-1 from the device counter, the ping-pong sets in the order the
+// eager loop would use them (G is a multiple of 4, so the parity returns).
+int capture_graph(fdtd_ctx* c, int variant, bool lists, int lty) {
+  if (!c->cap_stream) {  // the legacy default stream cannot be captured
+    hipError_t he = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (he != hipSuccess) return hip_fail(c, he, "capture stream");
+  }
+  const int cur0 = c->cur, G = c->graph_steps, adv = variant == FDTD_KERNEL_TB2 ? 2 : 1;
+  const int* dstep = (const int*)(c->ws + c->off_dstep);
+  hipError_t he = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (he != hipSuccess) return hip_fail(c, he, "begin capture");
+  int rc = FDTD_OK;
+  for (int off = 0; off < G && rc == FDTD_OK; off += adv) {
+    rc = launch_pass(c, c->cap_stream, variant, lists, lty, off, dstep, -1);
+    if (variant != FDTD_KERNEL_SPLIT) c->cur ^= 1;
+  }
+  c->cur = cur0;
+  hipGraph_t gr = nullptr;
+  he = hipStreamEndCapture(c->cap_stream, &gr);
+  if (rc) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return rc;
+  }
+  if (he != hipSuccess) return hip_fail(c, he, "end capture");
+  c->graph[cur0] = gr;
+  he = hipGraphInstantiate(&c->gexec[cur0], gr, nullptr, nullptr, 0);
+  if (he != hipSuccess) {
+    drop_graphs(c);
+    return hip_fail(c, he, "graph instantiate");
+  }
+  return FDTD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1221,19 +1328,25 @@ int fdtd_step(fdtd_ctx* c, int n) {
   if (c->npole) chosen = FDTD_KERNEL_SPLIT;  // Debye media: the split pass only
   // oblique wires sample E^n and feed E^{n+1}: one-step passes only
   if (!c->owr.empty() && chosen == FDTD_KERNEL_TB2) chosen = FDTD_KERNEL_FUSED;
+  const int lty = c->tile_y == 4 ? 4 : (c->tile_y == 12 && chosen == FDTD_KERNEL_TB2) ? 12 : 8;
+  const int G = c->graph_steps;
+  const long long key = ((long long)chosen * 16 + lty) * 65536 + c->tile_z;
+  if (G > 0 && key != c->graph_key) {
+    drop_graphs(c);
+    c->graph_key = key;
+  }
   for (int t = 0; t < n;) {
     // the two-step pass needs two steps; an odd remainder takes one fused step
     const int variant = (chosen == FDTD_KERNEL_TB2 && n - t < 2) ? FDTD_KERNEL_FUSED : chosen;
     const int adv = variant == FDTD_KERNEL_TB2 ? 2 : 1;
-    const int in = c->cur, out = variant == FDTD_KERNEL_SPLIT ? c->cur : 1 - c->cur;
-    const void* view = c->P.precision == 64 ? (const void*)&c->v64[in][out] : (const void*)&c->v32[in][out];
-    const void* pview = c->P.precision == 64 ? (const void*)&c->v64[out][out] : (const void*)&c->v32[out][out];
     // grids with a CPML run the fused and two-step passes over tile lists
     const bool lists = (variant == FDTD_KERNEL_FUSED || variant == FDTD_KERNEL_TB2) && listable;
-    const int lty = c->tile_y == 4 ? 4 : (c->tile_y == 12 && variant == FDTD_KERNEL_TB2) ? 12 : 8;
     const int lkz = std::max(8, c->tile_z > 0 ? c->tile_z : (variant == FDTD_KERNEL_TB2 ? 20 : 32));
+    // 12-row tiles exist for the two-step pass only (an odd last step's fused
+    // pass takes 8 rows)
+    const int vty = c->tile_y == 4 ? 4 : (c->tile_y == 12 && variant == FDTD_KERNEL_TB2) ? 12 : 8;
     if (lists) {
-      int rc = ensure_tiles(c, variant, lty, lkz);
+      int rc = ensure_tiles(c, variant, vty, lkz);
       if (rc) return rc;
       if (!c->aux) {
         hipError_t he = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
@@ -1242,6 +1355,7 @@ int fdtd_step(fdtd_ctx* c, int n) {
         if (he != hipSuccess) return hip_fail(c, he, "second stream");
       }
     }
+    const bool replay = G > 0 && n - t >= G && variant == chosen;
     int slot = -1;
     if (c->timing) {
       slot = c->ev_next;
@@ -1254,53 +1368,45 @@ int fdtd_step(fdtd_ctx* c, int n) {
         c->timed_steps += c->ev_steps[slot];
         --c->ev_pending;
       }
-      hipError_t er = hipEventRecord(c->ev0[slot], c->stream);
-      if (er != hipSuccess) return hip_fail(c, er, "hipEventRecord");
     }
     int e;
-    if (!c->owr.empty()) {
-      e = launch_owire_iq(c->P.precision, view, &c->ow_view, (int)c->steps_done, (void*)c->stream);
-      if (e) return fail(c, FDTD_EDEVICE, std::string("oblique-wire launch: ") + hipGetErrorString((hipError_t)e));
-    }
-    if (lists) {
-      hipError_t he = hipEventRecord(c->ev_fork, c->stream);
-      if (he == hipSuccess) he = hipStreamWaitEvent(c->aux, c->ev_fork, 0);
-      if (he != hipSuccess) return hip_fail(c, he, "stream fork");
-      e = launch_lists_step(c->P.precision, view, c->cls16, variant, (int)c->steps_done, lty, c->ws + c->off_tiles,
-                            c->tl_cnt, (void*)c->stream, (void*)c->aux);
-      if (!e) {
-        he = hipEventRecord(c->ev_join, c->aux);
-        if (he == hipSuccess) he = hipStreamWaitEvent(c->stream, c->ev_join, 0);
-        if (he != hipSuccess) return hip_fail(c, he, "stream join");
+    if (replay) {
+      if (!c->gexec[c->cur]) {
+        int rc = capture_graph(c, variant, lists, vty);
+        if (rc) return rc;
       }
-    } else if (c->npole) {
-      const void* dview = c->P.precision == 64 ? (const void*)&c->d64 : (const void*)&c->d32;
-      e = launch_step_debye(c->P.precision, view, dview, c->cls16, (int)c->steps_done, (void*)c->stream);
+      e = launch_set((int*)(c->ws + c->off_dstep), (int)c->steps_done, (void*)c->stream);
+      if (e) return fail(c, FDTD_EDEVICE, std::string("step counter: ") + hipGetErrorString((hipError_t)e));
+      if (slot >= 0 && hipEventRecord(c->ev0[slot], c->stream) != hipSuccess) return fail(c, FDTD_EDEVICE, "event");
+      hipError_t he = hipGraphLaunch(c->gexec[c->cur], c->stream);
+      if (he != hipSuccess) return hip_fail(c, he, "graph launch");
     } else {
-      e = launch_step(c->P.precision, view, c->cls16, variant, (int)c->steps_done, c->tile_y, c->tile_z,
-                      (void*)c->stream);
+      if (slot >= 0 && hipEventRecord(c->ev0[slot], c->stream) != hipSuccess) return fail(c, FDTD_EDEVICE, "event");
+      int rc = launch_pass(c, c->stream, variant, lists, vty, (int)c->steps_done, nullptr, slot);
+      if (rc) return rc;
     }
-    if (e) return fail(c, FDTD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString((hipError_t)e));
-    if (!c->owr.empty()) {
-      e = launch_owire_inject(c->P.precision, view, c->cls16, &c->ow_view, (void*)c->stream);
-      if (e) return fail(c, FDTD_EDEVICE, std::string("oblique-wire launch: ") + hipGetErrorString((hipError_t)e));
-    }
-    if (variant != FDTD_KERNEL_SPLIT) c->cur ^= 1;
+    const int done = replay ? G : adv;
+    if (!replay && variant != FDTD_KERNEL_SPLIT) c->cur ^= 1;
     if (slot >= 0) {
-      hipError_t er = hipEventRecord(c->ev1[slot], c->stream);
-      if (er != hipSuccess) return hip_fail(c, er, "hipEventRecord");
-      c->ev_steps[slot] = adv;
+      if (replay) {  // a replayed graph is timed whole, its probe launches included
+        hipError_t er = hipEventRecord(c->ev1[slot], c->stream);
+        if (er != hipSuccess) return hip_fail(c, er, "hipEventRecord");
+      }
+      c->ev_steps[slot] = done;
       c->ev_next = (slot + 1) % fdtd_ctx::kRing;
       ++c->ev_pending;
     }
-    if (variant == FDTD_KERNEL_TB2)
-      e = launch_probes2(c->P.precision, view, c->cls16, (int)c->steps_done, lists ? 0 : 1, (void*)c->stream);
-    else
-      e = launch_probes(c->P.precision, pview, (int)c->steps_done, (void*)c->stream);
-    if (e) return fail(c, FDTD_EDEVICE, std::string("probe launch: ") + hipGetErrorString((hipError_t)e));
-    c->steps_done += adv;
-    t += adv;
+    c->steps_done += done;
+    t += done;
   }
+  return FDTD_OK;
+}
+
+int fdtd_set_graph(fdtd_ctx* c, int graph_steps) {
+  if (!c) return FDTD_EINVAL;
+  if (graph_steps < 0 || graph_steps % 4) return fail(c, FDTD_EINVAL, "graph_steps must be a multiple of 4 (0: off)");
+  if (graph_steps != c->graph_steps) drop_graphs(c);
+  c->graph_steps = graph_steps;
   return FDTD_OK;
 }
 
@@ -1847,6 +1953,8 @@ void fdtd_destroy(fdtd_ctx* c) {
   if (!c) return;
   if (c->ws) (void)hipStreamSynchronize(c->stream);  // nothing may still use the workspace
   fdtd_static_release(c);
+  drop_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->aux) (void)hipStreamSynchronize(c->aux);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);

@@ -40,6 +40,13 @@ __device__ __forceinline__ void slabs(const GridView<T>& g, int x, int y, int k,
   l[2] = (AX & 4) ? slab_pos(k, g.nz, g.npml) : -1;
 }
 
+// The step a single-grid kernel works on: its argument, plus the device
+// counter when the launch is replayed from a captured graph.
+template <typename T>
+__device__ __forceinline__ int gstep(const GridView<T>& g, int step) {
+  return g.dstep ? *g.dstep + step : step;
+}
+
 // CPML state of one node: ps[axis][q], q = 0 for the component along
 // axis+1, q = 1 for axis+2; kind 0 = E-type, 1 = H-type.
 template <typename T>
@@ -243,6 +250,7 @@ __global__ __launch_bounds__(256) void k_h_split(GridView<T> g) {
 
 template <typename T, typename CI, bool PML>
 __global__ __launch_bounds__(256) void k_e_split(GridView<T> g, int step) {
+  step = gstep(g, step);
   const int i = blockIdx.x * 64 + threadIdx.x;
   const int j = blockIdx.y * 4 + threadIdx.y;
   const int k = blockIdx.z;
@@ -269,6 +277,7 @@ __global__ __launch_bounds__(256) void k_e_split(GridView<T> g, int step) {
 // their J stays 0 without traffic.
 template <typename T, typename CI, bool PML>
 __global__ __launch_bounds__(256) void k_e_split_debye(GridView<T> g, DebyeView<T> d, int step) {
+  step = gstep(g, step);
   const int i = blockIdx.x * 64 + threadIdx.x;
   const int j = blockIdx.y * 4 + threadIdx.y;
   const int k = blockIdx.z;
@@ -512,6 +521,7 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
 
 template <typename T, typename CI, bool PML, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) void k_fused(GridView<T> g, int step, int kz, int ntx, int nty) {
+  step = gstep(g, step);
   __shared__ FusedSmem<T, TX, TY> sm;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int tile_x = tile % ntx, rest = tile / ntx;
@@ -525,6 +535,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused(GridView<T> g, int step, int 
 // rest, which runs the CPML one.
 template <typename T, typename CI, bool PML, int TX, int TY, int AX>
 __global__ __launch_bounds__(TX * TY) void k_fused_list(GridView<T> g, const int4* __restrict__ tiles, int step) {
+  step = gstep(g, step);
   __shared__ FusedSmem<T, TX, TY> sm;
   const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   fused_tile<T, CI, PML, TX, TY, AX>(g, sm, t.x, t.y, t.z, t.w, step);
@@ -845,6 +856,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
 
 template <typename T, typename CI, bool PML, int TY>
 __global__ __launch_bounds__(64 * (TY + 4)) void k_tb2(GridView<T> g, int step, int kz, int ntx, int nty) {
+  step = gstep(g, step);
   __shared__ TB2Smem<T, TY> sm;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int tile_x = tile % ntx, rest = tile / ntx;
@@ -860,6 +872,7 @@ template <typename T, typename CI, bool PML, int TY, int AX>
 __global__ __launch_bounds__(64 * (TY + 4), (sizeof(T) == 8 ? 1 : 6)) void k_tb2_list(GridView<T> g,
                                                                                       const int4* __restrict__ tiles,
                                                                                       int step) {
+  step = gstep(g, step);
   __shared__ TB2Smem<T, TY> sm;
   const int4 t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   constexpr bool LEAN = AX == 7 && sizeof(T) == 4;
@@ -962,6 +975,7 @@ __device__ __forceinline__ void probe_tb2(const GridView<T>& g, int p, int step,
 
 template <typename T, typename CI, bool PML, bool S1 = true, bool S2 = true>
 __global__ __launch_bounds__(PR_NT) void k_probes_tb2(GridView<T> g, int step) {
+  step = gstep(g, step);
   __shared__ double red[8];
   if ((int)blockIdx.x >= g.n_probe) return;  // uniform per block
   probe_tb2<T, CI, PML, S1, S2>(g, blockIdx.x, step, red);
@@ -1014,6 +1028,7 @@ __device__ __forceinline__ void probe_one(const GridView<T>& g, int p, int step,
 
 template <typename T>
 __global__ __launch_bounds__(PR_NT) void k_probes(GridView<T> g, int step) {
+  step = gstep(g, step);
   __shared__ double red[4];
   if ((int)blockIdx.x >= g.n_probe) return;  // uniform per block
   probe_one(g, blockIdx.x, step, red);
@@ -1058,6 +1073,7 @@ hipError_t step_split(const GridView<T>& g, int step, hipStream_t st) {
 // order.
 template <typename T>
 __global__ void __launch_bounds__(256) k_owire_iq(GridView<T> g, OWireView w, int step) {
+  step = gstep(g, step);
   const OWireParam p = w.par[blockIdx.x];
   double* cur = w.cur + p.seg0;
   double* q = w.q + p.seg0 + blockIdx.x;
@@ -1450,6 +1466,15 @@ int launch_batch_pass_tb2(int prec, int cls16, const void* views, const void* ti
       hipLaunchKernelGGL((k_probes_tb2_batch<float, uint8_t>), grd, blk, 0, st, (const GridView<float>*)views,
                          (const int2*)plist, n_probes, d_step, offset);
   }
+  return (int)hipGetLastError();
+}
+
+__global__ void k_set(int* p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+int launch_set(int* d, int v, void* stream) {
+  hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, (hipStream_t)stream, d, v);
   return (int)hipGetLastError();
 }
 

@@ -56,6 +56,7 @@ SIGNATURES = [
     ("fdtd_bind_workspace", C.c_int, [_vp, _vp, C.c_size_t]),
     ("fdtd_bind_static", C.c_int, [_vp]),
     ("fdtd_set_kernel", C.c_int, [_vp, C.c_int, C.c_int, C.c_int]),
+    ("fdtd_set_graph", C.c_int, [_vp, C.c_int]),
     ("fdtd_step", C.c_int, [_vp, C.c_int]),
     ("fdtd_probe", C.c_int, [_vp, C.c_int, _vp, C.c_int, C.POINTER(C.c_int)]),
     ("fdtd_set_field", C.c_int, [_vp, C.c_int, _vp]),
@@ -218,6 +219,10 @@ class Grid:
 
     def set_kernel(self, variant=KERNEL_AUTO, tile_y=0, tile_z=0):
         self._chk(lib().fdtd_set_kernel(self._h, variant, tile_y, tile_z))
+
+    def set_graph(self, graph_steps):
+        """Replay runs of graph_steps steps from a captured HIP graph (0: off)."""
+        self._chk(lib().fdtd_set_graph(self._h, int(graph_steps)))
 
     # -- device ------------------------------------------------------------
     def finalize(self):
