@@ -25,12 +25,13 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # and x1.0), keyed by the hash of the kernel sources they were taken with:
 # once the kernels change the figure no longer applies and is reported null.
 # the kernels, and the host code that builds their tile lists and launches
-KERNEL_SOURCES = ("paper_2207_06908_amd/csrc/fdtd_kernels.hip", "paper_2207_06908_amd/csrc/yee_update.h",
+KERNEL_SOURCES = ("paper_2207_06908_amd/csrc/fdtd_kernels.hip", "paper_2207_06908_amd/csrc/fdtd_tile.h",
+                  "paper_2207_06908_amd/csrc/fdtd_debye.hip", "paper_2207_06908_amd/csrc/yee_update.h",
                   "paper_2207_06908_amd/csrc/fdtd_dev.h", "paper_2207_06908_amd/csrc/fdtd_host.cpp")
 MEASURED_TRAFFIC = {
     # (source hash, kernel variant, tile_y, tile_z): HBM bytes per step (all
     # launches of the step; a two-step pass counts half)
-    ("3f53def0605455f9", "tb2", 8, 20): 4.040e9,
+    ("924946271864c55e", "tb2", 8, 20): 4.043e9,
 }
 
 
@@ -164,14 +165,25 @@ def bench_batch(warmup: int = 100, graph_steps: int = 100, tune: bool = True):
 
 def bench_debye(steps: int = 400, warmup: int = 20):
     """The 512 x 512 x 384 scene with the paper's measured four-pole Debye
-    soil in both layers: the split pass with polarisation currents."""
+    soil in both layers: the split pass with polarisation currents (the
+    default for such grids), and the fused pass beside it."""
     import torch
     from paper_2207_06908_amd import fdtd
     from paper_2207_06908_amd import scenarios as S
-    sc = S.config2_debye(n_steps=warmup + steps)
+    sc = S.config2_debye(n_steps=2 * (warmup + steps))
     g = fdtd.Grid.from_params(sc.params(), precision=32)
     S.apply(sc, g)
     g.bind()
+    g.set_kernel(2)
+    g.step(warmup)
+    torch.cuda.synchronize()
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record()
+    g.step(steps)
+    f1.record()
+    torch.cuda.synchronize()
+    fused_ms = f0.elapsed_time(f1) / steps
+    g.set_kernel(0)
     g.step(warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -192,7 +204,10 @@ def bench_debye(steps: int = 400, warmup: int = 20):
            "ms_per_step": round(ms / steps, 5),
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_step": bytes_step,
-                        "kernel_ms_per_step": round(kms / max(kn, 1), 5)}}
+                        "kernel_ms_per_step": round(kms / max(kn, 1), 5)},
+           "fused": {"kernel": "k_fused_list_debye (one launch per step and CPML tile group)",
+                     "ms_per_step": round(fused_ms, 5),
+                     "value": round(sc.cells / (fused_ms / 1e3) / 1e6, 1)}}
     del g
     torch.cuda.empty_cache()
     return out

@@ -112,7 +112,9 @@ int fdtd_set_materials(fdtd_ctx* c, const uint8_t* cell_mat, const fdtd_material
  *   tau_p dJ_p/dt + J_p = eps0 d_eps_p dE/dt,
  * taken at n + 1/2 with the trapezoidal rule, like sigma E; J_p lives in the
  * workspace (3 n_poles extra arrays of nx*ny*nz values).  Such a grid runs
- * the split pass whatever fdtd_set_kernel selects, and cannot join a batch.
+ * the split pass, or the fused pass when fdtd_set_kernel asks for it (8-row
+ * tiles whatever tile_y asks; a two-step request takes the split pass), and
+ * cannot join a batch.
  * Needs the semi-implicit loss form.  Errors: EINVAL, ENONFINITE, ESTATE. */
 int fdtd_set_debye(fdtd_ctx* c, int n_poles, const double* tau, const double* d_eps);
 

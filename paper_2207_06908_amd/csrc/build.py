@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 OUT = os.path.join(PKG, "libmi355fdtd.so")
-SOURCES = ["fdtd_host.cpp", "fdtd_kernels.hip", "fdtd_static.hip", "sur_host.cpp", "sur_kernels.hip"]
+SOURCES = ["fdtd_host.cpp", "fdtd_kernels.hip", "fdtd_debye.hip", "fdtd_static.hip", "sur_host.cpp", "sur_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

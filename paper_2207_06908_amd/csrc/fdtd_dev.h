@@ -67,9 +67,10 @@ struct GridView {
   const int* dstep;
 };
 
-// Debye media (auxiliary differential equation), for the split E update:
-// per E component a and pole p the polarisation current J (one array of
-// ncell values each, j[a * 4 + p]), per class and component the pole
+// Debye media (auxiliary differential equation): per E component a and
+// pole p the polarisation current J (one array of ncell values each,
+// j[a * 4 + p]; poles p >= npole point at pole npole - 1's array, which the
+// kernels read but neither use nor write), per class and component the pole
 // factors dtab[(class * 3 + a) * 8 + 2 p] = beta_p and [.. + 1] = gam_p,
 // a per-class flag (any pole term), and the decay factors kp.  The update:
 //   E^{n+1} = Ca E^n + Cb curl H - sources - sum_p gam_p J_p^n,
@@ -133,6 +134,12 @@ int launch_step(int prec, const void* view, int cls16, int variant, int step, in
 int launch_owire_iq(int prec, const void* view, const OWireView* ow, int step, void* stream);
 int launch_owire_inject(int prec, const void* view, int cls16, const OWireView* ow, void* stream);
 int launch_step_debye(int prec, const void* view, const void* dview, int cls16, int step, void* stream);
+// Fused one-step pass (reads one field set, writes the other) of a grid with
+// Debye poles (fdtd_debye.hip): over the 4-group tile list `tiles` / counts
+// (as for launch_lists_step, variant 2, 8-row tiles; groups 1-3 on
+// `stream2`) or, with tiles == nullptr, over 64 x 8 tiles of tile_z planes.
+int launch_fused_debye(int prec, const void* view, const void* dview, int cls16, int step, int tile_z,
+                       const void* tiles, const int* counts, void* stream, void* stream2);
 
 // Fused (variant 2) or two-step (variant 3) pass of one grid over a tile
 // list: `tiles` is a device array of int4 in 4 groups of counts[q] tiles, by

@@ -804,8 +804,9 @@ int upload(fdtd_ctx* c) {
     DebyeView<T>& d = debye_view_of<T>(c);
     d = DebyeView<T>{};
     for (int a = 0; a < 3; ++a)
-      for (int p = 0; p < c->npole; ++p)
-        d.j[a * D_MAXPOLE + p] = (T*)(c->ws + c->off_j) + (size_t)(a * c->npole + p) * (size_t)c->ncell;
+      for (int p = 0; p < D_MAXPOLE; ++p)  // poles beyond npole alias the last one (read only)
+        d.j[a * D_MAXPOLE + p] =
+            (T*)(c->ws + c->off_j) + (size_t)(a * c->npole + std::min(p, c->npole - 1)) * (size_t)c->ncell;
     d.dtab = (const T*)(c->ws + c->off_dtab);
     d.dflag = (const unsigned char*)(c->ws + c->off_dflag);
     for (int p = 0; p < c->npole; ++p) d.kp[p] = (T)((2.0 * c->tau[p] - c->dt) / (2.0 * c->tau[p] + c->dt));
@@ -1230,22 +1231,29 @@ int launch_pass(fdtd_ctx* c, hipStream_t st, int variant, bool lists, int lty, i
     e = launch_owire_iq(c->P.precision, view, &c->ow_view, step, (void*)st);
     if (e) return fail(c, FDTD_EDEVICE, std::string("oblique-wire launch: ") + hipGetErrorString((hipError_t)e));
   }
+  DebyeView<float> d32 = c->d32;
+  DebyeView<double> d64v = c->d64;
+  const void* dview = d64 ? (const void*)&d64v : (const void*)&d32;
   if (lists) {
     hipError_t he = hipEventRecord(c->ev_fork, st);
     if (he == hipSuccess) he = hipStreamWaitEvent(c->aux, c->ev_fork, 0);
     if (he != hipSuccess) return hip_fail(c, he, "stream fork");
-    e = launch_lists_step(c->P.precision, view, c->cls16, variant, step, lty, c->ws + c->off_tiles, c->tl_cnt,
-                          (void*)st, (void*)c->aux);
+    if (c->npole)
+      e = launch_fused_debye(c->P.precision, view, dview, c->cls16, step, c->tile_z, c->ws + c->off_tiles,
+                             c->tl_cnt, (void*)st, (void*)c->aux);
+    else
+      e = launch_lists_step(c->P.precision, view, c->cls16, variant, step, lty, c->ws + c->off_tiles, c->tl_cnt,
+                            (void*)st, (void*)c->aux);
     if (!e) {
       he = hipEventRecord(c->ev_join, c->aux);
       if (he == hipSuccess) he = hipStreamWaitEvent(st, c->ev_join, 0);
       if (he != hipSuccess) return hip_fail(c, he, "stream join");
     }
   } else if (c->npole) {
-    DebyeView<float> d32 = c->d32;
-    DebyeView<double> d64v = c->d64;
-    const void* dview = d64 ? (const void*)&d64v : (const void*)&d32;
-    e = launch_step_debye(c->P.precision, view, dview, c->cls16, step, (void*)st);
+    e = variant == FDTD_KERNEL_SPLIT
+            ? launch_step_debye(c->P.precision, view, dview, c->cls16, step, (void*)st)
+            : launch_fused_debye(c->P.precision, view, dview, c->cls16, step, c->tile_z, nullptr, nullptr, (void*)st,
+                                 nullptr);
   } else {
     e = launch_step(c->P.precision, view, c->cls16, variant, step, c->tile_y, c->tile_z, (void*)st);
   }
@@ -1325,10 +1333,15 @@ int fdtd_step(fdtd_ctx* c, int n) {
   int chosen = c->variant != FDTD_KERNEL_AUTO ? c->variant : listable ? FDTD_KERNEL_TB2 : FDTD_KERNEL_FUSED;
   if (chosen == FDTD_KERNEL_TB2 && !tb2_ok) chosen = FDTD_KERNEL_FUSED;
   if (c->npole && !c->owr.empty()) return fail(c, FDTD_EINVAL, "oblique wires in a grid with Debye media");
-  if (c->npole) chosen = FDTD_KERNEL_SPLIT;  // Debye media: the split pass only
+  // Debye media: the split pass, or the fused pass when asked for (the pole
+  // currents would have to live across the two-step pass's stages).  The
+  // fused pass with pole currents ran 1% faster than the split pass on
+  // 512 x 512 x 384 cells and slower on every smaller grid measured (its
+  // CPML slab groups dominate there).
+  if (c->npole) chosen = c->variant == FDTD_KERNEL_FUSED ? FDTD_KERNEL_FUSED : FDTD_KERNEL_SPLIT;
   // oblique wires sample E^n and feed E^{n+1}: one-step passes only
   if (!c->owr.empty() && chosen == FDTD_KERNEL_TB2) chosen = FDTD_KERNEL_FUSED;
-  const int lty = c->tile_y == 4 ? 4 : (c->tile_y == 12 && chosen == FDTD_KERNEL_TB2) ? 12 : 8;
+  const int lty = c->npole ? 8 : c->tile_y == 4 ? 4 : (c->tile_y == 12 && chosen == FDTD_KERNEL_TB2) ? 12 : 8;
   const int G = c->graph_steps;
   const long long key = ((long long)chosen * 16 + lty) * 65536 + c->tile_z;
   if (G > 0 && key != c->graph_key) {
@@ -1344,7 +1357,8 @@ int fdtd_step(fdtd_ctx* c, int n) {
     const int lkz = std::max(8, c->tile_z > 0 ? c->tile_z : (variant == FDTD_KERNEL_TB2 ? 20 : 32));
     // 12-row tiles exist for the two-step pass only (an odd last step's fused
     // pass takes 8 rows)
-    const int vty = c->tile_y == 4 ? 4 : (c->tile_y == 12 && variant == FDTD_KERNEL_TB2) ? 12 : 8;
+    // (Debye grids: 8 rows)
+    const int vty = c->npole ? 8 : c->tile_y == 4 ? 4 : (c->tile_y == 12 && variant == FDTD_KERNEL_TB2) ? 12 : 8;
     if (lists) {
       int rc = ensure_tiles(c, variant, vty, lkz);
       if (rc) return rc;

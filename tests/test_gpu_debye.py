@@ -1,7 +1,8 @@
 """GPU parity for Debye media (Section 2.4, auxiliary differential equation):
-the split pass with polarisation currents against the FP64 oracle on the
-same seeded inputs, element by element (FP64 1e-11, FP32 2e-5 of the largest
-value), and the special cases that must reproduce other runs bit for bit."""
+the fused and split passes with polarisation currents against the FP64
+oracle on the same seeded inputs, element by element (FP64 1e-11, FP32 2e-5
+of the largest value), and the special cases that must reproduce other runs
+bit for bit."""
 import numpy as np
 import pytest
 
@@ -25,10 +26,11 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _debye_case(nx, ny, nz, npml, seed, nsteps=60):
+def _debye_case(nx, ny, nz, npml, seed, nsteps=60, n_mats=None):
     """The random case (CPML, wires along all axes, sources, every probe
     kind) with pole increments on half of its materials."""
-    sc = S.random_case(nx, ny, nz, npml, seed=seed, nsteps=nsteps)
+    kw = {} if n_mats is None else {"n_mats": n_mats}
+    sc = S.random_case(nx, ny, nz, npml, seed=seed, nsteps=nsteps, **kw)
     rng = np.random.default_rng(seed + 100)
     de = rng.uniform(0.5, 30.0, size=(len(sc.materials), len(TAU)))
     de[::2] = 0.0
@@ -36,16 +38,19 @@ def _debye_case(nx, ny, nz, npml, seed, nsteps=60):
     return sc
 
 
-@pytest.mark.parametrize("dims,npml", [((70, 13, 11), 3), ((33, 41, 17), 4), ((64, 8, 8), 0)])
-def test_debye_fields_elementwise(fd, oracle_mod, dims, npml):
-    sc = _debye_case(*dims, npml, seed=dims[0] + dims[2])
-    _say(f"debye fields {dims} npml={npml}")
+@pytest.mark.parametrize("variant", [2, 1])   # fused, split (the default)
+@pytest.mark.parametrize("dims,npml", [((70, 13, 11), 3), ((33, 41, 17), 4), ((64, 8, 8), 0),
+                                       ((130, 19, 37), 5)])
+def test_debye_fields_elementwise(fd, oracle_mod, dims, npml, variant):
+    sc = _debye_case(*dims, npml, seed=dims[0] + dims[2], n_mats=3 if dims[0] > 100 else None)
+    _say(f"debye fields {dims} npml={npml} variant={variant}")
     o = oracle_mod.Oracle.from_params(sc.params())
     ids_o = S.apply(sc, o)
     o.step(sc.n_steps)
     for prec, tol in ((64, 1e-11), (32, 2e-5)):
         g = fd.Grid.from_params(sc.params(), precision=prec)
         ids = S.apply(sc, g)
+        g.set_kernel(variant)
         g.step(sc.n_steps)
         for c in range(6):
             ref, got = o.get_field(c), g.get_field(c)
@@ -95,21 +100,31 @@ def test_debye_zero_increments_bitwise_split(fd):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("variant,ty,tz", [(0, 0, 0), (2, 8, 32), (3, 8, 20)])
-def test_debye_grid_takes_the_split_pass(fd, variant, ty, tz):
-    """Whatever variant is asked for, a Debye grid runs the split pass: the
-    same bits as an explicit split request, in odd step chunks."""
+@pytest.mark.parametrize("dims,npml", [((50, 19, 15), 3), ((150, 70, 40), 6), ((70, 21, 19), 0)])
+def test_debye_variants_bitwise_equal(fd, dims, npml):
+    """Every kernel request on a Debye grid gives the bits of the split pass,
+    in odd step chunks and with split and fused steps mixed: the fused pass
+    over CPML tile lists (the larger grid has tiles in all four slab groups)
+    or, without a CPML, over plain 64 x 8 tiles, also when 4-row tiles are
+    asked for (it takes 8); the default and a two-step request run the split
+    pass."""
+    runs = [((1, 0, 0), (3, 20, 18)), ((0, 0, 0), (3, 20, 18)), ((2, 8, 32), (41,)), ((2, 4, 7), (2, 39)),
+            ((3, 8, 20), (5, 36)), ((3, 12, 16), (41,)), ("mixed", (10, 11, 20))]
     outs = []
-    for v, y, z in ((1, 0, 0), (variant, ty, tz)):
-        sc = _debye_case(50, 19, 15, 3, seed=12, nsteps=41)
+    for kern, chunks in runs:
+        sc = _debye_case(*dims, npml, seed=12, nsteps=41, n_mats=3)
         g = fd.Grid.from_params(sc.params(), precision=32)
-        S.apply(sc, g)
-        g.set_kernel(v, y, z)
-        for c in (3, 20, 18):
+        ids = S.apply(sc, g)
+        for q, c in enumerate(chunks):
+            g.set_kernel(*((1 + (q % 2), 0, 0) if kern == "mixed" else kern))
             g.step(c)
-        outs.append([g.get_field(c) for c in range(6)])
-    for a, b in zip(*outs):
-        assert np.array_equal(a, b)
+        outs.append(([g.get_field(c) for c in range(6)], [g.probe(i) for i in ids]))
+    _say(f"debye variants {dims} npml={npml}")
+    for r in range(1, len(runs)):
+        for a, b in zip(outs[0][0], outs[r][0]):
+            assert np.array_equal(a, b), runs[r]
+        for a, b in zip(outs[0][1], outs[r][1]):
+            assert np.array_equal(a, b), runs[r]
 
 
 def test_config2_debye_small_probes(fd, oracle_mod):

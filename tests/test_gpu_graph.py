@@ -1,6 +1,6 @@
 """Graph replay of a single grid (fdtd_set_graph) against eager stepping,
-bit for bit: the split pass with Debye media, the two-step pass over CPML
-tile lists, and the fused pass with an oblique wire.  Each graph is replayed
+bit for bit: the fused and split passes with Debye media, the two-step
+pass over CPML tile lists, and the fused pass with an oblique wire.  Each graph is replayed
 several times, with eager steps, probe reads and field reads (which
 synchronise) between the replays, and every replay's probe samples and the
 final fields are compared with the eager run."""
@@ -23,10 +23,10 @@ def fd():
 
 
 def _case(kind):
-    if kind == "debye":
+    if kind in ("debye", "debye_split"):
         sc = S.random_case(31, 23, 19, 3, seed=12, nsteps=48)
         sc.debye = ([1e-9, 3e-8], np.random.default_rng(3).uniform(0, 6, size=(len(sc.materials), 2)))
-        return sc, 0
+        return sc, 2 if kind == "debye" else 1
     if kind == "tb2":
         return S.random_case(70, 29, 27, 4, seed=13, nsteps=48), 3
     sc = S.random_case(40, 24, 22, 4, seed=14, nsteps=48)
@@ -50,7 +50,7 @@ def _run(fd, sc, variant, graph, chunks):
     return seen, fields, wires
 
 
-@pytest.mark.parametrize("kind", ["debye", "tb2", "owire"])
+@pytest.mark.parametrize("kind", ["debye", "debye_split", "tb2", "owire"])
 def test_graph_replay_equals_eager(fd, kind):
     sc, variant = _case(kind)
     chunks = [3, G, G + 2, 1, G, 2 * G - 4, sc.n_steps - (3 + G + G + 2 + 1 + G + 2 * G - 4)]

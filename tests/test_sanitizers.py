@@ -29,10 +29,12 @@ def test_oracle_under_address_and_ub_sanitizers(tmp_path):
 
 
 def test_host_runtime_under_address_and_ub_sanitizers(tmp_path):
+    from paper_2207_06908_amd.csrc import build as hipbuild
     build = os.path.join(ROOT, "paper_2207_06908_amd", "_build")
-    objs = [os.path.join(build, f) for f in ("fdtd_kernels.hip.o", "fdtd_static.hip.o")]
+    # the FDTD kernel objects (device code as built; only the host side is
+    # instrumented)
+    objs = [os.path.join(build, f + ".o") for f in hipbuild.SOURCES if f.startswith("fdtd_") and f.endswith(".hip")]
     if not all(os.path.exists(o) for o in objs):
-        from paper_2207_06908_amd.csrc import build as hipbuild
         hipbuild.build()
     rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
     if not os.path.exists(os.path.join(rocm, "lib", "libamdhip64.so")):
