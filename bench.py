@@ -402,6 +402,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="batched leg: fixed 32x8 tiles, TZ 32")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-in-the-loop measurement")
     ap.add_argument("--no-debye", action="store_true", help="skip the Debye-soil, lumped-element, oblique-wire and array measurements")
+    ap.add_argument("--legs", default="debye,lumped,oblique,array",
+                    help="which of the Debye-soil, lumped-element, oblique-wire and array measurements to run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run plain copies of MIB MiB (profiler counter calibration)")
     a = ap.parse_args()
@@ -490,10 +492,11 @@ def main():
     if not a.no_batch:
         out["batched"] = bench_batch(tune=not a.no_tune)
     if not a.no_debye:
-        out["debye"] = bench_debye()
-        out["lumped"] = bench_lumped()
-        out["oblique"] = bench_oblique()
-        out["array"] = bench_array()
+        legs = a.legs.split(",")
+        for leg, fn in (("debye", bench_debye), ("lumped", bench_lumped), ("oblique", bench_oblique),
+                        ("array", bench_array)):
+            if leg in legs:
+                out[leg] = fn()
     if not a.no_surrogate:
         out["surrogate"] = bench_surrogate()
     if not a.no_cpu_baseline:
