@@ -658,30 +658,30 @@ hipError_t step_split(const GridView<T>& g, int step, hipStream_t st) {
 // Oblique thin wires: one block per wire.  New segment currents from E^n (the
 // input field set) and the charges q^n (the driven segment takes its sample),
 // then the charges from the new currents; both before the step's field pass,
-// which they do not depend on.  Each segment sums its gather terms in table
-// order.
+// which they do not depend on.  One wave per segment: lane l sums the gather
+// terms l, l + 64, ... in table order, then the 64 partial sums meet in a
+// fixed shuffle tree, so the result does not depend on scheduling.
+constexpr int OW_NT = 1024;
 template <typename T>
-__global__ void __launch_bounds__(256) k_owire_iq(GridView<T> g, OWireView w, int step) {
+__global__ void __launch_bounds__(OW_NT) k_owire_iq(GridView<T> g, OWireView w, int step) {
   step = gstep(g, step);
   const OWireParam p = w.par[blockIdx.x];
   double* cur = w.cur + p.seg0;
   double* q = w.q + p.seg0 + blockIdx.x;
-  for (int s = threadIdx.x; s < p.nseg; s += blockDim.x) {
-    double v;
-    if (s == p.src) {
-      v = w.amp[(size_t)blockIdx.x * w.max_steps + step];
-    } else {
-      double et = 0.0;
-      for (int e = w.seg_off[p.seg0 + s], e1 = w.seg_off[p.seg0 + s + 1]; e < e1; ++e) {
-        const long long key = w.g_key[e];
-        et += w.g_w[e] * (double)g.fi[(int)(key >> 40)][key & ((1ll << 40) - 1)];
-      }
-      v = cur[s] + p.dtL * (et - (q[s + 1] - q[s]) * p.invCdl);
+  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+  for (int s = wave; s < p.nseg; s += OW_NT / 64) {  // uniform per wave
+    double et = 0.0;
+    for (int e = w.seg_off[p.seg0 + s] + lane, e1 = w.seg_off[p.seg0 + s + 1]; e < e1; e += 64) {
+      const long long key = w.g_key[e];
+      et += w.g_w[e] * (double)g.fi[(int)(key >> 40)][key & ((1ll << 40) - 1)];
     }
-    cur[s] = v;
+    for (int off = 32; off > 0; off >>= 1) et += __shfl_down(et, off, 64);
+    if (lane == 0)
+      cur[s] = s == p.src ? w.amp[(size_t)blockIdx.x * w.max_steps + step]
+                          : cur[s] + p.dtL * (et - (q[s + 1] - q[s]) * p.invCdl);
   }
   __syncthreads();
-  for (int j = threadIdx.x; j <= p.nseg; j += blockDim.x) {
+  for (int j = threadIdx.x; j <= p.nseg; j += OW_NT) {
     const double il = j > 0 ? cur[j - 1] : 0.0, ir = j < p.nseg ? cur[j] : 0.0;
     q[j] -= ((j == 0 || j == p.nseg) ? 2.0 * p.dtdl : p.dtdl) * (ir - il);
   }
@@ -722,9 +722,9 @@ hipError_t step_split_debye(const GridView<T>& g, const DebyeView<T>& d, int ste
 int launch_owire_iq(int prec, const void* view, const OWireView* ow, int step, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (prec == 64)
-    hipLaunchKernelGGL((k_owire_iq<double>), dim3(ow->n_wire), dim3(256), 0, st, *(const GridView<double>*)view, *ow, step);
+    hipLaunchKernelGGL((k_owire_iq<double>), dim3(ow->n_wire), dim3(OW_NT), 0, st, *(const GridView<double>*)view, *ow, step);
   else
-    hipLaunchKernelGGL((k_owire_iq<float>), dim3(ow->n_wire), dim3(256), 0, st, *(const GridView<float>*)view, *ow, step);
+    hipLaunchKernelGGL((k_owire_iq<float>), dim3(ow->n_wire), dim3(OW_NT), 0, st, *(const GridView<float>*)view, *ow, step);
   return (int)hipGetLastError();
 }
 
