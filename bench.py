@@ -151,8 +151,9 @@ def bench_batch(warmup: int = 100, graph_steps: int = 100, tune: bool = True):
     bytes_step = b.algorithmic_bytes_per_step()
     achieved = bytes_step * steps / (ms / 1e3) / 1e9
     out = {"workload": f"{len(scs)} independent electrode grids, 32-96^3 (x grown to fit the electrode), "
-                       f"dx 0.25 m, 8-cell CPML, {steps} steps, one launch per step, HIP graph of "
-                       f"{graph_steps} steps",
+                       f"dx 0.25 m, 8-cell CPML, {steps} steps, HIP graph of {graph_steps} steps",
+           "kernel": ("k_tb2_batch_q: one persistent work-queue launch per two-step pass" if tile[0] == 60
+                      else "k_fused_batch: one launch per step"),
            "tile": list(tile),
            "cells": cells, "value": round(cells * steps / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
            "cases_per_s": round(len(scs) / (ms / 1e3), 2), "ms_per_step": round(ms / steps, 5),

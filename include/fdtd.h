@@ -293,9 +293,10 @@ void fdtd_destroy(fdtd_ctx* c);
 
 /* ---------------------------------------------------------------------------
  * Batched engine: many independent grids (e.g. a parameter sweep of small,
- * uneven electrode grids) stepped together, one kernel launch per step over
- * a tile list that spans every grid, optionally replayed from a captured
- * HIP graph.  Each grid's results are bit-identical to running it alone.
+ * uneven electrode grids) stepped together, one kernel launch per step (or
+ * one persistent launch per two-step pass) over a tile list that spans
+ * every grid, optionally replayed from a captured HIP graph.  Each grid's
+ * results are bit-identical to running it alone.
  * ------------------------------------------------------------------------- */
 typedef struct fdtd_batch fdtd_batch;
 
@@ -319,6 +320,13 @@ int fdtd_batch_bind_workspace(fdtd_batch* b, void* dev_ptr, size_t bytes);
  * single-step launch.  Results do not depend on the choice.
  * Default (32, 8, 32, 0).  Errors: EINVAL. */
 int fdtd_batch_set_kernel(fdtd_batch* b, int tile_x, int tile_y, int tile_z, int graph_steps);
+/* Two-step passes only: on = 1 (the default) runs each pass as one
+ * persistent launch whose blocks take tiles from a work queue (every CPML
+ * group in the one launch, each XCD starting on its own run of the tiles,
+ * grid by grid); on = 0 launches the CPML groups separately (the x-slab
+ * group on the second stream).  Results do not depend on the choice.
+ * Errors: EINVAL. */
+int fdtd_batch_set_persistent(fdtd_batch* b, int on);
 /* Advance every grid n_steps steps.  Errors: ESTATE, ERANGE (beyond the
  * smallest max_steps), EDEVICE. */
 int fdtd_batch_run(fdtd_batch* b, int n_steps);

@@ -21,6 +21,8 @@
 // contraction off, so they agree bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fdtd_dev.h"
 #include "fdtd_tile.h"
 #include "yee_update.h"
@@ -598,6 +600,53 @@ __global__ __launch_bounds__(64 * (TY + 4), (sizeof(T) == 8 ? 1 : 6)) void k_tb2
                                              *d_step + offset);
 }
 
+// Batched two-step pass as one persistent launch.  The tile list holds every
+// grid's tiles, grid by grid (larger grids first), each tagged with its CPML
+// group (grid | group << 24, i0 | iw << 16, j0 | jh << 16, k0 | kz << 16),
+// and is cut into 8 contiguous runs, one per XCD, so that a grid's tiles
+// share that XCD's L2.  A block takes tiles from its own XCD's run through
+// an atomic counter, then from the other runs in turn, and leaves once every
+// run is empty: each counter only grows, so every block finishes.  Tiles of
+// one pass write disjoint outputs and read only the pass's input set, so no
+// block waits for another.  The counters start at 0 (k_qreset before the
+// launch).
+template <typename T, typename CI>
+__global__ __launch_bounds__(768, (sizeof(T) == 8 ? 1 : 6)) void k_tb2_batch_q(const GridView<T>* __restrict__ views,
+                                                                             const int4* __restrict__ tiles,
+                                                                             QRuns runs, int* __restrict__ ctr,
+                                                                             const int* __restrict__ d_step,
+                                                                             int offset) {
+  __shared__ TB2Smem<T, 8> sm;
+  __shared__ int pick;
+  const int step = *d_step + offset;
+  const int x0 = (int)(blockIdx.x % 8);
+  for (int r = 0; r < 8; ++r) {
+    const int x = (x0 + r) % 8, base = runs.start[x], n = runs.start[x + 1] - base;
+    for (;;) {
+      __syncthreads();  // the previous tile is done with the LDS and with `pick`
+      if (threadIdx.x == 0) pick = atomicAdd(ctr + x, 1);
+      __syncthreads();
+      const int q = __builtin_amdgcn_readfirstlane(pick);  // uniform: the tile is read into scalar registers
+      if (q >= n) break;
+      const int4 t = tiles[base + q];
+      const GridView<T>& g = views[t.x & 0xffffff];
+      const int i0 = t.y & 0xffff, j0 = t.z & 0xffff, iw = t.y >> 16, jh = t.z >> 16;
+      const int k0 = t.w & 0xffff, k1 = k0 + (t.w >> 16), grp = t.x >> 24;
+      // two code paths (more spill at the 80-register cap): the x-slab one
+      // also serves tiles clear of the x and y slabs, the all-axes one the
+      // y-slab and corner tiles
+      if (sizeof(T) == 8 || (grp & 2))
+        tb2_tile<T, CI, true, 8, 7, false, true>(g, sm, i0, j0, iw, jh, k0, k1, step);
+      else
+        tb2_tile<T, CI, true, 8, 5, false, true>(g, sm, i0, j0, iw, jh, k0, k1, step);
+    }
+  }
+}
+
+__global__ void k_qreset(int* ctr) {
+  if (threadIdx.x < 8) ctr[threadIdx.x] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // probes of a one-step pass: one block per probe, the fixed FP64 order of
 // probe_block_sum
@@ -997,6 +1046,30 @@ int launch_batch_probes(int prec, const void* views, const void* plist, int n, c
   return (int)hipGetLastError();
 }
 
+// Probes of both steps of a batched two-step pass (one block per (grid,
+// probe) pair).
+int batch_probes_tb2(int prec, int cls16, const void* views, const void* plist, int n_probes, const int* d_step,
+                     int offset, hipStream_t st) {
+  if (n_probes <= 0) return 0;
+  const dim3 grd((unsigned)n_probes), blk(PR_NT);
+  if (prec == 64) {
+    if (cls16)
+      hipLaunchKernelGGL((k_probes_tb2_batch<double, uint16_t>), grd, blk, 0, st, (const GridView<double>*)views,
+                         (const int2*)plist, n_probes, d_step, offset);
+    else
+      hipLaunchKernelGGL((k_probes_tb2_batch<double, uint8_t>), grd, blk, 0, st, (const GridView<double>*)views,
+                         (const int2*)plist, n_probes, d_step, offset);
+  } else {
+    if (cls16)
+      hipLaunchKernelGGL((k_probes_tb2_batch<float, uint16_t>), grd, blk, 0, st, (const GridView<float>*)views,
+                         (const int2*)plist, n_probes, d_step, offset);
+    else
+      hipLaunchKernelGGL((k_probes_tb2_batch<float, uint8_t>), grd, blk, 0, st, (const GridView<float>*)views,
+                         (const int2*)plist, n_probes, d_step, offset);
+  }
+  return (int)hipGetLastError();
+}
+
 // Group q of the pass's tile list runs the instantiation for the slabs its
 // tiles reach (FP64: the all-axes one).
 template <typename T, typename CI>
@@ -1010,6 +1083,45 @@ hipError_t batch_group_t(int q, const void* views, const int4* t, int count, con
   if (q == 2) hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, D ? 7 : 6>), grd, blk, 0, st, v, t, d_step, offset);
   if (q == 3) hipLaunchKernelGGL((k_tb2_batch<T, CI, 8, 7>), grd, blk, 0, st, v, t, d_step, offset);
   return hipGetLastError();
+}
+
+template <typename T, typename CI>
+hipError_t batch_queue_t(const void* views, const int4* tiles, const QRuns& runs, int* ctr, int n_blocks,
+                         const int* d_step, int offset, hipStream_t st) {
+  hipLaunchKernelGGL(k_qreset, dim3(1), dim3(64), 0, st, ctr);
+  hipLaunchKernelGGL((k_tb2_batch_q<T, CI>), dim3((unsigned)n_blocks), dim3(768), 0, st, (const GridView<T>*)views,
+                     tiles, runs, ctr, d_step, offset);
+  return hipGetLastError();
+}
+
+template <typename T, typename CI>
+int queue_blocks_t() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tb2_batch_q<T, CI>, 768, 0) != hipSuccess) return 0;
+  return cus * std::max(per, 1);
+}
+
+int batch_queue_blocks(int prec, int cls16) {
+  if (prec == 64) return cls16 ? queue_blocks_t<double, uint16_t>() : queue_blocks_t<double, uint8_t>();
+  return cls16 ? queue_blocks_t<float, uint16_t>() : queue_blocks_t<float, uint8_t>();
+}
+
+int launch_batch_pass_queue(int prec, int cls16, const void* views, const void* tiles, const QRuns* runs, int* ctr,
+                            int n_blocks, const void* plist, int n_probes, const int* d_step, int offset,
+                            void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int4* t = (const int4*)tiles;
+  hipError_t e;
+  if (prec == 64)
+    e = cls16 ? batch_queue_t<double, uint16_t>(views, t, *runs, ctr, n_blocks, d_step, offset, st)
+              : batch_queue_t<double, uint8_t>(views, t, *runs, ctr, n_blocks, d_step, offset, st);
+  else
+    e = cls16 ? batch_queue_t<float, uint16_t>(views, t, *runs, ctr, n_blocks, d_step, offset, st)
+              : batch_queue_t<float, uint8_t>(views, t, *runs, ctr, n_blocks, d_step, offset, st);
+  if (e != hipSuccess) return (int)e;
+  return batch_probes_tb2(prec, cls16, views, plist, n_probes, d_step, offset, st);
 }
 
 int launch_batch_pass_tb2(int prec, int cls16, const void* views, const void* tiles, const int* counts,
@@ -1038,24 +1150,8 @@ int launch_batch_pass_tb2(int prec, int cls16, const void* views, const void* ti
     e = hipEventRecord((hipEvent_t)ev_join, st2);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, (hipEvent_t)ev_join, 0);
   }
-  if (e != hipSuccess || n_probes <= 0) return (int)e;
-  const dim3 grd((unsigned)n_probes), blk(PR_NT);
-  if (prec == 64) {
-    if (cls16)
-      hipLaunchKernelGGL((k_probes_tb2_batch<double, uint16_t>), grd, blk, 0, st, (const GridView<double>*)views,
-                         (const int2*)plist, n_probes, d_step, offset);
-    else
-      hipLaunchKernelGGL((k_probes_tb2_batch<double, uint8_t>), grd, blk, 0, st, (const GridView<double>*)views,
-                         (const int2*)plist, n_probes, d_step, offset);
-  } else {
-    if (cls16)
-      hipLaunchKernelGGL((k_probes_tb2_batch<float, uint16_t>), grd, blk, 0, st, (const GridView<float>*)views,
-                         (const int2*)plist, n_probes, d_step, offset);
-    else
-      hipLaunchKernelGGL((k_probes_tb2_batch<float, uint8_t>), grd, blk, 0, st, (const GridView<float>*)views,
-                         (const int2*)plist, n_probes, d_step, offset);
-  }
-  return (int)hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  return batch_probes_tb2(prec, cls16, views, plist, n_probes, d_step, offset, st);
 }
 
 __global__ void k_set(int* p, int v) {

@@ -73,6 +73,7 @@ SIGNATURES = [
     ("fdtd_batch_workspace_bytes", C.c_size_t, [_vp]),
     ("fdtd_batch_bind_workspace", C.c_int, [_vp, _vp, C.c_size_t]),
     ("fdtd_batch_set_kernel", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int]),
+    ("fdtd_batch_set_persistent", C.c_int, [_vp, C.c_int]),
     ("fdtd_batch_run", C.c_int, [_vp, C.c_int]),
     ("fdtd_batch_probe", C.c_int, [_vp, C.c_int, C.c_int, _vp, C.c_int, C.POINTER(C.c_int)]),
     ("fdtd_batch_timing", C.c_int, [_vp, C.c_int]),
@@ -322,7 +323,7 @@ class Batch:
     their tiles; optional HIP-graph replay).  Build each member with
     :class:`Grid` (set-up only, no stepping), then pack them here."""
 
-    def __init__(self, grids, device="cuda:0", stream=None, tile=(32, 8, 32), graph_steps=0):
+    def __init__(self, grids, device="cuda:0", stream=None, tile=(32, 8, 32), graph_steps=0, persistent=None):
         self.grids = list(grids)
         self.device = device
         arr = (C.c_void_p * len(self.grids))(*[g._h for g in self.grids])
@@ -334,6 +335,8 @@ class Batch:
         self._h = h
         self._ws = None
         self.set_kernel(*tile, graph_steps)
+        if persistent is not None:
+            self.set_persistent(persistent)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -350,6 +353,9 @@ class Batch:
 
     def set_kernel(self, tile_x=32, tile_y=8, tile_z=32, graph_steps=0):
         self._chk(lib().fdtd_batch_set_kernel(self._h, tile_x, tile_y, tile_z, graph_steps))
+
+    def set_persistent(self, on=True):
+        self._chk(lib().fdtd_batch_set_persistent(self._h, 1 if on else 0))
 
     def bind(self):
         if self._ws is not None:

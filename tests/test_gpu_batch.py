@@ -45,13 +45,13 @@ def _solo(fd, sc):
     return {p[0]: g.probe(i) for p, i in zip(sc.probes, ids)}, [g.get_field(c) for c in range(6)]
 
 
-def _batch(fd, scs, tile=(32, 8, 32), graph_steps=0, chunks=None, fields=True):
+def _batch(fd, scs, tile=(32, 8, 32), graph_steps=0, chunks=None, fields=True, persistent=None):
     grids, ids = [], []
     for sc in scs:
         g = fd.Grid.from_params(sc.params())
         ids.append(S.apply(sc, g))
         grids.append(g)
-    b = fd.Batch(grids, tile=tile, graph_steps=graph_steps)
+    b = fd.Batch(grids, tile=tile, graph_steps=graph_steps, persistent=persistent)
     for n in (chunks or [scs[0].n_steps]):
         b.run(n)
         import torch
@@ -63,11 +63,14 @@ def _batch(fd, scs, tile=(32, 8, 32), graph_steps=0, chunks=None, fields=True):
     return probes, fields
 
 
-@pytest.mark.parametrize("tile", [(32, 8, 32), (32, 16, 16), (64, 8, 64), (60, 8, 32), (60, 8, 16)])
-def test_batch_bitwise_equals_solo(fd, tile):
+@pytest.mark.parametrize("tile,persistent", [((32, 8, 32), None), ((32, 16, 16), None), ((64, 8, 64), None),
+                                             ((60, 8, 32), True), ((60, 8, 32), False), ((60, 8, 16), True)])
+def test_batch_bitwise_equals_solo(fd, tile, persistent):
+    """Two-step passes as one persistent work-queue launch and as one launch
+    per CPML group give the same bits as the solo runs."""
     scs = _small_sweep()
-    _say(f"batch vs solo tile={tile}: " + ", ".join(f"{s.nx}x{s.ny}x{s.nz}" for s in scs))
-    bp, bf = _batch(fd, scs, tile=tile)
+    _say(f"batch vs solo tile={tile} persistent={persistent}: " + ", ".join(f"{s.nx}x{s.ny}x{s.nz}" for s in scs))
+    bp, bf = _batch(fd, scs, tile=tile, persistent=persistent)
     for gi, sc in enumerate(scs):
         sp, sf = _solo(fd, sc)
         for k in sp:
@@ -76,19 +79,41 @@ def test_batch_bitwise_equals_solo(fd, tile):
             assert np.array_equal(bf[gi][c], sf[c]), (gi, c)
 
 
-@pytest.mark.parametrize("tile", [(32, 8, 32), (60, 8, 32)])
-def test_batch_graph_replay_matches_eager(fd, tile):
+@pytest.mark.parametrize("tile,persistent", [((32, 8, 32), None), ((60, 8, 32), True), ((60, 8, 32), False)])
+def test_batch_graph_replay_matches_eager(fd, tile, persistent):
     """(60, 8, ...) selects the two-step passes: odd chunks end with one fused
-    step, graphs hold whole passes."""
+    step, graphs hold whole passes (with the persistent launch, its counter
+    reset kernel too)."""
     scs = _small_sweep(n=5, steps=250)
     ep, ef = _batch(fd, scs)
     # 250 = 3 eager + 4 x 60 graph + 7 eager, in pieces with eager work between
-    gp, gf = _batch(fd, scs, tile=tile, graph_steps=20, chunks=[3, 60, 60, 1, 60, 59, 7])
+    gp, gf = _batch(fd, scs, tile=tile, graph_steps=20, chunks=[3, 60, 60, 1, 60, 59, 7], persistent=persistent)
     for gi in range(len(scs)):
         for k in ep[gi]:
             assert np.array_equal(ep[gi][k], gp[gi][k]), (gi, k)
         for c in range(6):
             assert np.array_equal(ef[gi][c], gf[gi][c]), (gi, c)
+
+
+def test_persistent_pass_with_every_tile_group(fd):
+    """Larger grids in one batch give tiles in all four CPML groups (clear of
+    the x and y slabs, x slabs, y slabs, corners), which the persistent
+    launch serves with two code paths: bit for bit the solo runs and the
+    per-group launches."""
+    scs = [S.random_case(150, 70, 40, 6, seed=21, nsteps=25, n_mats=3),
+           S.random_case(190, 45, 33, 3, seed=22, nsteps=25, n_mats=3),
+           S.random_case(77, 21, 15, 4, seed=23, nsteps=25, n_mats=3)]
+    _say("persistent pass, every tile group")
+    qp, qf = _batch(fd, scs, tile=(60, 8, 16), persistent=True)
+    gp, gf = _batch(fd, scs, tile=(60, 8, 16), persistent=False)
+    for gi, sc in enumerate(scs):
+        sp, sf = _solo(fd, sc)
+        for k in sp:
+            assert np.array_equal(qp[gi][k], sp[k]), (gi, k)
+            assert np.array_equal(gp[gi][k], sp[k]), (gi, k)
+        for c in range(6):
+            assert np.array_equal(qf[gi][c], sf[c]), (gi, c)
+            assert np.array_equal(gf[gi][c], sf[c]), (gi, c)
 
 
 @pytest.mark.parametrize("tile", [(32, 8, 16), (60, 8, 32)])
