@@ -136,12 +136,14 @@ def bench_batch(warmup: int = 100, graph_steps: int = 100, tune: bool = True):
         S.apply(sc, g)
         grids.append(g)
     tile = (32, 8, 32)
+    persistent = True
     b = fdtd.Batch(grids, tile=tile, graph_steps=graph_steps)
     if tune:
         b.bind()
         c = autotune.tune_batch(b, autotune.batch_key([(s.nx, s.ny, s.nz) for s in scs], scs[0].npml))
         tile = (c["tile_x"], c["tile_y"], c["tile_z"])
-        b.set_kernel(*tile, graph_steps)
+        autotune.apply_batch(b, c, graph_steps)
+        persistent = c.get("persistent", True)
     b.run(warmup)
     torch.cuda.synchronize()
     b.timing(True)
@@ -152,7 +154,8 @@ def bench_batch(warmup: int = 100, graph_steps: int = 100, tune: bool = True):
     achieved = bytes_step * steps / (ms / 1e3) / 1e9
     out = {"workload": f"{len(scs)} independent electrode grids, 32-96^3 (x grown to fit the electrode), "
                        f"dx 0.25 m, 8-cell CPML, {steps} steps, HIP graph of {graph_steps} steps",
-           "kernel": ("k_tb2_batch_q: one persistent work-queue launch per two-step pass" if tile[0] == 60
+           "kernel": (("k_tb2_batch_q: one persistent work-queue launch per two-step pass" if persistent
+                       else "k_tb2_batch: one launch per CPML group and two-step pass") if tile[0] == 60
                       else "k_fused_batch: one launch per step"),
            "tile": list(tile),
            "cells": cells, "value": round(cells * steps / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",

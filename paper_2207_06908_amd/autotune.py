@@ -18,14 +18,21 @@ from typing import Iterable, List, Sequence, Tuple
 
 from . import fdtd
 
+# (variant, TY, TZ): the split pass; fused tiles 64 x TY; two-step tiles
+# 60 x TY in 64 x (TY + 4) regions.
 GRID_CANDIDATES: List[Tuple[int, int, int]] = (
     [(fdtd.KERNEL_SPLIT, 0, 0)]
-    + [(fdtd.KERNEL_FUSED, ty, tz) for ty in (4, 8) for tz in (16, 32, 64)]
-    + [(fdtd.KERNEL_TB2, 8, tz) for tz in (18, 20, 22, 28)] + [(fdtd.KERNEL_TB2, 12, 24)]
+    + [(fdtd.KERNEL_FUSED, ty, tz) for ty in (4, 8) for tz in (16, 24, 32, 48, 64)]
+    + [(fdtd.KERNEL_TB2, 8, tz) for tz in (16, 18, 20, 22, 24, 28, 32, 40)]
+    + [(fdtd.KERNEL_TB2, 4, tz) for tz in (16, 20, 28)]
+    + [(fdtd.KERNEL_TB2, 12, tz) for tz in (16, 20, 24)]
 )
-BATCH_CANDIDATES: List[Tuple[int, int, int]] = (
-    [(tx, ty, tz) for (tx, ty) in ((32, 8), (32, 16), (64, 8)) for tz in (16, 32, 64)]
-    + [(60, 8, tz) for tz in (16, 32, 64)])
+# (TX, TY, TZ, persistent): one-step batch tiles, then two-step 60 x 8
+# tiles launched per CPML group (0) or as one persistent launch (1).
+BATCH_CANDIDATES: List[Tuple[int, int, int, int]] = (
+    [(tx, ty, tz, 0) for (tx, ty) in ((32, 8), (32, 16), (64, 8)) for tz in (16, 32, 64)]
+    + [(60, 8, tz, p) for tz in (16, 20, 24, 32, 48, 64) for p in (1, 0)]
+    + [(60, 8, tz, 1) for tz in (96, 128)])
 
 
 def tuning_steps(batch: bool = False, warmup: int = 4, steps: int = None) -> int:
@@ -115,30 +122,38 @@ def apply_grid(g: "fdtd.Grid", choice: dict) -> None:
     g.set_kernel(choice["variant"], choice["tile_y"], choice["tile_z"])
 
 
+def apply_batch(b: "fdtd.Batch", choice: dict, graph_steps: int = 0) -> None:
+    b.set_kernel(choice["tile_x"], choice["tile_y"], choice["tile_z"], graph_steps)
+    if choice["tile_x"] == 60:
+        b.set_persistent(choice.get("persistent", True))
+
+
 def tune_batch(make_batch, key: str, candidates: Iterable = None, warmup: int = 4, steps: int = 20,
                path: str = None, force: bool = False, log=None) -> dict:
     """make_batch(max_steps) -> an fdtd.Batch, or a Batch with room for
     tuning_steps() more steps.  Returns the best {tile_x, tile_y, tile_z,
-    ms_per_step}."""
+    persistent, ms_per_step} (apply it with apply_batch)."""
     cache = load_cache(path)
     if key in cache and not force:
         return cache[key]
     cands = list(candidates or BATCH_CANDIDATES)
     b = make_batch if isinstance(make_batch, fdtd.Batch) else make_batch(len(cands) * (warmup + steps) + 4)
     results = []
-    for tx, ty, tz in cands:
+    for tx, ty, tz, per in cands:
         b.set_kernel(tx, ty, tz, 0)
+        if tx == 60:
+            b.set_persistent(bool(per))
         b.run(warmup)
         b.timing(True)
         b.time()
         b.run(steps)
         ms, n = b.time()
         b.timing(False)
-        results.append((ms / max(n, 1), (tx, ty, tz)))
+        results.append((ms / max(n, 1), (tx, ty, tz, per)))
         if log:
-            log(f"tune {key}: tile {tx}x{ty} TZ {tz}: {ms / max(n, 1):.4f} ms/step")
+            log(f"tune {key}: tile {tx}x{ty} TZ {tz} persistent {per}: {ms / max(n, 1):.4f} ms/step")
     ms, best = min(results)
-    value = {"tile_x": best[0], "tile_y": best[1], "tile_z": best[2], "ms_per_step": ms,
-             "candidates": len(cands)}
+    value = {"tile_x": best[0], "tile_y": best[1], "tile_z": best[2], "persistent": bool(best[3]),
+             "ms_per_step": ms, "candidates": len(cands)}
     store(key, value, path)
     return value

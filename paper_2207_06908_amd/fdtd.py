@@ -393,7 +393,7 @@ class Batch:
         return lib().fdtd_batch_algorithmic_bytes_per_step(self._h)
 
 
-def run_batch(scenarios, apply_fn, precision=32, tile=(32, 8, 32), graph_steps=0):
+def run_batch(scenarios, apply_fn, precision=32, tile=(32, 8, 32), graph_steps=0, persistent=None):
     """Run scenarios (equal step counts) as one batch; returns a list of
     {probe name: waveform} dicts."""
     grids, ids = [], []
@@ -401,7 +401,7 @@ def run_batch(scenarios, apply_fn, precision=32, tile=(32, 8, 32), graph_steps=0
         g = Grid.from_params(sc.params(), precision=precision)
         ids.append(apply_fn(sc, g))
         grids.append(g)
-    b = Batch(grids, tile=tile, graph_steps=graph_steps)
+    b = Batch(grids, tile=tile, graph_steps=graph_steps, persistent=persistent)
     b.run(scenarios[0].n_steps)
     out = [{p[0]: b.probe(gi, i) for p, i in zip(sc.probes, gid)}
            for gi, (sc, gid) in enumerate(zip(scenarios, ids))]

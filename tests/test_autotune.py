@@ -79,9 +79,9 @@ def test_tuned_grid_and_batch_match_defaults(tmp_path):
 
     kb = T.batch_key([(s.nx, s.ny, s.nz) for s in scs], 8)
     cb = T.tune_batch(make_b, kb, path=p, steps=4, warmup=2)
-    assert (cb["tile_x"], cb["tile_y"], cb["tile_z"]) in T.BATCH_CANDIDATES
+    assert (cb["tile_x"], cb["tile_y"], cb["tile_z"], int(cb["persistent"])) in T.BATCH_CANDIDATES
     a = fdtd.run_batch(scs, S.apply)
-    b = fdtd.run_batch(scs, S.apply, tile=(cb["tile_x"], cb["tile_y"], cb["tile_z"]))
+    b = fdtd.run_batch(scs, S.apply, tile=(cb["tile_x"], cb["tile_y"], cb["tile_z"]), persistent=cb["persistent"])
     for x, y in zip(a, b):
         for name in x:
             assert np.array_equal(x[name], y[name])
