@@ -246,7 +246,8 @@ def bench_lumped(steps: int = 1000, warmup: int = 20):
 
 def bench_oblique(steps: int = 400, warmup: int = 20):
     """The 512 x 512 x 384 scene with a slanted 37-segment conductor: the
-    wire's current/charge kernel, the fused one-step pass, the injection."""
+    two-step pass, with the wire's current, charge and source-amplitude
+    kernels beside it."""
     import torch
     from paper_2207_06908_amd import fdtd
     from paper_2207_06908_amd import scenarios as S
@@ -264,7 +265,8 @@ def bench_oblique(steps: int = 400, warmup: int = 20):
     ms = e0.elapsed_time(e1)
     out = {"workload": "512x512x384 Yee FDTD as above plus a slanted 5 cm conductor (20 x 12 x 30 cells, "
                        "37 segments), driven at its base",
-           "kernel": "k_owire_iq, k_fused_list (CPML groups on two streams), k_owire_inject",
+           "kernel": "k_tb2_list (two-step pass over CPML groups; the wire's edges are sources whose amplitudes "
+                     "k_owire_cur/k_owire_q/k_owire_amp/k_owire_e1 write on a third stream)",
            "steps": steps, "value": round(sc.cells * steps / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
            "ms_per_step": round(ms / steps, 5)}
     del g

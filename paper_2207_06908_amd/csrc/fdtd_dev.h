@@ -46,12 +46,17 @@ struct GridView {
   const void* cls;               // class id per node (uint8 or uint16)
   const T* ctab;                 // [ncls][K_STRIDE]
   const T* prof[3];              // per axis [P_NROW][2*npml]
-  // sources: E[src_comp][src_idx] -= src_amp[s * max_steps + n] after the update
+  // sources: E[src_comp][src_idx] -= src_amp[s * max_steps + n] after the
+  // update; the list is grouped by column (x + nx*y), a node's own sources in
+  // the order they were added, and src_first[column] is the first source of
+  // a column (-1: none)
   int n_src;
   int max_steps;
   const int* src_comp;
   const long long* src_idx;
   const T* src_amp;
+  const int* src_first;          // [nx * ny]
+  const int* src_kr;             // [nx * ny]: planes of a column's sources, kmin | kmax << 16
   // probes: value p = sum over terms t in [pr_off[p], pr_off[p+1]) of
   // term_w[t] * field[term_comp[t]][term_idx[t]]
   int n_probe;
@@ -89,12 +94,13 @@ struct DebyeView {
 
 namespace mi355fdtd {
 
-// Oblique thin wires, for the split pass.  Wire w has nseg segments
-// starting at seg0 in the segment arrays and nseg + 1 end-point charges
-// starting at seg0 + w.  Segment s samples and feeds E through 24 entries
-// e = s * 24 + a * 8 + corner (a the E component): node index idx[e], sample
-// weight ws[e] = t_a * (trilinear weight) and injection weight
-// wj[e] = ws[e] * dl / dx^2, so that E_a[idx] -= (Cb / dx) * I_s * wj.
+// Oblique thin wires.  Wire w has nseg segments starting at seg0 in the
+// segment arrays and nseg + 1 end-point charges starting at seg0 + w.  A
+// segment samples E through its gather terms (the charge-conserving edge
+// weights of its displacement) and feeds the same edges back: every edge a
+// wire touches is a source of the grid (row wsrc[e] of the source list)
+// whose amplitude, (Cb / dx) sum_t j_w I_seg, the wire kernels write for each
+// step before the field pass applies it.
 struct OWireParam {
   int seg0, nseg, src, rec;   // first segment, count, driven and recorded segment (-1: none)
   double dtL;                 // dt / L'
@@ -103,7 +109,7 @@ struct OWireParam {
   double pad;
 };
 struct OWireView {
-  int n_wire, max_steps, n_edge, pad;
+  int n_wire, max_steps, n_edge, max_seg;  // max_seg: segments of the longest wire
   const OWireParam* par;
   const int* seg_off;         // [total segments + 1]: gather terms of each segment
   const long long* g_key;     // E component << 40 | node index of a gather term
@@ -116,6 +122,9 @@ struct OWireView {
   double* cur;                // segment currents (A)
   double* q;                  // end-point charges per unit length (C/m)
   double* rec;                // [n_wire][max_steps] recorded segment current
+  const int* wsrc;            // [n_edge] source-list row of each touched edge
+  const int* g_edge;          // per gather term: its edge's index in e_key
+  double* e1;                 // [n_edge] E^{n+1} at the touched edges (two-step passes)
 };
 
 // Kernel launchers (fdtd_kernels.hip).  `view` points to a GridView<float>
@@ -128,11 +137,16 @@ int launch_step(int prec, const void* view, int cls16, int variant, int step, in
                 void* stream);
 // Split step (H then E, in place) of a grid with Debye poles: `dview` is a
 // DebyeView<float> or DebyeView<double>.
-// Oblique wires around one one-step field pass (split or fused): the wire
-// currents and charges from the input E before it, the wires' currents onto
-// the output E after it (n_seg segments over all wires).
-int launch_owire_iq(int prec, const void* view, const OWireView* ow, int step, void* stream);
-int launch_owire_inject(int prec, const void* view, int cls16, const OWireView* ow, void* stream);
+// Oblique wires, before the field pass.  launch_owire_iq: the segment
+// currents of step `step` from the input E (from_e1 = 0) or from the edge
+// values of launch_owire_e1 (from_e1 = 1), then the charges; the record.
+// launch_owire_amp: the touched edges' source amplitudes of step `step` from
+// the current segment currents.  launch_owire_e1: E^{step+1} at the touched
+// edges, recomputed from the input set (its sources of `step` included),
+// for the second step of a two-step pass.
+int launch_owire_iq(int prec, const void* view, const OWireView* ow, int step, int from_e1, void* stream);
+int launch_owire_amp(int prec, const void* view, int cls16, const OWireView* ow, int step, void* stream);
+int launch_owire_e1(int prec, const void* view, int cls16, const OWireView* ow, int step, void* stream);
 int launch_step_debye(int prec, const void* view, const void* dview, int cls16, int step, void* stream);
 // Fused one-step pass (reads one field set, writes the other) of a grid with
 // Debye poles (fdtd_debye.hip): over the 4-group tile list `tiles` / counts
@@ -150,10 +164,13 @@ int launch_fused_debye(int prec, const void* view, const void* dview, int cls16,
 //   variant 3: (i0 | iw << 16, j0 | jh << 16, k0, k1) with iw <= 60,
 //              jh <= tile_y.
 // Group 0 runs on `stream`, groups 1-3 on `stream2` (the caller orders the
-// two streams around the call; they write disjoint tiles).  Variant 3 also
-// records the probes of `step` on `stream2`.
+// two streams around the call; they write disjoint tiles).  counts[4] tiles
+// after group 3 (fused: 32 x tile_y) read an oblique wire's source
+// amplitudes: they run last on `stream2`, after it waits for the event
+// `ev_src` (nullptr: no wait) that follows the wire kernels.  Variant 3 also
+// records the probes of `step` on `stream2`, after that wait.
 int launch_lists_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, const void* tiles,
-                      const int* counts, void* stream, void* stream2);
+                      const int* counts, void* stream, void* stream2, void* ev_src);
 // Record the probes of step `step` from the view's output set.
 int launch_probes(int prec, const void* view, int step, void* stream);
 

@@ -78,6 +78,8 @@ struct fdtd_ctx {
   std::vector<long long> ow_gkey, ow_ekey;
   std::vector<double> ow_gw, ow_jw, ow_amp;
   int ow_seg = 0;
+  std::vector<int> ow_wsrc, ow_gedge;  // source-list row of each touched edge; edge of each gather term
+  size_t off_ow_wsrc = 0, off_ow_gedge = 0, off_ow_e1 = 0;
   size_t off_ow_par = 0, off_ow_segoff = 0, off_ow_gkey = 0, off_ow_gw = 0, off_ow_ekey = 0, off_ow_eoff = 0,
          off_ow_jseg = 0, off_ow_jw = 0, off_ow_amp = 0, off_ow_cur = 0, off_ow_q = 0, off_ow_rec = 0;
   OWireView ow_view{};
@@ -94,6 +96,9 @@ struct fdtd_ctx {
   std::vector<int> src_comp;
   std::vector<long long> src_idx;
   std::vector<double> src_amp;        // [n_src][max_steps], Cb I / dx^2
+  std::vector<int> src_first;         // [nx * ny] first source of each column, -1 if none
+  std::vector<int> src_kr;            // [nx * ny] planes of a column's sources, kmin | kmax << 16
+  size_t off_src_first = 0, off_src_kr = 0;
   std::vector<int> pr_off, term_comp;
   std::vector<long long> term_idx;
   std::vector<double> term_w;
@@ -107,11 +112,15 @@ struct fdtd_ctx {
   // interior tiles first, then the CPML tiles; rebuilt when TY or TZ change
   size_t off_tiles = 0, max_tiles = 0;
   std::vector<int> tl;
-  int tl_cnt[4] = {0, 0, 0, 0}, tl_var = -1, tl_ty = -1, tl_kz = -1;
+  int tl_cnt[5] = {0, 0, 0, 0, 0}, tl_var = -1, tl_ty = -1, tl_kz = -1;
   // the CPML tile groups run on a second stream, concurrently with the
   // clear tiles: fork and join events around each pass
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // third stream for the oblique-wire kernels of a pass over tile lists;
+  // ev_src marks their end for the tiles that read their amplitudes
+  hipStream_t aux2 = nullptr;
+  hipEvent_t ev_src = nullptr;
 
   // bound state
   char* ws = nullptr;
@@ -642,6 +651,54 @@ void build_owires(fdtd_ctx* c) {
     c->ow_jw.push_back(inj[e].w);
   }
   c->ow_eoff.push_back((int)inj.size());
+  c->ow_gedge.clear();  // e_key is sorted, so each gather term finds its edge by bisection
+  for (long long key : c->ow_gkey)
+    c->ow_gedge.push_back((int)(std::lower_bound(c->ow_ekey.begin(), c->ow_ekey.end(), key) - c->ow_ekey.begin()));
+}
+
+// The wires' touched edges join the source list after the ideal sources
+// (their amplitudes, zero here, are written on the device each step).  The
+// list is then grouped by column (stable, so a node keeps its sources in
+// the order they were added, the wires' last), and each column records its
+// first source.
+void group_sources(fdtd_ctx* c) {
+  const size_t ms = (size_t)c->P.max_steps, nreg = c->src_comp.size(), ne = c->ow_ekey.size();
+  const long long sxy = (long long)c->N[0] * c->N[1];
+  for (long long key : c->ow_ekey) {
+    c->src_comp.push_back((int)(key >> 40));
+    c->src_idx.push_back(key & ((1ll << 40) - 1));
+  }
+  c->src_amp.resize((nreg + ne) * ms, 0.0);
+  const size_t n = c->src_comp.size();
+  std::vector<int> ord(n);
+  for (size_t s = 0; s < n; ++s) ord[s] = (int)s;
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int a, int b) { return c->src_idx[a] % sxy < c->src_idx[b] % sxy; });
+  std::vector<int> comp(n);
+  std::vector<long long> idx(n);
+  std::vector<double> amp(n * ms);
+  c->ow_wsrc.assign(ne, 0);
+  for (size_t s = 0; s < n; ++s) {
+    const int o = ord[s];
+    comp[s] = c->src_comp[o];
+    idx[s] = c->src_idx[o];
+    std::copy(c->src_amp.begin() + (size_t)o * ms, c->src_amp.begin() + (size_t)(o + 1) * ms,
+              amp.begin() + s * ms);
+    if ((size_t)o >= nreg) c->ow_wsrc[o - nreg] = (int)s;
+  }
+  c->src_comp.swap(comp);
+  c->src_idx.swap(idx);
+  c->src_amp.swap(amp);
+  c->src_first.assign((size_t)sxy, -1);
+  c->src_kr.assign((size_t)sxy, 0);
+  for (size_t s = n; s-- > 0;) c->src_first[(size_t)(c->src_idx[s] % sxy)] = (int)s;
+  for (size_t s = 0; s < n; ++s) {  // planes below 65536 (a larger grid keeps the full range)
+    const size_t col = (size_t)(c->src_idx[s] % sxy);
+    const int k = (int)std::min<long long>(c->src_idx[s] / sxy, 0xffff);
+    const int lo = c->src_first[col] == (int)s ? k : std::min(k, c->src_kr[col] & 0xffff);
+    const int hi = c->src_first[col] == (int)s ? k : std::max(k, c->src_kr[col] >> 16);
+    c->src_kr[col] = lo | (c->N[2] > 0xffff ? 0xffff : hi) << 16;
+  }
 }
 
 void layout(fdtd_ctx* c) {
@@ -670,9 +727,11 @@ void layout(fdtd_ctx* c) {
   c->off_dtab = take(c->npole ? (size_t)c->ncls * D_STRIDE * ts : 0);
   c->off_dflag = take(c->npole ? (size_t)c->ncls : 0);
   c->off_prof = take(3 * (size_t)P_NROW * 2 * np * ts);
-  c->off_src_comp = take(c->srcs.size() * sizeof(int));
-  c->off_src_idx = take(c->srcs.size() * sizeof(long long));
+  c->off_src_comp = take(c->src_comp.size() * sizeof(int));
+  c->off_src_idx = take(c->src_idx.size() * sizeof(long long));
   c->off_amp = take(c->src_amp.size() * ts);
+  c->off_src_first = take(c->src_first.size() * sizeof(int));
+  c->off_src_kr = take(c->src_kr.size() * sizeof(int));
   c->off_pr_off = take(c->pr_off.size() * sizeof(int));
   c->off_term_comp = take(c->term_comp.size() * sizeof(int));
   c->off_term_idx = take(c->term_idx.size() * sizeof(long long));
@@ -687,13 +746,16 @@ void layout(fdtd_ctx* c) {
   c->off_ow_jseg = take(c->ow_jseg.size() * sizeof(int));
   c->off_ow_jw = take(c->ow_jw.size() * sizeof(double));
   c->off_ow_amp = take(c->ow_amp.size() * sizeof(double));
+  c->off_ow_wsrc = take(c->ow_wsrc.size() * sizeof(int));
+  c->off_ow_gedge = take(c->ow_gedge.size() * sizeof(int));
+  c->off_ow_e1 = take(c->ow_ekey.size() * sizeof(double));
   c->off_ow_cur = take((size_t)c->ow_seg * sizeof(double));
   c->off_ow_q = take((size_t)(c->ow_seg + c->owr.size()) * sizeof(double));
   c->off_ow_rec = take(c->owr.size() * (size_t)c->P.max_steps * sizeof(double));
   c->off_dstep = take(sizeof(int));
   c->max_tiles = 0;
-  if (np > 0) {  // bound for 32-wide, 4-high tiles and chunks of >= 8 planes
-    c->max_tiles = (size_t)(c->N[0] / 32 + 6) * (c->N[1] / 4 + 6) * (c->N[2] / 8 + 6);
+  if (np > 0) {  // bound for 32-wide, 4-high tiles and chunks of >= 4 planes
+    c->max_tiles = (size_t)(c->N[0] / 32 + 6) * (c->N[1] / 4 + 6) * (c->N[2] / 4 + 6);
     c->off_tiles = take(c->max_tiles * 4 * sizeof(int));
   }
   // the kernels address every array with 32-bit byte offsets
@@ -738,11 +800,13 @@ void fill_view(fdtd_ctx* c, GridView<T>& g, int in, int out) {
   g.cls = w + c->off_cls;
   g.ctab = (const T*)(w + c->off_ctab);
   for (int u = 0; u < 3; ++u) g.prof[u] = (const T*)(w + c->off_prof) + (size_t)u * P_NROW * 2 * np;
-  g.n_src = (int)c->srcs.size();
+  g.n_src = (int)c->src_comp.size();
   g.max_steps = c->P.max_steps;
   g.src_comp = (const int*)(w + c->off_src_comp);
   g.src_idx = (const long long*)(w + c->off_src_idx);
   g.src_amp = (const T*)(w + c->off_amp);
+  g.src_first = (const int*)(w + c->off_src_first);
+  g.src_kr = (const int*)(w + c->off_src_kr);
   g.n_probe = (int)c->probes.size();
   g.pr_off = (const int*)(w + c->off_pr_off);
   g.term_comp = (const int*)(w + c->off_term_comp);
@@ -789,6 +853,8 @@ int upload(fdtd_ctx* c) {
       {(void*)g.src_comp, c->src_comp.data(), c->src_comp.size() * sizeof(int)},
       {(void*)g.src_idx, c->src_idx.data(), c->src_idx.size() * sizeof(long long)},
       {(void*)g.src_amp, amp.data(), amp.size() * sizeof(T)},
+      {(void*)g.src_first, c->src_first.data(), c->src_first.size() * sizeof(int)},
+      {(void*)g.src_kr, c->src_kr.data(), c->src_kr.size() * sizeof(int)},
       {(void*)g.pr_off, c->pr_off.data(), c->pr_off.size() * sizeof(int)},
       {(void*)g.term_comp, c->term_comp.data(), c->term_comp.size() * sizeof(int)},
       {(void*)g.term_idx, c->term_idx.data(), c->term_idx.size() * sizeof(long long)},
@@ -824,6 +890,8 @@ int upload(fdtd_ctx* c) {
     w.n_wire = (int)c->owr.size();
     w.max_steps = c->P.max_steps;
     w.n_edge = (int)c->ow_ekey.size();
+    w.max_seg = 0;
+    for (const OWireParam& q : c->ow_par) w.max_seg = std::max(w.max_seg, q.nseg);
     w.par = (const OWireParam*)(c->ws + c->off_ow_par);
     w.seg_off = (const int*)(c->ws + c->off_ow_segoff);
     w.g_key = (const long long*)(c->ws + c->off_ow_gkey);
@@ -836,6 +904,9 @@ int upload(fdtd_ctx* c) {
     w.cur = (double*)(c->ws + c->off_ow_cur);
     w.q = (double*)(c->ws + c->off_ow_q);
     w.rec = (double*)(c->ws + c->off_ow_rec);
+    w.wsrc = (const int*)(c->ws + c->off_ow_wsrc);
+    w.g_edge = (const int*)(c->ws + c->off_ow_gedge);
+    w.e1 = (double*)(c->ws + c->off_ow_e1);
     const Up wups[] = {
         {(void*)w.par, c->ow_par.data(), c->ow_par.size() * sizeof(OWireParam)},
         {(void*)w.seg_off, c->ow_seg_off.data(), c->ow_seg_off.size() * sizeof(int)},
@@ -846,6 +917,8 @@ int upload(fdtd_ctx* c) {
         {(void*)w.j_seg, c->ow_jseg.data(), c->ow_jseg.size() * sizeof(int)},
         {(void*)w.j_w, c->ow_jw.data(), c->ow_jw.size() * sizeof(double)},
         {(void*)w.amp, c->ow_amp.data(), c->ow_amp.size() * sizeof(double)},
+        {(void*)w.wsrc, c->ow_wsrc.data(), c->ow_wsrc.size() * sizeof(int)},
+        {(void*)w.g_edge, c->ow_gedge.data(), c->ow_gedge.size() * sizeof(int)},
     };
     for (const Up& u : wups) {
       e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, st);
@@ -868,6 +941,7 @@ int freeze(fdtd_ctx* c) {
   build_cpml(c);
   build_sources_probes(c);
   build_owires(c);
+  group_sources(c);
   layout(c);
   if (c->ws_bytes == 0) return fail(c, FDTD_EINVAL, "a CPML state array or the source table exceeds 4 GiB");
   c->frozen = true;
@@ -1194,16 +1268,55 @@ int ensure_tiles(fdtd_ctx* c, int variant, int ty, int kz) {
             grp[q].insert(grp[q].end(), {x.a, y.a, z.a, z.b});
           }
         }
-  size_t nt = 0;
+  // Group 4: the tiles whose region (halo and pipeline planes included) holds
+  // an oblique wire's source edge.  They read the source amplitudes that the
+  // wire kernels write before the pass, so they run after those kernels on
+  // the second stream (with the all-axes instantiation; fused tiles 32 wide),
+  // while the other tiles start at once.
+  std::vector<int> grp4;
+  if (!c->ow_ekey.empty()) {
+    const long long nxl = c->N[0], sxy = nxl * c->N[1];
+    std::vector<std::array<int, 3>> pts;
+    for (long long key : c->ow_ekey) {
+      const long long n = key & ((1ll << 40) - 1);
+      pts.push_back({(int)(n % nxl), (int)((n / nxl) % c->N[1]), (int)(n / sxy)});
+    }
+    for (int q = 0; q < 4; ++q) {
+      std::vector<int> keep;
+      const int tw = tb2 ? 0 : (q & 1) ? 32 : 64;
+      for (size_t t = 0; t < grp[q].size(); t += 4) {
+        const int* v = &grp[q][t];
+        const int x0 = v[0] & 0xffff, y0 = v[1] & (tb2 ? 0xffff : ~0);
+        const int w = tb2 ? v[0] >> 16 : tw, h = tb2 ? v[1] >> 16 : ty;
+        bool hit = false;
+        for (const auto& p : pts)
+          hit = hit || (p[0] >= x0 - 2 && p[0] < x0 + w + 2 && p[1] >= y0 - 2 && p[1] < y0 + h + 2 &&
+                        p[2] >= v[2] - 2 && p[2] < v[3] + 2);
+        if (!hit) {
+          keep.insert(keep.end(), v, v + 4);
+          continue;
+        }
+        // their per-plane source scans make these tiles slow: chunks of 4
+        // planes spread them over more blocks (fused tiles 32 wide)
+        for (int z = v[2]; z < v[3]; z += 4)
+          for (int xx = 0; xx < (tw == 64 ? 2 : 1); ++xx)
+            grp4.insert(grp4.end(), {v[0] + 32 * xx, v[1], z, std::min(z + 4, v[3])});
+      }
+      grp[q].swap(keep);
+    }
+  }
+  size_t nt = grp4.size() / 4;
   for (int q = 0; q < 4; ++q) nt += grp[q].size() / 4;
   if (nt > c->max_tiles) return fail(c, FDTD_EINVAL, "tile list larger than its reservation");
   hipError_t e = hipStreamSynchronize(c->stream);  // a previous upload may still read c->tl
   if (e != hipSuccess) return hip_fail(c, e, "tile list");
   c->tl.clear();
+  c->tl_cnt[4] = (int)(grp4.size() / 4);
   for (int q = 0; q < 4; ++q) {
     c->tl.insert(c->tl.end(), grp[q].begin(), grp[q].end());
     c->tl_cnt[q] = (int)(grp[q].size() / 4);
   }
+  c->tl.insert(c->tl.end(), grp4.begin(), grp4.end());
   e = hipMemcpyAsync(c->ws + c->off_tiles, c->tl.data(), c->tl.size() * sizeof(int), hipMemcpyHostToDevice,
                      c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "tile list upload");
@@ -1227,9 +1340,27 @@ int launch_pass(fdtd_ctx* c, hipStream_t st, int variant, bool lists, int lty, i
   const void* view = d64 ? (const void*)&v64 : (const void*)&v32;
   const void* pview = d64 ? (const void*)&p64 : (const void*)&p32;
   int e;
-  if (!c->owr.empty()) {
-    e = launch_owire_iq(c->P.precision, view, &c->ow_view, step, (void*)st);
-    if (e) return fail(c, FDTD_EDEVICE, std::string("oblique-wire launch: ") + hipGetErrorString((hipError_t)e));
+  // Oblique wires: the currents of the pass's (first) step from its input E
+  // and their source amplitudes; for a two-step pass also E^{n+1} at the
+  // touched edges, the currents of the second step from it, and their
+  // amplitudes.  Over tile lists they run on the second stream, ahead of
+  // the tiles that read the amplitudes (group 4), beside the others.
+  auto wires = [&](hipStream_t ws) -> int {
+    const int p = c->P.precision, c16 = c->cls16;
+    const OWireView* w = &c->ow_view;
+    int r = launch_owire_iq(p, view, w, step, 0, (void*)ws);
+    if (!r) r = launch_owire_amp(p, view, c16, w, step, (void*)ws);
+    if (!r && variant == FDTD_KERNEL_TB2) {
+      r = launch_owire_e1(p, view, c16, w, step, (void*)ws);
+      if (!r) r = launch_owire_iq(p, view, w, step + 1, 1, (void*)ws);
+      if (!r) r = launch_owire_amp(p, view, c16, w, step + 1, (void*)ws);
+    }
+    if (r) return fail(c, FDTD_EDEVICE, std::string("oblique-wire launch: ") + hipGetErrorString((hipError_t)r));
+    return FDTD_OK;
+  };
+  if (!c->owr.empty() && !lists) {
+    int rc = wires(st);
+    if (rc) return rc;
   }
   DebyeView<float> d32 = c->d32;
   DebyeView<double> d64v = c->d64;
@@ -1238,12 +1369,21 @@ int launch_pass(fdtd_ctx* c, hipStream_t st, int variant, bool lists, int lty, i
     hipError_t he = hipEventRecord(c->ev_fork, st);
     if (he == hipSuccess) he = hipStreamWaitEvent(c->aux, c->ev_fork, 0);
     if (he != hipSuccess) return hip_fail(c, he, "stream fork");
+    if (!c->owr.empty()) {
+      he = hipStreamWaitEvent(c->aux2, c->ev_fork, 0);
+      if (he != hipSuccess) return hip_fail(c, he, "stream fork");
+      int rc = wires(c->aux2);
+      if (rc) return rc;
+      he = hipEventRecord(c->ev_src, c->aux2);
+      if (he != hipSuccess) return hip_fail(c, he, "wire event");
+    }
+    void* ev_src = c->owr.empty() ? nullptr : (void*)c->ev_src;
     if (c->npole)
       e = launch_fused_debye(c->P.precision, view, dview, c->cls16, step, c->tile_z, c->ws + c->off_tiles,
                              c->tl_cnt, (void*)st, (void*)c->aux);
     else
       e = launch_lists_step(c->P.precision, view, c->cls16, variant, step, lty, c->ws + c->off_tiles, c->tl_cnt,
-                            (void*)st, (void*)c->aux);
+                            (void*)st, (void*)c->aux, ev_src);
     if (!e) {
       he = hipEventRecord(c->ev_join, c->aux);
       if (he == hipSuccess) he = hipStreamWaitEvent(st, c->ev_join, 0);
@@ -1258,10 +1398,6 @@ int launch_pass(fdtd_ctx* c, hipStream_t st, int variant, bool lists, int lty, i
     e = launch_step(c->P.precision, view, c->cls16, variant, step, c->tile_y, c->tile_z, (void*)st);
   }
   if (e) return fail(c, FDTD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString((hipError_t)e));
-  if (!c->owr.empty()) {
-    e = launch_owire_inject(c->P.precision, view, c->cls16, &c->ow_view, (void*)st);
-    if (e) return fail(c, FDTD_EDEVICE, std::string("oblique-wire launch: ") + hipGetErrorString((hipError_t)e));
-  }
   if (slot >= 0) {  // the timed span ends with the update kernels
     hipError_t he = hipEventRecord(c->ev1[slot], st);
     if (he != hipSuccess) return hip_fail(c, he, "hipEventRecord");
@@ -1339,8 +1475,6 @@ int fdtd_step(fdtd_ctx* c, int n) {
   // 512 x 512 x 384 cells and slower on every smaller grid measured (its
   // CPML slab groups dominate there).
   if (c->npole) chosen = c->variant == FDTD_KERNEL_FUSED ? FDTD_KERNEL_FUSED : FDTD_KERNEL_SPLIT;
-  // oblique wires sample E^n and feed E^{n+1}: one-step passes only
-  if (!c->owr.empty() && chosen == FDTD_KERNEL_TB2) chosen = FDTD_KERNEL_FUSED;
   const int lty = c->npole ? 8 : c->tile_y == 4 ? 4 : (c->tile_y == 12 && chosen == FDTD_KERNEL_TB2) ? 12 : 8;
   const int G = c->graph_steps;
   const long long key = ((long long)chosen * 16 + lty) * 65536 + c->tile_z;
@@ -1366,6 +1500,8 @@ int fdtd_step(fdtd_ctx* c, int n) {
         hipError_t he = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
         if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
         if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+        if (he == hipSuccess && !c->owr.empty()) he = hipStreamCreateWithFlags(&c->aux2, hipStreamNonBlocking);
+        if (he == hipSuccess && !c->owr.empty()) he = hipEventCreateWithFlags(&c->ev_src, hipEventDisableTiming);
         if (he != hipSuccess) return hip_fail(c, he, "second stream");
       }
     }
@@ -2032,6 +2168,9 @@ void fdtd_destroy(fdtd_ctx* c) {
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->aux) (void)hipStreamDestroy(c->aux);
+  if (c->aux2) (void)hipStreamSynchronize(c->aux2);
+  if (c->ev_src) (void)hipEventDestroy(c->ev_src);
+  if (c->aux2) (void)hipStreamDestroy(c->aux2);
   for (int q = 0; q < fdtd_ctx::kRing; ++q) {
     if (c->ev0[q]) (void)hipEventDestroy(c->ev0[q]);
     if (c->ev1[q]) (void)hipEventDestroy(c->ev1[q]);

@@ -74,7 +74,8 @@ __global__ __launch_bounds__(256) void k_e_split(GridView<T> g, int step) {
   const T hz_j = (j > 0) ? ldg(g.fi[5], n - (unsigned)g.nx) : T(0);
   const T eold[3] = {ldg(g.fi[0], n), ldg(g.fi[1], n), ldg(g.fi[2], n)};
   T e[3];
-  e_point<T, PML>(g, i, j, k, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, e);
+  e_point<T, PML>(g, i, j, k, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, e,
+                  src_node(g, i, j, k));
   stg(g.fo[0], n, e[0]);
   stg(g.fo[1], n, e[1]);
   stg(g.fo[2], n, e[2]);
@@ -102,7 +103,8 @@ __global__ __launch_bounds__(256) void k_e_split_debye(GridView<T> g, DebyeView<
   const T hz_j = (j > 0) ? ldg(g.fi[5], n - (unsigned)g.nx) : T(0);
   const T eold[3] = {ldg(g.fi[0], n), ldg(g.fi[1], n), ldg(g.fi[2], n)};
   T e[3];
-  e_point<T, PML>(g, i, j, k, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, e);
+  e_point<T, PML>(g, i, j, k, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, e,
+                  src_node(g, i, j, k));
   debye_point(d, cid, n, eold, e);
   stg(g.fo[0], n, e[0]);
   stg(g.fo[1], n, e[1]);
@@ -224,7 +226,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
   const int lx = PML && (AX & 1) && dom ? slab_pos(x, nx, g.npml) : -1;
   const int ly = PML && (AX & 2) && dom ? slab_pos(y, ny, g.npml) : -1;
   constexpr bool PZ = PML && (AX & 4);
-  const bool srcc = src_column(g, n0, inB);
+  const int srcc = src_column(g, n0, inB), srckr = src_range(g, n0, srcc);
   if (PML) {
     const int tn = 2 * g.npml;
     if ((AX & 1) && v == 0) {
@@ -369,7 +371,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
         if (PML) psi_load(g, 0, l, x, y, k, psen);
         e_core_pf<T, PML>(pf, g, l, n0 + sxy * (unsigned)k, coef(cc), h1c[0], h1c[1], h1c[2], sm.sh1[0][v - 1][u],
                        h1p[0], sm.sh1[1][v][u - 1], h1p[1], sm.sh1[2][v][u - 1], sm.sh1[2][v - 1][u], e0c, step,
-                       psen, e1c, srcc);
+                       psen, e1c, src_at(srcc, srckr, k));
       };
       if (lz >= 0) {
         const int l[3] = {lx, ly, lz};
@@ -413,7 +415,8 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
     if (pend) {
       int l[3] = {lx, ly, PZ ? slab_pos(km, nz, g.npml) : -1};
       e_core_pf<T, PML>(pf, g, l, nst, coef(cp), h2c[0], h2c[1], h2c[2], sm.sh2[0][v - 1][u], h2p[0], sm.sh2[1][v][u - 1],
-                     h2p[1], sm.sh2[2][v][u - 1], sm.sh2[2][v - 1][u], e1p, step + 1, pse, e2, srcc);
+                     h2p[1], sm.sh2[2][v][u - 1], sm.sh2[2][v - 1][u], e1p, step + 1, pse, e2,
+                     src_at(srcc, srckr, km));
       if (!DEFER) {
         stg(g.fo[0], nst, e2[0]);
         stg(g.fo[1], nst, e2[1]);
@@ -514,7 +517,8 @@ __device__ __forceinline__ void e1_at(const GridView<T>& g, int x, int y, int k,
     slabs(g, x, y, k, l);
     psi_load(g, 0, l, x, y, k, ps);
   }
-  e_core<T, PML>(g, l, n, cf, h[0], h[1], h[2], hj[0], hk[0], hi[1], hk[1], hi[2], hj[2], eold, step, ps, e, true);
+  e_core<T, PML>(g, l, n, cf, h[0], h[1], h[2], hj[0], hk[0], hi[1], hk[1], hi[2], hj[2], eold, step, ps, e,
+                 src_node(g, x, y, k));
 }
 
 // Probes: one block of PR_NT threads per probe.  Thread `tid` sums terms
@@ -704,45 +708,58 @@ hipError_t step_split(const GridView<T>& g, int step, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Oblique thin wires: one block per wire.  New segment currents from E^n (the
-// input field set) and the charges q^n (the driven segment takes its sample),
-// then the charges from the new currents; both before the step's field pass,
-// which they do not depend on.  One wave per segment: lane l sums the gather
-// terms l, l + 64, ... in table order, then the 64 partial sums meet in a
-// fixed shuffle tree, so the result does not depend on scheduling.
-constexpr int OW_NT = 1024;
-template <typename T>
-__global__ void __launch_bounds__(OW_NT) k_owire_iq(GridView<T> g, OWireView w, int step) {
+// Oblique thin wires.  k_owire_cur: the new segment currents from E^n (the
+// input field set, or with E1 the values of k_owire_e1) and the charges q^n
+// (the driven segment takes its sample); k_owire_q: then the charges from
+// the new currents, and the record.  Both before the step's field pass,
+// which they do not depend on.  One one-wave block per segment (block
+// (s, wire)): lane l sums the gather terms l, l + 64, ... in table order,
+// then the 64 partial sums meet in a fixed shuffle tree, so the result does
+// not depend on scheduling.  The blocks are single waves so that they find
+// room on CUs that the field pass's blocks keep busy.
+template <typename T, bool E1>
+__global__ void __launch_bounds__(64) k_owire_cur(GridView<T> g, OWireView w, int step) {
   step = gstep(g, step);
-  const OWireParam p = w.par[blockIdx.x];
+  const OWireParam p = w.par[blockIdx.y];
+  const int s = (int)blockIdx.x;
+  if (s >= p.nseg) return;  // uniform per block
   double* cur = w.cur + p.seg0;
-  double* q = w.q + p.seg0 + blockIdx.x;
-  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
-  for (int s = wave; s < p.nseg; s += OW_NT / 64) {  // uniform per wave
-    double et = 0.0;
-    for (int e = w.seg_off[p.seg0 + s] + lane, e1 = w.seg_off[p.seg0 + s + 1]; e < e1; e += 64) {
+  const double* q = w.q + p.seg0 + blockIdx.y;
+  const int lane = (int)threadIdx.x;
+  double et = 0.0;
+  for (int e = w.seg_off[p.seg0 + s] + lane, e1 = w.seg_off[p.seg0 + s + 1]; e < e1; e += 64) {
+    if (E1) {
+      et += w.g_w[e] * w.e1[w.g_edge[e]];
+    } else {
       const long long key = w.g_key[e];
       et += w.g_w[e] * (double)g.fi[(int)(key >> 40)][key & ((1ll << 40) - 1)];
     }
-    for (int off = 32; off > 0; off >>= 1) et += __shfl_down(et, off, 64);
-    if (lane == 0)
-      cur[s] = s == p.src ? w.amp[(size_t)blockIdx.x * w.max_steps + step]
-                          : cur[s] + p.dtL * (et - (q[s + 1] - q[s]) * p.invCdl);
   }
-  __syncthreads();
-  for (int j = threadIdx.x; j <= p.nseg; j += OW_NT) {
+  for (int off = 32; off > 0; off >>= 1) et += __shfl_down(et, off, 64);
+  if (lane == 0)
+    cur[s] = s == p.src ? w.amp[(size_t)blockIdx.y * w.max_steps + step]
+                        : cur[s] + p.dtL * (et - (q[s + 1] - q[s]) * p.invCdl);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_owire_q(GridView<T> g, OWireView w, int step) {
+  step = gstep(g, step);
+  const OWireParam p = w.par[blockIdx.y];
+  const double* cur = w.cur + p.seg0;
+  double* q = w.q + p.seg0 + blockIdx.y;
+  const int j = (int)(blockIdx.x * 64 + threadIdx.x);
+  if (j <= p.nseg) {
     const double il = j > 0 ? cur[j - 1] : 0.0, ir = j < p.nseg ? cur[j] : 0.0;
     q[j] -= ((j == 0 || j == p.nseg) ? 2.0 * p.dtdl : p.dtdl) * (ir - il);
   }
-  if (threadIdx.x == 0 && p.rec >= 0) w.rec[(size_t)blockIdx.x * w.max_steps + step] = cur[p.rec];
+  if (j == 0 && p.rec >= 0) w.rec[(size_t)blockIdx.y * w.max_steps + step] = cur[p.rec];
 }
 
-// The wires' currents onto the output E after the step's field pass (its
-// lumped sources included): one thread per touched E edge sums its terms in
-// increasing segment order and updates the edge once, so the result does
-// not depend on scheduling.
+// The touched edges' source amplitudes of step `step`: one thread per edge
+// sums its terms in increasing segment order (FP64), times the edge's Cb / dx.
 template <typename T, typename CI>
-__global__ void __launch_bounds__(256) k_owire_inject(GridView<T> g, OWireView w) {
+__global__ void __launch_bounds__(64) k_owire_amp(GridView<T> g, OWireView w, int step) {
+  step = gstep(g, step);
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= w.n_edge) return;
   const long long key = w.e_key[e];
@@ -752,7 +769,25 @@ __global__ void __launch_bounds__(256) k_owire_inject(GridView<T> g, OWireView w
   for (int t = w.e_off[e], t1 = w.e_off[e + 1]; t < t1; ++t) sum += w.j_w[t] * w.cur[w.j_seg[t]];
   const int cls = ((const CI*)g.cls)[n];
   const double cbdx = (double)g.ctab[cls * K_STRIDE + K_CBX + 2 * a];
-  g.fo[a][n] = (T)((double)g.fo[a][n] - cbdx * sum);
+  T* amp = const_cast<T*>(g.src_amp);
+  amp[(size_t)w.wsrc[e] * (size_t)g.max_steps + (size_t)step] = (T)(cbdx * sum);
+}
+
+// E^{step+1} at the touched edges for a two-step pass: the step's update
+// at the edge's node, recomputed from the input set as the pass will do it
+// (its sources, the wires' included, and CPML).
+template <typename T, typename CI, bool PML>
+__global__ void __launch_bounds__(64) k_owire_e1(GridView<T> g, OWireView w, int step) {
+  step = gstep(g, step);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= w.n_edge) return;
+  const long long key = w.e_key[e];
+  const int a = (int)(key >> 40);
+  const long long n = key & ((1ll << 40) - 1);
+  const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), k = (int)(n / g.sxy);
+  T v[3];
+  e1_at<T, CI, PML>(g, x, y, k, step, v);
+  w.e1[e] = (double)v[a];
 }
 
 template <typename T, typename CI>
@@ -768,28 +803,55 @@ hipError_t step_split_debye(const GridView<T>& g, const DebyeView<T>& d, int ste
   return hipGetLastError();
 }
 
-int launch_owire_iq(int prec, const void* view, const OWireView* ow, int step, void* stream) {
+int launch_owire_iq(int prec, const void* view, const OWireView* ow, int step, int from_e1, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  if (prec == 64)
-    hipLaunchKernelGGL((k_owire_iq<double>), dim3(ow->n_wire), dim3(OW_NT), 0, st, *(const GridView<double>*)view, *ow, step);
-  else
-    hipLaunchKernelGGL((k_owire_iq<float>), dim3(ow->n_wire), dim3(OW_NT), 0, st, *(const GridView<float>*)view, *ow, step);
+  const dim3 gc((unsigned)ow->max_seg, (unsigned)ow->n_wire), gq((unsigned)(ow->max_seg / 64 + 1), (unsigned)ow->n_wire);
+  if (prec == 64) {
+    const GridView<double>& g = *(const GridView<double>*)view;
+    if (from_e1) hipLaunchKernelGGL((k_owire_cur<double, true>), gc, dim3(64), 0, st, g, *ow, step);
+    else hipLaunchKernelGGL((k_owire_cur<double, false>), gc, dim3(64), 0, st, g, *ow, step);
+    hipLaunchKernelGGL((k_owire_q<double>), gq, dim3(64), 0, st, g, *ow, step);
+  } else {
+    const GridView<float>& g = *(const GridView<float>*)view;
+    if (from_e1) hipLaunchKernelGGL((k_owire_cur<float, true>), gc, dim3(64), 0, st, g, *ow, step);
+    else hipLaunchKernelGGL((k_owire_cur<float, false>), gc, dim3(64), 0, st, g, *ow, step);
+    hipLaunchKernelGGL((k_owire_q<float>), gq, dim3(64), 0, st, g, *ow, step);
+  }
   return (int)hipGetLastError();
 }
 
-int launch_owire_inject(int prec, const void* view, int cls16, const OWireView* ow, void* stream) {
-  hipStream_t st = (hipStream_t)stream;
-  const dim3 grd((unsigned)((ow->n_edge + 255) / 256)), blk(256);
-  if (prec == 64) {
-    const GridView<double>& g = *(const GridView<double>*)view;
-    if (cls16) hipLaunchKernelGGL((k_owire_inject<double, uint16_t>), grd, blk, 0, st, g, *ow);
-    else hipLaunchKernelGGL((k_owire_inject<double, uint8_t>), grd, blk, 0, st, g, *ow);
+template <typename T>
+hipError_t owire_amp_t(const GridView<T>& g, int cls16, const OWireView& w, int step, hipStream_t st) {
+  const dim3 grd((unsigned)((w.n_edge + 63) / 64)), blk(64);
+  if (cls16) hipLaunchKernelGGL((k_owire_amp<T, uint16_t>), grd, blk, 0, st, g, w, step);
+  else hipLaunchKernelGGL((k_owire_amp<T, uint8_t>), grd, blk, 0, st, g, w, step);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t owire_e1_t(const GridView<T>& g, int cls16, const OWireView& w, int step, hipStream_t st) {
+  const dim3 grd((unsigned)((w.n_edge + 63) / 64)), blk(64);
+  const bool pml = g.npml > 0;
+  if (cls16) {
+    if (pml) hipLaunchKernelGGL((k_owire_e1<T, uint16_t, true>), grd, blk, 0, st, g, w, step);
+    else hipLaunchKernelGGL((k_owire_e1<T, uint16_t, false>), grd, blk, 0, st, g, w, step);
   } else {
-    const GridView<float>& g = *(const GridView<float>*)view;
-    if (cls16) hipLaunchKernelGGL((k_owire_inject<float, uint16_t>), grd, blk, 0, st, g, *ow);
-    else hipLaunchKernelGGL((k_owire_inject<float, uint8_t>), grd, blk, 0, st, g, *ow);
+    if (pml) hipLaunchKernelGGL((k_owire_e1<T, uint8_t, true>), grd, blk, 0, st, g, w, step);
+    else hipLaunchKernelGGL((k_owire_e1<T, uint8_t, false>), grd, blk, 0, st, g, w, step);
   }
-  return (int)hipGetLastError();
+  return hipGetLastError();
+}
+
+int launch_owire_amp(int prec, const void* view, int cls16, const OWireView* ow, int step, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == 64) return (int)owire_amp_t(*(const GridView<double>*)view, cls16, *ow, step, st);
+  return (int)owire_amp_t(*(const GridView<float>*)view, cls16, *ow, step, st);
+}
+
+int launch_owire_e1(int prec, const void* view, int cls16, const OWireView* ow, int step, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == 64) return (int)owire_e1_t(*(const GridView<double>*)view, cls16, *ow, step, st);
+  return (int)owire_e1_t(*(const GridView<float>*)view, cls16, *ow, step, st);
 }
 
 int launch_step_debye(int prec, const void* view, const void* dview, int cls16, int step, void* stream) {
@@ -833,7 +895,7 @@ hipError_t step_fused(const GridView<T>& g, int step, int tile_y, int tile_z, hi
 // precision) keeps the all-axes instantiation for every group.
 template <typename T, typename CI, int TY>
 hipError_t launch_lists(const GridView<T>& g, int step, const int4* tiles, const int* counts, hipStream_t st,
-                        hipStream_t st2) {
+                        hipStream_t st2, void* ev_src) {
   if (sizeof(CI) == 1 && g.ncls > 256) return hipErrorInvalidValue;
   constexpr bool D = sizeof(T) == 8;
   const int4* t = tiles;
@@ -852,12 +914,20 @@ hipError_t launch_lists(const GridView<T>& g, int step, const int4* tiles, const
   if (counts[3] > 0)
     hipLaunchKernelGGL((k_fused_list<T, CI, true, 32, TY, 7>), dim3((unsigned)counts[3]), dim3(32 * TY), 0, st2, g, t,
                        step);
+  t += counts[3];
+  if (ev_src) {
+    const hipError_t we = hipStreamWaitEvent(st2, (hipEvent_t)ev_src, 0);
+    if (we != hipSuccess) return we;
+  }
+  if (counts[4] > 0)  // tiles that read an oblique wire's source amplitudes, once written
+    hipLaunchKernelGGL((k_fused_list<T, CI, true, 32, TY, 7>), dim3((unsigned)counts[4]), dim3(32 * TY), 0, st2, g, t,
+                       step);
   return hipGetLastError();
 }
 
 template <typename T, typename CI, int TY>
 hipError_t launch_lists_tb2(const GridView<T>& g, int step, const int4* tiles, const int* counts, hipStream_t st,
-                            hipStream_t st2) {
+                            hipStream_t st2, void* ev_src) {
   if (sizeof(CI) == 1 && g.ncls > 256) return hipErrorInvalidValue;
   constexpr bool D = sizeof(T) == 8;
   const dim3 blk(64 * (TY + 4));
@@ -875,6 +945,15 @@ hipError_t launch_lists_tb2(const GridView<T>& g, int step, const int4* tiles, c
     hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 5>), dim3((unsigned)counts[1]), blk, 0, st2, g, t1, step);
   if (counts[2] > 0)
     hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 6>), dim3((unsigned)counts[2]), blk, 0, st2, g, t2, step);
+  // tiles that read an oblique wire's source amplitudes, once the wire
+  // kernels (on a third stream) have written them
+  if (ev_src) {
+    const hipError_t we = hipStreamWaitEvent(st2, (hipEvent_t)ev_src, 0);
+    if (we != hipSuccess) return we;
+  }
+  if (counts[4] > 0)
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, 7>), dim3((unsigned)counts[4]), blk, 0, st2, g, t3 + counts[3],
+                       step);
   // The probes' first sample, recomputed from the input set (which no group
   // writes), runs on the second stream beside the clear tiles; the caller
   // reads the second sample after the join (launch_probes2 with first = 0).
@@ -886,22 +965,22 @@ hipError_t launch_lists_tb2(const GridView<T>& g, int step, const int4* tiles, c
 
 template <typename T>
 hipError_t lists_any(const GridView<T>& g, int cls16, int variant, int step, int ty, const int4* tiles,
-                     const int* counts, hipStream_t st, hipStream_t st2) {
+                     const int* counts, hipStream_t st, hipStream_t st2, void* ev) {
   if (variant == 3) {
     if (ty == 4)
-      return cls16 ? launch_lists_tb2<T, uint16_t, 4>(g, step, tiles, counts, st, st2)
-                   : launch_lists_tb2<T, uint8_t, 4>(g, step, tiles, counts, st, st2);
+      return cls16 ? launch_lists_tb2<T, uint16_t, 4>(g, step, tiles, counts, st, st2, ev)
+                   : launch_lists_tb2<T, uint8_t, 4>(g, step, tiles, counts, st, st2, ev);
     if (ty == 12)
-      return cls16 ? launch_lists_tb2<T, uint16_t, 12>(g, step, tiles, counts, st, st2)
-                   : launch_lists_tb2<T, uint8_t, 12>(g, step, tiles, counts, st, st2);
-    return cls16 ? launch_lists_tb2<T, uint16_t, 8>(g, step, tiles, counts, st, st2)
-                 : launch_lists_tb2<T, uint8_t, 8>(g, step, tiles, counts, st, st2);
+      return cls16 ? launch_lists_tb2<T, uint16_t, 12>(g, step, tiles, counts, st, st2, ev)
+                   : launch_lists_tb2<T, uint8_t, 12>(g, step, tiles, counts, st, st2, ev);
+    return cls16 ? launch_lists_tb2<T, uint16_t, 8>(g, step, tiles, counts, st, st2, ev)
+                 : launch_lists_tb2<T, uint8_t, 8>(g, step, tiles, counts, st, st2, ev);
   }
   if (ty == 4)
-    return cls16 ? launch_lists<T, uint16_t, 4>(g, step, tiles, counts, st, st2)
-                 : launch_lists<T, uint8_t, 4>(g, step, tiles, counts, st, st2);
-  return cls16 ? launch_lists<T, uint16_t, 8>(g, step, tiles, counts, st, st2)
-               : launch_lists<T, uint8_t, 8>(g, step, tiles, counts, st, st2);
+    return cls16 ? launch_lists<T, uint16_t, 4>(g, step, tiles, counts, st, st2, ev)
+                 : launch_lists<T, uint8_t, 4>(g, step, tiles, counts, st, st2, ev);
+  return cls16 ? launch_lists<T, uint16_t, 8>(g, step, tiles, counts, st, st2, ev)
+               : launch_lists<T, uint8_t, 8>(g, step, tiles, counts, st, st2, ev);
 }
 
 template <typename T, typename CI, bool PML, int TY>
@@ -938,14 +1017,14 @@ hipError_t step_any(const GridView<T>& g, int cls16, int variant, int step, int 
 }
 
 int launch_lists_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, const void* tiles,
-                      const int* counts, void* stream, void* stream2) {
+                      const int* counts, void* stream, void* stream2, void* ev_src) {
   hipStream_t st = (hipStream_t)stream, st2 = (hipStream_t)stream2;
   const int4* t = (const int4*)tiles;
   const int ty = tile_y == 4 ? 4 : (tile_y == 12 && variant == 3) ? 12 : 8;
   hipError_t e = prec == 64 ? lists_any<double>(*(const GridView<double>*)view, cls16, variant, step, ty, t, counts,
-                                                st, st2)
+                                                st, st2, ev_src)
                             : lists_any<float>(*(const GridView<float>*)view, cls16, variant, step, ty, t, counts,
-                                               st, st2);
+                                               st, st2, ev_src);
   return (int)e;
 }
 

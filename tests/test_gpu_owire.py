@@ -21,11 +21,11 @@ def fd():
     return fdtd
 
 
-def _owire_case(nx, ny, nz, npml, seed, nsteps=60):
+def _owire_case(nx, ny, nz, npml, seed, nsteps=60, n_mats=6):
     """The random case (random media, axis wires, sources, probes) plus a
     driven skew wire, a second undriven skew wire that is recorded, and a
     wire along z on Ez samples."""
-    sc = S.random_case(nx, ny, nz, npml, seed=seed, nsteps=nsteps)
+    sc = S.random_case(nx, ny, nz, npml, seed=seed, nsteps=nsteps, n_mats=n_mats)
     amps = S.gaussian(nsteps, sc.dt, 12 * sc.dt, 4 * sc.dt, 3.0)
     lo = npml + 1.0
     hx, hy, hz = nx - npml - 2.0, ny - npml - 2.0, nz - npml - 2.0
@@ -35,7 +35,7 @@ def _owire_case(nx, ny, nz, npml, seed, nsteps=60):
     return sc
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])   # auto, split, fused; the two-step pass gives way to fused
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])   # auto, split, fused, two-step
 @pytest.mark.parametrize("dims,npml", [((40, 24, 22), 4), ((21, 19, 17), 0)])
 def test_owire_fields_and_wire_state_elementwise(fd, oracle_mod, variant, dims, npml):
     sc = _owire_case(*dims, npml, seed=dims[0] + 11)
@@ -130,6 +130,33 @@ def test_owire_edge_cases_elementwise(fd, oracle_mod, dims, npml):
                 scale = max(float(np.abs(ref).max()), 1e-300)
                 assert float(np.abs(got - ref).max()) / scale <= tol, (prec, w)
         assert g.oblique_wire(2)[0][2] == 0.0       # driven by an empty waveform
+
+
+@pytest.mark.parametrize("dims,npml", [((77, 21, 15), 4), ((150, 70, 40), 6), ((41, 19, 17), 0)])
+def test_owire_variants_bitwise_equal(fd, dims, npml):
+    """The wires enter every pass as sources whose amplitudes the wire
+    kernels write before it (for a two-step pass, those of its second step
+    from E^{n+1} recomputed at the touched edges), so every variant and tile
+    shape gives the bits of the split pass, also in odd step chunks (a
+    two-step run then ends with a fused step) and over every CPML tile group
+    (the 150 x 70 x 40 grid)."""
+    sc = _owire_case(*dims, npml, seed=dims[0] + 3, nsteps=41, n_mats=3)
+    runs = [(1, 0, 0, [41]), (2, 8, 32, [41]), (2, 4, 7, [20, 21]), (3, 8, 20, [41]), (3, 12, 16, [5, 36]),
+            (3, 4, 8, [2, 39]), (0, 0, 0, [41])]
+    print(f"owire variants {dims} npml={npml}", flush=True)
+    outs = []
+    for variant, ty, kz, chunks in runs:
+        g = fd.Grid.from_params(sc.params(), precision=32)
+        ids = S.apply(sc, g)
+        g.set_kernel(variant, ty, kz)
+        for c in chunks:
+            g.step(c)
+        outs.append([g.get_field(c) for c in range(6)] + [g.probe(i) for i in ids]
+                    + [x for w in range(3) for x in g.oblique_wire(w)])
+    assert np.abs(outs[0][0]).max() > 0
+    for r in range(1, len(runs)):
+        for a, b in zip(outs[0], outs[r]):
+            assert np.array_equal(a, b), runs[r]
 
 
 def test_owire_runs_are_bitwise_reproducible(fd):
