@@ -48,8 +48,8 @@ struct GridView {
   const T* prof[3];              // per axis [P_NROW][2*npml]
   // sources: E[src_comp][src_idx] -= src_amp[s * max_steps + n] after the
   // update; the list is grouped by column (x + nx*y), a node's own sources in
-  // the order they were added, and src_first[column] is the first source of
-  // a column (-1: none)
+  // the order they were added, and src_first[column] is the column's run,
+  // first | count << 20 (-1: none)
   int n_src;
   int max_steps;
   const int* src_comp;

@@ -660,8 +660,8 @@ void build_owires(fdtd_ctx* c) {
 // (their amplitudes, zero here, are written on the device each step).  The
 // list is then grouped by column (stable, so a node keeps its sources in
 // the order they were added, the wires' last), and each column records its
-// first source.
-void group_sources(fdtd_ctx* c) {
+// run and planes.  At most 2^20 sources, 2047 in one column (EINVAL).
+int group_sources(fdtd_ctx* c) {
   const size_t ms = (size_t)c->P.max_steps, nreg = c->src_comp.size(), ne = c->ow_ekey.size();
   const long long sxy = (long long)c->N[0] * c->N[1];
   for (long long key : c->ow_ekey) {
@@ -670,6 +670,7 @@ void group_sources(fdtd_ctx* c) {
   }
   c->src_amp.resize((nreg + ne) * ms, 0.0);
   const size_t n = c->src_comp.size();
+  if (n >= (size_t(1) << 20)) return fail(c, FDTD_EINVAL, "more than 2^20 sources and oblique-wire edges");
   std::vector<int> ord(n);
   for (size_t s = 0; s < n; ++s) ord[s] = (int)s;
   std::stable_sort(ord.begin(), ord.end(),
@@ -689,16 +690,26 @@ void group_sources(fdtd_ctx* c) {
   c->src_comp.swap(comp);
   c->src_idx.swap(idx);
   c->src_amp.swap(amp);
+  // per column: its run (first | count << 20) and its planes (kmin | kmax
+  // << 16, planes beyond 65535 clamped: such a column is always scanned)
   c->src_first.assign((size_t)sxy, -1);
   c->src_kr.assign((size_t)sxy, 0);
-  for (size_t s = n; s-- > 0;) c->src_first[(size_t)(c->src_idx[s] % sxy)] = (int)s;
-  for (size_t s = 0; s < n; ++s) {  // planes below 65536 (a larger grid keeps the full range)
+  for (size_t s = 0; s < n;) {
     const size_t col = (size_t)(c->src_idx[s] % sxy);
-    const int k = (int)std::min<long long>(c->src_idx[s] / sxy, 0xffff);
-    const int lo = c->src_first[col] == (int)s ? k : std::min(k, c->src_kr[col] & 0xffff);
-    const int hi = c->src_first[col] == (int)s ? k : std::max(k, c->src_kr[col] >> 16);
-    c->src_kr[col] = lo | (c->N[2] > 0xffff ? 0xffff : hi) << 16;
+    size_t e = s;
+    int lo = 0xffff, hi = 0;
+    for (; e < n && (size_t)(c->src_idx[e] % sxy) == col; ++e) {
+      const int k = (int)std::min<long long>(c->src_idx[e] / sxy, 0xffff);
+      lo = std::min(lo, k);
+      hi = std::max(hi, k);
+    }
+    if (c->N[2] > 0xffff) hi = 0xffff;
+    if (e - s >= 2048) return fail(c, FDTD_EINVAL, "more than 2047 sources and oblique-wire edges in one column");
+    c->src_first[col] = (int)s | (int)(e - s) << 20;
+    c->src_kr[col] = lo | hi << 16;
+    s = e;
   }
+  return FDTD_OK;
 }
 
 void layout(fdtd_ctx* c) {
@@ -941,7 +952,8 @@ int freeze(fdtd_ctx* c) {
   build_cpml(c);
   build_sources_probes(c);
   build_owires(c);
-  group_sources(c);
+  rc = group_sources(c);
+  if (rc) return rc;
   layout(c);
   if (c->ws_bytes == 0) return fail(c, FDTD_EINVAL, "a CPML state array or the source table exceeds 4 GiB");
   c->frozen = true;

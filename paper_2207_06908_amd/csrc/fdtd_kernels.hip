@@ -74,8 +74,8 @@ __global__ __launch_bounds__(256) void k_e_split(GridView<T> g, int step) {
   const T hz_j = (j > 0) ? ldg(g.fi[5], n - (unsigned)g.nx) : T(0);
   const T eold[3] = {ldg(g.fi[0], n), ldg(g.fi[1], n), ldg(g.fi[2], n)};
   T e[3];
-  e_point<T, PML>(g, i, j, k, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, e,
-                  src_node(g, i, j, k));
+  const SrcRange sr = src_node(g, i, j, k);
+  e_point<T, PML>(g, i, j, k, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, e, sr.lo, sr.hi);
   stg(g.fo[0], n, e[0]);
   stg(g.fo[1], n, e[1]);
   stg(g.fo[2], n, e[2]);
@@ -103,8 +103,8 @@ __global__ __launch_bounds__(256) void k_e_split_debye(GridView<T> g, DebyeView<
   const T hz_j = (j > 0) ? ldg(g.fi[5], n - (unsigned)g.nx) : T(0);
   const T eold[3] = {ldg(g.fi[0], n), ldg(g.fi[1], n), ldg(g.fi[2], n)};
   T e[3];
-  e_point<T, PML>(g, i, j, k, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, e,
-                  src_node(g, i, j, k));
+  const SrcRange sr = src_node(g, i, j, k);
+  e_point<T, PML>(g, i, j, k, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, e, sr.lo, sr.hi);
   debye_point(d, cid, n, eold, e);
   stg(g.fo[0], n, e[0]);
   stg(g.fo[1], n, e[1]);
@@ -226,7 +226,8 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
   const int lx = PML && (AX & 1) && dom ? slab_pos(x, nx, g.npml) : -1;
   const int ly = PML && (AX & 2) && dom ? slab_pos(y, ny, g.npml) : -1;
   constexpr bool PZ = PML && (AX & 4);
-  const int srcc = src_column(g, n0, inB), srckr = src_range(g, n0, srcc);
+  // (E is updated on planes k0 - 1 .. k1: the first step's cone, then the outputs)
+  const SrcRange srcr = src_wave(g, n0, inB, k0 - 1, k1);
   if (PML) {
     const int tn = 2 * g.npml;
     if ((AX & 1) && v == 0) {
@@ -371,7 +372,7 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
         if (PML) psi_load(g, 0, l, x, y, k, psen);
         e_core_pf<T, PML>(pf, g, l, n0 + sxy * (unsigned)k, coef(cc), h1c[0], h1c[1], h1c[2], sm.sh1[0][v - 1][u],
                        h1p[0], sm.sh1[1][v][u - 1], h1p[1], sm.sh1[2][v][u - 1], sm.sh1[2][v - 1][u], e0c, step,
-                       psen, e1c, src_at(srcc, srckr, k));
+                       psen, e1c, srcr.first(k), srcr.last(k));
       };
       if (lz >= 0) {
         const int l[3] = {lx, ly, lz};
@@ -415,8 +416,8 @@ __device__ __forceinline__ void tb2_tile(const GridView<T>& g, TB2Smem<T, TY>& s
     if (pend) {
       int l[3] = {lx, ly, PZ ? slab_pos(km, nz, g.npml) : -1};
       e_core_pf<T, PML>(pf, g, l, nst, coef(cp), h2c[0], h2c[1], h2c[2], sm.sh2[0][v - 1][u], h2p[0], sm.sh2[1][v][u - 1],
-                     h2p[1], sm.sh2[2][v][u - 1], sm.sh2[2][v - 1][u], e1p, step + 1, pse, e2,
-                     src_at(srcc, srckr, km));
+                     h2p[1], sm.sh2[2][v][u - 1], sm.sh2[2][v - 1][u], e1p, step + 1, pse, e2, srcr.first(km),
+                     srcr.last(km));
       if (!DEFER) {
         stg(g.fo[0], nst, e2[0]);
         stg(g.fo[1], nst, e2[1]);
@@ -517,8 +518,9 @@ __device__ __forceinline__ void e1_at(const GridView<T>& g, int x, int y, int k,
     slabs(g, x, y, k, l);
     psi_load(g, 0, l, x, y, k, ps);
   }
-  e_core<T, PML>(g, l, n, cf, h[0], h[1], h[2], hj[0], hk[0], hi[1], hk[1], hi[2], hj[2], eold, step, ps, e,
-                 src_node(g, x, y, k));
+  const SrcRange sr = src_node(g, x, y, k);
+  e_core<T, PML>(g, l, n, cf, h[0], h[1], h[2], hj[0], hk[0], hi[1], hk[1], hi[2], hj[2], eold, step, ps, e, sr.lo,
+                 sr.hi);
 }
 
 // Probes: one block of PR_NT threads per probe.  Thread `tid` sums terms

@@ -111,7 +111,8 @@ __device__ __forceinline__ void h_core_pf(const PF& pf, const int l[3], const T*
 template <typename T, bool PML, typename PF>
 __device__ __forceinline__ void e_core_pf(const PF& pf, const GridView<T>& g, const int l[3], unsigned n,
                                           const T* cf, T hx, T hy, T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i,
-                                          T hz_j, const T eold[3], int step, T ps[3][2], T enew[3], int src) {
+                                          T hz_j, const T eold[3], int step, T ps[3][2], T enew[3], int slo,
+                                          int shi) {
   T a_ex = hz - hz_j, b_ex = hy - hy_k;  // Ex: dHz/dy - dHy/dz
   T a_ey = hx - hx_k, b_ey = hz - hz_i;  // Ey: dHx/dz - dHz/dx
   T a_ez = hy - hy_i, b_ez = hx - hx_j;  // Ez: dHy/dx - dHx/dy
@@ -135,21 +136,17 @@ __device__ __forceinline__ void e_core_pf(const PF& pf, const GridView<T>& g, co
   enew[0] = e_new(eold[0], cf[K_CAX], cf[K_CBX], a_ex, b_ex);
   enew[1] = e_new(eold[1], cf[K_CAY], cf[K_CBY], a_ey, b_ey);
   enew[2] = e_new(eold[2], cf[K_CAZ], cf[K_CBZ], a_ez, b_ez);
-  // ideal current sources: E -= Cb I / dx^2 (precomputed per step).  src is
-  // the first source of the node's column (-1 where the column holds none):
-  // the scan stops at the end of the column's run of the list.
-  if (src >= 0) {
-    const unsigned col = n % (unsigned)g.sxy;
-    for (int s = src; s < g.n_src; ++s) {
-      const unsigned si = (unsigned)ldg(g.src_idx, (unsigned)s);
-      if (si % (unsigned)g.sxy != col) break;
-      if (si != n) continue;
-      const T v = ldg(g.src_amp, (unsigned)s * (unsigned)g.max_steps + (unsigned)step);
-      const int comp = ldg(g.src_comp, (unsigned)s);
-      enew[0] = comp == 0 ? enew[0] - v : enew[0];
-      enew[1] = comp == 1 ? enew[1] - v : enew[1];
-      enew[2] = comp == 2 ? enew[2] - v : enew[2];
-    }
+  // ideal current sources: E -= Cb I / dx^2 (precomputed per step), from the
+  // entries [slo, shi) of the source list (empty where none can apply).  The
+  // tile kernels pass a range that is uniform across the wave, so that the
+  // scan reads the list with scalar loads.
+  for (int s = slo; s < shi; ++s) {
+    if ((unsigned)ldg(g.src_idx, (unsigned)s) != n) continue;
+    const T v = ldg(g.src_amp, (unsigned)s * (unsigned)g.max_steps + (unsigned)step);
+    const int comp = ldg(g.src_comp, (unsigned)s);
+    enew[0] = comp == 0 ? enew[0] - v : enew[0];
+    enew[1] = comp == 1 ? enew[1] - v : enew[1];
+    enew[2] = comp == 2 ? enew[2] - v : enew[2];
   }
 }
 
@@ -162,37 +159,56 @@ __device__ __forceinline__ void h_core(const GridView<T>& g, const int l[3], con
 template <typename T, bool PML>
 __device__ __forceinline__ void e_core(const GridView<T>& g, const int l[3], unsigned n, const T* cf, T hx, T hy,
                                        T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j, const T eold[3],
-                                       int step, T ps[3][2], T enew[3], int src) {
+                                       int step, T ps[3][2], T enew[3], int slo, int shi) {
   e_core_pf<T, PML>(ProfG<T>{g}, g, l, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, ps, enew,
-                    src);
+                    slo, shi);
 }
 
-// First source of column n0 (= x + nx*y) in the grouped list, -1 if the
-// column holds none (or if !on).  The tile kernels read it once per tile, so
-// that the per-plane source scan, whose global loads would make the wave
-// wait for every load and store it has in flight, runs only in waves that
-// hold a source column.
+// Sources of column n0 (= x + nx*y) as a range [lo, hi) of the grouped
+// source list with their planes [klo, khi]; empty (lo = hi = 0, no planes)
+// if the column holds none, if !on, or if they all lie outside planes
+// [ka, kb].
+struct SrcRange {
+  int lo, hi, klo, khi;
+  // the range to scan for plane k
+  __device__ __forceinline__ int first(int k) const { return k >= klo && k <= khi ? lo : 0; }
+  __device__ __forceinline__ int last(int k) const { return k >= klo && k <= khi ? hi : 0; }
+};
 template <typename T>
-__device__ __forceinline__ int src_column(const GridView<T>& g, unsigned n0, bool on) {
-  return on ? ldg(g.src_first, n0) : -1;
+__device__ __forceinline__ SrcRange src_column(const GridView<T>& g, unsigned n0, bool on, int ka, int kb) {
+  SrcRange r{0, 0, 1, 0};
+  const int f = on ? ldg(g.src_first, n0) : -1;
+  if (f >= 0) {
+    const int kr = ldg(g.src_kr, n0), kl = kr & 0xffff, kh = (int)((unsigned)kr >> 16);
+    if (kb >= kl && ka <= kh) r = SrcRange{f & 0xfffff, (f & 0xfffff) + (f >> 20), kl, kh};
+  }
+  return r;
 }
-// Planes of column n0's sources (kmin | kmax << 16), read only for a column
-// that has some (first >= 0).
+// The same over a whole wave: the union of its lanes' ranges (contiguous in
+// the list when the lanes' columns are, as along one row), uniform across
+// the wave.  The tile kernels evaluate it once per tile, so that the
+// per-plane scan reads the list with scalar loads, and waves with no source
+// skip it.  Every lane of the wave must call it.
 template <typename T>
-__device__ __forceinline__ int src_range(const GridView<T>& g, unsigned n0, int first) {
-  return first >= 0 ? ldg(g.src_kr, n0) : 0;
+__device__ __forceinline__ SrcRange src_wave(const GridView<T>& g, unsigned n0, bool on, int ka, int kb) {
+  const SrcRange c = src_column(g, n0, on, ka, kb);
+  const bool has = c.hi > c.lo;
+  int lo = has ? c.lo : 0x7fffffff, hi = has ? c.hi : 0, klo = has ? c.klo : 0x7fffffff, khi = has ? c.khi : -1;
+  for (int m = 1; m < 64; m <<= 1) {
+    lo = min(lo, __shfl_xor(lo, m, 64));
+    hi = max(hi, __shfl_xor(hi, m, 64));
+    klo = min(klo, __shfl_xor(klo, m, 64));
+    khi = max(khi, __shfl_xor(khi, m, 64));
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  hi = __builtin_amdgcn_readfirstlane(hi);
+  if (hi <= lo) return SrcRange{0, 0, 1, 0};
+  return SrcRange{lo, hi, __builtin_amdgcn_readfirstlane(klo), __builtin_amdgcn_readfirstlane(khi)};
 }
-// The first source to scan for plane k: -1 outside the column's source
-// planes, so that a column with sources at other heights costs no scan.
-__device__ __forceinline__ int src_at(int first, int kr, int k) {
-  return (first >= 0 && k >= (kr & 0xffff) && k <= (int)((unsigned)kr >> 16)) ? first : -1;
-}
-// Both for one node (x, y, k).
+// For one node (x, y, k): its column's range if it covers plane k.
 template <typename T>
-__device__ __forceinline__ int src_node(const GridView<T>& g, int x, int y, int k) {
-  const unsigned col = (unsigned)x + (unsigned)g.nx * (unsigned)y;
-  const int f = src_column(g, col, true);
-  return src_at(f, src_range(g, col, f), k);
+__device__ __forceinline__ SrcRange src_node(const GridView<T>& g, int x, int y, int k) {
+  return src_column(g, (unsigned)x + (unsigned)g.nx * (unsigned)y, true, k, k);
 }
 
 // One-step wrappers: CPML state from the input set, written (optionally for
@@ -214,14 +230,14 @@ __device__ __forceinline__ void h_point(const GridView<T>& g, int x, int y, int 
 template <typename T, bool PML, int AX = 7>
 __device__ __forceinline__ void e_point(const GridView<T>& g, int x, int y, int k, unsigned n, const T* cf,
                                         T hx, T hy, T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j,
-                                        const T eold[3], int step, T enew[3], int src) {
+                                        const T eold[3], int step, T enew[3], int slo, int shi) {
   int l[3] = {-1, -1, -1};
   T ps[3][2];
   if (PML) {
     slabs<T, AX>(g, x, y, k, l);
     psi_load(g, 0, l, x, y, k, ps);
   }
-  e_core<T, PML>(g, l, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, ps, enew, src);
+  e_core<T, PML>(g, l, n, cf, hx, hy, hz, hx_j, hx_k, hy_i, hy_k, hz_i, hz_j, eold, step, ps, enew, slo, shi);
   if (PML) psi_store(g, 0, l, x, y, k, ps);
 }
 
@@ -350,7 +366,7 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
   const int i = i0 + tx, j = j0 + ty;
   const bool own = i < nx && j < ny;
   const unsigned n0 = own ? (unsigned)i + (unsigned)nx * (unsigned)j : 0u;  // + sxy * k
-  const int srcc = src_column(g, n0, own), srckr = src_range(g, n0, srcc);
+  const SrcRange srcr = src_wave(g, n0, own, k0, k1 - 1);
   // E halo point (threads NT-NHE .. NT-1)
   int er = 0, ec = 0;
   bool eh = false;
@@ -487,7 +503,7 @@ __device__ __forceinline__ void fused_tile(const GridView<T>& g, FusedSmem<T, TX
       T e[3];
       e_point<T, PML, AX>(g, i, j, k, n, coef(cls_cur), hown[0], hown[1], hown[2], sh[0][ty][tx + 1], hm[0],
                       sh[1][ty + 1][tx], hm[1], sh[2][ty + 1][tx], sh[2][ty][tx + 1], ecur, step, e,
-                      src_at(srcc, srckr, k));
+                      srcr.first(k), srcr.last(k));
       if (DB && dcur) {
         if (DLDS) debye_apply<T, true>(*dv, sdt + cls_cur * D_STRIDE, n, ecur, e, jcur);
         else debye_apply<T, false>(*dv, dv->dtab + cls_cur * D_STRIDE, n, ecur, e, jcur);
