@@ -53,7 +53,10 @@ struct AdamArgs {
 // output width <= MLP_NOUT (its FP32 rows are staged in the same LDS).  Net q's bfloat16 weight copies start at bf + q bf_stride,
 // its FP32 parameters at p + q p_stride; its outputs go to
 // out[q ld_net + row ldo + col] for rows < m_valid.
-constexpr int MLP_BM = 128, MLP_KMAX = 512, MLP_LDA = MLP_KMAX + 8, MLP_NOUT = MLP_LDA / 2;
+// Block shape of k_mlp_infer: MLP_BM rows, MLP_NW waves, MLP_CF column
+// fragments per wave.
+constexpr int MLP_BM = 128, MLP_NW = 16, MLP_CF = 2;
+constexpr int MLP_KMAX = 512, MLP_LDA = MLP_KMAX + 8, MLP_NOUT = MLP_LDA / 2;
 struct MlpLayer {
   long long w16;   // element offset of W [n x kp] in a net's bfloat16 copies
   int bias;        // offset of b in a net's FP32 parameters

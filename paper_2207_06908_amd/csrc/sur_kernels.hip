@@ -39,8 +39,33 @@ __device__ __forceinline__ bf16x8 ld_frag(const uint16_t* p) {
   return __builtin_bit_cast(bf16x8, q);
 }
 
-constexpr float kInvSqrt2 = 0.70710678118654752f;
 constexpr float kInvSqrt2Pi = 0.39894228040143268f;
+
+// Prefetch distance (K steps) of the weight fragments in k_mlp_infer.
+constexpr int MLP_PD = 3;
+
+// The standard normal distribution function Phi(z), and exp(-z^2 / 2), for
+// the exact GELU z Phi(z) and its derivative Phi(z) + z phi(z).  Phi comes
+// from the erfc approximation of Abramowitz and Stegun, formula 7.1.26
+// (absolute error of erf at most 1.5e-7, against a bfloat16 step of 2^-8 in
+// the activations it feeds): with x = |z| / sqrt 2 and t = 1 / (1 + p x),
+// erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2), and
+// Phi(z) = erfc(x) / 2 for z < 0, 1 - erfc(x) / 2 otherwise.  No branch, one
+// reciprocal and one exponential per value.
+__device__ __forceinline__ float norm_cdf(float z, float& gz) {
+  constexpr float kP = 0.3275911f * 0.70710678118654752f;  // p / sqrt 2
+  constexpr float c1 = 0.5f * 0.254829592f, c2 = 0.5f * -0.284496736f, c3 = 0.5f * 1.421413741f,
+                  c4 = 0.5f * -1.453152027f, c5 = 0.5f * 1.061405429f;  // a_i / 2
+  const float t = __builtin_amdgcn_rcpf(fmaf(kP, fabsf(z), 1.0f));
+  float s = fmaf(t, c5, c4);
+  s = fmaf(t, s, c3);
+  s = fmaf(t, s, c2);
+  s = fmaf(t, s, c1);
+  s *= t;
+  gz = __builtin_amdgcn_exp2f(z * z * -0.72134752044448170f);  // 2^(-z^2 log2(e) / 2)
+  const float h = s * gz;  // erfc(x) / 2
+  return z < 0.0f ? h : 1.0f - h;
+}
 
 // One (32 F) x (32 F) output tile per block of four waves; each wave owns a
 // (16 F) x (16 F) quarter, F x F fragments.  F = 2 for small products (the
@@ -109,12 +134,11 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         const float v = c[i][j][r];
         if (EPI == EPI_GELU_TRAIN || EPI == EPI_GELU_INFER) {
           const float z = v + g.bias[n];
-          const float e = erff(z * kInvSqrt2);
-          const float a = 0.5f * z * (1.0f + e);
-          t16[r] = f2bf(a);
+          float gz;
+          const float ph = norm_cdf(z, gz);
+          t16[r] = f2bf(z * ph);
           g.o16[(size_t)m * g.ld16 + n] = (uint16_t)t16[r];
-          if (EPI == EPI_GELU_TRAIN)
-            g.o32[(size_t)m * g.ld32 + n] = 0.5f * (1.0f + e) + z * expf(-0.5f * z * z) * kInvSqrt2Pi;
+          if (EPI == EPI_GELU_TRAIN) g.o32[(size_t)m * g.ld32 + n] = ph + z * (gz * kInvSqrt2Pi);
         } else if (EPI == EPI_LINEAR) {
           if (m < g.m_valid) g.o32[(size_t)m * g.ld32 + n] = v + g.bias[n];
         } else if (EPI == EPI_BWD) {
@@ -132,30 +156,36 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   }
 }
 
-// Fused inference: every layer of one net over MLP_BM = 128 rows in one
-// block of 16 waves.  The block's activations stay in LDS from layer to
-// layer (bfloat16, rows padded by 16 bytes so that the 16 rows of a fragment
-// fall in different banks); only the gathered inputs, the weights (a few MB
-// per net, L2-resident) and the last layer's FP32 outputs touch memory.  The
-// product of a 64K-row activation block with 512 x 512 weights moves 128 MB
-// through HBM when every layer round-trips; here it moves none.
-// Wave w owns the output column fragments w and w + 16 (16 columns each;
-// widths up to 512) for all 8 row fragments of the block, so every weight
-// fragment it loads serves 8 products and the block reads each weight once.
-// The weight fragments run two K steps ahead of the products.  The loop has
-// no branches: rows past M hold zero inputs, a column fragment past the
-// layer's width multiplies fragment 0's weights, and neither result is ever
-// stored, so the wave waits only for the loads its next products need.  Each
-// accumulator takes its K steps in order with the instruction k_gemm uses,
-// and the epilogue is k_gemm's, so the outputs equal the layer-by-layer
-// products bit for bit.
-__global__ __launch_bounds__(1024) void k_mlp_infer(MlpArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t act[MLP_BM * MLP_LDA];
+// Fused inference: every layer of one net over BM rows in one block.  The
+// block's activations stay in LDS from layer to layer (bfloat16, rows padded
+// by 16 bytes so that the 16 rows of a fragment fall in different banks);
+// only the gathered inputs, the weights (a few MB per net, L2-resident) and
+// the last layer's FP32 outputs touch memory.  (Layer by layer, a 64K-row
+// activation block with 512 x 512 weights moves 128 MB through HBM per
+// layer; here it moves none.)  NW waves; the waves split the block's rows
+// into NW / (32 / CF) groups and the 32 column fragments of a 512-wide layer
+// (16 columns each) into 32 / CF groups: wave w owns the row fragments of
+// group w / (32 / CF) and the column fragments c, c + 32 / CF, ... (CF of
+// them, c = w % (32 / CF)).  Each activation fragment a wave reads from LDS
+// serves CF products, each weight fragment it reads from L2 serves RF.  The
+// weight fragments run MLP_PD K steps ahead of the products, the bias of the
+// layer is loaded before them.  The K loop has no branches: rows past M hold
+// zero inputs, a column fragment past the layer's width multiplies fragment
+// 0's weights, and neither result is ever stored.  Each accumulator takes its
+// K steps in order with the instruction k_gemm uses, and the epilogue is
+// k_gemm's, so the outputs equal the layer-by-layer products bit for bit.
+// (At most 64 accumulator registers a lane: 4 waves per SIMD, else 2.)
+template <int BM, int NW, int CF>
+__global__ __launch_bounds__(64 * NW, (BM / 16) * 32 / NW * 4 <= 64 ? 4 : 2) void k_mlp_infer(MlpArgs a) {
+  constexpr int NT = 64 * NW, NWC = 32 / CF, NWR = NW / NWC, RF = BM / 16 / NWR;
+  static_assert(NWC * CF == 32 && NWR * NWC == NW && RF * NWR * 16 == BM, "block shape");
+  __shared__ __attribute__((aligned(16))) uint16_t act[BM * MLP_LDA];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int net = blockIdx.y, m0 = blockIdx.x * MLP_BM;
+  const int cg = w % NWC, r0 = (w / NWC) * RF;  // column group, first row fragment
+  const int net = blockIdx.y, m0 = blockIdx.x * BM;
   const uint16_t* bfn = a.bf + (size_t)net * a.bf_stride;
   const float* pn = a.p + (size_t)net * a.p_stride;
-  for (int e = tid; e < MLP_BM * 4; e += 1024) {  // inputs: 32 bfloat16 per row, as four 16-byte pieces
+  for (int e = tid; e < BM * 4; e += NT) {  // inputs: 32 bfloat16 per row, as four 16-byte pieces
     const int r = e >> 2, q = e & 3;
     uint4 v = make_uint4(0, 0, 0, 0);
     if (m0 + r < a.M) v = *(const uint4*)(a.X16 + (size_t)(m0 + r) * 32 + q * 8);
@@ -163,77 +193,103 @@ __global__ __launch_bounds__(1024) void k_mlp_infer(MlpArgs a) {
   }
   __syncthreads();
   const int r16 = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
-  const uint16_t* pa = act + r16 * MLP_LDA + kq;
+  const uint16_t* pa = act + (16 * r0 + r16) * MLP_LDA + kq;
 #pragma unroll 1
   for (int l = 0; l < a.L; ++l) {
     const MlpLayer ly = a.lay[l];
     const int nf = ly.n >> 4;
-    const bool vn0 = w < nf, vn1 = w + 16 < nf;
-    // column fragment 1 of this wave starts 256 rows of W after fragment 0;
-    // a fragment past the width reads fragment 0's rows (its products are
-    // never stored)
-    const uint16_t* pb0 = bfn + ly.w16 + (size_t)((vn0 ? w : 0) * 16 + r16) * ly.kp + kq;
-    const uint16_t* pb1 = vn1 ? pb0 + (size_t)256 * ly.kp : pb0;
-    f32x4 c[8][2];
+    // a fragment past the width reads fragment 0's rows and bias (its
+    // products are never stored)
+    bool vn[CF];
+    const uint16_t* pb[CF];
+    float bn[CF];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) c[i][0] = c[i][1] = f32x4{0, 0, 0, 0};
-    const int last = ly.kp - 32;
-    bf16x8 b0[2], b1[2];   // weights of steps k and k + 1
-    b0[0] = ld_frag(pb0);
-    b0[1] = ld_frag(pb1);
-    b1[0] = ld_frag(pb0 + min(32, last));
-    b1[1] = ld_frag(pb1 + min(32, last));
-#pragma unroll 1
-    for (int k0 = 0; k0 < ly.kp; k0 += 32) {
-      bf16x8 fa[8];
+    for (int j = 0; j < CF; ++j) {
+      vn[j] = cg + NWC * j < nf;
+      const int f = vn[j] ? cg + NWC * j : 0;
+      pb[j] = bfn + ly.w16 + (size_t)(f * 16 + r16) * ly.kp + kq;
+      bn[j] = pn[ly.bias + f * 16 + r16];
+    }
+    f32x4 c[RF][CF];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) fa[i] = *(const bf16x8*)(pa + 16 * i * MLP_LDA + k0);
+    for (int i = 0; i < RF; ++i)
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        c[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], b0[0], c[i][0], 0, 0, 0);
-        c[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], b0[1], c[i][1], 0, 0, 0);
+      for (int j = 0; j < CF; ++j) c[i][j] = f32x4{0, 0, 0, 0};
+    // One K step: the wave's activation fragments from LDS, RF x CF products
+    // with this step's weight fragments.
+    auto kstep = [&](int k0, const bf16x8* b) {
+      bf16x8 fa[RF];
+#pragma unroll
+      for (int i = 0; i < RF; ++i) fa[i] = *(const bf16x8*)(pa + 16 * i * MLP_LDA + k0);
+#pragma unroll
+      for (int i = 0; i < RF; ++i)
+#pragma unroll
+        for (int j = 0; j < CF; ++j) c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], b[j], c[i][j], 0, 0, 0);
+    };
+    // The empty asm statements between steps keep each load in the step that
+    // issues it: nothing is stored in the loop, so the compiler would
+    // otherwise move the loads down to the step that uses them, and every
+    // step would wait for its own loads.
+    if (ly.kp == MLP_KMAX) {
+      // the 16 steps of a 512-wide layer unrolled: step s reads the register
+      // set s % MLP_PD, so the prefetched values are never copied (a copy
+      // would wait for the load)
+      constexpr int NS = MLP_KMAX / 32;
+      bf16x8 b[MLP_PD][CF];
+#pragma unroll
+      for (int q = 0; q < MLP_PD; ++q)
+#pragma unroll
+        for (int j = 0; j < CF; ++j) b[q][j] = ld_frag(pb[j] + 32 * q);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        asm volatile("" ::: "memory");
+        kstep(32 * s, b[s % MLP_PD]);
+        if (s + MLP_PD < NS)
+#pragma unroll
+          for (int j = 0; j < CF; ++j) b[s % MLP_PD][j] = ld_frag(pb[j] + 32 * (s + MLP_PD));
       }
-      // step k + 2's weights into the registers step k has finished with
-      const int kn = min(k0 + 64, last);
-      b0[0] = b1[0];
-      b0[1] = b1[1];
-      b1[0] = ld_frag(pb0 + kn);
-      b1[1] = ld_frag(pb1 + kn);
+    } else {
+      // other widths (the first layer, small nets): one step at a time
+#pragma unroll 1
+      for (int k0 = 0; k0 < ly.kp; k0 += 32) {
+        asm volatile("" ::: "memory");
+        bf16x8 b[CF];
+#pragma unroll
+        for (int j = 0; j < CF; ++j) b[j] = ld_frag(pb[j] + k0);
+        kstep(k0, b);
+      }
     }
     __syncthreads();  // every wave has read this layer's input
-    const float* bias = pn + ly.bias;
     if (l + 1 < a.L) {  // hidden layer: bias, exact GELU, bfloat16 into LDS
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        if (!(j ? vn1 : vn0)) continue;
-        const int n = (w + 16 * j) * 16 + r16;
-        const float bn = bias[n];
+      for (int j = 0; j < CF; ++j) {
+        if (!vn[j]) continue;
+        const int n = (cg + NWC * j) * 16 + r16;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < RF; ++i) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const float z = c[i][j][r] + bn;
-            const float e = erff(z * kInvSqrt2);
-            const float y = 0.5f * z * (1.0f + e);
-            act[(16 * i + rq + r) * MLP_LDA + n] = (uint16_t)f2bf(y);
+            const float z = c[i][j][r] + bn[j];
+            float gz;
+            const float ph = norm_cdf(z, gz);
+            act[(16 * (r0 + i) + rq + r) * MLP_LDA + n] = (uint16_t)f2bf(z * ph);
           }
         }
       }
     } else {  // output layer: bias, FP32 staged in LDS, then rows < m_valid out as whole rows
       float* of = (float*)act;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        if (!(j ? vn1 : vn0)) continue;
-        const int n = (w + 16 * j) * 16 + r16;
-        const float bn = bias[n];
+      for (int j = 0; j < CF; ++j) {
+        if (!vn[j]) continue;
+        const int n = (cg + NWC * j) * 16 + r16;
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < RF; ++i)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) of[(16 * i + rq + r) * ly.n + n] = c[i][j][r] + bn;
+          for (int r = 0; r < 4; ++r) of[(16 * (r0 + i) + rq + r) * ly.n + n] = c[i][j][r] + bn[j];
       }
       __syncthreads();
-      const int rows = min(MLP_BM, a.m_valid - m0);
-      for (int e = tid; e < rows * ly.n; e += 1024) {
+      const int rows = min(BM, a.m_valid - m0);
+      for (int e = tid; e < rows * ly.n; e += NT) {
         const int m = e / ly.n, n = e - m * ly.n;
         a.out[(size_t)net * a.ld_net + (size_t)(m0 + m) * a.ldo + n] = of[e];
       }
@@ -485,7 +541,7 @@ int launch_gemm(int epi, const GemmArgs& a, void* stream) {
 
 int launch_mlp_infer(const MlpArgs& a, int nets, void* stream) {
   if (a.M <= 0) return 0;
-  k_mlp_infer<<<dim3((a.M + MLP_BM - 1) / MLP_BM, nets), 1024, 0, (hipStream_t)stream>>>(a);
+  k_mlp_infer<MLP_BM, MLP_NW, MLP_CF><<<dim3((a.M + MLP_BM - 1) / MLP_BM, nets), 64 * MLP_NW, 0, (hipStream_t)stream>>>(a);
   return last();
 }
 
