@@ -60,8 +60,11 @@ struct Probe { int kind, axis, p[3], n; std::vector<double> rec; };
 struct OWire {
   double A[3], t[3], dl, Lp, Cp;
   int n, src, rec;
+  int junc[2] = {-1, -1};  // junction of the start (0) and end (1) node, -1: open end
   std::vector<double> amps, I, q, rec_v;
 };
+// Junction: end nodes of several oblique wires that meet at one point.
+struct OJunction { std::vector<int> wire, end; };
 
 }  // namespace
 
@@ -82,6 +85,7 @@ struct orc_sim {
   std::vector<Lumped> lumped;
   std::vector<Probe> probes;
   std::vector<OWire> owires;
+  std::vector<OJunction> ojunc;
 
   // fields at their natural Yee extents
   A3 E[3], H[3];
@@ -641,6 +645,13 @@ static void owire_pattern(const OWire& w, int k, std::vector<OwEntry>& out) {
 }
 
 // I^{n+1/2} from E^n and q^n, then q^{n+1} from I^{n+1/2} (before the E update).
+//
+// Junctions (the multiwire junctions of the oblique-wire model): the end
+// nodes of several wires that meet at one point form one node.  Its charge
+// Q_J = sum_m q_m len_m (len_m the half segment of member m) changes by the
+// currents that flow into the point, and the members share one potential
+// V = q_m / C'_m, so q_m = C'_m Q_J / sum_m C'_m len_m.  A wire cut at one of
+// its nodes and rejoined there is the uncut wire again.
 void owire_currents(orc_sim* s) {
   std::vector<OwEntry> pat;
   for (OWire& w : s->owires) {
@@ -656,12 +667,32 @@ void owire_currents(orc_sim* s) {
       et /= w.dl;
       w.I[k] += s->dt / w.Lp * (et - (w.q[k + 1] - w.q[k]) / (w.Cp * dlm));
     }
+    if (w.rec >= 0) w.rec_v[s->step] = w.I[w.rec];
+  }
+  for (OWire& w : s->owires) {
+    const double dlm = w.dl * s->dx;
     for (int j = 0; j <= w.n; ++j) {
+      if ((j == 0 && w.junc[0] >= 0) || (j == w.n && w.junc[1] >= 0)) continue;
       const double il = j > 0 ? w.I[j - 1] : 0.0, ir = j < w.n ? w.I[j] : 0.0;
       const double len = (j == 0 || j == w.n) ? 0.5 * dlm : dlm;
       w.q[j] -= s->dt * (ir - il) / len;
     }
-    if (w.rec >= 0) w.rec_v[s->step] = w.I[w.rec];
+  }
+  for (const OJunction& J : s->ojunc) {
+    double Q = 0.0, inflow = 0.0, cap = 0.0;
+    for (size_t m = 0; m < J.wire.size(); ++m) {
+      const OWire& w = s->owires[J.wire[m]];
+      const double len = 0.5 * w.dl * s->dx;
+      const int j = J.end[m] ? w.n : 0;
+      Q += w.q[j] * len;
+      inflow += J.end[m] ? w.I[w.n - 1] : -w.I[0];  // a segment ending at the point brings its current
+      cap += w.Cp * len;
+    }
+    const double V = (Q + s->dt * inflow) / cap;
+    for (size_t m = 0; m < J.wire.size(); ++m) {
+      OWire& w = s->owires[J.wire[m]];
+      w.q[J.end[m] ? w.n : 0] = w.Cp * V;
+    }
   }
 }
 
@@ -906,6 +937,33 @@ int orc_add_oblique_wire(orc_sim* s, const double* a, const double* b, double ra
   w.rec_v.assign(rec_seg >= 0 ? s->P.max_steps : 0, 0.0);
   s->owires.push_back(w);
   if (id) *id = (int)s->owires.size() - 1;
+  return ORC_OK;
+}
+
+int orc_join_oblique_wires(orc_sim* s, int n, const int* ids, const int* ends) {
+  if (!s || n < 2 || !ids || !ends) return ORC_EINVAL;
+  if (s->finalized) return fail(s, ORC_ESTATE, "grid already stepped");
+  OJunction J;
+  double p0[3] = {0, 0, 0};
+  for (int m = 0; m < n; ++m) {
+    if (ids[m] < 0 || ids[m] >= (int)s->owires.size() || (ends[m] != 0 && ends[m] != 1))
+      return fail(s, ORC_EINVAL, "bad wire id or end");
+    const OWire& w = s->owires[ids[m]];
+    if (w.junc[ends[m]] >= 0) return fail(s, ORC_EINVAL, "wire end already in a junction");
+    for (int q = 0; q < m; ++q)
+      if (ids[q] == ids[m] && ends[q] == ends[m]) return fail(s, ORC_EINVAL, "wire end listed twice");
+    double p[3];
+    for (int u = 0; u < 3; ++u) p[u] = w.A[u] + (ends[m] ? w.n * w.dl * w.t[u] : 0.0);
+    if (m == 0)
+      std::memcpy(p0, p, sizeof(p0));
+    else
+      for (int u = 0; u < 3; ++u)
+        if (std::fabs(p[u] - p0[u]) > 1e-6) return fail(s, ORC_EINVAL, "joined wire ends do not meet");
+    J.wire.push_back(ids[m]);
+    J.end.push_back(ends[m]);
+  }
+  for (int m = 0; m < n; ++m) s->owires[ids[m]].junc[ends[m]] = (int)s->ojunc.size();
+  s->ojunc.push_back(J);
   return ORC_OK;
 }
 

@@ -79,6 +79,11 @@ int  orc_add_probe(orc_sim* s, int kind, int axis, int i, int j, int k, int n_ce
  * segment's current each step.  Not with Debye media. */
 int  orc_add_oblique_wire(orc_sim* s, const double* a, const double* b, double radius, int src_seg,
                           const double* amps, int n_amps, int rec_seg, int* id);
+/* Junction: the listed wire ends (ends[m] = 0: the wire's start a, 1: its
+ * end b) meet at one point (within 1e-6 cells) and become one node: its
+ * charge follows the currents flowing into it, and its members share one
+ * potential q / C'.  Each wire end joins at most one junction; n >= 2. */
+int  orc_join_oblique_wires(orc_sim* s, int n, const int* ids, const int* ends);
 /* Segment currents (n_seg), end-point charges per unit length (n_seg + 1),
  * and the record (any pointer may be NULL). */
 int  orc_oblique_wire_read(orc_sim* s, int id, double* cur, double* q, double* rec, int n_rec_max,

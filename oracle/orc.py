@@ -66,6 +66,7 @@ def lib():
                                            C.c_int, C.POINTER(C.c_int)]
         L.orc_oblique_wire_read.argtypes = [vp, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                                             C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_join_oblique_wires.argtypes = [vp, C.c_int, C.c_void_p, C.c_void_p]
         L.orc_step.argtypes = [vp, C.c_int]
         L.orc_probe.argtypes = [vp, C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_int)]
         L.orc_set_field.argtypes = [vp, C.c_int, C.c_void_p]
@@ -170,6 +171,15 @@ class Oracle:
         self._chk(lib().orc_add_oblique_wire(self._h, pa.ctypes.data, pb.ctypes.data, float(radius), int(src_seg),
                                              am.ctypes.data, am.size, int(rec_seg), C.byref(wid)))
         return wid.value
+
+    def join_oblique_wires(self, ids, ends) -> None:
+        """Junction of the listed wire ends (0: the wire's start a, 1: its end
+        b), which must meet at one point."""
+        iv = np.ascontiguousarray(ids, dtype=np.int32)
+        ev = np.ascontiguousarray(ends, dtype=np.int32)
+        if iv.size != ev.size:
+            raise ValueError("ids and ends differ in length")
+        self._chk(lib().orc_join_oblique_wires(self._h, int(iv.size), iv.ctypes.data, ev.ctypes.data))
 
     def oblique_wire(self, wid):
         """(segment currents, end-point charges per unit length, record)."""

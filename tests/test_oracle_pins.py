@@ -839,6 +839,74 @@ def test_oblique_wire_swapping_x_and_y_swaps_the_fields():
     np.testing.assert_allclose(x1, y2.swapaxes(1, 2), rtol=1e-9, atol=1e-12 * np.abs(x1).max())
 
 
+def test_oblique_wire_cut_and_joined_at_a_node_is_the_uncut_wire():
+    """A junction of two wire ends is the ordinary node of a wire that runs
+    through it: a 10-cell skew wire (3-4-5 direction, unit segments) and the
+    same wire as two 5-cell wires joined at its node 5 give the same segment
+    currents, node charges, record and fields for 150 steps of a pulse (to
+    rounding: the second half's nodes are recomputed from the junction
+    point).  Catches a wrong sign of the inflow at either kind of end, a
+    wrong half-length, or charge not shared."""
+    amps = np.exp(-(((np.arange(150) - 40.0) / 12.0) ** 2))
+    A, P, B = np.array([6.0, 5.0, 9.5]), np.array([9.0, 9.0, 9.5]), np.array([12.0, 13.0, 9.5])
+    a = _owire_box(steps=150)
+    w = a.add_oblique_wire(A, B, 0.002, src_seg=2, amps=amps, rec_seg=7)
+    a.step(150)
+    cur, q, rec = a.oblique_wire(w)
+    b = _owire_box(steps=150)
+    w1 = b.add_oblique_wire(A, P, 0.002, src_seg=2, amps=amps)
+    w2 = b.add_oblique_wire(P, B, 0.002, rec_seg=2)
+    b.join_oblique_wires([w1, w2], [1, 0])
+    b.step(150)
+    c1, q1, _ = b.oblique_wire(w1)
+    c2, q2, rec2 = b.oblique_wire(w2)
+    assert cur.size == 10 and c1.size == 5 and c2.size == 5
+    assert np.abs(cur).max() > 0 and np.abs(rec).max() > 0
+    tol = 1e-9 * np.abs(cur).max()
+    np.testing.assert_allclose(np.concatenate([c1, c2]), cur, rtol=1e-9, atol=tol)
+    assert q1[-1] == q2[0]
+    qt = np.abs(q).max()
+    np.testing.assert_allclose(np.concatenate([q1, q2[1:]]), q, rtol=1e-9, atol=1e-9 * qt)
+    np.testing.assert_allclose(rec2, rec, rtol=1e-9, atol=tol)
+    for comp in range(6):
+        fa, fb = a.get_field(comp), b.get_field(comp)
+        np.testing.assert_allclose(fb, fa, rtol=1e-9, atol=1e-9 * np.abs(fa).max())
+
+
+def test_oblique_wire_junction_of_mirror_branches():
+    """A driven trunk along z meets two branches at (10, 10, 10), mirror
+    images of each other in the plane x = 10 of a 20-cell vacuum box; one
+    branch starts at the junction, the other ends there.  By symmetry the
+    branches carry the same current away from the junction: in their own
+    orientations, I_1[k] = -I_2[n-1-k] and q_1[k] = q_2[n-k].  The open
+    wires' total charge sum q len stays zero, the junction counted once per
+    member's half segment."""
+    amps = np.exp(-(((np.arange(200) - 50.0) / 15.0) ** 2))
+    o = _owire_box(steps=200)
+    J = (10.0, 10.0, 10.0)
+    t = o.add_oblique_wire((10.0, 10.0, 5.0), J, 0.002, src_seg=1, amps=amps)
+    b1 = o.add_oblique_wire(J, (13.0, 10.0, 14.0), 0.002)
+    b2 = o.add_oblique_wire((7.0, 10.0, 14.0), J, 0.002)
+    o.join_oblique_wires([t, b1, b2], [1, 0, 1])
+    o.step(200)
+    ct, qt, _ = o.oblique_wire(t)
+    c1, q1, _ = o.oblique_wire(b1)
+    c2, q2, _ = o.oblique_wire(b2)
+    assert np.abs(c1).max() > 1e-3 * np.abs(ct).max() > 0
+    np.testing.assert_allclose(c1, -c2[::-1], rtol=1e-9, atol=1e-9 * np.abs(c1).max())
+    np.testing.assert_allclose(q1, q2[::-1], rtol=1e-9, atol=1e-9 * np.abs(q1).max())
+    assert qt[-1] == q1[0] == q2[-1]
+    # all three wires are 5 cells long in 5 unit segments
+    total, scale = 0.0, 0.0
+    for c, q in ((ct, qt), (c1, q1), (c2, q2)):
+        assert c.size == 5
+        wt = np.ones(q.size)
+        wt[0] = wt[-1] = 0.5
+        total += float(q @ wt)
+        scale += float(np.abs(q) @ wt)
+    assert scale > 0 and abs(total) <= 1e-12 * scale
+
+
 # ---------------------------------------------------------------------------
 # Heterogeneous media: the edge and face averaging of eps, sigma, mu and the
 # pole increments (Section 2.1, eqs. 2-5 with per-cell parameters)
