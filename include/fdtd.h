@@ -153,15 +153,28 @@ int fdtd_add_source(fdtd_ctx* c, int kind, int axis, int i, int j, int k,
  * is the same-weighted sum of those edges' E over the segment length.
  * src_seg >= 0 drives that segment's current with amps[n] (A, at
  * (n + 1/2) dt; 0 after the last sample; n_amps may be 0); rec_seg >= 0
- * records that segment's current every step.  Grids with oblique wires run
- * one-step passes (the two-step pass, asked for or chosen by default, gives
- * way to the fused pass; the split pass stays available), cannot take
- * Debye media (FDTD_EINVAL either way round) and cannot join a batch.  id (may be NULL) receives the wire's index.
+ * records that segment's current every step.  Every pass variant takes
+ * oblique wires (in the two-step pass the touched edges are sources whose
+ * amplitudes the wire kernels write before each pass; all variants give the
+ * same bits).  Grids with oblique wires cannot take Debye media
+ * (FDTD_EINVAL either way round) and cannot join a batch.  id (may be NULL)
+ * receives the wire's index.
  * FDTD_ERANGE for an end point out of range or a segment index outside
  * [-1, n_seg), FDTD_ENONFINITE for a non-finite end point or sample,
  * FDTD_ESTATE after the workspace size was taken. */
 int fdtd_add_oblique_wire(fdtd_ctx* ctx, const double* a, const double* b, double radius, int src_seg,
                           const double* amps, int n_amps, int rec_seg, int* id);
+
+/* Junction of oblique wires (the multiwire junctions of the oblique-wire
+ * formalism Section 2.3 cites): the n >= 2 wire ends ids[m], ends[m] (0: the
+ * wire's start a, 1: its end b), which must meet at one point (within 1e-6
+ * cells), become one node.  Its charge Q = sum_m q_m dl_m / 2 changes by
+ * the currents that flow into the point, and the members share one
+ * potential: q_m = C'_m Q / sum_m C'_m dl_m / 2.  A wire cut at one of its
+ * nodes and rejoined there is the uncut wire.  FDTD_EINVAL for n < 2, a bad
+ * id or end, an end listed twice or already in a junction, or ends that do
+ * not meet; FDTD_ESTATE after the workspace size was taken. */
+int fdtd_join_oblique_wires(fdtd_ctx* ctx, int n, const int* ids, const int* ends);
 
 /* State of oblique wire id: segment currents (n_seg values, A), end-point
  * charges per unit length (n_seg + 1, C/m) and the recorded current

@@ -125,6 +125,13 @@ struct OWireView {
   const int* wsrc;            // [n_edge] source-list row of each touched edge
   const int* g_edge;          // per gather term: its edge's index in e_key
   double* e1;                 // [n_edge] E^{n+1} at the touched edges (two-step passes)
+  // junctions: members jn_off[J] .. jn_off[J+1] of junction J, each the
+  // index of its end node in q, its half segment (m) and its C' (F/m)
+  int n_junc;
+  const int* jn_off;
+  const int* jn_q;
+  const double* jn_a;
+  const double* jn_c;
 };
 
 // Kernel launchers (fdtd_kernels.hip).  `view` points to a GridView<float>

@@ -30,7 +30,13 @@ struct WireRec { int axis, p[3], n; double radius; };
 struct SrcRec { int axis, p[3]; std::vector<double> amps; };
 // oblique thin wire as given: end points in cells, radius, driven and
 // recorded segment, driving current
-struct OWireRec { double a[3], b[3], radius; int src, rec; std::vector<double> amps; };
+struct OWireRec {
+  double a[3], b[3], radius;
+  int src, rec;
+  int junc[2] = {-1, -1};  // junction of the start (0) and end (1) node, -1: open end
+  std::vector<double> amps;
+};
+struct OJuncRec { std::vector<int> wire, end; };
 struct LumpedRec { int kind, axis, p[3]; double value; };
 struct ProbeRec { int kind, axis, p[3], n; };
 
@@ -73,6 +79,10 @@ struct fdtd_ctx {
   std::vector<WireRec> wires;
   std::vector<SrcRec> srcs;
   std::vector<OWireRec> owr;
+  std::vector<OJuncRec> ojn;
+  std::vector<int> jn_off, jn_q;
+  std::vector<double> jn_a, jn_c;
+  size_t off_jn_off = 0, off_jn_q = 0, off_jn_a = 0, off_jn_c = 0;
   std::vector<OWireParam> ow_par;
   std::vector<int> ow_seg_off, ow_eoff, ow_jseg;
   std::vector<long long> ow_gkey, ow_ekey;
@@ -654,6 +664,24 @@ void build_owires(fdtd_ctx* c) {
   c->ow_gedge.clear();  // e_key is sorted, so each gather term finds its edge by bisection
   for (long long key : c->ow_gkey)
     c->ow_gedge.push_back((int)(std::lower_bound(c->ow_ekey.begin(), c->ow_ekey.end(), key) - c->ow_ekey.begin()));
+  // junction members: index of the end node in q (wire w's nodes start at
+  // seg0 + w), half segment length (m) and C'
+  c->jn_off.assign(1, 0);
+  c->jn_q.clear(); c->jn_a.clear(); c->jn_c.clear();
+  for (const OJuncRec& J : c->ojn) {
+    for (size_t m = 0; m < J.wire.size(); ++m) {
+      const int w = J.wire[m];
+      const OWireRec& r = c->owr[w];
+      const OWireParam& p = c->ow_par[w];
+      double len = 0.0;
+      for (int u = 0; u < 3; ++u) len += (r.b[u] - r.a[u]) * (r.b[u] - r.a[u]);
+      const double dlm = std::sqrt(len) / p.nseg * dx, lg = std::log(r0 / r.radius);
+      c->jn_q.push_back(p.seg0 + w + (J.end[m] ? p.nseg : 0));
+      c->jn_a.push_back(0.5 * dlm);
+      c->jn_c.push_back(2.0 * kPi * kEps0 / lg);
+    }
+    c->jn_off.push_back((int)c->jn_q.size());
+  }
 }
 
 // The wires' touched edges join the source list after the ideal sources
@@ -760,6 +788,10 @@ void layout(fdtd_ctx* c) {
   c->off_ow_wsrc = take(c->ow_wsrc.size() * sizeof(int));
   c->off_ow_gedge = take(c->ow_gedge.size() * sizeof(int));
   c->off_ow_e1 = take(c->ow_ekey.size() * sizeof(double));
+  c->off_jn_off = take(c->jn_off.size() * sizeof(int));
+  c->off_jn_q = take(c->jn_q.size() * sizeof(int));
+  c->off_jn_a = take(c->jn_a.size() * sizeof(double));
+  c->off_jn_c = take(c->jn_c.size() * sizeof(double));
   c->off_ow_cur = take((size_t)c->ow_seg * sizeof(double));
   c->off_ow_q = take((size_t)(c->ow_seg + c->owr.size()) * sizeof(double));
   c->off_ow_rec = take(c->owr.size() * (size_t)c->P.max_steps * sizeof(double));
@@ -918,6 +950,11 @@ int upload(fdtd_ctx* c) {
     w.wsrc = (const int*)(c->ws + c->off_ow_wsrc);
     w.g_edge = (const int*)(c->ws + c->off_ow_gedge);
     w.e1 = (double*)(c->ws + c->off_ow_e1);
+    w.n_junc = (int)c->ojn.size();
+    w.jn_off = (const int*)(c->ws + c->off_jn_off);
+    w.jn_q = (const int*)(c->ws + c->off_jn_q);
+    w.jn_a = (const double*)(c->ws + c->off_jn_a);
+    w.jn_c = (const double*)(c->ws + c->off_jn_c);
     const Up wups[] = {
         {(void*)w.par, c->ow_par.data(), c->ow_par.size() * sizeof(OWireParam)},
         {(void*)w.seg_off, c->ow_seg_off.data(), c->ow_seg_off.size() * sizeof(int)},
@@ -930,6 +967,10 @@ int upload(fdtd_ctx* c) {
         {(void*)w.amp, c->ow_amp.data(), c->ow_amp.size() * sizeof(double)},
         {(void*)w.wsrc, c->ow_wsrc.data(), c->ow_wsrc.size() * sizeof(int)},
         {(void*)w.g_edge, c->ow_gedge.data(), c->ow_gedge.size() * sizeof(int)},
+        {(void*)w.jn_off, c->jn_off.data(), c->jn_off.size() * sizeof(int)},
+        {(void*)w.jn_q, c->jn_q.data(), c->jn_q.size() * sizeof(int)},
+        {(void*)w.jn_a, c->jn_a.data(), c->jn_a.size() * sizeof(double)},
+        {(void*)w.jn_c, c->jn_c.data(), c->jn_c.size() * sizeof(double)},
     };
     for (const Up& u : wups) {
       e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, st);
@@ -1104,6 +1145,37 @@ int fdtd_add_oblique_wire(fdtd_ctx* c, const double* a, const double* b, double 
   if (n_amps) r.amps.assign(amps, amps + n_amps);
   c->owr.push_back(r);
   if (id) *id = (int)c->owr.size() - 1;
+  return FDTD_OK;
+}
+
+int fdtd_join_oblique_wires(fdtd_ctx* c, int n, const int* ids, const int* ends) {
+  if (!c || n < 2 || !ids || !ends) return fail(c, FDTD_EINVAL, "bad junction arguments");
+  if (c->frozen) return fail(c, FDTD_ESTATE, "set-up after the workspace size was taken");
+  OJuncRec J;
+  double p0[3] = {0, 0, 0};
+  for (int m = 0; m < n; ++m) {
+    if (ids[m] < 0 || ids[m] >= (int)c->owr.size() || (ends[m] != 0 && ends[m] != 1))
+      return fail(c, FDTD_EINVAL, "bad oblique-wire id or end in a junction");
+    const OWireRec& r = c->owr[ids[m]];
+    if (r.junc[ends[m]] >= 0) return fail(c, FDTD_EINVAL, "oblique-wire end already in a junction");
+    for (int q = 0; q < m; ++q)
+      if (ids[q] == ids[m] && ends[q] == ends[m]) return fail(c, FDTD_EINVAL, "oblique-wire end listed twice");
+    // the end node as the wire's own segmentation places it
+    const int ns = owire_segments(r);
+    double d[3], len = 0.0, p[3];
+    for (int u = 0; u < 3; ++u) { d[u] = r.b[u] - r.a[u]; len += d[u] * d[u]; }
+    len = std::sqrt(len);
+    for (int u = 0; u < 3; ++u) p[u] = r.a[u] + (ends[m] ? ns * (len / ns) * d[u] / len : 0.0);
+    if (m == 0)
+      std::memcpy(p0, p, sizeof(p0));
+    else
+      for (int u = 0; u < 3; ++u)
+        if (std::fabs(p[u] - p0[u]) > 1e-6) return fail(c, FDTD_EINVAL, "joined oblique-wire ends do not meet");
+    J.wire.push_back(ids[m]);
+    J.end.push_back(ends[m]);
+  }
+  for (int m = 0; m < n; ++m) c->owr[ids[m]].junc[ends[m]] = (int)c->ojn.size();
+  c->ojn.push_back(J);
   return FDTD_OK;
 }
 

@@ -757,6 +757,23 @@ __global__ void __launch_bounds__(64) k_owire_q(GridView<T> g, OWireView w, int 
   if (j == 0 && p.rec >= 0) w.rec[(size_t)blockIdx.y * w.max_steps + step] = cur[p.rec];
 }
 
+// Junctions, after k_owire_q: that kernel moved each member end node's
+// charge by its own segment's current as for an open end, so the members'
+// charges sum (times their half segments) to the junction's new charge;
+// they then take the shared potential, q_m = C'_m Q / sum_m C'_m len_m.  One
+// thread per junction, members in table order (FP64).
+__global__ void __launch_bounds__(64) k_owire_junc(OWireView w) {
+  const int J = (int)(blockIdx.x * 64 + threadIdx.x);
+  if (J >= w.n_junc) return;
+  double Q = 0.0, cap = 0.0;
+  for (int m = w.jn_off[J]; m < w.jn_off[J + 1]; ++m) {
+    Q += w.q[w.jn_q[m]] * w.jn_a[m];
+    cap += w.jn_c[m] * w.jn_a[m];
+  }
+  const double V = Q / cap;
+  for (int m = w.jn_off[J]; m < w.jn_off[J + 1]; ++m) w.q[w.jn_q[m]] = w.jn_c[m] * V;
+}
+
 // The touched edges' source amplitudes of step `step`: one thread per edge
 // sums its terms in increasing segment order (FP64), times the edge's Cb / dx.
 template <typename T, typename CI>
@@ -819,6 +836,7 @@ int launch_owire_iq(int prec, const void* view, const OWireView* ow, int step, i
     else hipLaunchKernelGGL((k_owire_cur<float, false>), gc, dim3(64), 0, st, g, *ow, step);
     hipLaunchKernelGGL((k_owire_q<float>), gq, dim3(64), 0, st, g, *ow, step);
   }
+  if (ow->n_junc > 0) hipLaunchKernelGGL(k_owire_junc, dim3((unsigned)((ow->n_junc + 63) / 64)), dim3(64), 0, st, *ow);
   return (int)hipGetLastError();
 }
 

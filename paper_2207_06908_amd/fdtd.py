@@ -46,6 +46,7 @@ SIGNATURES = [
                                         C.POINTER(C.c_int)]),
     ("fdtd_oblique_wire_read", C.c_int, [_vp, C.c_int, _vp, _vp, _vp, C.c_int, C.POINTER(C.c_int),
                                          C.POINTER(C.c_int)]),
+    ("fdtd_join_oblique_wires", C.c_int, [_vp, C.c_int, _vp, _vp]),
     ("fdtd_add_source_r", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int, C.c_double]),
     ("fdtd_add_wire", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]),
     ("fdtd_add_source", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int]),
@@ -184,6 +185,15 @@ class Grid:
         self._chk(lib().fdtd_add_oblique_wire(self._h, pa.ctypes.data, pb.ctypes.data, float(radius), int(src_seg),
                                               am.ctypes.data, am.size, int(rec_seg), C.byref(wid)))
         return wid.value
+
+    def join_oblique_wires(self, ids, ends) -> None:
+        """Junction of the listed wire ends (0: the wire's start a, 1: its end
+        b), which must meet at one point."""
+        iv = np.ascontiguousarray(ids, dtype=np.int32)
+        ev = np.ascontiguousarray(ends, dtype=np.int32)
+        if iv.size != ev.size:
+            raise ValueError("ids and ends differ in length")
+        self._chk(lib().fdtd_join_oblique_wires(self._h, int(iv.size), iv.ctypes.data, ev.ctypes.data))
 
     def oblique_wire_segments(self, wid) -> int:
         ns = C.c_int(0)

@@ -166,6 +166,8 @@ class Scenario:
     sources_r: List[Tuple[int, int, int, int, int, np.ndarray, float]] = field(default_factory=list)
     # oblique thin wires: (end a, end b in cells, radius, driven segment, amps, recorded segment)
     owires: List[tuple] = field(default_factory=list)
+    # junctions of oblique wires: (wire ids, ends: 0 the wire's start, 1 its end)
+    ojunctions: List[tuple] = field(default_factory=list)
     meta: dict = field(default_factory=dict)
 
     @property
@@ -196,6 +198,8 @@ def apply(sc: Scenario, sim) -> List[int]:
         sim.add_lumped(kind, ax, i, j, k, v)
     for (a, b, r, src, amps, rec) in sc.owires:
         sim.add_oblique_wire(a, b, r, src, amps, rec)
+    for (ids, ends) in sc.ojunctions:
+        sim.join_oblique_wires(ids, ends)
     ids = []
     for (_name, kind, ax, i, j, k, n) in sc.probes:
         ids.append(sim.add_probe(kind, ax, i, j, k, n))

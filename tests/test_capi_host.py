@@ -230,6 +230,27 @@ def test_lumped_and_nonideal_source_validation():
     assert _code(lambda: w.workspace_bytes() or w.finalize()) == -2
 
 
+def test_oblique_wire_junction_validation():
+    """fdtd_join_oblique_wires: at least two ends, valid ids and ends (0 or
+    1), no end listed twice or joined twice, ends that meet (within 1e-6
+    cells), and only before the workspace size is taken."""
+    g = _grid(npml=0)
+    w0 = g.add_oblique_wire((2, 2, 2), (5, 5, 5), 0.01)
+    w1 = g.add_oblique_wire((5, 5, 5), (2, 6, 3), 0.01)
+    w2 = g.add_oblique_wire((2, 2, 5), (5, 2, 2), 0.01)
+    w3 = g.add_oblique_wire((2, 2, 2), (2, 6, 6), 0.004)
+    assert _code(lambda: g.join_oblique_wires([w0], [1])) == -1                 # one end
+    assert _code(lambda: g.join_oblique_wires([w0, 4], [1, 0])) == -1           # no wire 4
+    assert _code(lambda: g.join_oblique_wires([w0, w1], [1, 2])) == -1          # end not 0 or 1
+    assert _code(lambda: g.join_oblique_wires([w0, w2], [1, 0])) == -1          # (5,5,5) vs (2,2,5)
+    assert _code(lambda: g.join_oblique_wires([w0, w1, w0], [1, 0, 1])) == -1   # listed twice
+    g.join_oblique_wires([w0, w1], [1, 0])
+    assert _code(lambda: g.join_oblique_wires([w1, w0], [0, 1])) == -1          # already joined
+    g.join_oblique_wires([w3, w0], [0, 0])                                      # both start at (2,2,2)
+    g.workspace_bytes()
+    assert _code(lambda: g.join_oblique_wires([w2, w1], [1, 1])) == -3
+
+
 def test_oblique_wire_validation():
     """fdtd_add_oblique_wire: ends one cell clear of the walls (and CPML), at
     least one cell long, 0 < radius < r0, segment indices in [-1, n_seg),

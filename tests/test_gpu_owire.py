@@ -159,6 +159,84 @@ def test_owire_variants_bitwise_equal(fd, dims, npml):
             assert np.array_equal(a, b), runs[r]
 
 
+def _junction_case(nx, ny, nz, npml, seed, nsteps=60, n_mats=6):
+    """The random case plus a driven trunk that meets three branches at one
+    off-grid point J (two start there, with radii 4 and 10 mm; one ends
+    there, 2 mm), and a second junction at K, where one branch ends and a
+    further wire starts."""
+    sc = S.random_case(nx, ny, nz, npml, seed=seed, nsteps=nsteps, n_mats=n_mats)
+    amps = S.gaussian(nsteps, sc.dt, 12 * sc.dt, 4 * sc.dt, 3.0)
+    lo = npml + 1.0
+    hx, hy, hz = nx - npml - 2.0, ny - npml - 2.0, nz - npml - 2.0
+    J = (0.5 * (lo + hx) + 0.37, 0.5 * (lo + hy) - 0.21, 0.5 * (lo + hz) + 0.43)
+    K = (hx - 0.3, hy - 0.6, hz - 0.4)
+    sc.owires = [((lo + 0.3, lo + 0.6, lo + 0.2), J, 0.004, 1, amps, 2),
+                 (J, K, 0.004, -1, None, 1),
+                 (J, (lo + 0.4, hy - 0.3, hz - 0.5), 0.01, -1, None, 0),
+                 ((hx - 0.2, lo + 0.5, hz - 0.7), J, 0.002, -1, None, 1),
+                 (K, (hx - 0.5, lo + 1.2, lo + 0.9), 0.003, -1, None, 0)]
+    sc.ojunctions = [([0, 1, 2, 3], [1, 0, 0, 1]), ([1, 4], [1, 0])]
+    return sc
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])   # auto, split, fused, two-step
+@pytest.mark.parametrize("dims,npml", [((40, 24, 22), 4), ((21, 19, 17), 0)])
+def test_owire_junctions_elementwise(fd, oracle_mod, variant, dims, npml):
+    """Junctions of oblique wires: fields, currents, charges and records
+    against the oracle, element by element; every wire picks up current
+    through the junctions, and the members of a junction share one
+    potential (q / C')."""
+    sc = _junction_case(*dims, npml, seed=dims[0] + 23)
+    print(f"owire junctions {dims} npml={npml} variant={variant}", flush=True)
+    o = oracle_mod.Oracle.from_params(sc.params())
+    S.apply(sc, o)
+    o.step(sc.n_steps)
+    for w in range(1, 5):
+        assert np.abs(o.oblique_wire(w)[0]).max() > 0, w
+    for prec, tol in ((64, 1e-11), (32, 2e-5)):
+        g = fd.Grid.from_params(sc.params(), precision=prec)
+        S.apply(sc, g)
+        g.set_kernel(variant)
+        g.step(sc.n_steps)
+        for c in range(6):
+            ref, got = o.get_field(c), g.get_field(c)
+            scale = max(float(np.abs(ref).max()), 1e-300)
+            assert float(np.abs(got - ref).max()) / scale <= tol, (prec, c)
+        for w in range(len(sc.owires)):
+            for ref, got in zip(o.oblique_wire(w), g.oblique_wire(w)):
+                assert ref.shape == got.shape
+                scale = max(float(np.abs(ref).max()), 1e-300)
+                assert float(np.abs(got - ref).max()) / scale <= tol, (prec, w)
+        # members of J: q_end / C' equal, C' = 2 pi eps0 / ln(r0 / a)
+        r0 = sc.wire_r0_factor * sc.dx
+        pot = [g.oblique_wire(w)[1][-1 if e else 0] * np.log(r0 / sc.owires[w][2])
+               for w, e in zip(*sc.ojunctions[0])]
+        np.testing.assert_allclose(pot, pot[0], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("dims,npml", [((77, 21, 15), 4), ((41, 19, 17), 0)])
+def test_owire_junctions_variants_bitwise_equal(fd, dims, npml):
+    """With junctions, too, every variant and tile shape gives the bits of
+    the split pass (the junction update runs with the wire kernels before
+    each pass, and twice in a two-step pass)."""
+    sc = _junction_case(*dims, npml, seed=dims[0] + 5, nsteps=41, n_mats=3)
+    runs = [(1, 0, 0, [41]), (2, 8, 32, [41]), (3, 8, 20, [41]), (3, 4, 8, [2, 39]), (0, 0, 0, [41])]
+    print(f"owire junction variants {dims} npml={npml}", flush=True)
+    outs = []
+    for variant, ty, kz, chunks in runs:
+        g = fd.Grid.from_params(sc.params(), precision=32)
+        ids = S.apply(sc, g)
+        g.set_kernel(variant, ty, kz)
+        for c in chunks:
+            g.step(c)
+        outs.append([g.get_field(c) for c in range(6)] + [g.probe(i) for i in ids]
+                    + [x for w in range(5) for x in g.oblique_wire(w)])
+    assert np.abs(outs[0][0]).max() > 0
+    for r in range(1, len(runs)):
+        for a, b in zip(outs[0], outs[r]):
+            assert np.array_equal(a, b), runs[r]
+
+
 def test_owire_runs_are_bitwise_reproducible(fd):
     """FP32: two runs of the skew-wire case give the same bits in every
     field and in the wire state (each touched edge sums its wire terms in a
