@@ -274,6 +274,38 @@ def bench_oblique(steps: int = 400, warmup: int = 20):
     return out
 
 
+def bench_tower(steps: int = 400, warmup: int = 20):
+    """The 512 x 512 x 384 scene with a lightning strike to a 30 m lattice
+    tower of 15 oblique wires joined at 5 junctions (scenarios.config2_tower):
+    the two-step pass with the wire kernels beside it."""
+    import torch
+    from paper_2207_06908_amd import fdtd
+    from paper_2207_06908_amd import scenarios as S
+    sc = S.config2_tower(n_steps=warmup + steps)
+    g = fdtd.Grid.from_params(sc.params(), precision=32)
+    S.apply(sc, g)
+    g.bind()
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    segs = sum(g.oblique_wire_segments(w) for w in range(len(sc.owires)))
+    out = {"workload": "512x512x384 Yee FDTD grid and soil as above; a 30 m lattice tower of oblique wires (4 legs "
+                       f"cut at a ring, a 4-wire ring, 2 cross-arms; {len(sc.owires)} wires, {segs} segments, "
+                       f"{len(sc.ojunctions)} junctions) struck through a channel wire by 10 kA 1/50 us",
+           "kernel": "k_tb2_list (two-step pass over CPML groups; the wires' edges are sources written by "
+                     "k_owire_cur/k_owire_q/k_owire_junc/k_owire_amp/k_owire_e1 on a third stream)",
+           "steps": steps, "value": round(sc.cells * steps / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
+           "ms_per_step": round(ms / steps, 5)}
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_array(steps: int = 20000, warmup: int = 2000):
     """The apparent-resistivity array (100 x 100 x 80 cells, three Debye soil
     layers, Heidler source): a bounded window of its 4.2M-step run."""
@@ -408,7 +440,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="batched leg: fixed 32x8 tiles, TZ 32")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-in-the-loop measurement")
     ap.add_argument("--no-debye", action="store_true", help="skip the Debye-soil, lumped-element, oblique-wire and array measurements")
-    ap.add_argument("--legs", default="debye,lumped,oblique,array",
+    ap.add_argument("--legs", default="debye,lumped,oblique,tower,array",
                     help="which of the Debye-soil, lumped-element, oblique-wire and array measurements to run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run plain copies of MIB MiB (profiler counter calibration)")
@@ -500,7 +532,7 @@ def main():
     if not a.no_debye:
         legs = a.legs.split(",")
         for leg, fn in (("debye", bench_debye), ("lumped", bench_lumped), ("oblique", bench_oblique),
-                        ("array", bench_array)):
+                        ("tower", bench_tower), ("array", bench_array)):
             if leg in legs:
                 out[leg] = fn()
     if not a.no_surrogate:

@@ -480,6 +480,54 @@ def config3(n_grids: int = 256, seed: int = 3, n_steps: int = 2000) -> List[Scen
     return out
 
 
+def config2_tower(**kw) -> Scenario:
+    """A lightning strike to a lattice tower of oblique wires, like the
+    tower example of Section 4.2 (whose dimensions the paper takes from an
+    earlier publication; these are this scene's own): the config-2 grid and
+    soil (any of config2's size arguments), without its mast and source.
+
+    A 30 m tower: four legs (5 cm) from footings 1 m deep at the corners of
+    an 8 m square to an apex, each cut at 15 m, where a ring of four wires
+    (2 cm) joins them; two inclined cross-arms (3 cm) from the apex to tips
+    7 m out and 3 m lower; above the apex a vertical channel wire (5 mm) to
+    the top of the domain, driven at its lowest segment by the scene's
+    10 kA 1/50 us current.  Five junctions: the apex (seven wire ends) and
+    the four ring corners (four each).  Every point sits off the lattice by
+    a fraction of a cell.  Probes: the voltage from each arm tip 2 m down
+    (across an insulator string to a phase conductor that the scene leaves
+    out), the ground-surface fields of config 2; records: the channel
+    current and the current into one footing."""
+    sc = config2(**kw)
+    sc.name = sc.name.replace("config2", "config2_tower")
+    _ax, ic, jc, ks, _n, _a = sc.wires[0]
+    amps = sc.sources[0][4]
+    sc.wires, sc.sources = [], []
+    sc.probes = [p for p in sc.probes if p[1] == PR_E]
+    dx, top = sc.dx, sc.nz - sc.npml - 2.6
+    c = lambda x, y, z: (ic + x / dx + 0.3, jc + y / dx - 0.2, ks + z / dx + 0.4)
+    T = np.array(c(0.0, 0.0, 30.0))
+    feet = [np.array(c(sx * 4.0, sy * 4.0, -1.0)) for sx, sy in ((1, 1), (-1, 1), (-1, -1), (1, -1))]
+    zr = ks + 15.0 / dx + 0.4
+    rings = [F + (zr - F[2]) / (T[2] - F[2]) * (T - F) for F in feet]
+    tips = [np.array(c(sx * 7.0, 0.0, 27.0)) for sx in (1, -1)]
+    tup = lambda v: tuple(float(x) for x in v)
+    ow = [(tup(T), (T[0], T[1], top), 0.005, 0, amps, 0)]                      # 0: channel
+    ow += [(tup(F), tup(M), 0.05, -1, None, 0 if q == 0 else -1) for q, (F, M) in enumerate(zip(feet, rings))]
+    ow += [(tup(M), tup(T), 0.05, -1, None, -1) for M in rings]                # 5..8: upper legs
+    ow += [(tup(rings[q]), tup(rings[(q + 1) % 4]), 0.02, -1, None, -1) for q in range(4)]  # 9..12: ring
+    ow += [(tup(T), tup(A), 0.03, -1, None, -1) for A in tips]                 # 13, 14: cross-arms
+    sc.owires = ow
+    sc.ojunctions = [([0, 5, 6, 7, 8, 13, 14], [0, 1, 1, 1, 1, 0, 0])]
+    for q in range(4):
+        sc.ojunctions.append(([1 + q, 5 + q, 9 + q, 9 + (q - 1) % 4], [1, 0, 0, 1]))
+    drop = max(1, int(round(2.0 / dx)))
+    for name, A in zip(("V_arm+x", "V_arm-x"), tips):
+        i, j, k = (int(np.floor(v)) for v in A)
+        sc.probes.append((name, PR_VLINE, AX_Z, i, j, k - drop, drop))
+    sc.meta.update(tower_top=tup(T), arm_tips=[tup(A) for A in tips])
+    return sc
+
+
 def config2_oblique(**kw) -> Scenario:
     """The config-2 scene (any of config2's size arguments) plus a slanted
     5 cm conductor in the air beside the vertical wire, like a tower leg:

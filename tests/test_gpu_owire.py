@@ -237,6 +237,40 @@ def test_owire_junctions_variants_bitwise_equal(fd, dims, npml):
             assert np.array_equal(a, b), runs[r]
 
 
+def test_tower_against_the_oracle_and_across_variants(fd, oracle_mod):
+    """The lattice-tower strike (15 oblique wires, 5 junctions, soil and
+    CPML) at 96 x 96 x 80 cells of 2 m: probes, fields and wire state against
+    the oracle for the split, fused and two-step passes (FP32), and the same
+    bits from all three."""
+    sc = S.config2_tower(nx=96, ny=96, nz=80, dx=2.0, npml=6, n_steps=120)
+    print("tower 96x96x80", flush=True)
+    o = oracle_mod.Oracle.from_params(sc.params())
+    oids = S.apply(sc, o)
+    o.step(sc.n_steps)
+    outs = []
+    for variant in (1, 2, 3):
+        g = fd.Grid.from_params(sc.params(), precision=32)
+        ids = S.apply(sc, g)
+        g.set_kernel(variant)
+        g.step(sc.n_steps)
+        for c in range(6):
+            ref, got = o.get_field(c), g.get_field(c)
+            assert float(np.abs(got - ref).max()) <= 2e-5 * float(np.abs(ref).max()), (variant, c)
+        for i, j in zip(oids, ids):
+            ref, got = o.probe(i), g.probe(j)
+            assert float(np.abs(got - ref).max()) <= 2e-5 * float(np.abs(ref).max()), (variant, i)
+        for w in range(len(sc.owires)):
+            for ref, got in zip(o.oblique_wire(w), g.oblique_wire(w)):
+                if ref.size:
+                    assert float(np.abs(got - ref).max()) <= 2e-5 * float(np.abs(ref).max()), (variant, w)
+        outs.append([g.get_field(c) for c in range(6)] + [g.probe(i) for i in ids]
+                    + [x for w in range(len(sc.owires)) for x in g.oblique_wire(w)])
+    assert np.abs(o.probe(oids[-1])).max() > 0 and np.abs(o.oblique_wire(1)[2]).max() > 0
+    for r in (1, 2):
+        for a, b in zip(outs[0], outs[r]):
+            assert np.array_equal(a, b), r
+
+
 def test_owire_runs_are_bitwise_reproducible(fd):
     """FP32: two runs of the skew-wire case give the same bits in every
     field and in the wire state (each touched edge sums its wire terms in a
