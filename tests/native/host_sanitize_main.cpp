@@ -45,6 +45,14 @@ static fdtd_ctx* grid(int nx, int ny, int nz, int npml, int steps, bool debye, b
     const double b[3] = {nx - npml - 2.5, ny - npml - 2.2, nz - npml - 2.1};
     int id = -1;
     EXPECT(fdtd_add_oblique_wire(c, a, b, 0.002, 1, amps.data(), steps, 2, &id) == FDTD_OK && id == 0);
+    // a second wire from the first one's end, joined there
+    const double e[3] = {npml + 1.6, ny - npml - 2.4, nz - npml - 2.6};
+    EXPECT(fdtd_add_oblique_wire(c, b, e, 0.004, -1, nullptr, 0, -1, &id) == FDTD_OK && id == 1);
+    const int ids[2] = {0, 1}, ends[2] = {1, 0}, bad[2] = {0, 7};
+    EXPECT(fdtd_join_oblique_wires(c, 1, ids, ends) == FDTD_EINVAL);
+    EXPECT(fdtd_join_oblique_wires(c, 2, bad, ends) == FDTD_EINVAL);
+    EXPECT(fdtd_join_oblique_wires(c, 2, ids, ends) == FDTD_OK);
+    EXPECT(fdtd_join_oblique_wires(c, 2, ids, ends) == FDTD_EINVAL);   // already joined
   }
   int pid = -1;
   EXPECT(fdtd_add_probe(c, FDTD_PR_E, 2, nx / 2, ny / 2 + 1, nz / 2 + 1, 1, &pid) == FDTD_OK);

@@ -84,6 +84,14 @@ int main() {
   EXPECT(orc_add_oblique_wire(s, a, far, 0.002, -1, nullptr, 0, -1, &wid) != ORC_OK);
   EXPECT(orc_add_oblique_wire(s, a, b, 0.002, 3, amps.data(), n, 5, &wid) == ORC_OK);
   EXPECT(orc_add_oblique_wire(s, a, b, 0.002, 99, amps.data(), n, 5, &wid) != ORC_OK);
+  // a second wire from the first one's end, joined there
+  const double e[3] = {4.4, 15.6, 9.2};
+  int w2 = -1;
+  EXPECT(orc_add_oblique_wire(s, b, e, 0.004, -1, nullptr, 0, -1, &w2) == ORC_OK);
+  const int ids[2] = {wid, w2}, ends[2] = {1, 0}, mism[2] = {0, 0};
+  EXPECT(orc_join_oblique_wires(s, 2, ids, mism) != ORC_OK);        // the two starts do not meet
+  EXPECT(orc_join_oblique_wires(s, 2, ids, ends) == ORC_OK);
+  EXPECT(orc_join_oblique_wires(s, 2, ids, ends) != ORC_OK);        // already joined
   EXPECT(orc_step(s, 40) == ORC_OK);
   int ns = 0, nr = 0;
   EXPECT(orc_oblique_wire_read(s, wid, nullptr, nullptr, nullptr, 0, &ns, &nr) == ORC_OK && ns > 0);

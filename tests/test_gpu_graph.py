@@ -29,6 +29,14 @@ def _case(kind):
         return sc, 2 if kind == "debye" else 1
     if kind == "tb2":
         return S.random_case(70, 29, 27, 4, seed=13, nsteps=48), 3
+    if kind == "junction":   # three oblique wires meeting at one point, two-step pass
+        sc = S.random_case(40, 24, 22, 4, seed=15, nsteps=48)
+        amps = S.gaussian(48, sc.dt, 10 * sc.dt, 3 * sc.dt, 2.0)
+        J = (20.37, 12.29, 11.93)
+        sc.owires = [((5.3, 5.7, 5.6), J, 0.004, 2, amps, 4), (J, (33.6, 17.1, 15.2), 0.01, -1, None, 1),
+                     ((33.2, 6.1, 6.4), J, 0.002, -1, None, 0)]
+        sc.ojunctions = [([0, 1, 2], [1, 0, 1])]
+        return sc, 3
     sc = S.random_case(40, 24, 22, 4, seed=14, nsteps=48)
     amps = S.gaussian(48, sc.dt, 10 * sc.dt, 3 * sc.dt, 2.0)
     sc.owires = [((5.3, 5.7, 5.6), (33.6, 17.1, 15.2), 0.004, 2, amps, 4)]
@@ -50,7 +58,7 @@ def _run(fd, sc, variant, graph, chunks):
     return seen, fields, wires
 
 
-@pytest.mark.parametrize("kind", ["debye", "debye_split", "tb2", "owire"])
+@pytest.mark.parametrize("kind", ["debye", "debye_split", "tb2", "owire", "junction"])
 def test_graph_replay_equals_eager(fd, kind):
     sc, variant = _case(kind)
     chunks = [3, G, G + 2, 1, G, 2 * G - 4, sc.n_steps - (3 + G + G + 2 + 1 + G + 2 * G - 4)]
