@@ -27,6 +27,11 @@ GRID_CANDIDATES: List[Tuple[int, int, int]] = (
     + [(fdtd.KERNEL_TB2, 4, tz) for tz in (16, 20, 28)]
     + [(fdtd.KERNEL_TB2, 12, tz) for tz in (16, 20, 24)]
 )
+# Grids with Debye media take the split pass or the fused pass (8-row tiles;
+# TZ-plane chunks of the CPML tile groups).  Their cache key needs its own
+# suffix (grid_key does not see the poles).
+DEBYE_CANDIDATES: List[Tuple[int, int, int]] = (
+    [(fdtd.KERNEL_SPLIT, 0, 0)] + [(fdtd.KERNEL_FUSED, 8, tz) for tz in (16, 24, 32, 48, 64)])
 # (TX, TY, TZ, persistent): one-step batch tiles, then two-step 60 x 8
 # tiles launched per CPML group (0) or as one persistent launch (1).
 BATCH_CANDIDATES: List[Tuple[int, int, int, int]] = (
