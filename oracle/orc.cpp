@@ -12,13 +12,16 @@
 // the thread count.
 //
 // Parity unpinned (no closed form or published value to check against): the
-// interface averaging of eps, sigma, mu and pole increments, and the thin-wire
-// scaling of pole increments in Debye media.  The oblique wire's equivalent
-// radius (the same r0 as the axis wires) and its vacuum L' and C' are a
-// reading (the paper names the model, not its equations); its transfer
-// weights, telegraph step and charge bookkeeping are pinned, and so is the
-// line it forms (speed c0; impedance within the accuracy stated at its
-// test).
+// exact thin-wire factor of the cited wire papers and their adaptation to
+// Debye media; the wires are pinned only at the method's accuracy against
+// transmission-line closed forms (in vacuum and in Debye soil).  The
+// interface averaging of eps, sigma, mu and pole increments is pinned by
+// mirror, rotation, resistor- and capacitor-network and layered-cavity
+// tests.  The oblique wire's equivalent radius (the same r0 as the axis
+// wires), its vacuum L' and C' and its junctions are a reading (the paper
+// names the model, not its equations); its transfer weights, telegraph step,
+// charge bookkeeping and junction update are pinned, and so is the line it
+// forms (speed c0; impedance within the accuracy stated at its test).
 #include "orc.h"
 
 #include <cmath>
