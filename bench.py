@@ -31,7 +31,7 @@ KERNEL_SOURCES = ("paper_2207_06908_amd/csrc/fdtd_kernels.hip", "paper_2207_0690
 MEASURED_TRAFFIC = {
     # (source hash, kernel variant, tile_y, tile_z): HBM bytes per step (all
     # launches of the step; a two-step pass counts half)
-    ("26452a23c07ee32f", "tb2", 8, 20): 4.031e9,
+    ("1d68a5ddc507c37a", "tb2", 8, 20): 4.029e9,
 }
 
 
@@ -154,7 +154,8 @@ def bench_batch(warmup: int = 100, graph_steps: int = 100, tune: bool = True):
     achieved = bytes_step * steps / (ms / 1e3) / 1e9
     out = {"workload": f"{len(scs)} independent electrode grids, 32-96^3 (x grown to fit the electrode), "
                        f"dx 0.25 m, 8-cell CPML, {steps} steps, HIP graph of {graph_steps} steps",
-           "kernel": (("k_tb2_batch_q: one persistent work-queue launch per two-step pass" if persistent
+           "kernel": (("k_tb2_batch_q: two persistent work-queue launches per two-step pass (tiles clear of "
+                        "the y slabs; the rest)" if persistent
                        else "k_tb2_batch: one launch per CPML group and two-step pass") if tile[0] == 60
                       else "k_fused_batch: one launch per step"),
            "tile": list(tile),

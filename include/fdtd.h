@@ -333,12 +333,13 @@ int fdtd_batch_bind_workspace(fdtd_batch* b, void* dev_ptr, size_t bytes);
  * single-step launch.  Results do not depend on the choice.
  * Default (32, 8, 32, 0).  Errors: EINVAL. */
 int fdtd_batch_set_kernel(fdtd_batch* b, int tile_x, int tile_y, int tile_z, int graph_steps);
-/* Two-step passes only: on = 1 (the default) runs each pass as one
- * persistent launch whose blocks take tiles from a work queue (every CPML
- * group in the one launch, each XCD starting on its own run of the tiles,
- * grid by grid); on = 0 launches the CPML groups separately (the x-slab
- * group on the second stream).  Results do not depend on the choice.
- * Errors: EINVAL. */
+/* Two-step passes only: on = 1 (the default) runs each pass as persistent
+ * launches whose blocks take tiles from work queues: one launch for the
+ * tiles clear of the y slabs (the x-slab code path), one on the second
+ * stream for the rest (the all-axes path; every tile in FP64), each XCD
+ * starting on its own run of a queue's tiles, grid by grid.  on = 0
+ * launches the CPML groups separately (the x-slab group on the second
+ * stream).  Results do not depend on the choice.  Errors: EINVAL. */
 int fdtd_batch_set_persistent(fdtd_batch* b, int on);
 /* Advance every grid n_steps steps.  Errors: ESTATE, ERANGE (beyond the
  * smallest max_steps), EDEVICE. */

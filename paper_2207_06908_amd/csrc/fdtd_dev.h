@@ -206,19 +206,25 @@ int launch_batch_probes(int prec, const void* views, const void* plist, int n, c
 int launch_batch_pass_tb2(int prec, int cls16, const void* views, const void* tiles, const int* counts,
                           const void* plist, int n_probes, const int* d_step, int offset, void* stream,
                           void* stream2, void* ev_fork, void* ev_join);
-// Batched two-step pass as one persistent launch (k_tb2_batch_q) of n_blocks
-// blocks over `tiles`: int4 (grid | group << 24, i0 | iw << 16, j0 | jh << 16,
-// k0 | kz << 16), grid by grid, in 8 runs [runs.start[x], runs.start[x + 1]),
-// one per XCD; `ctr` is 8 device ints (reset on the stream before the
-// launch).  Then the probes of both steps, as for launch_batch_pass_tb2.
+// Batched two-step pass as persistent launches (k_tb2_batch_q), one per code
+// path: path A (the x-slab instantiation) over tiles_a with blocks_a blocks
+// on `stream`, path B (the all-axes one) over tiles_b with blocks_b blocks
+// on `stream2` (forked and joined with the events when both have tiles; a
+// path with 0 blocks is skipped).  Tiles are int4 (grid | group << 24,
+// i0 | iw << 16, j0 | jh << 16, k0 | kz << 16), grid by grid, in 8 runs
+// [runs.start[x], runs.start[x + 1]), one per XCD; `ctr` is 16 device ints
+// (A's 8, then B's; reset on the stream before the launches).  Then the
+// probes of both steps, as for launch_batch_pass_tb2.
 struct QRuns {
   int start[9];
 };
-// Blocks of k_tb2_batch_q that fit on the device at once (0 on error).
-int batch_queue_blocks(int prec, int cls16);
-int launch_batch_pass_queue(int prec, int cls16, const void* views, const void* tiles, const QRuns* runs, int* ctr,
-                            int n_blocks, const void* plist, int n_probes, const int* d_step, int offset,
-                            void* stream);
+// Blocks of k_tb2_batch_q for path axp (5: A, 7: B) that fit on the device
+// at once (0 on error).
+int batch_queue_blocks(int prec, int cls16, int axp);
+int launch_batch_pass_queue(int prec, int cls16, const void* views, const void* tiles_a, const QRuns* runs_a,
+                            int blocks_a, const void* tiles_b, const QRuns* runs_b, int blocks_b, int* ctr,
+                            const void* plist, int n_probes, const int* d_step, int offset, void* stream,
+                            void* stream2, void* ev_fork, void* ev_join);
 // *d += v on the stream (advances the device step counter).
 int launch_add(int* d, int v, void* stream);
 // *d = v on the stream.

@@ -1783,13 +1783,15 @@ struct fdtd_batch {
   std::vector<int> tiles2;
   int tcnt[4] = {0, 0, 0, 0};
   size_t off_tiles2 = 0;
-  // the same tiles for the persistent launch (fdtd_batch_set_persistent):
-  // grid by grid, tagged with their group, in 8 runs (one per XCD), and the
-  // runs' 8 counters
+  // the same tiles for the persistent launches (fdtd_batch_set_persistent):
+  // one list per code path (x-slab instantiation, then all-axes), each grid
+  // by grid, tagged with their group, in 8 runs (one per XCD), and the runs'
+  // 2 x 8 counters
   bool persistent = true;
   std::vector<int> tiles_q;
-  QRuns runs{};
-  int q_blocks = 0;
+  QRuns runs[2] = {};
+  int nq[2] = {0, 0};
+  int q_blocks[2] = {0, 0};
   size_t off_tiles_q = 0, off_qctr = 0;
   char* ws = nullptr;
   int cur = 0;
@@ -1869,33 +1871,41 @@ void build_tiles_tb2(fdtd_batch* b) {
     b->tiles2.insert(b->tiles2.end(), grp[q].begin(), grp[q].end());
     b->tcnt[q] = (int)(grp[q].size() / 4);
   }
-  // Persistent list: the same tiles grid by grid (in the order above), the
-  // group in the top byte of the grid field, cut into 8 runs of about equal
-  // cell count.
+  // Persistent lists: the same tiles grid by grid (in the order above), the
+  // group in the top byte of the grid field; list 0 for the x-slab code path
+  // (groups 0 and 1), list 1 for the all-axes one (groups 2 and 3; every
+  // tile in FP64); each cut into 8 runs of about equal cell count.
   std::vector<std::vector<int>> per(b->grids.size());
   for (int q = 0; q < 4; ++q)
     for (size_t t = 0; t < grp[q].size(); t += 4)
       per[grp[q][t]].insert(per[grp[q][t]].end(), {grp[q][t] | (q << 24), grp[q][t + 1], grp[q][t + 2],
                                                    grp[q][t + 3]});
-  b->tiles_q.clear();
-  double total = 0;
-  std::vector<double> cells;
+  std::vector<int> lst[2];
+  std::vector<double> cells[2];
+  double total[2] = {0, 0};
   for (int g : order)
     for (size_t t = 0; t < per[g].size(); t += 4) {
-      b->tiles_q.insert(b->tiles_q.end(), per[g].begin() + t, per[g].begin() + t + 4);
       const int* e = &per[g][t];
-      cells.push_back((double)(e[1] >> 16) * (e[2] >> 16) * (e[3] >> 16));
-      total += cells.back();
+      const int w = (b->prec == 64 || ((e[0] >> 24) & 2)) ? 1 : 0;
+      lst[w].insert(lst[w].end(), e, e + 4);
+      cells[w].push_back((double)(e[1] >> 16) * (e[2] >> 16) * (e[3] >> 16));
+      total[w] += cells[w].back();
     }
-  const int n = (int)cells.size();
-  b->runs.start[0] = 0;
-  double acc = 0;
-  int x = 1;
-  for (int t = 0; t < n && x < 8; ++t) {
-    acc += cells[t];
-    while (x < 8 && acc >= total * x / 8.0) b->runs.start[x++] = t + 1;
+  b->tiles_q = lst[0];
+  b->tiles_q.insert(b->tiles_q.end(), lst[1].begin(), lst[1].end());
+  for (int w = 0; w < 2; ++w) {
+    const int n = (int)cells[w].size();
+    QRuns& r = b->runs[w];
+    b->nq[w] = n;
+    r.start[0] = 0;
+    double acc = 0;
+    int x = 1;
+    for (int t = 0; t < n && x < 8; ++t) {
+      acc += cells[w][t];
+      while (x < 8 && acc >= total[w] * x / 8.0) r.start[x++] = t + 1;
+    }
+    while (x <= 8) r.start[x++] = n;
   }
-  while (x <= 8) b->runs.start[x++] = n;
 }
 
 template <typename T>
@@ -1935,9 +1945,10 @@ int upload_tiles(fdtd_batch* b) {
     if (e == hipSuccess)
       e = hipMemcpyAsync(b->ws + b->off_tiles_q, b->tiles_q.data(), b->tiles_q.size() * sizeof(int),
                          hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess && !b->q_blocks) {
-      b->q_blocks = batch_queue_blocks(b->prec, b->cls16);
-      if (b->q_blocks <= 0) return bfail(b, FDTD_EDEVICE, "persistent launch size");
+    if (e == hipSuccess && !b->q_blocks[0]) {
+      b->q_blocks[0] = batch_queue_blocks(b->prec, b->cls16, 5);
+      b->q_blocks[1] = batch_queue_blocks(b->prec, b->cls16, 7);
+      if (b->q_blocks[0] <= 0 || b->q_blocks[1] <= 0) return bfail(b, FDTD_EDEVICE, "persistent launch size");
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -1966,10 +1977,12 @@ int batch_launch_pass(fdtd_batch* b, hipStream_t st, int p, int off) {
   const size_t vb = view_bytes(b->prec);
   const int* d_step = (const int*)(b->ws + b->off_step);
   if (b->persistent) {
-    const int nt = (int)(b->tiles_q.size() / 4);
-    int e = launch_batch_pass_queue(b->prec, b->cls16, b->ws + b->off_views + p * nv * vb, b->ws + b->off_tiles_q,
-                                    &b->runs, (int*)(b->ws + b->off_qctr), std::min(b->q_blocks, std::max(nt, 1)),
-                                    b->ws + b->off_plist, (int)(b->plist.size() / 2), d_step, off, (void*)st);
+    const int* tq = (const int*)(b->ws + b->off_tiles_q);
+    int e = launch_batch_pass_queue(b->prec, b->cls16, b->ws + b->off_views + p * nv * vb, tq, &b->runs[0],
+                                    std::min(b->q_blocks[0], b->nq[0]), tq + 4 * b->nq[0], &b->runs[1],
+                                    std::min(b->q_blocks[1], b->nq[1]), (int*)(b->ws + b->off_qctr),
+                                    b->ws + b->off_plist, (int)(b->plist.size() / 2), d_step, off, (void*)st,
+                                    (void*)b->aux, (void*)b->ev_fork, (void*)b->ev_join);
     if (e) return bfail(b, FDTD_EDEVICE, std::string("batch pass: ") + hipGetErrorString((hipError_t)e));
     return FDTD_OK;
   }
@@ -2046,7 +2059,7 @@ int fdtd_batch_pack(fdtd_ctx* const* grids, int n, void* hip_stream, fdtd_batch*
   b->off_tiles = take(max_tiles(b) * 4 * sizeof(int));
   b->off_tiles2 = take(max_tiles_tb2(b) * 4 * sizeof(int));
   b->off_tiles_q = take(max_tiles_tb2(b) * 4 * sizeof(int));
-  b->off_qctr = take(8 * sizeof(int));
+  b->off_qctr = take(16 * sizeof(int));
   b->off_plist = take(b->plist.size() * sizeof(int) + 8);
   b->off_step = take(sizeof(int));
   b->ws_bytes = o;

@@ -606,17 +606,21 @@ __global__ __launch_bounds__(64 * (TY + 4), (sizeof(T) == 8 ? 1 : 6)) void k_tb2
                                              *d_step + offset);
 }
 
-// Batched two-step pass as one persistent launch.  The tile list holds every
-// grid's tiles, grid by grid (larger grids first), each tagged with its CPML
-// group (grid | group << 24, i0 | iw << 16, j0 | jh << 16, k0 | kz << 16),
-// and is cut into 8 contiguous runs, one per XCD, so that a grid's tiles
-// share that XCD's L2.  A block takes tiles from its own XCD's run through
-// an atomic counter, then from the other runs in turn, and leaves once every
-// run is empty: each counter only grows, so every block finishes.  Tiles of
-// one pass write disjoint outputs and read only the pass's input set, so no
-// block waits for another.  The counters start at 0 (k_qreset before the
-// launch).
-template <typename T, typename CI>
+// Batched two-step pass as persistent launches, one per code path (AXP 5:
+// the x-slab instantiation, which also serves tiles clear of the x and y
+// slabs; AXP 7: the all-axes one, for y-slab and corner tiles, and every FP64
+// tile).  One kernel holding both paths spilled at its 80-register cap, and
+// each reload of a spill waited for all loads in flight.  A path's tile list
+// holds its tiles grid by grid (larger grids first), (grid | group << 24,
+// i0 | iw << 16, j0 | jh << 16, k0 | kz << 16), cut into 8 contiguous runs,
+// one per XCD, so that a grid's tiles share that XCD's L2.  A block takes
+// tiles from its own XCD's run through an atomic counter, then from the
+// other runs in turn, and leaves once every run is empty: each counter only
+// grows, so every block finishes.  Tiles of one pass write disjoint outputs
+// and read only the pass's input set, so no block waits for another (nor a
+// kernel for the other path's).  The counters start at 0 (k_qreset before
+// the launches).
+template <typename T, typename CI, int AXP>
 __global__ __launch_bounds__(768, (sizeof(T) == 8 ? 1 : 6)) void k_tb2_batch_q(const GridView<T>* __restrict__ views,
                                                                              const int4* __restrict__ tiles,
                                                                              QRuns runs, int* __restrict__ ctr,
@@ -637,20 +641,14 @@ __global__ __launch_bounds__(768, (sizeof(T) == 8 ? 1 : 6)) void k_tb2_batch_q(c
       const int4 t = tiles[base + q];
       const GridView<T>& g = views[t.x & 0xffffff];
       const int i0 = t.y & 0xffff, j0 = t.z & 0xffff, iw = t.y >> 16, jh = t.z >> 16;
-      const int k0 = t.w & 0xffff, k1 = k0 + (t.w >> 16), grp = t.x >> 24;
-      // two code paths (more spill at the 80-register cap): the x-slab one
-      // also serves tiles clear of the x and y slabs, the all-axes one the
-      // y-slab and corner tiles
-      if (sizeof(T) == 8 || (grp & 2))
-        tb2_tile<T, CI, true, 8, 7, false, true>(g, sm, i0, j0, iw, jh, k0, k1, step);
-      else
-        tb2_tile<T, CI, true, 8, 5, false, true>(g, sm, i0, j0, iw, jh, k0, k1, step);
+      const int k0 = t.w & 0xffff, k1 = k0 + (t.w >> 16);
+      tb2_tile<T, CI, true, 8, AXP, false, true>(g, sm, i0, j0, iw, jh, k0, k1, step);
     }
   }
 }
 
 __global__ void k_qreset(int* ctr) {
-  if (threadIdx.x < 8) ctr[threadIdx.x] = 0;
+  if (threadIdx.x < 16) ctr[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1185,40 +1183,71 @@ hipError_t batch_group_t(int q, const void* views, const int4* t, int count, con
 }
 
 template <typename T, typename CI>
-hipError_t batch_queue_t(const void* views, const int4* tiles, const QRuns& runs, int* ctr, int n_blocks,
-                         const int* d_step, int offset, hipStream_t st) {
+hipError_t batch_queue_t(const void* views, const int4* tiles_a, const QRuns& runs_a, int blocks_a,
+                         const int4* tiles_b, const QRuns& runs_b, int blocks_b, int* ctr, const int* d_step,
+                         int offset, hipStream_t st, hipStream_t st2, hipEvent_t ev_fork, hipEvent_t ev_join) {
+  const GridView<T>* v = (const GridView<T>*)views;
   hipLaunchKernelGGL(k_qreset, dim3(1), dim3(64), 0, st, ctr);
-  hipLaunchKernelGGL((k_tb2_batch_q<T, CI>), dim3((unsigned)n_blocks), dim3(768), 0, st, (const GridView<T>*)views,
-                     tiles, runs, ctr, d_step, offset);
+  // the all-axes path (slower per cell) on the second stream, launched
+  // first: both launches fill the device, so the x-slab path's blocks start
+  // as the all-axes ones drain and fill the end of the pass
+  const bool fork = blocks_a > 0 && blocks_b > 0;
+  hipError_t e = hipSuccess;
+  if (fork) {
+    e = hipEventRecord(ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st2, ev_fork, 0);
+    if (e != hipSuccess) return e;
+  }
+  if (blocks_b > 0)
+    hipLaunchKernelGGL((k_tb2_batch_q<T, CI, 7>), dim3((unsigned)blocks_b), dim3(768), 0, fork ? st2 : st, v,
+                       tiles_b, runs_b, ctr + 8, d_step, offset);
+  if (blocks_a > 0)
+    hipLaunchKernelGGL((k_tb2_batch_q<T, CI, 5>), dim3((unsigned)blocks_a), dim3(768), 0, st, v, tiles_a, runs_a, ctr,
+                       d_step, offset);
+  if (fork) {
+    e = hipEventRecord(ev_join, st2);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ev_join, 0);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 
-template <typename T, typename CI>
+template <typename T, typename CI, int AXP>
 int queue_blocks_t() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tb2_batch_q<T, CI>, 768, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tb2_batch_q<T, CI, AXP>, 768, 0) != hipSuccess) return 0;
   return cus * std::max(per, 1);
 }
 
-int batch_queue_blocks(int prec, int cls16) {
-  if (prec == 64) return cls16 ? queue_blocks_t<double, uint16_t>() : queue_blocks_t<double, uint8_t>();
-  return cls16 ? queue_blocks_t<float, uint16_t>() : queue_blocks_t<float, uint8_t>();
+int batch_queue_blocks(int prec, int cls16, int axp) {
+  if (prec == 64) {
+    if (axp == 5) return cls16 ? queue_blocks_t<double, uint16_t, 5>() : queue_blocks_t<double, uint8_t, 5>();
+    return cls16 ? queue_blocks_t<double, uint16_t, 7>() : queue_blocks_t<double, uint8_t, 7>();
+  }
+  if (axp == 5) return cls16 ? queue_blocks_t<float, uint16_t, 5>() : queue_blocks_t<float, uint8_t, 5>();
+  return cls16 ? queue_blocks_t<float, uint16_t, 7>() : queue_blocks_t<float, uint8_t, 7>();
 }
 
-int launch_batch_pass_queue(int prec, int cls16, const void* views, const void* tiles, const QRuns* runs, int* ctr,
-                            int n_blocks, const void* plist, int n_probes, const int* d_step, int offset,
-                            void* stream) {
-  hipStream_t st = (hipStream_t)stream;
-  const int4* t = (const int4*)tiles;
+int launch_batch_pass_queue(int prec, int cls16, const void* views, const void* tiles_a, const QRuns* runs_a,
+                            int blocks_a, const void* tiles_b, const QRuns* runs_b, int blocks_b, int* ctr,
+                            const void* plist, int n_probes, const int* d_step, int offset, void* stream,
+                            void* stream2, void* ev_fork, void* ev_join) {
+  hipStream_t st = (hipStream_t)stream, st2 = (hipStream_t)stream2;
+  hipEvent_t ef = (hipEvent_t)ev_fork, ej = (hipEvent_t)ev_join;
+  const int4 *ta = (const int4*)tiles_a, *tb = (const int4*)tiles_b;
   hipError_t e;
   if (prec == 64)
-    e = cls16 ? batch_queue_t<double, uint16_t>(views, t, *runs, ctr, n_blocks, d_step, offset, st)
-              : batch_queue_t<double, uint8_t>(views, t, *runs, ctr, n_blocks, d_step, offset, st);
+    e = cls16 ? batch_queue_t<double, uint16_t>(views, ta, *runs_a, blocks_a, tb, *runs_b, blocks_b, ctr, d_step,
+                                                offset, st, st2, ef, ej)
+              : batch_queue_t<double, uint8_t>(views, ta, *runs_a, blocks_a, tb, *runs_b, blocks_b, ctr, d_step,
+                                               offset, st, st2, ef, ej);
   else
-    e = cls16 ? batch_queue_t<float, uint16_t>(views, t, *runs, ctr, n_blocks, d_step, offset, st)
-              : batch_queue_t<float, uint8_t>(views, t, *runs, ctr, n_blocks, d_step, offset, st);
+    e = cls16 ? batch_queue_t<float, uint16_t>(views, ta, *runs_a, blocks_a, tb, *runs_b, blocks_b, ctr, d_step,
+                                               offset, st, st2, ef, ej)
+              : batch_queue_t<float, uint8_t>(views, ta, *runs_a, blocks_a, tb, *runs_b, blocks_b, ctr, d_step,
+                                              offset, st, st2, ef, ej);
   if (e != hipSuccess) return (int)e;
   return batch_probes_tb2(prec, cls16, views, plist, n_probes, d_step, offset, st);
 }
