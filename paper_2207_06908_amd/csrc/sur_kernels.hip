@@ -67,6 +67,49 @@ __device__ __forceinline__ float norm_cdf(float z, float& gz) {
   return z < 0.0f ? h : 1.0f - h;
 }
 
+// Epilogue of a wave's FM x FN fragments at (mw, nw): fragment (i, j) is
+// skipped unless vm[i] and vn[j].
+template <int EPI, int FM, int FN>
+__device__ __forceinline__ void gemm_store(const GemmArgs& g, const f32x4 (&c)[FM][FN], int mw, int nw, int lane,
+                                           const bool (&vm)[FM], const bool (&vn)[FN]) {
+  const int r16 = lane & 15;
+  const int rq = (lane >> 4) * 4;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    if (!vm[i]) continue;
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      if (!vn[j]) continue;
+      const int m0 = mw + 16 * i + rq, n = nw + 16 * j + r16;
+      uint32_t t16[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + r;
+        const float v = c[i][j][r];
+        if (EPI == EPI_GELU_TRAIN || EPI == EPI_GELU_INFER) {
+          const float z = v + g.bias[n];
+          float gz;
+          const float ph = norm_cdf(z, gz);
+          t16[r] = f2bf(z * ph);
+          g.o16[(size_t)m * g.ld16 + n] = (uint16_t)t16[r];
+          if (EPI == EPI_GELU_TRAIN) g.o32[(size_t)m * g.ld32 + n] = ph + z * (gz * kInvSqrt2Pi);
+        } else if (EPI == EPI_LINEAR) {
+          if (m < g.m_valid) g.o32[(size_t)m * g.ld32 + n] = v + g.bias[n];
+        } else if (EPI == EPI_BWD) {
+          const float dz = v * g.aux[(size_t)m * g.ldaux + n];
+          t16[r] = f2bf(dz);
+          g.o16[(size_t)m * g.ld16 + n] = (uint16_t)t16[r];
+          g.o32[(size_t)m * g.ld32 + n] = dz;
+        } else {  // EPI_DW
+          if (n < g.n_valid) g.o32[(size_t)m * g.ld32 + n] = v;
+        }
+      }
+      if (EPI == EPI_GELU_TRAIN || EPI == EPI_BWD)
+        *(uint2*)(g.oT + (size_t)n * g.ldT + m0) = make_uint2(t16[0] | (t16[1] << 16), t16[2] | (t16[3] << 16));
+    }
+  }
+}
+
 // One (32 F) x (32 F) output tile per block of four waves; each wave owns a
 // (16 F) x (16 F) quarter, F x F fragments.  F = 2 for small products (the
 // training batches: more blocks), F = 4 for large ones (twice the reuse of
@@ -119,40 +162,152 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   int k0 = 0;
   for (; k0 + 32 * KU <= g.K; k0 += 32 * KU) steps(k0, std::integral_constant<int, KU>());
   for (; k0 < g.K; k0 += 32) steps(k0, std::integral_constant<int, 1>());
-  const int rq = (lane >> 4) * 4;
+  gemm_store<EPI, F, F>(g, c, mw, nw, lane, vm, vn);
+}
+
+// Large aligned inference products (M and N multiples of 128, K of 64; the
+// hidden layers' GELU and the output layer's linear epilogue): the 128 x 128
+// output tile of k_gemm<EPI, 4>, four waves of 4 x 4 fragments each, with
+// the operands staged through LDS.  K advances in tiles of 64: the block
+// copies the 128 x 64 tiles of A and B into LDS once and every wave reads
+// its fragments there (in k_gemm two waves fetch each fragment from L2),
+// while the loads of the next K tile are in flight in registers.  Rows are
+// padded by 16 bytes (144-byte pitch), so the 16 rows of a fragment start
+// in 16 distinct groups of four banks.  Each accumulator takes its K steps
+// in the same order with the same instruction as k_gemm, and the epilogue
+// is k_gemm's: the outputs are the same bits.
+constexpr int GL_BM = 128, GL_BK = 64, GL_LD = GL_BK + 8;
+
+// k_gemm_lds's GELU epilogue: gemm_store<EPI_GELU_INFER, 4>'s arithmetic,
+// with the bfloat16 outputs staged in the wave's own 64 x 64 slice of LDS
+// (lt, pitch GL_LD) so that they leave in 16-byte row pieces instead of one
+// 2-byte store per value.
+__device__ __forceinline__ void gemm_store_gelu_lds(const GemmArgs& g, const f32x4 (&c)[4][4], int mw, int nw,
+                                                    int lane, uint16_t* lt) {
+  const int r16 = lane & 15, rq = (lane >> 4) * 4;
 #pragma unroll
-  for (int i = 0; i < F; ++i) {
-    if (!vm[i]) continue;
+  for (int i = 0; i < 4; ++i) {
 #pragma unroll
-    for (int j = 0; j < F; ++j) {
-      if (!vn[j]) continue;
-      const int m0 = mw + 16 * i + rq, n = nw + 16 * j + r16;
-      uint32_t t16[4];
+    for (int j = 0; j < 4; ++j) {
+      const int n = nw + 16 * j + r16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + r;
-        const float v = c[i][j][r];
-        if (EPI == EPI_GELU_TRAIN || EPI == EPI_GELU_INFER) {
-          const float z = v + g.bias[n];
-          float gz;
-          const float ph = norm_cdf(z, gz);
-          t16[r] = f2bf(z * ph);
-          g.o16[(size_t)m * g.ld16 + n] = (uint16_t)t16[r];
-          if (EPI == EPI_GELU_TRAIN) g.o32[(size_t)m * g.ld32 + n] = ph + z * (gz * kInvSqrt2Pi);
-        } else if (EPI == EPI_LINEAR) {
-          if (m < g.m_valid) g.o32[(size_t)m * g.ld32 + n] = v + g.bias[n];
-        } else if (EPI == EPI_BWD) {
-          const float dz = v * g.aux[(size_t)m * g.ldaux + n];
-          t16[r] = f2bf(dz);
-          g.o16[(size_t)m * g.ld16 + n] = (uint16_t)t16[r];
-          g.o32[(size_t)m * g.ld32 + n] = dz;
-        } else {  // EPI_DW
-          if (n < g.n_valid) g.o32[(size_t)m * g.ld32 + n] = v;
-        }
+        const float z = c[i][j][r] + g.bias[n];
+        float gz;
+        const float ph = norm_cdf(z, gz);
+        lt[(16 * i + rq + r) * GL_LD + 16 * j + r16] = (uint16_t)f2bf(z * ph);
       }
-      if (EPI == EPI_GELU_TRAIN || EPI == EPI_BWD)
-        *(uint2*)(g.oT + (size_t)n * g.ldT + m0) = make_uint2(t16[0] | (t16[1] << 16), t16[2] | (t16[3] << 16));
     }
+  }
+  // the slice is this wave's alone: its LDS writes done, its lanes read rows
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  const int ch = (lane & 7) * 8;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int row = (lane >> 3) + 8 * t;
+    *(uint4*)(g.o16 + (size_t)(mw + row) * g.ld16 + nw + ch) = *(const uint4*)(lt + row * GL_LD + ch);
+  }
+}
+
+template <int EPI>
+__global__ __launch_bounds__(256, 3) void k_gemm_lds(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t sm[2 * GL_BM * GL_LD];
+  uint16_t* const sa = sm;
+  uint16_t* const sb = sm + GL_BM * GL_LD;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // Blocks are dealt to the 8 XCDs round robin.  The column tiles of one row
+  // tile go to one XCD, one after another, so that the row tile of A comes
+  // from HBM once and from that XCD's L2 for the other column tiles (dealt
+  // in plain order, they would land on N / 128 different XCDs, and each
+  // would read it from HBM).
+  const int nt = g.N / GL_BM, b = blockIdx.x;
+  int mi, ni;
+  if ((g.M / GL_BM) % 8 == 0) {
+    const int q = b >> 3;
+    ni = q % nt;
+    mi = (b & 7) + 8 * (q / nt);
+  } else {
+    mi = b / nt;
+    ni = b % nt;
+  }
+  const int m0 = mi * GL_BM, n0 = ni * GL_BM;
+  // this thread's 16-byte pieces of a K tile: rows cr + 32 i, k offset ck
+  const int cr = tid >> 3, ck = (tid & 7) * 8;
+  const uint16_t* ga = g.A + (size_t)(m0 + cr) * g.lda + ck;
+  const uint16_t* gb = g.B + (size_t)(n0 + cr) * g.ldb + ck;
+  const size_t a32 = (size_t)32 * g.lda, b32 = (size_t)32 * g.ldb;
+  uint16_t* const la = sa + cr * GL_LD + ck;
+  uint16_t* const lb = sb + cr * GL_LD + ck;
+  // (named values, not arrays: an array would be kept in scratch memory
+  // across the asm statement below)
+  uint4 a0, a1, a2, a3, b0, b1, b2, b3;
+#define GL_FETCH(k0)                             \
+  a0 = *(const uint4*)(ga + (k0));               \
+  a1 = *(const uint4*)(ga + a32 + (k0));         \
+  a2 = *(const uint4*)(ga + 2 * a32 + (k0));     \
+  a3 = *(const uint4*)(ga + 3 * a32 + (k0));     \
+  b0 = *(const uint4*)(gb + (k0));               \
+  b1 = *(const uint4*)(gb + b32 + (k0));         \
+  b2 = *(const uint4*)(gb + 2 * b32 + (k0));     \
+  b3 = *(const uint4*)(gb + 3 * b32 + (k0));
+#define GL_STASH()                               \
+  *(uint4*)(la) = a0;                            \
+  *(uint4*)(la + 32 * GL_LD) = a1;               \
+  *(uint4*)(la + 64 * GL_LD) = a2;               \
+  *(uint4*)(la + 96 * GL_LD) = a3;               \
+  *(uint4*)(lb) = b0;                            \
+  *(uint4*)(lb + 32 * GL_LD) = b1;               \
+  *(uint4*)(lb + 64 * GL_LD) = b2;               \
+  *(uint4*)(lb + 96 * GL_LD) = b3;
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
+  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  const uint16_t* fa0 = sa + (wm + r16) * GL_LD + kq;
+  const uint16_t* fb0 = sb + (wn + r16) * GL_LD + kq;
+  f32x4 c[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[i][j] = f32x4{0, 0, 0, 0};
+  GL_FETCH(0)
+  GL_STASH()
+  __syncthreads();
+  for (int k0 = 0; k0 < g.K; k0 += GL_BK) {
+    const bool more = k0 + GL_BK < g.K;
+    if (more) {
+      GL_FETCH(k0 + GL_BK)
+    }
+    // keep the next tile's loads here, ahead of the products (the compiler
+    // would otherwise move them down to the LDS stores that use them)
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      bf16x8 fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        fa[i] = ld_frag(fa0 + 16 * i * GL_LD + 32 * s);
+        fb[i] = ld_frag(fb0 + 16 * i * GL_LD + 32 * s);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], c[i][j], 0, 0, 0);
+    }
+    __syncthreads();  // every wave is done with this tile
+    if (more) {
+      GL_STASH()
+      __syncthreads();
+    }
+  }
+#undef GL_FETCH
+#undef GL_STASH
+  if (EPI == EPI_GELU_INFER) {
+    // the last barrier of the loop has freed the tiles: wave w takes rows
+    // [64 w, 64 w + 64) of them
+    gemm_store_gelu_lds(g, c, m0 + wm, n0 + wn, lane, sm + w * 64 * GL_LD);
+  } else {
+    const bool all[4] = {true, true, true, true};
+    gemm_store<EPI, 4>(g, c, m0 + wm, n0 + wn, lane, all, all);
   }
 }
 
@@ -531,11 +686,25 @@ void launch_gemm_f(int epi, const GemmArgs& a, hipStream_t s) {
 }
 
 int launch_gemm(int epi, const GemmArgs& a, void* stream) {
-  // 128 x 128 block tiles once they still give every CU a few blocks
-  if ((long long)((a.M + 127) / 128) * ((a.N + 127) / 128) >= 1024)
-    launch_gemm_f<4>(epi, a, (hipStream_t)stream);
-  else
-    launch_gemm_f<2>(epi, a, (hipStream_t)stream);
+  const hipStream_t s = (hipStream_t)stream;
+  // 128 x 128 block tiles once they still give every CU a few blocks; the
+  // inference products staged through LDS where the shape is aligned to the
+  // tiles
+  if ((long long)((a.M + 127) / 128) * ((a.N + 127) / 128) >= 1024) {
+    const bool infer = epi == EPI_GELU_INFER || epi == EPI_LINEAR;
+    if (infer && a.M % GL_BM == 0 && a.N % GL_BM == 0 && a.K % GL_BK == 0 && a.K > 0 &&
+        (epi == EPI_LINEAR || a.ld16 % 8 == 0)) {
+      const dim3 grid((a.N / GL_BM) * (a.M / GL_BM)), block(256);
+      if (epi == EPI_GELU_INFER)
+        k_gemm_lds<EPI_GELU_INFER><<<grid, block, 0, s>>>(a);
+      else
+        k_gemm_lds<EPI_LINEAR><<<grid, block, 0, s>>>(a);
+    } else {
+      launch_gemm_f<4>(epi, a, s);
+    }
+  } else {
+    launch_gemm_f<2>(epi, a, s);
+  }
   return last();
 }
 
