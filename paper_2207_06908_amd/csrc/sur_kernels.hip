@@ -626,6 +626,103 @@ __global__ __launch_bounds__(256) void k_route(const float* __restrict__ ys, int
   if (lane == 0) spread[row] = any_out ? INFINITY : (pmax - pmin) / fabsf(psum / (float)nets);
 }
 
+// k_route for four nets and W a multiple of 4: a lane takes 4 adjacent
+// columns, with 16-byte loads and no branch around them.  Each column's sum
+// runs over the nets in the same order from 0, the peaks are exact maxima,
+// and the spread is formed as in k_route: the same bits.
+__global__ __launch_bounds__(256) void k_route4(const float* __restrict__ ys, long long ld_net, int m, int W,
+                                                const float* __restrict__ x, int kin, float xbound, float* ymean,
+                                                float* spread) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= m) return;
+  const bool out = lane < kin && !(fabsf(x[(long long)row * kin + lane]) <= xbound);
+  const bool any_out = __ballot(out) != 0;
+  float pk0 = -INFINITY, pk1 = -INFINITY, pk2 = -INFINITY, pk3 = -INFINITY;
+  const float* y0 = ys + (long long)row * W;
+  for (int c = 4 * lane; c < W; c += 256) {
+    const float4 v0 = *(const float4*)(y0 + c);
+    const float4 v1 = *(const float4*)(y0 + ld_net + c);
+    const float4 v2 = *(const float4*)(y0 + 2 * ld_net + c);
+    const float4 v3 = *(const float4*)(y0 + 3 * ld_net + c);
+    float4 sm;
+    sm.x = (((0.0f + v0.x) + v1.x) + v2.x) + v3.x;
+    sm.y = (((0.0f + v0.y) + v1.y) + v2.y) + v3.y;
+    sm.z = (((0.0f + v0.z) + v1.z) + v2.z) + v3.z;
+    sm.w = (((0.0f + v0.w) + v1.w) + v2.w) + v3.w;
+    *(float4*)(ymean + (long long)row * W + c) =
+        make_float4(sm.x / 4.0f, sm.y / 4.0f, sm.z / 4.0f, sm.w / 4.0f);
+    pk0 = fmaxf(pk0, fmaxf(fmaxf(v0.x, v0.y), fmaxf(v0.z, v0.w)));
+    pk1 = fmaxf(pk1, fmaxf(fmaxf(v1.x, v1.y), fmaxf(v1.z, v1.w)));
+    pk2 = fmaxf(pk2, fmaxf(fmaxf(v2.x, v2.y), fmaxf(v2.z, v2.w)));
+    pk3 = fmaxf(pk3, fmaxf(fmaxf(v3.x, v3.y), fmaxf(v3.z, v3.w)));
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    pk0 = fmaxf(pk0, __shfl_xor(pk0, o, 64));
+    pk1 = fmaxf(pk1, __shfl_xor(pk1, o, 64));
+    pk2 = fmaxf(pk2, __shfl_xor(pk2, o, 64));
+    pk3 = fmaxf(pk3, __shfl_xor(pk3, o, 64));
+  }
+  float pmax = -INFINITY, pmin = INFINITY, psum = 0.0f;
+  pmax = fmaxf(pmax, pk0), pmin = fminf(pmin, pk0), psum += pk0;
+  pmax = fmaxf(pmax, pk1), pmin = fminf(pmin, pk1), psum += pk1;
+  pmax = fmaxf(pmax, pk2), pmin = fminf(pmin, pk2), psum += pk2;
+  pmax = fmaxf(pmax, pk3), pmin = fminf(pmin, pk3), psum += pk3;
+  if (lane == 0) spread[row] = any_out ? INFINITY : (pmax - pmin) / fabsf(psum / 4.0f);
+}
+
+// Ordered list of the rows whose spread is above the threshold or not
+// finite, in one block of 1024 threads.  Thread t owns the contiguous rows
+// [t L, t L + L), L a multiple of 64 (64 for up to 65,536 rows).  It flags
+// them 64 at a time into a bit mask (16 16-byte loads issued together), and
+// a block scan of the counts gives each thread's first position.  The thread
+// then writes its rows in order from the masks (the first segment's mask is
+// kept, later ones are read again).
+__device__ __forceinline__ unsigned long long flag_mask(const float* __restrict__ spread, int s, int b, float thr) {
+  unsigned long long m = 0;
+  if (s + 64 <= b) {
+    float4 v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = *(const float4*)(spread + s + 4 * j);
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      m |= ((unsigned long long)!(v[j].x <= thr) << (4 * j)) | ((unsigned long long)!(v[j].y <= thr) << (4 * j + 1)) |
+           ((unsigned long long)!(v[j].z <= thr) << (4 * j + 2)) | ((unsigned long long)!(v[j].w <= thr) << (4 * j + 3));
+  } else {
+    for (int r = s; r < b; ++r) m |= (unsigned long long)!(spread[r] <= thr) << (r - s);
+  }
+  return m;
+}
+
+__global__ __launch_bounds__(1024) void k_compact_chunks(const float* __restrict__ spread, int n, float thr,
+                                                         int* __restrict__ ids, int* __restrict__ count) {
+  __shared__ int wsum[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int L = (((n + 1023) / 1024) + 63) & ~63;
+  const int a = min(t * L, n), b = min(a + L, n);
+  const unsigned long long m0 = a < b ? flag_mask(spread, a, b, thr) : 0ull;
+  int c = __popcll(m0);
+  for (int s = a + 64; s < b; s += 64) c += __popcll(flag_mask(spread, s, b, thr));
+  int incl = c;  // inclusive scan within the wave
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int base = 0;
+  for (int q = 0; q < w; ++q) base += wsum[q];
+  if (t == 1023) *count = base + incl;
+  int pos = base + incl - c;
+  for (int s = a; s < b; s += 64) {
+    unsigned long long m = s == a ? m0 : flag_mask(spread, s, b, thr);
+    while (m) {
+      ids[pos++] = s + __builtin_ctzll(m);
+      m &= m - 1;
+    }
+  }
+}
+
 // Ordered list of the rows whose spread is above the threshold or not finite,
 // in one block of 16 waves: the spreads are read 64 at a time (one per lane,
 // coalesced), counted by ballot, the counts of the 64-row pieces scanned in
@@ -746,12 +843,20 @@ int launch_adam(const AdamArgs& a, void* stream) {
 int launch_route(const float* ys, int nets, int ld_net, int m, int W, const float* x, int kin, float xbound,
                  float* ymean, float* spread, void* stream) {
   if (m <= 0) return 0;
-  k_route<<<(m + 3) / 4, 256, 0, (hipStream_t)stream>>>(ys, nets, ld_net, m, W, x, kin, xbound, ymean, spread);
+  const bool vec = nets == 4 && W % 4 == 0 && ld_net % 4 == 0 && ((uintptr_t)ys & 15) == 0 &&
+                   ((uintptr_t)ymean & 15) == 0;
+  if (vec)
+    k_route4<<<(m + 3) / 4, 256, 0, (hipStream_t)stream>>>(ys, ld_net, m, W, x, kin, xbound, ymean, spread);
+  else
+    k_route<<<(m + 3) / 4, 256, 0, (hipStream_t)stream>>>(ys, nets, ld_net, m, W, x, kin, xbound, ymean, spread);
   return last();
 }
 
 int launch_compact(const float* spread, int n, float threshold, int* ids, int* count, void* stream) {
-  k_compact<<<1, 1024, 0, (hipStream_t)stream>>>(spread, n, threshold, ids, count);
+  if (((uintptr_t)spread & 15) == 0)
+    k_compact_chunks<<<1, 1024, 0, (hipStream_t)stream>>>(spread, n, threshold, ids, count);
+  else
+    k_compact<<<1, 1024, 0, (hipStream_t)stream>>>(spread, n, threshold, ids, count);
   return last();
 }
 

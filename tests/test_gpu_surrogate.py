@@ -144,6 +144,44 @@ def test_infer_route_matches_reference():
     assert _rel(y0, ys[0]) < 2e-3
 
 
+def test_four_net_route_and_fallback_list_exact():
+    """Four nets take the vectorized routing kernel: its means and spreads
+    equal an FP32 emulation from the nets' own outputs (sums over the nets in
+    order from 0, exact peaks, the spread formed in the same order) bit for
+    bit, and the fallback list is exactly the rows whose spread is above the
+    threshold or not finite, in order (5,003 rows: chunks of several rows per
+    thread and a ragged tail)."""
+    e, ps, X, T = _setup(SMALL, nets=4, rows=8192, n=5003, seed=4)
+    Xd = _dev(X)
+    ym, spread, ids, cnt = e.infer_route(Xd, 0.05)
+    torch.cuda.synchronize()
+    ys = [e.forward(q, Xd).cpu().numpy().astype(np.float32) for q in range(4)]
+    acc = np.zeros_like(ys[0])
+    for y in ys:
+        acc = (acc + y).astype(np.float32)
+    assert np.array_equal(ym.cpu().numpy(), (acc / np.float32(4)).astype(np.float32))
+    pk = [y.max(axis=1) for y in ys]
+    pmax = np.full(pk[0].shape, -np.inf, np.float32)
+    pmin = np.full(pk[0].shape, np.inf, np.float32)
+    psum = np.zeros(pk[0].shape, np.float32)
+    for p in pk:
+        pmax, pmin, psum = np.maximum(pmax, p), np.minimum(pmin, p), (psum + p).astype(np.float32)
+    sp = ((pmax - pmin) / np.abs(psum / np.float32(4))).astype(np.float32)
+    got = spread.cpu().numpy()
+    assert np.array_equal(got, sp)
+    for thr in (0.05, float(np.median(got)), 0.0, float("inf")):
+        ym, spread, ids, cnt = e.infer_route(Xd, thr)
+        want = np.nonzero(~(spread.cpu().numpy() <= thr))[0]
+        n = int(cnt.item())
+        assert n == want.size and np.array_equal(ids[:n].cpu().numpy(), want), thr
+    # 70,001 rows: two 64-row segments per thread of the compaction, and a tail
+    Xb = _dev(np.random.default_rng(9).uniform(-1, 1, (70001, SMALL[0])).astype(np.float32))
+    ym, spread, ids, cnt = e.infer_route(Xb, 0.05)
+    want = np.nonzero(~(spread.cpu().numpy() <= 0.05))[0]
+    n = int(cnt.item())
+    assert 0 < n < 70001 and n == want.size and np.array_equal(ids[:n].cpu().numpy(), want)
+
+
 def test_infer_route_empty_and_chunked():
     e, ps, X, T = _setup(SMALL, nets=2, rows=64, n=200)
     ym, spread, ids, cnt = e.infer_route(_dev(X[:0]), 0.02)
