@@ -174,8 +174,10 @@ int launch_fused_debye(int prec, const void* view, const void* dview, int cls16,
 // two streams around the call; they write disjoint tiles).  counts[4] tiles
 // after group 3 (fused: 32 x tile_y) read an oblique wire's source
 // amplitudes: they run last on `stream2`, after it waits for the event
-// `ev_src` (nullptr: no wait) that follows the wire kernels.  Variant 3 also
-// records the probes of `step` on `stream2`, after that wait.
+// `ev_src` (nullptr: no wait) that follows the wire kernels; in variant 3 the
+// first counts[5] of them are clear of the x and y slabs and run as z-only
+// tiles.  Variant 3 also records the probes of `step` on `stream2`, after
+// that wait.
 int launch_lists_step(int prec, const void* view, int cls16, int variant, int step, int tile_y, const void* tiles,
                       const int* counts, void* stream, void* stream2, void* ev_src);
 // Record the probes of step `step` from the view's output set.

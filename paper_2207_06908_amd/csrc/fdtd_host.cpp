@@ -122,7 +122,10 @@ struct fdtd_ctx {
   // interior tiles first, then the CPML tiles; rebuilt when TY or TZ change
   size_t off_tiles = 0, max_tiles = 0;
   std::vector<int> tl;
-  int tl_cnt[5] = {0, 0, 0, 0, 0}, tl_var = -1, tl_ty = -1, tl_kz = -1;
+  // tile counts of the 4 CPML groups, of group 4 (tiles that read an oblique
+  // wire's amplitudes) and of its first part, the tiles clear of the x and y
+  // slabs (two-step pass only)
+  int tl_cnt[6] = {0, 0, 0, 0, 0, 0}, tl_var = -1, tl_ty = -1, tl_kz = -1;
   // the CPML tile groups run on a second stream, concurrently with the
   // clear tiles: fork and join events around each pass
   hipStream_t aux = nullptr;
@@ -1317,6 +1320,14 @@ std::vector<Seg> segments_tb2(int n, int np, int w, int h) {
   return s;
 }
 
+// z chunk (planes) of the tiles that read an oblique wire's amplitudes.
+// They start only once the wire kernels are done, so many short blocks finish
+// the pass sooner than a few tall ones: on the lattice-tower scene, one
+// plane gave 94.6k Mcell-updates/s, two 93.3k, four 85.8k, eight 74.4k and
+// whole chunks 52.2k (the single slanted wire: 101.0k, 101.1k, 99.2k,
+// 96.4k, 93.7k).
+constexpr int G4_CHUNK = 1;
+
 // Tile lists of the fused and two-step passes for a grid with a CPML (see
 // fdtd_ctx::tl and launch_lists_step).
 int ensure_tiles(fdtd_ctx* c, int variant, int ty, int kz) {
@@ -1357,7 +1368,7 @@ int ensure_tiles(fdtd_ctx* c, int variant, int ty, int kz) {
   // wire kernels write before the pass, so they run after those kernels on
   // the second stream (with the all-axes instantiation; fused tiles 32 wide),
   // while the other tiles start at once.
-  std::vector<int> grp4;
+  std::vector<int> grp4, grp4x;  // group 4: from the z-only group, from the others
   if (!c->ow_ekey.empty()) {
     const long long nxl = c->N[0], sxy = nxl * c->N[1];
     std::vector<std::array<int, 3>> pts;
@@ -1380,15 +1391,17 @@ int ensure_tiles(fdtd_ctx* c, int variant, int ty, int kz) {
           keep.insert(keep.end(), v, v + 4);
           continue;
         }
-        // their per-plane source scans make these tiles slow: chunks of 4
-        // planes spread them over more blocks (fused tiles 32 wide)
-        for (int z = v[2]; z < v[3]; z += 4)
+        // chunks of G4_CHUNK planes (fused tiles 32 wide)
+        std::vector<int>& dst = (tb2 && q == 0) ? grp4 : grp4x;
+        for (int z = v[2]; z < v[3]; z += G4_CHUNK)
           for (int xx = 0; xx < (tw == 64 ? 2 : 1); ++xx)
-            grp4.insert(grp4.end(), {v[0] + 32 * xx, v[1], z, std::min(z + 4, v[3])});
+            dst.insert(dst.end(), {v[0] + 32 * xx, v[1], z, std::min(z + G4_CHUNK, v[3])});
       }
       grp[q].swap(keep);
     }
   }
+  c->tl_cnt[5] = (int)(grp4.size() / 4);
+  grp4.insert(grp4.end(), grp4x.begin(), grp4x.end());
   size_t nt = grp4.size() / 4;
   for (int q = 0; q < 4; ++q) nt += grp[q].size() / 4;
   if (nt > c->max_tiles) return fail(c, FDTD_EINVAL, "tile list larger than its reservation");

@@ -969,9 +969,13 @@ hipError_t launch_lists_tb2(const GridView<T>& g, int step, const int4* tiles, c
     const hipError_t we = hipStreamWaitEvent(st2, (hipEvent_t)ev_src, 0);
     if (we != hipSuccess) return we;
   }
-  if (counts[4] > 0)
-    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, 7>), dim3((unsigned)counts[4]), blk, 0, st2, g, t3 + counts[3],
-                       step);
+  // (those clear of the x and y slabs, listed first, as z-only tiles)
+  const int4* t4 = t3 + counts[3];
+  if (counts[5] > 0)
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, D ? 7 : 4>), dim3((unsigned)counts[5]), blk, 0, st2, g, t4, step);
+  if (counts[4] > counts[5])
+    hipLaunchKernelGGL((k_tb2_list<T, CI, true, TY, 7>), dim3((unsigned)(counts[4] - counts[5])), blk, 0, st2, g,
+                       t4 + counts[5], step);
   // The probes' first sample, recomputed from the input set (which no group
   // writes), runs on the second stream beside the clear tiles; the caller
   // reads the second sample after the join (launch_probes2 with first = 0).
