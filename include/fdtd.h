@@ -307,9 +307,9 @@ void fdtd_destroy(fdtd_ctx* c);
 /* ---------------------------------------------------------------------------
  * Batched engine: many independent grids (e.g. a parameter sweep of small,
  * uneven electrode grids) stepped together, one kernel launch per step (or
- * one persistent launch per two-step pass) over a tile list that spans
- * every grid, optionally replayed from a captured HIP graph.  Each grid's
- * results are bit-identical to running it alone.
+ * two persistent launches per two-step pass, one per code path) over tile
+ * lists that span every grid, optionally replayed from a captured HIP
+ * graph.  Each grid's results are bit-identical to running it alone.
  * ------------------------------------------------------------------------- */
 typedef struct fdtd_batch fdtd_batch;
 

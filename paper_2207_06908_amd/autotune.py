@@ -33,7 +33,7 @@ GRID_CANDIDATES: List[Tuple[int, int, int]] = (
 DEBYE_CANDIDATES: List[Tuple[int, int, int]] = (
     [(fdtd.KERNEL_SPLIT, 0, 0)] + [(fdtd.KERNEL_FUSED, 8, tz) for tz in (16, 24, 32, 48, 64)])
 # (TX, TY, TZ, persistent): one-step batch tiles, then two-step 60 x 8
-# tiles launched per CPML group (0) or as one persistent launch (1).
+# tiles launched per CPML group (0) or as persistent work-queue launches (1).
 BATCH_CANDIDATES: List[Tuple[int, int, int, int]] = (
     [(tx, ty, tz, 0) for (tx, ty) in ((32, 8), (32, 16), (64, 8)) for tz in (16, 32, 64)]
     + [(60, 8, tz, p) for tz in (16, 20, 24, 32, 48, 64) for p in (1, 0)]
