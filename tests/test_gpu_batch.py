@@ -116,6 +116,37 @@ def test_persistent_pass_with_every_tile_group(fd):
             assert np.array_equal(gf[gi][c], sf[c]), (gi, c)
 
 
+@pytest.mark.parametrize("precision,npml", [(32, 0), (64, 4)])
+def test_persistent_pass_with_one_code_path(fd, precision, npml):
+    """The persistent two-step pass launches one queue per code path and
+    skips an empty one: FP32 grids without a CPML have no y-slab tiles (only
+    the x-slab path runs), FP64 grids send every tile to the all-axes path.
+    Each grid stays bit for bit its solo run."""
+    scs = [S.random_case(130, 30, 24, npml, seed=31, nsteps=21, n_mats=3),
+           S.random_case(70, 52, 17, npml, seed=32, nsteps=21, n_mats=3)]
+    _say(f"persistent pass, one code path: FP{precision}, npml {npml}")
+
+    def grid(sc):
+        g = fd.Grid.from_params(sc.params(), precision=precision)
+        return g, S.apply(sc, g)
+
+    solo = []
+    for sc in scs:
+        g, ids = grid(sc)
+        g.step(sc.n_steps)
+        solo.append(({p[0]: g.probe(i) for p, i in zip(sc.probes, ids)}, [g.get_field(c) for c in range(6)]))
+    made = [grid(sc) for sc in scs]
+    b = fd.Batch([g for g, _ in made], tile=(60, 8, 16), persistent=True)
+    b.run(scs[0].n_steps)
+    for gi, (sc, (g, ids)) in enumerate(zip(scs, made)):
+        sp, sf = solo[gi]
+        for p, i in zip(sc.probes, ids):
+            assert np.array_equal(b.probe(gi, i), sp[p[0]]), (gi, p[0])
+        for c in range(6):
+            assert np.array_equal(g.get_field(c), sf[c]), (gi, c)
+    del b
+
+
 @pytest.mark.parametrize("tile", [(32, 8, 16), (60, 8, 32)])
 def test_full_sweep_against_stored_oracle_subset(fd, tile):
     path = os.path.join(GOLD, "config3_subset.npz")
