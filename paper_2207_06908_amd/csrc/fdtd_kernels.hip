@@ -35,10 +35,10 @@ namespace mi355fdtd {
 
 template <typename T, typename CI, bool PML>
 __global__ __launch_bounds__(256) void k_h_split(GridView<T> g) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * 4 + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
+  const unsigned t = blockIdx.x * 256u + threadIdx.x;  // node of the xy plane, x fastest
+  if (t >= (unsigned)g.sxy) return;
+  const int i = (int)(t % (unsigned)g.nx), j = (int)(t / (unsigned)g.nx);
+  const int k = blockIdx.y;
   const unsigned n = (unsigned)i + (unsigned)g.nx * ((unsigned)j + (unsigned)g.ny * (unsigned)k);
   const T* cf = g.ctab + (int)ldg((const CI*)g.cls, n) * K_STRIDE;
   const T ex = ldg(g.fi[0], n), ey = ldg(g.fi[1], n), ez = ldg(g.fi[2], n);
@@ -59,10 +59,10 @@ __global__ __launch_bounds__(256) void k_h_split(GridView<T> g) {
 template <typename T, typename CI, bool PML>
 __global__ __launch_bounds__(256) void k_e_split(GridView<T> g, int step) {
   step = gstep(g, step);
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * 4 + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
+  const unsigned t = blockIdx.x * 256u + threadIdx.x;  // node of the xy plane, x fastest
+  if (t >= (unsigned)g.sxy) return;
+  const int i = (int)(t % (unsigned)g.nx), j = (int)(t / (unsigned)g.nx);
+  const int k = blockIdx.y;
   const unsigned n = (unsigned)i + (unsigned)g.nx * ((unsigned)j + (unsigned)g.ny * (unsigned)k);
   const T* cf = g.ctab + (int)ldg((const CI*)g.cls, n) * K_STRIDE;
   const T hx = ldg(g.fi[3], n), hy = ldg(g.fi[4], n), hz = ldg(g.fi[5], n);
@@ -87,10 +87,10 @@ __global__ __launch_bounds__(256) void k_e_split(GridView<T> g, int step) {
 template <typename T, typename CI, bool PML>
 __global__ __launch_bounds__(256) void k_e_split_debye(GridView<T> g, DebyeView<T> d, int step) {
   step = gstep(g, step);
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * 4 + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
+  const unsigned t = blockIdx.x * 256u + threadIdx.x;  // node of the xy plane, x fastest
+  if (t >= (unsigned)g.sxy) return;
+  const int i = (int)(t % (unsigned)g.nx), j = (int)(t / (unsigned)g.nx);
+  const int k = blockIdx.y;
   const unsigned n = (unsigned)i + (unsigned)g.nx * ((unsigned)j + (unsigned)g.ny * (unsigned)k);
   const int cid = (int)ldg((const CI*)g.cls, n);
   const T* cf = g.ctab + cid * K_STRIDE;
@@ -697,7 +697,9 @@ __global__ void k_add(int* p, int v) {
 
 template <typename T, typename CI>
 hipError_t step_split(const GridView<T>& g, int step, hipStream_t st) {
-  const dim3 blk(64, 4, 1), grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+  // one thread per node, 256 consecutive nodes of a plane per block (full
+  // waves whatever nx is)
+  const dim3 blk(256), grd((unsigned)((g.sxy + 255) / 256), (unsigned)g.nz);
   if (g.npml > 0) {
     hipLaunchKernelGGL((k_h_split<T, CI, true>), grd, blk, 0, st, g);
     hipLaunchKernelGGL((k_e_split<T, CI, true>), grd, blk, 0, st, g, step);
@@ -809,7 +811,9 @@ __global__ void __launch_bounds__(64) k_owire_e1(GridView<T> g, OWireView w, int
 
 template <typename T, typename CI>
 hipError_t step_split_debye(const GridView<T>& g, const DebyeView<T>& d, int step, hipStream_t st) {
-  const dim3 blk(64, 4, 1), grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+  // one thread per node, 256 consecutive nodes of a plane per block (full
+  // waves whatever nx is)
+  const dim3 blk(256), grd((unsigned)((g.sxy + 255) / 256), (unsigned)g.nz);
   if (g.npml > 0) {
     hipLaunchKernelGGL((k_h_split<T, CI, true>), grd, blk, 0, st, g);
     hipLaunchKernelGGL((k_e_split_debye<T, CI, true>), grd, blk, 0, st, g, d, step);
