@@ -484,9 +484,7 @@ __global__ __launch_bounds__(64 * (TY + 4), (sizeof(T) == 8 ? 1 : 6)) void k_tb2
                                                                                       int step) {
   step = gstep(g, step);
   __shared__ TB2Smem<T, TY> sm;
-  // blocks dealt to the XCDs in plain order: on the 512 x 512 x 384 grid
-  // this ran 1.6% faster than giving each XCD a contiguous run of the list
-  const int4 t = tiles[blockIdx.x];
+  const int4 t = tiles[xcd_runs(blockIdx.x, gridDim.x)];
   constexpr bool LEAN = AX == 7 && sizeof(T) == 4;
   tb2_tile<T, CI, PML, TY, AX, !LEAN, LEAN>(g, sm, t.x & 0xffff, t.y & 0xffff, t.x >> 16, t.y >> 16, t.z, t.w,
                                            step);
