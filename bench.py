@@ -32,6 +32,7 @@ MEASURED_TRAFFIC = {
     # (source hash, kernel variant, tile_y, tile_z): HBM bytes per step (all
     # launches of the step; a two-step pass counts half)
     ("bcecac58d1d08ec9", "tb2", 8, 20): 4.452e9,
+    ("bcecac58d1d08ec9", "tb2", 8, 16): 4.471e9,
 }
 
 
